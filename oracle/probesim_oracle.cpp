@@ -1,0 +1,403 @@
+// ProbeSim CPU oracle (FP64).  TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, single-threaded implementation of ProbeSim's single-source
+// query, written from the paper (Liu et al., "ProbeSim: Scalable
+// Single-Source and Top-k SimRank Computations on Dynamic Graphs", VLDB 2017)
+// to check the GPU library against.  Only the tests, the smoke check and the
+// benchmark's CPU-baseline leg may load it.  It shares no code with the GPU
+// library: graph build, random numbers, walks, probes and sums are all
+// written here again.
+//
+// What each function follows:
+//   orc_params_derive   Alg. 1 (number of trials), Pruning Rule 1 (walk
+//                       truncation), Theorem 2 (error split)
+//   orc_philox4x32_10   Philox4x32-10 of Salmon et al., SC'11 (the paper leaves
+//                       the random source open; parity unpinned against an
+//                       external known-answer table, which is not available)
+//   orc_walk            Definition of the sqrt(c)-walk (Section 2.2)
+//   orc_probe           Alg. 2 (deterministic PROBE) with Pruning Rule 2
+//   orc_single_source   Alg. 1 (basic ProbeSim) with Pruning Rules 1 and 2
+//   orc_batch           Alg. 3 (reverse reachability tree), same estimate
+//   orc_topk            Definition 2 (top-k by sorting the estimates)
+//
+// Readings where the paper is silent or inconsistent (see the design notes):
+// natural log in n_r; the squared error in n_r; the stop test is taken at every
+// visited node including u_1 and a node with no in-neighbour ends the walk;
+// Rule 2 removes x when Score(x) * sqrt(c)^(i-j-1) <= eps_p, for levels
+// j = 0..i-2 only (never the returned level); the estimate of u itself is 1.
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <algorithm>
+#include <unordered_map>
+#include <vector>
+
+extern "C" {
+
+typedef struct {
+  int32_t n;
+  int64_t m;
+  int64_t* in_ptr;   // n+1 offsets into in_col
+  int32_t* in_col;   // in-neighbours of each node, ascending source id
+  int64_t* out_ptr;  // n+1 offsets into out_col
+  int32_t* out_col;  // out-neighbours of each node, ascending target id
+} orc_graph;
+
+typedef struct {
+  double c, eps_a, delta;
+  double eps_s, eps_t, eps_p;  // sampling error, truncation, pruning
+  int64_t n_r;                 // number of sqrt(c)-walks
+  int32_t L;                   // walk truncation: keep nodes u_1..u_L
+  uint32_t t_stop;             // stop when the first 32-bit word < t_stop
+} orc_params;
+
+typedef struct {
+  int64_t walk_nodes;        // sum of walk lengths
+  int64_t probes;            // PROBE invocations
+  int64_t entries_expanded;  // frontier entries that survived Rule 2
+  int64_t entries_pruned;    // frontier entries removed by Rule 2
+  int64_t edges_scanned;     // out-edges looked at (excluded node included)
+  int64_t next_entries;      // distinct entries created in non-final levels
+  int64_t final_entries;     // entries of returned score sets
+  int64_t near_threshold;    // Rule 2 tests within 1e-5 relative of eps_p
+  double flip_allowance;     // sum of Score*sqrt(c)^e / n_r over those tests
+  int64_t tree_nodes;        // Alg. 3 only: tree nodes below the root
+} orc_stats;
+
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ERANGE = 2, ORC_ESELF = 3, ORC_EDUP = 4 };
+
+// ---------------------------------------------------------------- graph ----
+
+// Builds in- and out-adjacency from an edge list x->y (x is an in-neighbour
+// of y).  The paper's graphs are simple digraphs (Section 2.1): self-loops,
+// duplicates and out-of-range ids are rejected.
+int orc_graph_build(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                    orc_graph** out) {
+  *out = nullptr;
+  if (n <= 0 || m < 0) return ORC_EINVAL;
+  std::vector<std::pair<int32_t, int32_t>> e((size_t)m);
+  for (int64_t i = 0; i < m; ++i) {
+    if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return ORC_ERANGE;
+    if (src[i] == dst[i]) return ORC_ESELF;
+    e[i] = {src[i], dst[i]};
+  }
+  std::sort(e.begin(), e.end());
+  for (int64_t i = 1; i < m; ++i)
+    if (e[i] == e[i - 1]) return ORC_EDUP;
+  orc_graph* g = (orc_graph*)calloc(1, sizeof(orc_graph));
+  g->n = n;
+  g->m = m;
+  g->in_ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  g->out_ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  g->in_col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
+  g->out_col = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m ? m : 1));
+  for (auto& p : e) {
+    g->out_ptr[p.first + 1]++;
+    g->in_ptr[p.second + 1]++;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    g->out_ptr[v + 1] += g->out_ptr[v];
+    g->in_ptr[v + 1] += g->in_ptr[v];
+  }
+  std::vector<int64_t> fo(g->out_ptr, g->out_ptr + n), fi(g->in_ptr, g->in_ptr + n);
+  // e is sorted by (src, dst): out-rows come out ascending by target and,
+  // because sources are visited in ascending order, in-rows ascending by
+  // source.
+  for (auto& p : e) {
+    g->out_col[fo[p.first]++] = p.second;
+    g->in_col[fi[p.second]++] = p.first;
+  }
+  *out = g;
+  return ORC_OK;
+}
+
+void orc_graph_free(orc_graph* g) {
+  if (!g) return;
+  free(g->in_ptr);
+  free(g->in_col);
+  free(g->out_ptr);
+  free(g->out_col);
+  free(g);
+}
+
+static inline int64_t indeg(const orc_graph* g, int32_t v) { return g->in_ptr[v + 1] - g->in_ptr[v]; }
+
+// ----------------------------------------------------------- parameters ----
+
+// n_r = 3c/eps^2 * ln(n/delta) (Alg. 1, first line; rounded up), walks cut to
+// L = floor(ln eps_t / ln sqrt(c)) nodes (Pruning Rule 1).  The default split
+// of eps_a into (eps_s, eps_t, eps_p) satisfies Theorem 2 with the optional
+// eps_t/2 shift switched off:
+//   eps_s = eps_a/2, eps_t = eps_a/4, eps_p = (eps_a/4)(1-sqrt c)/(1+eps_s).
+// A negative override keeps the default; L_in > 0 overrides L.
+int orc_params_derive(int32_t n, double c, double eps_a, double delta, double eps_s_in,
+                      double eps_t_in, double eps_p_in, int32_t L_in, orc_params* p) {
+  if (!(c > 0.0 && c < 1.0) || !(eps_a > 0.0 && eps_a < 1.0) || !(delta > 0.0 && delta < 1.0) ||
+      n <= 0)
+    return ORC_EINVAL;
+  const double sc = std::sqrt(c);
+  p->c = c;
+  p->eps_a = eps_a;
+  p->delta = delta;
+  p->eps_s = eps_s_in >= 0.0 ? eps_s_in : eps_a / 2.0;
+  p->eps_t = eps_t_in >= 0.0 ? eps_t_in : eps_a / 4.0;
+  p->eps_p = eps_p_in >= 0.0 ? eps_p_in : (eps_a / 4.0) * (1.0 - sc) / (1.0 + p->eps_s);
+  if (!(p->eps_s > 0.0) || !(p->eps_t > 0.0 && p->eps_t < 1.0)) return ORC_EINVAL;
+  p->n_r = (int64_t)std::ceil(3.0 * c * std::log((double)n / delta) / (p->eps_s * p->eps_s));
+  p->L = L_in > 0 ? L_in : (int32_t)std::floor(std::log(p->eps_t) / std::log(sc));
+  if (p->L < 2) return ORC_EINVAL;
+  p->t_stop = (uint32_t)std::floor((1.0 - sc) * 4294967296.0);
+  return ORC_OK;
+}
+
+// ---------------------------------------------------------------- Philox ----
+
+// Philox4x32 with 10 rounds.  One round maps the counter (c0,c1,c2,c3) with
+// key (k0,k1) to (hi(B*c2)^c1^k0, lo(B*c2), hi(A*c0)^c3^k1, lo(A*c0)) with
+// A = 0xD2511F53, B = 0xCD9E8D57; between rounds the key is advanced by the
+// Weyl constants (0x9E3779B9, 0xBB67AE85).
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t pa = (uint64_t)0xD2511F53u * x0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t y0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+    const uint32_t y1 = (uint32_t)pb;
+    const uint32_t y2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+    const uint32_t y3 = (uint32_t)pa;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// ----------------------------------------------------------------- walks ----
+
+// One sqrt(c)-walk from u (Definition of the sqrt(c)-walk, Section 2.2): at
+// every visited node draw one Philox block keyed by the seed with counter
+// (walk k, step t, u, 0); the walk stops there when the node has no
+// in-neighbour or the first word is below t_stop (probability ~ 1-sqrt c);
+// otherwise it moves to the in-neighbour with index floor(r64 * |I(v)| / 2^64),
+// r64 = (word2 << 32) | word1, of the ascending in-row.  Walks are cut at L
+// nodes (Pruning Rule 1).  Writes the nodes, returns the length.
+int32_t orc_walk(const orc_graph* g, int32_t u, int64_t k, uint64_t seed, const orc_params* p,
+                 int32_t* nodes) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  int32_t len = 0;
+  int32_t v = u;
+  nodes[len++] = v;
+  for (uint32_t t = 0; len < p->L; ++t) {
+    const uint32_t ctr[4] = {(uint32_t)k, t, (uint32_t)u, 0u};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    const int64_t d = indeg(g, v);
+    if (d == 0 || w[0] < p->t_stop) break;
+    const uint64_t r = ((uint64_t)w[2] << 32) | w[1];
+    const uint64_t idx = (uint64_t)(((unsigned __int128)r * (uint64_t)d) >> 64);
+    v = g->in_col[g->in_ptr[v] + (int64_t)idx];
+    nodes[len++] = v;
+  }
+  return len;
+}
+
+// ----------------------------------------------------------------- probe ----
+
+// A hash_set of (node, score) pairs as Alg. 2 uses them, kept as a dense score
+// array plus the list of present keys in insertion order.
+struct ScoreSet {
+  std::vector<double> val;
+  std::vector<char> present;
+  std::vector<int32_t> keys;
+  explicit ScoreSet(int32_t n) : val((size_t)n, 0.0), present((size_t)n, 0) {}
+  void add(int32_t v, double x) {
+    if (!present[v]) {
+      present[v] = 1;
+      val[v] = 0.0;
+      keys.push_back(v);
+    }
+    val[v] += x;
+  }
+  void clear() {
+    for (int32_t v : keys) {
+      present[v] = 0;
+      val[v] = 0.0;
+    }
+    keys.clear();
+  }
+};
+
+// Alg. 2 on the partial walk path[0..i-1] = (u_1..u_i), with Pruning Rule 2
+// when eps_p > 0.  H_0 = {u_i: 1}; for j = 0..i-2: remove x from H_j when
+// Score(x) * sqrt(c)^(i-j-1) <= eps_p, then for each kept x and each
+// out-neighbour v of x other than u_{i-j-1} add sqrt(c)/|I(v)| * Score(x) to
+// H_{j+1}[v].  The returned set is H_{i-1}; by Lemma 2 (Score) its value at v
+// is the first-meeting probability P(v, (u_1..u_i)).
+static void probe(const orc_graph* g, const int32_t* path, int32_t i, double sc, double eps_p,
+                  double n_r, ScoreSet& cur, ScoreSet& nxt, orc_stats* st) {
+  cur.clear();
+  cur.add(path[i - 1], 1.0);
+  for (int32_t j = 0; j <= i - 2; ++j) {
+    const int32_t excl = path[i - j - 2];  // u_{i-j-1}
+    const double pw = std::pow(sc, (double)(i - j - 1));
+    nxt.clear();
+    for (int32_t x : cur.keys) {
+      const double s = cur.val[x];
+      if (eps_p > 0.0) {
+        const double proj = s * pw;
+        if (st && std::fabs(proj - eps_p) <= 1e-5 * eps_p) {
+          st->near_threshold++;
+          st->flip_allowance += proj / n_r;
+        }
+        if (proj <= eps_p) {
+          if (st) st->entries_pruned++;
+          continue;
+        }
+      }
+      if (st) st->entries_expanded++;
+      for (int64_t e = g->out_ptr[x]; e < g->out_ptr[x + 1]; ++e) {
+        const int32_t v = g->out_col[e];
+        if (st) st->edges_scanned++;
+        if (v == excl) continue;
+        nxt.add(v, sc / (double)indeg(g, v) * s);
+      }
+    }
+    if (st && j < i - 2) st->next_entries += (int64_t)nxt.keys.size();
+    std::swap(cur.val, nxt.val);
+    std::swap(cur.present, nxt.present);
+    std::swap(cur.keys, nxt.keys);
+  }
+  if (st) {
+    st->probes++;
+    st->final_entries += (int64_t)cur.keys.size();
+  }
+}
+
+// Alg. 2 alone, for tests: dense scores of PROBE((u_1..u_i)).
+int orc_probe(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p,
+              double* out) {
+  if (i < 2) return ORC_EINVAL;
+  for (int32_t t = 0; t < i; ++t)
+    if (path[t] < 0 || path[t] >= g->n) return ORC_ERANGE;
+  ScoreSet cur(g->n), nxt(g->n);
+  probe(g, path, i, std::sqrt(c), eps_p, 1.0, cur, nxt, nullptr);
+  std::fill(out, out + g->n, 0.0);
+  for (int32_t v : cur.keys) out[v] = cur.val[v];
+  return ORC_OK;
+}
+
+static void finish(const orc_graph* g, int32_t u, const orc_params* p, int bias_shift,
+                   const std::vector<double>& acc, double* out) {
+  for (int32_t v = 0; v < g->n; ++v) {
+    out[v] = acc[v] / (double)p->n_r;
+    if (bias_shift && v != u) out[v] += p->eps_t / 2.0;  // Section 4.1, after Rule 1
+  }
+  out[u] = 1.0;
+}
+
+// Alg. 1: for walks k in [k_begin, k_end) sample W_k(u), PROBE every prefix
+// (u_1..u_i), i = 2..len, and sum the scores; the estimate is the sum over
+// walks divided by n_r (the running average of Alg. 1 is the same number).
+// A sub-range of walks gives that range's share of the sum.
+int orc_single_source(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
+                      int64_t k_begin, int64_t k_end, int bias_shift, double* out, orc_stats* st) {
+  if (u < 0 || u >= g->n) return ORC_ERANGE;
+  if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
+  if (st) memset(st, 0, sizeof(*st));
+  const double sc = std::sqrt(p->c);
+  std::vector<double> acc((size_t)g->n, 0.0);
+  std::vector<int32_t> walk((size_t)p->L);
+  ScoreSet cur(g->n), nxt(g->n);
+  for (int64_t k = k_begin; k < k_end; ++k) {
+    const int32_t len = orc_walk(g, u, k, seed, p, walk.data());
+    if (st) st->walk_nodes += len;
+    for (int32_t i = 2; i <= len; ++i) {
+      probe(g, walk.data(), i, sc, p->eps_p, (double)p->n_r, cur, nxt, st);
+      for (int32_t v : cur.keys) acc[v] += cur.val[v];
+    }
+  }
+  finish(g, u, p, bias_shift, acc, out);
+  return ORC_OK;
+}
+
+// Alg. 3: insert the walks into a reverse reachability tree (one tree node per
+// distinct prefix (u_1..u_q), q >= 2, weighted by the number of walks sharing
+// it), PROBE every tree node once and add weight/n_r * Score.
+int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
+              int64_t k_end, int bias_shift, double* out, orc_stats* st) {
+  if (u < 0 || u >= g->n) return ORC_ERANGE;
+  if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
+  if (st) memset(st, 0, sizeof(*st));
+  struct TNode {
+    int64_t parent;
+    int32_t node, depth;
+    int64_t weight;
+  };
+  std::vector<TNode> tree;
+  tree.push_back({-1, u, 1, 0});
+  std::unordered_map<uint64_t, int64_t> child;  // (parent id, graph node) -> id
+  std::vector<int32_t> walk((size_t)p->L);
+  for (int64_t k = k_begin; k < k_end; ++k) {
+    const int32_t len = orc_walk(g, u, k, seed, p, walk.data());
+    if (st) st->walk_nodes += len;
+    int64_t cur = 0;
+    for (int32_t i = 2; i <= len; ++i) {
+      const uint64_t key = ((uint64_t)cur << 32) | (uint32_t)walk[i - 1];
+      auto it = child.find(key);
+      if (it == child.end()) {
+        tree.push_back({cur, walk[i - 1], i, 0});
+        it = child.emplace(key, (int64_t)tree.size() - 1).first;
+      }
+      cur = it->second;
+      tree[cur].weight++;
+    }
+  }
+  if (st) st->tree_nodes = (int64_t)tree.size() - 1;
+  const double sc = std::sqrt(p->c);
+  std::vector<double> acc((size_t)g->n, 0.0);
+  std::vector<int32_t> path;
+  ScoreSet cur(g->n), nxt(g->n);
+  for (size_t q = 1; q < tree.size(); ++q) {
+    const int32_t i = tree[q].depth;
+    path.assign((size_t)i, 0);
+    for (int64_t a = (int64_t)q; a >= 0; a = tree[a].parent) path[tree[a].depth - 1] = tree[a].node;
+    probe(g, path.data(), i, sc, p->eps_p, (double)p->n_r / (double)tree[q].weight, cur, nxt, st);
+    const double w = (double)tree[q].weight;
+    for (int32_t v : cur.keys) acc[v] += w * cur.val[v];
+  }
+  finish(g, u, p, bias_shift, acc, out);
+  return ORC_OK;
+}
+
+// Definition 2: the k nodes v != u with the largest estimates; equal
+// estimates are ordered by ascending node id.  k must lie in [1, n-1].
+int orc_topk(const double* s, int32_t n, int32_t u, int32_t k, int32_t* nodes, double* scores) {
+  if (u < 0 || u >= n) return ORC_ERANGE;
+  if (k < 1 || k > n - 1) return ORC_EINVAL;
+  std::vector<int32_t> ids;
+  ids.reserve((size_t)n - 1);
+  for (int32_t v = 0; v < n; ++v)
+    if (v != u) ids.push_back(v);
+  std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+    if (s[a] != s[b]) return s[a] > s[b];
+    return a < b;
+  });
+  for (int32_t t = 0; t < k; ++t) {
+    nodes[t] = ids[t];
+    scores[t] = s[ids[t]];
+  }
+  return ORC_OK;
+}
+
+}  // extern "C"
