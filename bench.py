@@ -1,0 +1,161 @@
+"""Benchmark: single-source ProbeSim queries/s on one MI355X.
+
+Workload: directed Chung-Lu power-law graph, 1M nodes, 10M edges, in/out
+exponent 2.1 (synthetic stand-in for the paper's social/web graphs); 32 query
+nodes drawn uniformly from the nodes with in-edges; c = 0.6, eps = 0.05,
+delta = 0.01; walk seed 3 + query index.  One step = the 32 queries run one at
+a time through ps_single_source (plain mode), every stage on the GPU, inputs
+resident in HBM, estimates written to a device tensor.  The same 32 queries
+are also timed as one ps_batch launch (batched mode).
+
+Prints one JSON line.  The roofline entry covers the PROBE expansion kernel
+(k_expand), timed with HIP events on the stream it runs on; its algorithmic
+bytes per launch come from the kernel's own work counters.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "cl_1m_10m"
+C, EPS, DELTA = 0.6, 0.05, 0.01
+NQ = 32
+
+
+def expand_bytes(st: dict) -> float:
+    """Algorithmic bytes moved by k_expand for the given work counters:
+    20 B per expanded entry (list entry 8, score 4, row start/len 8),
+    8 B per scanned out-edge (neighbour id 4, 1/|I(v)| 4),
+    8 B per inner-level contribution (FP32 score read-modify-write),
+    8 B per new next-level entry (list write),
+    16 B per final contribution (FP64 estimate read-modify-write)."""
+    F, E = st["entries_expanded"], st["edges_scanned"]
+    N, Fin = st["next_entries"], st["final_adds"]
+    inner = max(E - Fin, 0)
+    return 20.0 * F + 8.0 * E + 8.0 * inner + 8.0 * N + 16.0 * Fin
+
+
+def cpu_baseline(n, s, d, q, seconds_target=15.0):
+    """The oracle (Alg. 1, FP64, one thread) on a bounded sample: the first
+    walks of the first query, scaled to queries/s by n_r (Alg. 1's cost is a
+    sum of independent per-walk costs)."""
+    import oracle
+
+    G = oracle.Graph(n, s, d)
+    p = oracle.params(n, C, EPS, DELTA)
+    u = int(q[0])
+    walks, spent, k = 0, 0.0, 0
+    chunk = 100
+    while spent < seconds_target and k < p.n_r:
+        t0 = time.perf_counter()
+        oracle.single_source(G, u, p, 3, k, min(k + chunk, p.n_r))
+        spent += time.perf_counter() - t0
+        walks += min(k + chunk, p.n_r) - k
+        k += chunk
+    per_query = spent / walks * p.n_r
+    return {"value": 1.0 / per_query, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": f"Alg. 1 oracle, query node {u}, walks [0, {walks}) of n_r = {p.n_r}, "
+                      f"{spent:.1f} s, scaled by n_r / {walks}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slots", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(queries shard across GPUs by data parallelism, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1709_06955_amd as ps
+    from synth import graphs
+
+    n, s, d = graphs.make_workload(WORKLOAD)
+    q = graphs.query_nodes(n, d, NQ)
+    stream = torch.cuda.current_stream()
+    ctx = ps.Context(0, stream=stream)
+    G = ps.Graph(ctx, n, s, d)
+    out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    ctx.set_timing(True)
+
+    def plain_step(acc):
+        for i, u in enumerate(q):
+            ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots)
+            if acc is not None:
+                st = ctx.stats()
+                for k in acc:
+                    acc[k] += st[k]
+
+    for _ in range(args.warmup):
+        plain_step(None)
+    keys = ["expand_ms", "expand_launches", "entries_expanded", "edges_scanned", "next_entries", "final_adds",
+            "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned"]
+    acc = {k: 0 for k in keys}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_step(acc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    queries = NQ * args.steps
+    qps = queries / dt
+
+    # Batched: the same 32 queries in one launch.
+    outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in range(NQ)]
+    qlist = [dict(u=int(u), k=0, c=C, eps=EPS, delta=DELTA, seed=3 + i) for i, u in enumerate(q)]
+    ps.ps_batch(G, qlist, outs=outs, slots=args.slots)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    ps.ps_batch(G, qlist, outs=outs, slots=args.slots)
+    torch.cuda.synchronize()
+    batched_qps = NQ / (time.perf_counter() - tb)
+
+    alg_bytes = expand_bytes(acc)
+    launches = max(acc["expand_launches"], 1)
+    avg_ms = acc["expand_ms"] / launches
+    achieved = (alg_bytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    result = {
+        "metric": "single-source queries/s at eps=0.05 (plain, one query at a time)",
+        "value": qps,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 probes, f64 accumulation",
+        "data": "synthetic (seeded Chung-Lu power-law graph; the paper's SNAP/LAW graphs are not available)",
+        "config": {"workload": "Chung-Lu directed power-law graph, 1M nodes, 10M edges, exponent 2.1; "
+                               "32 uniform query nodes with in-edges run one at a time; c=0.6, eps=0.05, "
+                               "delta=0.01", "queries_per_step": NQ},
+        "batched_qps": batched_qps,
+        "batched_speedup": batched_qps / qps,
+        "roofline": {"bound": "hbm", "kernel": "k_expand", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches},
+        "work_per_query": {k: acc[k] / queries for k in keys if k not in ("expand_ms",)},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(n, s, d, q)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,254 @@
+/*
+ * probesim.h -- C ABI of the MI355X ProbeSim library.
+ *
+ * The library answers approximate single-source and top-k SimRank queries
+ * with ProbeSim (Liu et al., "ProbeSim: Scalable Single-Source and Top-k
+ * SimRank Computations on Dynamic Graphs", PVLDB 11(1), 2017) on one AMD
+ * Instinct MI355X (gfx950).  Every step of a query -- sqrt(c)-walk sampling,
+ * the reverse reachability tree, PROBE level expansion with both pruning
+ * rules, accumulation of the estimate and top-k selection -- runs in the
+ * library's own HIP kernels.
+ *
+ * Conventions for every entry point:
+ *  - Nothing throws across the ABI; every call returns a ps_status.
+ *  - Graph input arrays are borrowed for the duration of the call only; the
+ *    library copies what it keeps.
+ *  - Output buffers are owned by the caller.  A pointer is accepted either as
+ *    host memory or as device memory of the context's GPU (for instance a
+ *    torch tensor's data_ptr()); the library tells the two apart with
+ *    hipPointerGetAttributes.  Synchronous calls have finished writing their
+ *    outputs when they return.
+ *  - Node ids are int32 in [0, n).  An edge x -> y means x is an in-neighbour
+ *    of y (x in I(y)); walks follow in-edges, PROBE follows out-edges.
+ *  - Calls on one context are not thread-safe unless stated otherwise; the
+ *    server (ps_server_*) is the thread-safe entry.
+ */
+#ifndef PROBESIM_H
+#define PROBESIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ps_status {
+  PS_OK = 0,
+  PS_ERR_INVALID_ARG = 1, /* c, eps or delta outside (0,1); bad k; bad options */
+  PS_ERR_NODE_RANGE = 2,  /* a node id outside [0, n) */
+  PS_ERR_SELF_LOOP = 3,   /* edge x -> x in a simple digraph (Section 2.1) */
+  PS_ERR_DUP_EDGE = 4,    /* edge already present */
+  PS_ERR_NO_EDGE = 5,     /* deleting an edge that is absent */
+  PS_ERR_OOM = 6,         /* device or host allocation failed */
+  PS_ERR_BUSY = 7,        /* server request ring is full */
+  PS_ERR_DEVICE = 8,      /* a HIP runtime call failed */
+  PS_ERR_TIMEOUT = 9,     /* ps_wait ran out of time */
+  PS_ERR_STATE = 10       /* call not valid in the object's current state */
+} ps_status;
+
+typedef struct ps_ctx ps_ctx;
+typedef struct ps_graph ps_graph;
+typedef struct ps_server ps_server;
+
+/* Human-readable name of a status code (static storage). */
+const char* ps_status_string(ps_status s);
+
+/* ------------------------------------------------------------ context -- */
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * to launch on (for example torch.cuda.current_stream().cuda_stream); NULL
+ * makes the library create its own stream.  The context owns its device
+ * workspace, which grows on demand and is freed by ps_ctx_destroy. */
+ps_status ps_ctx_create(int device, void* hip_stream, ps_ctx** out);
+void ps_ctx_destroy(ps_ctx* ctx);
+
+/* With enable != 0 every PROBE expansion launch is bracketed by HIP events on
+ * the context's stream; ps_get_stats then reports their summed duration. */
+ps_status ps_ctx_set_timing(ps_ctx* ctx, int enable);
+
+/* -------------------------------------------------------------- graph -- */
+
+#define PS_LOAD_DEDUP 1u           /* drop duplicate edges instead of failing */
+#define PS_LOAD_DROP_SELF_LOOPS 2u /* drop self-loops instead of failing */
+
+/* Loads the directed simple graph G = (V, E), |V| = n, with m edges
+ * src[i] -> dst[i] (host arrays of m int32).  Builds, on the device, the
+ * in-adjacency (each row in ascending source id: the canonical order walks
+ * index into) and the out-adjacency, plus 1/|I(v)|.  Errors:
+ * PS_ERR_NODE_RANGE for an id outside [0, n); PS_ERR_SELF_LOOP /
+ * PS_ERR_DUP_EDGE unless the matching PS_LOAD_* flag is set;
+ * PS_ERR_INVALID_ARG for n <= 0, m < 0 or m >= 2^31. */
+ps_status ps_graph_load(ps_ctx* ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                        uint32_t flags, ps_graph** out);
+void ps_graph_free(ps_graph* g);
+
+/* n, live edge count and version (starts at 0, +1 per applied update batch). */
+ps_status ps_graph_info(const ps_graph* g, int32_t* n, int64_t* m, uint64_t* version);
+
+/* Applies k edge updates in order: op[i] = 0 inserts src[i] -> dst[i], 1
+ * deletes it.  The paper's method is index-free (abstract; Section 1), so an
+ * update only rewrites the affected adjacency rows (copy-on-write into a
+ * device delta region) and 1/|I(v)|; queries issued afterwards see the new
+ * version.  Invalid single updates (self-loop, inserting an existing edge,
+ * deleting an absent one) are skipped; their status goes to per_edge[i]
+ * (nullable: without it the first such error is returned after all valid
+ * updates are applied).  An id outside [0, n) fails the whole call before
+ * anything changes.  *version (nullable) receives the new version. */
+ps_status ps_graph_update(ps_graph* g, int64_t k, const int32_t* src, const int32_t* dst,
+                          const uint8_t* op, int32_t* per_edge, uint64_t* version);
+
+/* Copies the current edge list (ascending by (src, dst)) into host arrays of
+ * capacity `cap`; *m receives the edge count.  PS_ERR_INVALID_ARG if cap is
+ * too small (with *m set). */
+ps_status ps_graph_edges(const ps_graph* g, int64_t cap, int32_t* src, int32_t* dst, int64_t* m);
+
+/* --------------------------------------------------------- parameters -- */
+
+typedef struct ps_options {
+  double eps_s;       /* sampling error; < 0: eps/2 */
+  double eps_t;       /* Rule 1 truncation parameter; < 0: eps/4 */
+  double eps_p;       /* Rule 2 pruning parameter; < 0: (eps/4)(1-sqrt c)/(1+eps_s); 0: no pruning */
+  int32_t max_len;    /* > 0: walk length cap L overriding Rule 1 (at most PS_MAX_WALK_LEN) */
+  int32_t bias_shift; /* nonzero: add eps_t/2 to every estimate but u's (Section 4.1) */
+  int64_t walk_begin; /* first walk index (default 0) */
+  int64_t walk_end;   /* one past the last walk index; < 0: n_r.  A sub-range
+                         returns that range's share of the sum over walks
+                         (still divided by the full n_r), so shards add up. */
+  int32_t slots;      /* concurrent probes on the device; 0: automatic */
+  int32_t reserved;
+} ps_options;
+
+#define PS_MAX_WALK_LEN 64
+
+/* Fills the defaults above. */
+void ps_options_default(ps_options* opt);
+
+typedef struct ps_params {
+  double c, eps_a, delta;
+  double eps_s, eps_t, eps_p;
+  int64_t n_r;     /* number of sqrt(c)-walks: ceil(3c ln(n/delta) / eps_s^2) (Alg. 1) */
+  int32_t L;       /* walks keep nodes u_1..u_L, L = floor(ln eps_t / ln sqrt c) (Rule 1) */
+  uint32_t t_stop; /* a walk stops at a node when its Philox word 0 < t_stop = floor((1-sqrt c) 2^32) */
+} ps_params;
+
+/* Derives the query parameters for a graph of n nodes.  Default split of the
+ * absolute error eps (Definition 1) into sampling, truncation and pruning
+ * error satisfies Theorem 2 with the optional shift off:
+ *   eps_s = eps/2, eps_t = eps/4, eps_p = (eps/4)(1 - sqrt c)/(1 + eps_s).
+ * PS_ERR_INVALID_ARG for c, eps, delta outside (0,1), for L < 2 or
+ * L > PS_MAX_WALK_LEN. */
+ps_status ps_derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt,
+                           ps_params* out);
+
+/* -------------------------------------------------------------- query -- */
+
+/* The sqrt(c)-walks of a query (Definition of the sqrt(c)-walk, Section 2.2),
+ * as the query itself samples them: walk k stops at a node v when v has no
+ * in-neighbour or word 0 of Philox4x32-10(key = seed, counter = (k, t, u, 0))
+ * is below t_stop (t = index of v in the walk, from 0); otherwise it moves to
+ * the in-neighbour with index floor(r64 * |I(v)| / 2^64), r64 = word2 << 32 |
+ * word1, of v's ascending in-row; it keeps at most L nodes (Rule 1).  Writes
+ * walks k_begin .. k_begin+count-1 as rows of L int32 (unused entries -1) to
+ * `nodes` and their lengths to `lens` (host or device). */
+ps_status ps_walks(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
+                   const ps_options* opt, int64_t k_begin, int64_t count, int32_t* nodes, int32_t* lens);
+
+/* Approximate single-source query (Definition 1): writes n doubles,
+ * out[v] = estimate of s(u, v), out[u] = 1.  Samples n_r sqrt(c)-walks
+ * from u, merges them into the reverse reachability tree (Alg. 3), runs
+ * deterministic PROBE (Alg. 2) once per tree node with Rule 2 pruning and
+ * adds weight/n_r * Score to the estimate.  Probe scores are FP32, the
+ * estimate is accumulated in FP64.  Deterministic for fixed (graph version,
+ * u, c, eps, delta, seed, options) up to floating-point summation order. */
+ps_status ps_single_source(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
+                           const ps_options* opt, double* out);
+
+/* Approximate top-k query (Definition 2): the k nodes v != u with the largest
+ * estimates, ties broken by ascending node id, written to nodes[k] and their
+ * estimates to scores[k].  k must lie in [1, n-1]. */
+ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
+                  const ps_options* opt, int32_t* nodes, double* scores);
+
+typedef struct ps_query {
+  int32_t u;
+  int32_t k; /* 0: single-source (n scores); > 0: top-k */
+  double c, eps, delta;
+  uint64_t seed;
+} ps_query;
+
+typedef struct ps_result {
+  double* scores; /* n doubles for single-source, k for top-k (caller-owned) */
+  int32_t* nodes; /* k node ids for top-k; unused for single-source */
+  int32_t status; /* ps_status of this query */
+  int32_t count;  /* entries written */
+} ps_result;
+
+/* Runs nq queries together: all their walks, trees and probes share the
+ * device's probe slots and one level-synchronous launch sequence.  Each
+ * result equals the same query run alone (up to summation order).  opt
+ * applies to every query (its walk range must be the default).  Per-query
+ * argument errors are reported in r[i].status and do not stop the others. */
+ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* q, const ps_options* opt, ps_result* r);
+
+/* Work counters and timings of the last query call on this context. */
+typedef struct ps_stats {
+  int64_t queries;
+  int64_t walks;            /* walks sampled */
+  int64_t walk_nodes;       /* sum of walk lengths */
+  int64_t tree_nodes;       /* probes: reverse reachability tree nodes below the roots */
+  int64_t probe_levels;     /* sum over probes of (depth - 1) */
+  int64_t steps;            /* level steps launched */
+  int64_t entries_expanded; /* frontier entries kept by Rule 2 and expanded */
+  int64_t entries_pruned;   /* frontier entries removed by Rule 2 */
+  int64_t edges_scanned;    /* out-edges of expanded entries */
+  int64_t next_entries;     /* distinct (probe, node) entries created in inner levels */
+  int64_t final_adds;       /* contributions added into estimates */
+  int64_t expand_launches;  /* PROBE expansion kernel launches */
+  double expand_ms;         /* their summed duration (timing enabled) */
+  double total_ms;          /* wall time of the call */
+} ps_stats;
+
+ps_status ps_get_stats(ps_ctx* ctx, ps_stats* out);
+
+/* ------------------------------------------------------------- server -- */
+
+typedef struct ps_server_cfg {
+  int32_t ring;           /* request ring capacity (0: 1024) */
+  int32_t max_inflight;   /* queries admitted on the device at once (0: 64) */
+  int32_t slots;          /* probe slots (0: automatic) */
+  int32_t reserved;
+  int64_t frontier_bytes; /* device memory budget for admitted queries (0: automatic) */
+} ps_server_cfg;
+
+/* Starts a serving loop on the graph's context: a host thread that drains
+ * the request ring, admits queries onto the device while slots and the
+ * memory budget allow, runs level steps of all admitted queries together
+ * (continuous batching: a query that arrives while others are running joins
+ * at the next level step) and applies edge updates between level steps.  The
+ * context must not be used directly while the server runs. */
+ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_server** out);
+
+/* Queues one query.  r->scores / r->nodes must be host buffers that stay
+ * valid until ps_wait returns for the ticket.  PS_ERR_BUSY when the ring is
+ * full.  Thread-safe. */
+ps_status ps_submit(ps_server* s, const ps_query* q, ps_result* r, uint64_t* ticket);
+
+/* Waits up to timeout_us microseconds (< 0: forever) for a ticket; returns
+ * the query's status, or PS_ERR_TIMEOUT.  Thread-safe. */
+ps_status ps_wait(ps_server* s, uint64_t ticket, int64_t timeout_us);
+
+/* Queues edge updates (as ps_graph_update); they are applied between level
+ * steps.  A query sees the graph version current when it was admitted.
+ * Thread-safe; the arrays are copied. */
+ps_status ps_server_update(ps_server* s, int64_t k, const int32_t* src, const int32_t* dst,
+                           const uint8_t* op);
+
+/* Stops accepting requests, finishes the queued and running ones, joins the
+ * loop and frees the server. */
+ps_status ps_server_stop(ps_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROBESIM_H */

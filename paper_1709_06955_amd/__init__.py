@@ -1,0 +1,346 @@
+"""Python binding of the MI355X ProbeSim library (libprobesim.so).
+
+Argument marshalling only: every step of a query runs in the library's HIP
+kernels.  PyTorch supplies device memory (output tensors) and the stream.
+The binding refuses to work without the built library; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprobesim.so")
+
+PS_OK = 0
+STATUS = {
+    0: "PS_OK", 1: "PS_ERR_INVALID_ARG", 2: "PS_ERR_NODE_RANGE", 3: "PS_ERR_SELF_LOOP",
+    4: "PS_ERR_DUP_EDGE", 5: "PS_ERR_NO_EDGE", 6: "PS_ERR_OOM", 7: "PS_ERR_BUSY",
+    8: "PS_ERR_DEVICE", 9: "PS_ERR_TIMEOUT", 10: "PS_ERR_STATE",
+}
+PS_LOAD_DEDUP = 1
+PS_LOAD_DROP_SELF_LOOPS = 2
+PS_MAX_WALK_LEN = 64
+
+# Every entry point declared in include/probesim.h.
+EXPORTS = [
+    "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
+    "ps_graph_free", "ps_graph_info", "ps_graph_update", "ps_graph_edges", "ps_options_default",
+    "ps_derive_params", "ps_walks", "ps_single_source", "ps_topk", "ps_batch", "ps_get_stats",
+    "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop",
+]
+
+
+class ProbeSimError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("eps_s", C.c_double), ("eps_t", C.c_double), ("eps_p", C.c_double),
+        ("max_len", C.c_int32), ("bias_shift", C.c_int32),
+        ("walk_begin", C.c_int64), ("walk_end", C.c_int64),
+        ("slots", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("c", C.c_double), ("eps_a", C.c_double), ("delta", C.c_double),
+        ("eps_s", C.c_double), ("eps_t", C.c_double), ("eps_p", C.c_double),
+        ("n_r", C.c_int64), ("L", C.c_int32), ("t_stop", C.c_uint32),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "queries", "walks", "walk_nodes", "tree_nodes", "probe_levels", "steps", "entries_expanded",
+        "entries_pruned", "edges_scanned", "next_entries", "final_adds", "expand_launches")] + [
+        ("expand_ms", C.c_double), ("total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Query(C.Structure):
+    _fields_ = [("u", C.c_int32), ("k", C.c_int32), ("c", C.c_double), ("eps", C.c_double),
+                ("delta", C.c_double), ("seed", C.c_uint64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("scores", C.c_void_p), ("nodes", C.c_void_p), ("status", C.c_int32), ("count", C.c_int32)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("ring", C.c_int32), ("max_inflight", C.c_int32), ("slots", C.c_int32),
+                ("reserved", C.c_int32), ("frontier_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libprobesim.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with python -m paper_1709_06955_amd.build")
+    L = C.CDLL(path)
+    P, vp = C.POINTER, C.c_void_p
+    sig = {
+        "ps_status_string": ([C.c_int], C.c_char_p),
+        "ps_ctx_create": ([C.c_int, vp, P(vp)], C.c_int),
+        "ps_ctx_destroy": ([vp], None),
+        "ps_ctx_set_timing": ([vp, C.c_int], C.c_int),
+        "ps_graph_load": ([vp, C.c_int32, C.c_int64, vp, vp, C.c_uint32, P(vp)], C.c_int),
+        "ps_graph_free": ([vp], None),
+        "ps_graph_info": ([vp, P(C.c_int32), P(C.c_int64), P(C.c_uint64)], C.c_int),
+        "ps_graph_update": ([vp, C.c_int64, vp, vp, vp, vp, P(C.c_uint64)], C.c_int),
+        "ps_graph_edges": ([vp, C.c_int64, vp, vp, P(C.c_int64)], C.c_int),
+        "ps_options_default": ([P(Options)], None),
+        "ps_derive_params": ([C.c_int32, C.c_double, C.c_double, C.c_double, P(Options), P(Params)], C.c_int),
+        "ps_walks": ([vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), C.c_int64,
+                      C.c_int64, vp, vp], C.c_int),
+        "ps_single_source": ([vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), vp],
+                             C.c_int),
+        "ps_topk": ([vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), vp,
+                     vp], C.c_int),
+        "ps_batch": ([vp, C.c_int32, P(Query), P(Options), P(Result)], C.c_int),
+        "ps_get_stats": ([vp, P(Stats)], C.c_int),
+        "ps_server_start": ([vp, P(ServerCfg), P(vp)], C.c_int),
+        "ps_submit": ([vp, P(Query), P(Result), P(C.c_uint64)], C.c_int),
+        "ps_wait": ([vp, C.c_uint64, C.c_int64], C.c_int),
+        "ps_server_update": ([vp, C.c_int64, vp, vp, vp], C.c_int),
+        "ps_server_stop": ([vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(code, what):
+    if code != PS_OK:
+        raise ProbeSimError(code, what)
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def options(**kw) -> Options:
+    o = Options()
+    load_library().ps_options_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def derive_params(n, c, eps, delta, **opt) -> Params:
+    p = Params()
+    o = options(**opt)
+    _check(load_library().ps_derive_params(int(n), c, eps, delta, C.byref(o), C.byref(p)), "ps_derive_params")
+    return p
+
+
+class Context:
+    """A device context; pass a torch stream to launch on it."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = load_library()
+        h = C.c_void_p()
+        s = None
+        if stream is not None:
+            s = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        _check(L.ps_ctx_create(int(device), s, C.byref(h)), "ps_ctx_create")
+        self._h = h
+        self.device = device
+
+    def set_timing(self, on: bool):
+        _check(load_library().ps_ctx_set_timing(self._h, int(on)), "ps_ctx_set_timing")
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(load_library().ps_get_stats(self._h, C.byref(st)), "ps_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ps_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A device-resident graph (edges src[i] -> dst[i])."""
+
+    def __init__(self, ctx: Context, n: int, src, dst, flags: int = 0):
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        h = C.c_void_p()
+        _check(load_library().ps_graph_load(ctx._h, int(n), int(s.size), s.ctypes.data, d.ctypes.data,
+                                            int(flags), C.byref(h)), "ps_graph_load")
+        self._h = h
+        self.ctx = ctx
+        self.n = int(n)
+
+    def info(self):
+        n, m, v = C.c_int32(), C.c_int64(), C.c_uint64()
+        _check(load_library().ps_graph_info(self._h, C.byref(n), C.byref(m), C.byref(v)), "ps_graph_info")
+        return n.value, m.value, v.value
+
+    def update(self, src, dst, op, per_edge: bool = True):
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        o = np.ascontiguousarray(op, dtype=np.uint8)
+        pe = np.zeros(s.size, dtype=np.int32)
+        ver = C.c_uint64()
+        _check(load_library().ps_graph_update(self._h, int(s.size), s.ctypes.data, d.ctypes.data, o.ctypes.data,
+                                              pe.ctypes.data if per_edge else None, C.byref(ver)),
+               "ps_graph_update")
+        return pe, ver.value
+
+    def edges(self):
+        _, m, _ = self.info()
+        s = np.zeros(max(m, 1), np.int32)
+        d = np.zeros(max(m, 1), np.int32)
+        mm = C.c_int64()
+        _check(load_library().ps_graph_edges(self._h, int(m), s.ctypes.data, d.ctypes.data, C.byref(mm)),
+               "ps_graph_edges")
+        return s[: mm.value], d[: mm.value]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ps_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ps_walks(g: Graph, u, c, eps, delta, seed, k_begin, count, out_nodes=None, out_lens=None, **opt):
+    """Walks k_begin .. k_begin+count-1 of the query (host arrays unless given)."""
+    p = derive_params(g.n, c, eps, delta, **opt)
+    nodes = out_nodes if out_nodes is not None else np.zeros((count, p.L), np.int32)
+    lens = out_lens if out_lens is not None else np.zeros(count, np.int32)
+    o = options(**opt)
+    _check(load_library().ps_walks(g._h, int(u), c, eps, delta, C.c_uint64(seed), C.byref(o), int(k_begin),
+                                   int(count), _ptr(nodes), _ptr(lens)), "ps_walks")
+    return nodes, lens
+
+
+def ps_single_source(g: Graph, u, c, eps, delta, seed, out=None, **opt):
+    """Approximate single-source SimRank from u; `out` may be a device tensor."""
+    if out is None:
+        out = np.zeros(g.n, np.float64)
+    o = options(**opt)
+    _check(load_library().ps_single_source(g._h, int(u), c, eps, delta, C.c_uint64(seed), C.byref(o), _ptr(out)),
+           "ps_single_source")
+    return out
+
+
+def ps_topk(g: Graph, u, k, c, eps, delta, seed, out_nodes=None, out_scores=None, **opt):
+    nodes = out_nodes if out_nodes is not None else np.zeros(k, np.int32)
+    scores = out_scores if out_scores is not None else np.zeros(k, np.float64)
+    o = options(**opt)
+    _check(load_library().ps_topk(g._h, int(u), int(k), c, eps, delta, C.c_uint64(seed), C.byref(o),
+                                  _ptr(nodes), _ptr(scores)), "ps_topk")
+    return nodes, scores
+
+
+def ps_batch(g: Graph, queries, outs=None, **opt):
+    """queries: list of dicts (u, k, c, eps, delta, seed).  Returns a list of
+    score arrays (single-source) or (nodes, scores) pairs (top-k)."""
+    nq = len(queries)
+    qa = (Query * max(nq, 1))()
+    ra = (Result * max(nq, 1))()
+    keep = []
+    for i, q in enumerate(queries):
+        qa[i] = Query(int(q["u"]), int(q.get("k", 0)), q["c"], q["eps"], q["delta"], int(q["seed"]))
+        if outs is not None:
+            sc, nd = outs[i]
+        elif q.get("k", 0) > 0:
+            sc, nd = np.zeros(q["k"], np.float64), np.zeros(q["k"], np.int32)
+        else:
+            sc, nd = np.zeros(g.n, np.float64), None
+        keep.append((sc, nd))
+        ra[i].scores = _ptr(sc)
+        ra[i].nodes = _ptr(nd) if nd is not None else None
+    o = options(**opt)
+    _check(load_library().ps_batch(g._h, nq, qa, C.byref(o), ra), "ps_batch")
+    res = []
+    for i, (sc, nd) in enumerate(keep):
+        _check(ra[i].status, f"query {i}")
+        res.append(sc if nd is None else (nd, sc))
+    return res
+
+
+class Server:
+    """Continuous-batching query server on one graph."""
+
+    def __init__(self, g: Graph, ring=1024, max_inflight=64, slots=0, frontier_bytes=0):
+        cfg = ServerCfg(ring, max_inflight, slots, 0, frontier_bytes)
+        h = C.c_void_p()
+        _check(load_library().ps_server_start(g._h, C.byref(cfg), C.byref(h)), "ps_server_start")
+        self._h = h
+        self.g = g
+        self._pending = {}
+
+    def submit(self, u, c, eps, delta, seed, k=0):
+        q = Query(int(u), int(k), c, eps, delta, int(seed))
+        if k > 0:
+            sc, nd = np.zeros(k, np.float64), np.zeros(k, np.int32)
+        else:
+            sc, nd = np.zeros(self.g.n, np.float64), None
+        r = Result(sc.ctypes.data, nd.ctypes.data if nd is not None else None, 0, 0)
+        t = C.c_uint64()
+        code = load_library().ps_submit(self._h, C.byref(q), C.byref(r), C.byref(t))
+        if code != PS_OK:
+            raise ProbeSimError(code, "ps_submit")
+        self._pending[t.value] = (q, r, sc, nd)
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        code = load_library().ps_wait(self._h, C.c_uint64(ticket), int(timeout_us))
+        if code == 9:
+            raise TimeoutError(ticket)
+        q, r, sc, nd = self._pending.pop(ticket)
+        _check(code, f"ticket {ticket}")
+        return sc if nd is None else (nd, sc)
+
+    def update(self, src, dst, op):
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        o = np.ascontiguousarray(op, dtype=np.uint8)
+        _check(load_library().ps_server_update(self._h, int(s.size), s.ctypes.data, d.ctypes.data, o.ctypes.data),
+               "ps_server_update")
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            _check(load_library().ps_server_stop(self._h), "ps_server_stop")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

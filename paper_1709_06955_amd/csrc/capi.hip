@@ -1,0 +1,222 @@
+// C ABI entry points: contexts, parameters, queries, statistics.
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "ps_internal.h"
+
+void ps_note_hip_error(hipError_t e, const char* what, const char* file, int line) {
+  fprintf(stderr, "probesim: %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+}
+
+bool ps_is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
+extern "C" const char* ps_status_string(ps_status s) {
+  switch (s) {
+    case PS_OK: return "ok";
+    case PS_ERR_INVALID_ARG: return "invalid argument";
+    case PS_ERR_NODE_RANGE: return "node id out of range";
+    case PS_ERR_SELF_LOOP: return "self-loop";
+    case PS_ERR_DUP_EDGE: return "duplicate edge";
+    case PS_ERR_NO_EDGE: return "edge not present";
+    case PS_ERR_OOM: return "out of memory";
+    case PS_ERR_BUSY: return "busy";
+    case PS_ERR_DEVICE: return "device error";
+    case PS_ERR_TIMEOUT: return "timeout";
+    case PS_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+extern "C" ps_status ps_ctx_create(int device, void* hip_stream, ps_ctx** out) {
+  if (!out) return PS_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  PS_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return PS_ERR_INVALID_ARG;
+  PS_HIP(hipSetDevice(device));
+  auto* c = new ps_ctx();
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return PS_ERR_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return PS_OK;
+}
+
+extern "C" void ps_ctx_destroy(ps_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  Engine& e = c->eng;
+  DevBuf* bufs[] = {&e.keys,     &e.t_parent,   &e.t_node,       &e.t_depth,      &e.t_query,     &e.t_weight,
+                    &e.probe_list, &e.slots,    &e.has_next,     &e.dense[0],     &e.dense[1],    &e.list[0],
+                    &e.list[1],  &e.item_val,   &e.small_list,   &e.chunk_list,   &e.counters,    &e.qdesc,
+                    &e.thr,      &e.acc,        &e.stage,        &e.sort_keys[0], &e.sort_keys[1], &e.sort_vals[0],
+                    &e.sort_vals[1], &e.sort_tmp};
+  for (DevBuf* b : bufs) devbuf_free(*b);
+  if (e.h_counters) (void)hipHostFree(e.h_counters);
+  for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" ps_status ps_ctx_set_timing(ps_ctx* c, int enable) {
+  if (!c) return PS_ERR_INVALID_ARG;
+  c->timing = enable != 0;
+  return PS_OK;
+}
+
+extern "C" void ps_options_default(ps_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->eps_s = -1.0;
+  o->eps_t = -1.0;
+  o->eps_p = -1.0;
+  o->walk_begin = 0;
+  o->walk_end = -1;
+}
+
+// Alg. 1 (number of walks), Rule 1 (truncation), Theorem 2 (error split).
+ps_status derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt, ps_params* p) {
+  if (!p || n <= 0) return PS_ERR_INVALID_ARG;
+  if (!(c > 0.0 && c < 1.0) || !(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0)) return PS_ERR_INVALID_ARG;
+  ps_options d;
+  ps_options_default(&d);
+  if (!opt) opt = &d;
+  const double sc = std::sqrt(c);
+  p->c = c;
+  p->eps_a = eps;
+  p->delta = delta;
+  p->eps_s = opt->eps_s >= 0.0 ? opt->eps_s : eps / 2.0;
+  p->eps_t = opt->eps_t >= 0.0 ? opt->eps_t : eps / 4.0;
+  p->eps_p = opt->eps_p >= 0.0 ? opt->eps_p : (eps / 4.0) * (1.0 - sc) / (1.0 + p->eps_s);
+  if (!(p->eps_s > 0.0) || !(p->eps_t > 0.0 && p->eps_t < 1.0)) return PS_ERR_INVALID_ARG;
+  const double nr = std::ceil(3.0 * c * std::log((double)n / delta) / (p->eps_s * p->eps_s));
+  if (!(nr >= 1.0) || nr > 2147483647.0) return PS_ERR_INVALID_ARG;
+  p->n_r = (int64_t)nr;
+  p->L = opt->max_len > 0 ? opt->max_len : (int32_t)std::floor(std::log(p->eps_t) / std::log(sc));
+  if (p->L < 2 || p->L > PS_MAX_WALK_LEN) return PS_ERR_INVALID_ARG;
+  p->t_stop = (uint32_t)std::floor((1.0 - sc) * 4294967296.0);
+  return PS_OK;
+}
+
+extern "C" ps_status ps_derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt,
+                                      ps_params* out) {
+  return derive_params(n, c, eps, delta, opt, out);
+}
+
+namespace {
+
+ps_status make_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
+                   const ps_options* opt, QueryRun* q) {
+  if (u < 0 || u >= g->n) return PS_ERR_NODE_RANGE;
+  if (k < 0 || (k > 0 && k > g->n - 1)) return PS_ERR_INVALID_ARG;
+  PS_TRY(derive_params(g->n, c, eps, delta, opt, &q->prm));
+  q->u = u;
+  q->k = k;
+  q->seed = seed;
+  q->walk_begin = opt ? opt->walk_begin : 0;
+  q->walk_end = (opt && opt->walk_end >= 0) ? opt->walk_end : q->prm.n_r;
+  q->bias_shift = opt ? opt->bias_shift : 0;
+  if (q->walk_begin < 0 || q->walk_end > q->prm.n_r || q->walk_begin > q->walk_end) return PS_ERR_INVALID_ARG;
+  return PS_OK;
+}
+
+ps_status run_locked(ps_graph* g, const std::vector<QueryRun>& qs, const std::vector<QueryOut>& outs, int slots) {
+  ps_ctx* ctx = g->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  PS_HIP(hipSetDevice(ctx->device));
+  GraphVersion* gv = graph_acquire(g);
+  ps_status s = engine_run(ctx, gv, g->n, qs, outs, slots);
+  graph_release(g, gv);
+  return s;
+}
+
+}  // namespace
+
+extern "C" ps_status ps_walks(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
+                              const ps_options* opt, int64_t k_begin, int64_t count, int32_t* nodes, int32_t* lens) {
+  if (!g || count < 0 || k_begin < 0 || (count > 0 && (!nodes || !lens))) return PS_ERR_INVALID_ARG;
+  QueryRun q;
+  PS_TRY(make_run(g, u, 0, c, eps, delta, seed, opt, &q));
+  if (k_begin + count > (int64_t)1 << 32) return PS_ERR_INVALID_ARG;
+  ps_ctx* ctx = g->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  PS_HIP(hipSetDevice(ctx->device));
+  GraphVersion* gv = graph_acquire(g);
+  ps_status s = engine_walks(ctx, gv, g->n, q, k_begin, count, nodes, lens);
+  graph_release(g, gv);
+  return s;
+}
+
+extern "C" ps_status ps_single_source(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
+                                      const ps_options* opt, double* out) {
+  if (!g || !out) return PS_ERR_INVALID_ARG;
+  QueryRun q;
+  PS_TRY(make_run(g, u, 0, c, eps, delta, seed, opt, &q));
+  QueryOut o;
+  o.scores = out;
+  return run_locked(g, {q}, {o}, opt ? opt->slots : 0);
+}
+
+extern "C" ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
+                             const ps_options* opt, int32_t* nodes, double* scores) {
+  if (!g || !nodes || !scores || k < 1) return PS_ERR_INVALID_ARG;
+  QueryRun q;
+  PS_TRY(make_run(g, u, k, c, eps, delta, seed, opt, &q));
+  QueryOut o;
+  o.scores = scores;
+  o.nodes = nodes;
+  return run_locked(g, {q}, {o}, opt ? opt->slots : 0);
+}
+
+extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const ps_options* opt, ps_result* r) {
+  if (!g || nq < 0 || (nq > 0 && (!qv || !r))) return PS_ERR_INVALID_ARG;
+  if (opt && (opt->walk_begin != 0 || opt->walk_end >= 0)) return PS_ERR_INVALID_ARG;
+  std::vector<QueryRun> qs;
+  std::vector<QueryOut> outs;
+  std::vector<int32_t> which;
+  for (int32_t i = 0; i < nq; ++i) {
+    QueryRun q;
+    ps_status s = make_run(g, qv[i].u, qv[i].k, qv[i].c, qv[i].eps, qv[i].delta, qv[i].seed, opt, &q);
+    if (s == PS_OK && (!r[i].scores || (qv[i].k > 0 && !r[i].nodes))) s = PS_ERR_INVALID_ARG;
+    r[i].status = s;
+    r[i].count = 0;
+    if (s != PS_OK) continue;
+    QueryOut o;
+    o.scores = r[i].scores;
+    o.nodes = r[i].nodes;
+    qs.push_back(q);
+    outs.push_back(o);
+    which.push_back(i);
+  }
+  ps_status s = run_locked(g, qs, outs, opt ? opt->slots : 0);
+  for (size_t j = 0; j < which.size(); ++j) {
+    ps_result& rr = r[which[j]];
+    rr.status = s;
+    rr.count = s == PS_OK ? (qs[j].k > 0 ? qs[j].k : g->n) : 0;
+  }
+  return s;
+}
+
+extern "C" ps_status ps_get_stats(ps_ctx* c, ps_stats* out) {
+  if (!c || !out) return PS_ERR_INVALID_ARG;
+  *out = c->last;
+  return PS_OK;
+}

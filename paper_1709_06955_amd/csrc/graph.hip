@@ -1,0 +1,377 @@
+// Device graph store: in- and out-adjacency, 1/|I(v)|, versioned updates.
+//
+// Layout in HBM (per adjacency direction):
+//   col[cap]      int32 neighbour ids.  The base CSR fills col[0, m); rows
+//                 rewritten by updates are appended after it (delta region).
+//   rows[n]       uint2 (start, len): row of node v is col[start, start+len).
+//   inv_indeg[n]  float 1/|I(v)|, read by every PROBE expansion.
+// In-rows are kept in ascending source-id order at every version, which is
+// the order walks index into, so walks are identical on a graph built by
+// updates and on the same edge set loaded from scratch.
+//
+// A graph version is immutable: an update batch copies the row index arrays,
+// appends the rewritten rows to the delta region and publishes the copy as
+// the new version.  Queries hold a reference to the version they started on.
+
+#include <algorithm>
+#include <cstring>
+
+#include "ps_internal.h"
+
+namespace {
+
+constexpr uint64_t kMinSlack = 1ull << 20;
+
+__global__ void k_patch_rows(const int32_t* __restrict__ node, const uint2* __restrict__ row, int32_t cnt,
+                             uint2* __restrict__ rows, float* __restrict__ inv_indeg) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t v = node[i];
+  rows[v] = row[i];
+  if (inv_indeg) inv_indeg[v] = row[i].y ? 1.0f / (float)row[i].y : 0.0f;
+}
+
+ps_status alloc_version_arrays(GraphVersion* v, int32_t n) {
+  PS_HIP(hipMalloc(&v->in_rows, sizeof(uint2) * (size_t)n));
+  PS_HIP(hipMalloc(&v->out_rows, sizeof(uint2) * (size_t)n));
+  PS_HIP(hipMalloc(&v->inv_indeg, sizeof(float) * (size_t)n));
+  return PS_OK;
+}
+
+void free_version(GraphVersion* v) {
+  if (!v) return;
+  (void)hipFree(v->in_rows);
+  (void)hipFree(v->out_rows);
+  (void)hipFree(v->inv_indeg);
+  if (v->in_store && --v->in_store->refs == 0) (void)hipFree(v->in_store->col);
+  if (v->out_store && --v->out_store->refs == 0) (void)hipFree(v->out_store->col);
+  delete v;
+}
+
+// Row of v in the host mirror (rewritten row if any, else the base CSR row).
+const int32_t* host_row(const std::vector<int64_t>& ptr, const std::vector<int32_t>& col,
+                        const std::unordered_map<int32_t, std::vector<int32_t>>& mod, int32_t v, int64_t* len) {
+  auto it = mod.find(v);
+  if (it != mod.end()) {
+    *len = (int64_t)it->second.size();
+    return it->second.data();
+  }
+  *len = ptr[v + 1] - ptr[v];
+  return col.data() + ptr[v];
+}
+
+std::vector<int32_t>& mutable_row(const std::vector<int64_t>& ptr, const std::vector<int32_t>& col,
+                                  std::unordered_map<int32_t, std::vector<int32_t>>& mod, int32_t v) {
+  auto it = mod.find(v);
+  if (it != mod.end()) return it->second;
+  auto& r = mod[v];
+  r.assign(col.begin() + ptr[v], col.begin() + ptr[v + 1]);
+  return r;
+}
+
+// Uploads the whole host mirror as a fresh column store pair + version.
+ps_status upload_full(ps_graph* g, GraphVersion* v) {
+  const int32_t n = g->n;
+  const uint64_t m = (uint64_t)g->m;
+  const uint64_t slack = std::max<uint64_t>(kMinSlack, m / 8);
+  auto in_store = std::make_shared<ColStore>();
+  auto out_store = std::make_shared<ColStore>();
+  in_store->cap = out_store->cap = m + slack;
+  if (in_store->cap >= (1ull << 32)) return PS_ERR_INVALID_ARG;
+  PS_HIP(hipMalloc(&in_store->col, sizeof(int32_t) * in_store->cap));
+  PS_HIP(hipMalloc(&out_store->col, sizeof(int32_t) * out_store->cap));
+  std::vector<int32_t> in_col, out_col;
+  std::vector<uint2> in_rows((size_t)n), out_rows((size_t)n);
+  std::vector<float> inv((size_t)n);
+  in_col.reserve(m);
+  out_col.reserve(m);
+  for (int32_t x = 0; x < n; ++x) {
+    int64_t li, lo;
+    const int32_t* ri = host_row(g->h_in_ptr, g->h_in_col, g->mod_in, x, &li);
+    const int32_t* ro = host_row(g->h_out_ptr, g->h_out_col, g->mod_out, x, &lo);
+    in_rows[x] = make_uint2((uint32_t)in_col.size(), (uint32_t)li);
+    out_rows[x] = make_uint2((uint32_t)out_col.size(), (uint32_t)lo);
+    in_col.insert(in_col.end(), ri, ri + li);
+    out_col.insert(out_col.end(), ro, ro + lo);
+    inv[x] = li ? 1.0f / (float)li : 0.0f;
+  }
+  in_store->used = in_col.size();
+  out_store->used = out_col.size();
+  hipStream_t st = g->ctx->stream;
+  if (!in_col.empty()) {
+    PS_HIP(hipMemcpyAsync(in_store->col, in_col.data(), sizeof(int32_t) * in_col.size(), hipMemcpyHostToDevice, st));
+    PS_HIP(hipMemcpyAsync(out_store->col, out_col.data(), sizeof(int32_t) * out_col.size(), hipMemcpyHostToDevice, st));
+  }
+  PS_TRY(alloc_version_arrays(v, n));
+  PS_HIP(hipMemcpyAsync(v->in_rows, in_rows.data(), sizeof(uint2) * (size_t)n, hipMemcpyHostToDevice, st));
+  PS_HIP(hipMemcpyAsync(v->out_rows, out_rows.data(), sizeof(uint2) * (size_t)n, hipMemcpyHostToDevice, st));
+  PS_HIP(hipMemcpyAsync(v->inv_indeg, inv.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, st));
+  PS_HIP(hipStreamSynchronize(st));
+  in_store->refs = out_store->refs = 1;
+  v->in_store = in_store;
+  v->out_store = out_store;
+  // Fold the rewritten rows into the base CSR of the mirror.
+  g->h_in_col.swap(in_col);
+  g->h_out_col.swap(out_col);
+  for (int32_t x = 0; x < n; ++x) {
+    g->h_in_ptr[x] = in_rows[x].x;
+    g->h_out_ptr[x] = out_rows[x].x;
+  }
+  g->h_in_ptr[n] = (int64_t)g->h_in_col.size();
+  g->h_out_ptr[n] = (int64_t)g->h_out_col.size();
+  g->mod_in.clear();
+  g->mod_out.clear();
+  return PS_OK;
+}
+
+}  // namespace
+
+GraphVersion* graph_acquire(ps_graph* g) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  g->cur->refs++;
+  return g->cur;
+}
+
+void graph_release(ps_graph* g, GraphVersion* v) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  if (--v->refs == 0) {
+    g->retired.erase(std::remove(g->retired.begin(), g->retired.end(), v), g->retired.end());
+    free_version(v);
+  }
+}
+
+int64_t graph_host_indeg(const ps_graph* g, int32_t v) {
+  int64_t len;
+  host_row(g->h_in_ptr, g->h_in_col, g->mod_in, v, &len);
+  return len;
+}
+
+extern "C" ps_status ps_graph_load(ps_ctx* ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                                   uint32_t flags, ps_graph** out) {
+  if (!out) return PS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!ctx || n <= 0 || m < 0 || m >= (1ll << 31) || (m > 0 && (!src || !dst))) return PS_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < m; ++i)
+    if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return PS_ERR_NODE_RANGE;
+  // Counting sort by source, then sort each out-row by target.
+  std::vector<int64_t> optr((size_t)n + 1, 0);
+  for (int64_t i = 0; i < m; ++i) optr[src[i] + 1]++;
+  for (int32_t v = 0; v < n; ++v) optr[v + 1] += optr[v];
+  std::vector<int32_t> ocol((size_t)m);
+  {
+    std::vector<int64_t> fill(optr.begin(), optr.end() - 1);
+    for (int64_t i = 0; i < m; ++i) ocol[fill[src[i]]++] = dst[i];
+  }
+  // Validate (self-loops, duplicates) and compact per row.
+  std::vector<int64_t> nptr((size_t)n + 1, 0);
+  int64_t w = 0;
+  for (int32_t x = 0; x < n; ++x) {
+    const int64_t b = optr[x], e = optr[x + 1];
+    std::sort(ocol.begin() + b, ocol.begin() + e);
+    nptr[x] = w;
+    for (int64_t i = b; i < e; ++i) {
+      const int32_t y = ocol[i];
+      if (y == x) {
+        if (flags & PS_LOAD_DROP_SELF_LOOPS) continue;
+        return PS_ERR_SELF_LOOP;
+      }
+      if (i > b && ocol[i - 1] == y) {
+        if (flags & PS_LOAD_DEDUP) continue;
+        return PS_ERR_DUP_EDGE;
+      }
+      ocol[w++] = y;
+    }
+  }
+  nptr[n] = w;
+  ocol.resize((size_t)w);
+  // In-rows: visiting sources in ascending order leaves each in-row sorted.
+  std::vector<int64_t> iptr((size_t)n + 1, 0);
+  for (int64_t i = 0; i < w; ++i) iptr[ocol[i] + 1]++;
+  for (int32_t v = 0; v < n; ++v) iptr[v + 1] += iptr[v];
+  std::vector<int32_t> icol((size_t)w);
+  {
+    std::vector<int64_t> fill(iptr.begin(), iptr.end() - 1);
+    for (int32_t x = 0; x < n; ++x)
+      for (int64_t i = nptr[x]; i < nptr[x + 1]; ++i) icol[fill[ocol[i]]++] = x;
+  }
+  auto* g = new ps_graph();
+  g->ctx = ctx;
+  g->n = n;
+  g->m = w;
+  g->h_in_ptr.swap(iptr);
+  g->h_in_col.swap(icol);
+  g->h_out_ptr.swap(nptr);
+  g->h_out_col.swap(ocol);
+  PS_HIP(hipSetDevice(ctx->device));
+  auto* v = new GraphVersion();
+  v->refs = 1;
+  ps_status s = upload_full(g, v);
+  if (s != PS_OK) {
+    free_version(v);
+    delete g;
+    return s;
+  }
+  g->cur = v;
+  *out = g;
+  return PS_OK;
+}
+
+extern "C" void ps_graph_free(ps_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->ctx->device);
+  (void)hipStreamSynchronize(g->ctx->stream);
+  for (auto* v : g->retired) free_version(v);
+  free_version(g->cur);
+  delete g;
+}
+
+extern "C" ps_status ps_graph_info(const ps_graph* g, int32_t* n, int64_t* m, uint64_t* version) {
+  if (!g) return PS_ERR_INVALID_ARG;
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (version) *version = g->cur->version;
+  return PS_OK;
+}
+
+extern "C" ps_status ps_graph_edges(const ps_graph* g, int64_t cap, int32_t* src, int32_t* dst, int64_t* m) {
+  if (!g || !m) return PS_ERR_INVALID_ARG;
+  *m = g->m;
+  if (cap < g->m || (g->m > 0 && (!src || !dst))) return PS_ERR_INVALID_ARG;
+  int64_t w = 0;
+  for (int32_t x = 0; x < g->n; ++x) {
+    int64_t len;
+    const int32_t* r = host_row(g->h_out_ptr, g->h_out_col, g->mod_out, x, &len);
+    for (int64_t i = 0; i < len; ++i) {
+      src[w] = x;
+      dst[w] = r[i];
+      ++w;
+    }
+  }
+  return PS_OK;
+}
+
+ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const int32_t* dst, const uint8_t* op,
+                              int32_t* per_edge, uint64_t* version) {
+  if (!g || k < 0 || (k > 0 && (!src || !dst || !op))) return PS_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < k; ++i) {
+    if (src[i] < 0 || src[i] >= g->n || dst[i] < 0 || dst[i] >= g->n) return PS_ERR_NODE_RANGE;
+    if (op[i] > 1) return PS_ERR_INVALID_ARG;
+  }
+  ps_status first_err = PS_OK;
+  std::vector<int32_t> touched_in, touched_out;
+  for (int64_t i = 0; i < k; ++i) {
+    const int32_t x = src[i], y = dst[i];
+    ps_status st = PS_OK;
+    if (x == y) {
+      st = PS_ERR_SELF_LOOP;
+    } else {
+      auto& orow = mutable_row(g->h_out_ptr, g->h_out_col, g->mod_out, x);
+      auto pos = std::lower_bound(orow.begin(), orow.end(), y);
+      const bool present = pos != orow.end() && *pos == y;
+      if (op[i] == 0 && present) {
+        st = PS_ERR_DUP_EDGE;
+      } else if (op[i] == 1 && !present) {
+        st = PS_ERR_NO_EDGE;
+      } else {
+        auto& irow = mutable_row(g->h_in_ptr, g->h_in_col, g->mod_in, y);
+        auto ipos = std::lower_bound(irow.begin(), irow.end(), x);
+        if (op[i] == 0) {
+          orow.insert(pos, y);
+          irow.insert(ipos, x);
+          g->m++;
+        } else {
+          orow.erase(pos);
+          irow.erase(ipos);
+          g->m--;
+        }
+        touched_out.push_back(x);
+        touched_in.push_back(y);
+      }
+    }
+    if (per_edge) per_edge[i] = st;
+    if (st != PS_OK && first_err == PS_OK) first_err = st;
+  }
+  std::sort(touched_in.begin(), touched_in.end());
+  touched_in.erase(std::unique(touched_in.begin(), touched_in.end()), touched_in.end());
+  std::sort(touched_out.begin(), touched_out.end());
+  touched_out.erase(std::unique(touched_out.begin(), touched_out.end()), touched_out.end());
+
+  if (!touched_in.empty()) {
+    ps_ctx* ctx = g->ctx;
+    hipStream_t st = ctx->stream;
+    PS_HIP(hipSetDevice(ctx->device));
+    GraphVersion* old = g->cur;
+    auto* v = new GraphVersion();
+    v->version = old->version + 1;
+    v->refs = 1;
+    uint64_t need_in = 0, need_out = 0;
+    for (int32_t y : touched_in) need_in += g->mod_in[y].size();
+    for (int32_t x : touched_out) need_out += g->mod_out[x].size();
+    const bool fits = old->in_store->used + need_in <= old->in_store->cap &&
+                      old->out_store->used + need_out <= old->out_store->cap;
+    if (!fits) {
+      // Delta region exhausted: compact everything into fresh column stores.
+      ps_status s = upload_full(g, v);
+      if (s != PS_OK) {
+        free_version(v);
+        return s;
+      }
+    } else {
+      PS_TRY(alloc_version_arrays(v, g->n));
+      PS_HIP(hipMemcpyAsync(v->in_rows, old->in_rows, sizeof(uint2) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
+      PS_HIP(hipMemcpyAsync(v->out_rows, old->out_rows, sizeof(uint2) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
+      PS_HIP(hipMemcpyAsync(v->inv_indeg, old->inv_indeg, sizeof(float) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
+      v->in_store = old->in_store;
+      v->out_store = old->out_store;
+      v->in_store->refs++;
+      v->out_store->refs++;
+      // Stage rewritten rows and their (start, len) patches.
+      auto stage = [&](const std::vector<int32_t>& nodes, std::unordered_map<int32_t, std::vector<int32_t>>& mod,
+                       ColStore* store, uint2* rows, float* inv) -> ps_status {
+        std::vector<int32_t> cols, pn;
+        std::vector<uint2> pr;
+        const uint64_t base = store->used;
+        for (int32_t a : nodes) {
+          auto& r = mod[a];
+          pn.push_back(a);
+          pr.push_back(make_uint2((uint32_t)(base + cols.size()), (uint32_t)r.size()));
+          cols.insert(cols.end(), r.begin(), r.end());
+        }
+        if (!cols.empty())
+          PS_HIP(hipMemcpyAsync(store->col + base, cols.data(), sizeof(int32_t) * cols.size(), hipMemcpyHostToDevice, st));
+        store->used = base + cols.size();
+        int32_t* d_node = nullptr;
+        uint2* d_row = nullptr;
+        PS_HIP(hipMalloc(&d_node, sizeof(int32_t) * pn.size()));
+        PS_HIP(hipMalloc(&d_row, sizeof(uint2) * pr.size()));
+        PS_HIP(hipMemcpyAsync(d_node, pn.data(), sizeof(int32_t) * pn.size(), hipMemcpyHostToDevice, st));
+        PS_HIP(hipMemcpyAsync(d_row, pr.data(), sizeof(uint2) * pr.size(), hipMemcpyHostToDevice, st));
+        const int32_t cnt = (int32_t)pn.size();
+        k_patch_rows<<<(cnt + 255) / 256, 256, 0, st>>>(d_node, d_row, cnt, rows, inv);
+        PS_HIP(hipGetLastError());
+        PS_HIP(hipStreamSynchronize(st));
+        (void)hipFree(d_node);
+        (void)hipFree(d_row);
+        return PS_OK;
+      };
+      PS_TRY(stage(touched_in, g->mod_in, v->in_store.get(), v->in_rows, v->inv_indeg));
+      PS_TRY(stage(touched_out, g->mod_out, v->out_store.get(), v->out_rows, nullptr));
+    }
+    {
+      std::lock_guard<std::mutex> lk(g->mu);
+      g->cur = v;
+      if (--old->refs == 0)
+        free_version(old);
+      else
+        g->retired.push_back(old);
+    }
+  }
+  if (version) *version = g->cur->version;
+  if (per_edge) return PS_OK;
+  return first_err;
+}
+
+extern "C" ps_status ps_graph_update(ps_graph* g, int64_t k, const int32_t* src, const int32_t* dst,
+                                     const uint8_t* op, int32_t* per_edge, uint64_t* version) {
+  return graph_apply_updates(g, k, src, dst, op, per_edge, version);
+}

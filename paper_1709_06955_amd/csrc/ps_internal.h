@@ -1,0 +1,191 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "probesim.h"
+
+#define PS_HIP(x)                                  \
+  do {                                             \
+    hipError_t e_ = (x);                           \
+    if (e_ != hipSuccess) {                        \
+      ps_note_hip_error(e_, #x, __FILE__, __LINE__); \
+      return PS_ERR_DEVICE;                        \
+    }                                              \
+  } while (0)
+
+#define PS_TRY(x)                \
+  do {                           \
+    ps_status s_ = (x);          \
+    if (s_ != PS_OK) return s_;  \
+  } while (0)
+
+void ps_note_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+// Grow-only device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+ps_status devbuf_reserve(DevBuf& b, size_t bytes);
+void devbuf_free(DevBuf& b);
+
+// Whether `p` is device memory of the current device.
+bool ps_is_device_ptr(const void* p);
+
+// ------------------------------------------------------------------ graph --
+
+// Column storage of one adjacency direction: rows live anywhere inside `col`
+// (the base CSR first, then rows rewritten by updates in the delta region).
+struct ColStore {
+  int32_t* col = nullptr;
+  uint64_t cap = 0;   // entries
+  uint64_t used = 0;  // entries in use (base + delta)
+  int refs = 0;       // graph versions pointing into it
+};
+
+// One immutable snapshot of the graph as queries read it.
+struct GraphVersion {
+  uint64_t version = 0;
+  uint2* in_rows = nullptr;   // (start, len) of each node's in-row in in_store->col
+  uint2* out_rows = nullptr;  // (start, len) of each node's out-row in out_store->col
+  float* inv_indeg = nullptr; // 1/|I(v)| (0 when I(v) is empty)
+  std::shared_ptr<ColStore> in_store, out_store;
+  int refs = 0;               // queries reading this version + 1 while current
+};
+
+struct ps_graph {
+  ps_ctx* ctx = nullptr;
+  int32_t n = 0;
+  int64_t m = 0;
+  // Host mirror: the base CSR plus rows rewritten since the last compaction.
+  std::vector<int64_t> h_in_ptr, h_out_ptr;
+  std::vector<int32_t> h_in_col, h_out_col;
+  std::unordered_map<int32_t, std::vector<int32_t>> mod_in, mod_out;
+  GraphVersion* cur = nullptr;
+  std::vector<GraphVersion*> retired;  // superseded versions still read by queries
+  std::mutex mu;
+};
+
+// Takes a reference on the current version (released with graph_release).
+GraphVersion* graph_acquire(ps_graph* g);
+void graph_release(ps_graph* g, GraphVersion* v);
+// In-degree of v in the current host mirror.
+int64_t graph_host_indeg(const ps_graph* g, int32_t v);
+// Applies a batch of updates (shared by ps_graph_update and the server).
+ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const int32_t* dst,
+                              const uint8_t* op, int32_t* per_edge, uint64_t* version);
+
+// ----------------------------------------------------------------- engine --
+
+// Device descriptor of one query in a launch.
+struct QueryDev {
+  int32_t u;
+  int32_t L;
+  uint32_t t_stop;
+  int32_t topk;
+  uint64_t seed;
+  int64_t walk_begin;  // first walk index k
+  int64_t walk_count;  // walks of this query in the launch
+  int64_t walk_base;   // offset of this query's walks in the launch's walk space
+  float sc;            // sqrt(c) in FP32 (multiplies probe scores)
+  float pad;
+  double inv_nr;       // 1 / n_r
+  double shift;        // eps_t/2 when the bias shift is on, else 0
+};
+
+// Host view of a query being run.
+struct QueryRun {
+  int32_t u = 0, k = 0;
+  ps_params prm{};
+  uint64_t seed = 0;
+  int64_t walk_begin = 0, walk_end = 0;
+  int bias_shift = 0;
+};
+
+// State of one probe slot on the device.
+struct Slot {
+  int32_t probe;   // tree node of the probe being run, -1 when idle
+  int32_t level;   // PROBE iteration j of the entries currently listed
+  int32_t depth;   // i: the probe runs on (u_1..u_i)
+  int32_t cursor;  // tree node whose graph node is excluded at this level
+  int32_t query;   // index of the query in the launch
+  int32_t excl;    // graph node u_{i-j-1}, skipped by this level's expansion
+  float thr;       // Rule 2: entries with score <= thr are removed
+  float sc;        // sqrt(c)
+  int32_t last;    // this level's expansion produces the returned score set
+  int32_t pad;
+  double w;        // number of walks sharing the probed prefix
+};
+
+enum CounterIdx {
+  C_TREE_BOUND = 0,  // sum over walks of (len - 1)
+  C_PROBES,          // tree nodes (probes) inserted
+  C_LEVELS,          // sum over probes of (depth - 1)
+  C_CURSOR,          // next probe handed to a slot
+  C_LIST0,           // entries in list 0
+  C_LIST1,           // entries in list 1
+  C_SMALL,           // small-row work items this step
+  C_CHUNK,           // chunk work items this step
+  C_WALK_NODES,
+  C_KEPT,
+  C_PRUNED,
+  C_EDGES,
+  C_NEXT,
+  C_FINAL,
+  C_LEVEL0,
+  C_COUNT
+};
+
+struct Engine {
+  int P = 0;                 // probe slots
+  int32_t n = 0;             // graph nodes the buffers are sized for
+  uint64_t tree_cap = 0;     // hash table capacity (power of two)
+  uint64_t list_cap = 0;     // entries per frontier list
+  uint64_t chunk_cap = 0;
+  int nq_cap = 0;
+  DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, probe_list;
+  DevBuf slots, has_next, dense[2], list[2], item_val, small_list, chunk_list;
+  DevBuf counters, qdesc, thr, acc, stage;
+  DevBuf sort_keys[2], sort_vals[2], sort_tmp;
+  uint64_t* h_counters = nullptr;  // pinned mirror
+};
+
+struct ps_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool timing = false;
+  Engine eng;
+  ps_stats last{};
+  std::vector<hipEvent_t> ev_pool;
+  std::mutex mu;
+};
+
+// Runs a set of queries on one graph version (all on the device) and writes
+// every result.  Shared by ps_single_source, ps_topk, ps_batch and the
+// server's synchronous fallback.
+struct QueryOut {
+  double* scores = nullptr;  // n (single-source) or k (top-k); host or device
+  int32_t* nodes = nullptr;  // k (top-k)
+};
+ps_status engine_run(ps_ctx* ctx, GraphVersion* gv, int32_t n, const std::vector<QueryRun>& qs,
+                     const std::vector<QueryOut>& outs, int slots_opt);
+
+ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun& q, int64_t k_begin,
+                       int64_t count, int32_t* nodes, int32_t* lens);
+
+ps_status derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt,
+                        ps_params* out);

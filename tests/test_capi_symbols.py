@@ -1,0 +1,61 @@
+"""The C-ABI library loads without a GPU and exports every declared symbol."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "probesim.h")
+LIB = os.path.join(ROOT, "paper_1709_06955_amd", "libprobesim.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ps_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("ps_graph_load", "ps_graph_update", "ps_single_source", "ps_topk", "ps_batch",
+                 "ps_server_start", "ps_submit", "ps_wait", "ps_walks"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_1709_06955_amd import EXPORTS
+
+    assert sorted(EXPORTS) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_only_calls_without_gpu():
+    import paper_1709_06955_amd as ps
+
+    L = ps.load_library()
+    assert L.ps_status_string(0) == b"ok"
+    assert L.ps_status_string(6) == b"out of memory"
+    p = ps.derive_params(1_000_000, 0.6, 0.05, 0.01)
+    assert (p.n_r, p.L, p.t_stop) == (53052, 17, 968099934)
+    with pytest.raises(ps.ProbeSimError):
+        ps.derive_params(10, 0.6, 1.5, 0.01)
+    with pytest.raises(ps.ProbeSimError):
+        ps.derive_params(10, 0.6, 0.1, 0.01, eps_t=1e-30)  # L above the supported maximum
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_params_agree_with_oracle(orc):
+    import paper_1709_06955_amd as ps
+
+    for n, c, eps, delta in [(1000, 0.6, 0.1, 0.01), (10**6, 0.6, 0.05, 0.01), (5 * 10**6, 0.6, 0.02, 0.01),
+                             (40 * 10**6, 0.6, 0.025, 0.01), (8, 0.25, 0.5, 0.1)]:
+        a = ps.derive_params(n, c, eps, delta)
+        b = orc.params(n, c, eps, delta)
+        assert (a.n_r, a.L, a.t_stop) == (b.n_r, b.L, b.t_stop)
+        assert a.eps_p == b.eps_p and a.eps_s == b.eps_s and a.eps_t == b.eps_t
