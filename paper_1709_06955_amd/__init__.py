@@ -7,6 +7,7 @@ The binding refuses to work without the built library; there is no fallback.
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 
@@ -82,6 +83,17 @@ class ServerCfg(C.Structure):
 
 
 _lib = None
+_exiting = False
+
+
+def _at_exit():
+    # Interpreter shutdown: leave device memory to process exit instead of
+    # freeing it from finalizers that may run after the HIP runtime is gone.
+    global _exiting
+    _exiting = True
+
+
+atexit.register(_at_exit)
 
 
 def load_library(path: str = LIB_PATH):
@@ -91,6 +103,13 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with python -m paper_1709_06955_amd.build")
+    # torch bundles its own HIP runtime (same soname, libamdhip64.so.7).  Load
+    # it first so that the library binds to that one: one HIP runtime per
+    # process, shared streams and device pointers with torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     P, vp = C.POINTER, C.c_void_p
     sig = {
@@ -177,7 +196,8 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().ps_ctx_destroy(self._h)
+            if not _exiting:
+                load_library().ps_ctx_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -227,7 +247,8 @@ class Graph:
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().ps_graph_free(self._h)
+            if not _exiting:
+                load_library().ps_graph_free(self._h)
             self._h = None
 
     def __del__(self):
@@ -336,7 +357,8 @@ class Server:
 
     def stop(self):
         if getattr(self, "_h", None):
-            _check(load_library().ps_server_stop(self._h), "ps_server_stop")
+            if not _exiting:
+                _check(load_library().ps_server_stop(self._h), "ps_server_stop")
             self._h = None
 
     def __del__(self):

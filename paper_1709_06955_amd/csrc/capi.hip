@@ -59,8 +59,16 @@ extern "C" ps_status ps_ctx_create(int device, void* hip_stream, ps_ctx** out) {
   return PS_OK;
 }
 
-extern "C" void ps_ctx_destroy(ps_ctx* c) {
+extern "C" void ps_ctx_destroy(ps_ctx* c) { ctx_release(c); }
+
+// Graphs keep their context alive, so destroying a context while graphs
+// still use it only drops the caller's reference.
+void ctx_release(ps_ctx* c) {
   if (!c) return;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (--c->refs > 0) return;
+  }
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   Engine& e = c->eng;

@@ -196,6 +196,10 @@ extern "C" ps_status ps_graph_load(ps_ctx* ctx, int32_t n, int64_t m, const int3
   }
   auto* g = new ps_graph();
   g->ctx = ctx;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->refs++;
+  }
   g->n = n;
   g->m = w;
   g->h_in_ptr.swap(iptr);
@@ -208,6 +212,7 @@ extern "C" ps_status ps_graph_load(ps_ctx* ctx, int32_t n, int64_t m, const int3
   ps_status s = upload_full(g, v);
   if (s != PS_OK) {
     free_version(v);
+    ctx_release(ctx);
     delete g;
     return s;
   }
@@ -222,7 +227,9 @@ extern "C" void ps_graph_free(ps_graph* g) {
   (void)hipStreamSynchronize(g->ctx->stream);
   for (auto* v : g->retired) free_version(v);
   free_version(g->cur);
+  ps_ctx* ctx = g->ctx;
   delete g;
+  ctx_release(ctx);
 }
 
 extern "C" ps_status ps_graph_info(const ps_graph* g, int32_t* n, int64_t* m, uint64_t* version) {

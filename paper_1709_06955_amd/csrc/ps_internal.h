@@ -164,6 +164,7 @@ struct Engine {
 };
 
 struct ps_ctx {
+  int refs = 1;          // the caller's handle + one per live graph
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -173,6 +174,9 @@ struct ps_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::mutex mu;
 };
+
+// Drops one reference; the context is freed with the last one.
+void ctx_release(ps_ctx* c);
 
 // Runs a set of queries on one graph version (all on the device) and writes
 // every result.  Shared by ps_single_source, ps_topk, ps_batch and the
