@@ -71,14 +71,8 @@ void ctx_release(ps_ctx* c) {
   }
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  Engine& e = c->eng;
-  DevBuf* bufs[] = {&e.keys,     &e.t_parent,   &e.t_node,       &e.t_depth,      &e.t_query,     &e.t_weight,
-                    &e.probe_list, &e.slots,    &e.has_next,     &e.dense[0],     &e.dense[1],    &e.list[0],
-                    &e.list[1],  &e.item_val,   &e.small_list,   &e.chunk_list,   &e.counters,    &e.qdesc,
-                    &e.thr,      &e.acc,        &e.stage,        &e.sort_keys[0], &e.sort_keys[1], &e.sort_vals[0],
-                    &e.sort_vals[1], &e.sort_tmp};
-  for (DevBuf* b : bufs) devbuf_free(*b);
-  if (e.h_counters) (void)hipHostFree(e.h_counters);
+  session_free(c->sess);
+  c->sess = nullptr;
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -129,9 +123,7 @@ extern "C" ps_status ps_derive_params(int32_t n, double c, double eps, double de
   return derive_params(n, c, eps, delta, opt, out);
 }
 
-namespace {
-
-ps_status make_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
+ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
                    const ps_options* opt, QueryRun* q) {
   if (u < 0 || u >= g->n) return PS_ERR_NODE_RANGE;
   if (k < 0 || (k > 0 && k > g->n - 1)) return PS_ERR_INVALID_ARG;
@@ -146,12 +138,14 @@ ps_status make_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps
   return PS_OK;
 }
 
+namespace {
+
 ps_status run_locked(ps_graph* g, const std::vector<QueryRun>& qs, const std::vector<QueryOut>& outs, int slots) {
   ps_ctx* ctx = g->ctx;
   std::lock_guard<std::mutex> lk(ctx->mu);
   PS_HIP(hipSetDevice(ctx->device));
   GraphVersion* gv = graph_acquire(g);
-  ps_status s = engine_run(ctx, gv, g->n, qs, outs, slots);
+  ps_status s = engine_run(ctx, g, gv, qs, outs, slots);
   graph_release(g, gv);
   return s;
 }
@@ -162,7 +156,7 @@ extern "C" ps_status ps_walks(ps_graph* g, int32_t u, double c, double eps, doub
                               const ps_options* opt, int64_t k_begin, int64_t count, int32_t* nodes, int32_t* lens) {
   if (!g || count < 0 || k_begin < 0 || (count > 0 && (!nodes || !lens))) return PS_ERR_INVALID_ARG;
   QueryRun q;
-  PS_TRY(make_run(g, u, 0, c, eps, delta, seed, opt, &q));
+  PS_TRY(make_query_run(g, u, 0, c, eps, delta, seed, opt, &q));
   if (k_begin + count > (int64_t)1 << 32) return PS_ERR_INVALID_ARG;
   ps_ctx* ctx = g->ctx;
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -177,7 +171,7 @@ extern "C" ps_status ps_single_source(ps_graph* g, int32_t u, double c, double e
                                       const ps_options* opt, double* out) {
   if (!g || !out) return PS_ERR_INVALID_ARG;
   QueryRun q;
-  PS_TRY(make_run(g, u, 0, c, eps, delta, seed, opt, &q));
+  PS_TRY(make_query_run(g, u, 0, c, eps, delta, seed, opt, &q));
   QueryOut o;
   o.scores = out;
   return run_locked(g, {q}, {o}, opt ? opt->slots : 0);
@@ -187,7 +181,7 @@ extern "C" ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double
                              const ps_options* opt, int32_t* nodes, double* scores) {
   if (!g || !nodes || !scores || k < 1) return PS_ERR_INVALID_ARG;
   QueryRun q;
-  PS_TRY(make_run(g, u, k, c, eps, delta, seed, opt, &q));
+  PS_TRY(make_query_run(g, u, k, c, eps, delta, seed, opt, &q));
   QueryOut o;
   o.scores = scores;
   o.nodes = nodes;
@@ -202,7 +196,7 @@ extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const
   std::vector<int32_t> which;
   for (int32_t i = 0; i < nq; ++i) {
     QueryRun q;
-    ps_status s = make_run(g, qv[i].u, qv[i].k, qv[i].c, qv[i].eps, qv[i].delta, qv[i].seed, opt, &q);
+    ps_status s = make_query_run(g, qv[i].u, qv[i].k, qv[i].c, qv[i].eps, qv[i].delta, qv[i].seed, opt, &q);
     if (s == PS_OK && (!r[i].scores || (qv[i].k > 0 && !r[i].nodes))) s = PS_ERR_INVALID_ARG;
     r[i].status = s;
     r[i].count = 0;

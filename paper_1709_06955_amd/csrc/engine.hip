@@ -1,26 +1,31 @@
 // ProbeSim query engine: sqrt(c)-walks, reverse reachability tree, PROBE
 // level expansion with both pruning rules, FP64 accumulation, top-k.
 //
-// Work of one launch (one or many queries, Alg. 3 of the paper):
-//   1. k_walk_bound   sample every walk once to size the tree (sum of len-1)
-//   2. k_walk_tree    sample the walks again (Philox is counter-based, so the
-//                     walks are identical) and insert every prefix
-//                     (u_1..u_i), i >= 2, into one hash-addressed tree; the
-//                     hash slot of a prefix is its tree node id and its
-//                     weight counts the walks sharing it
-//   3. level steps    every tree node is one PROBE (Alg. 2).  Probes run in
-//                     P device slots; a slot that finishes takes the next
-//                     probe, so short and long probes of all queries keep the
-//                     slots busy.  One step = k_sched (advance / refill slots)
-//                     -> k_prep (read and clear the level's scores, Rule 2,
-//                     bin rows by out-degree) -> k_expand (push along
-//                     out-edges).  Each slot has a dense FP32 score vector per
-//                     level parity; the first atomic add that turns an entry
-//                     nonzero appends (slot, node) to the next frontier list,
-//                     so frontiers stay sparse lists while sums stay exact.
-//                     The last level of a probe adds weight * score straight
-//                     into the query's FP64 estimate.
-//   4. k_finalize     divide by n_r, set s(u,u) = 1; top-k by sorting.
+// A session holds the device state that level steps run on; queries are
+// admitted into it at any time (continuous batching) and leave it when their
+// last probe finishes.
+//
+//   admission    k_walk_bound samples every walk of the admitted queries once
+//                to size their trees (sum of len-1); k_walk_tree samples the
+//                same walks again (Philox is counter-based) and inserts every
+//                prefix (u_1..u_i), i >= 2, into the query's hash-addressed
+//                tree region (Alg. 3).  The hash slot of a prefix is its tree
+//                node id, its weight counts the walks sharing it, and each new
+//                tree node is appended to the ring of pending probes.
+//   level step   every tree node is one PROBE (Alg. 2).  Probes run in P
+//                slots; k_sched (one workgroup) advances every slot by one
+//                iteration, retires finished probes (a query is complete when
+//                its last probe retires) and hands free slots the next
+//                pending probes; k_prep reads and clears the scores of the
+//                listed frontier entries, applies Rule 2 and bins the
+//                surviving rows by out-degree; k_expand pushes scores along
+//                out-edges.  Each slot owns a dense FP32 score vector per
+//                level parity; the atomic add that turns an entry nonzero
+//                appends (slot, node) to the next frontier list, so frontiers
+//                stay sparse lists while the sums stay exact.  A probe's last
+//                level adds weight * score straight into the query's FP64
+//                estimate.
+//   finish       k_finalize divides by n_r and sets s(u,u) = 1; top-k sorts.
 
 #include <hipcub/hipcub.hpp>
 
@@ -34,10 +39,12 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr uint32_t kSmallDeg = 32;  // rows up to this length: one lane per row
-constexpr uint32_t kChunk = 512;    // longer rows: one wavefront per 512 edges
+constexpr int kSchedThreads = 1024;
+constexpr int kSlotsPerSchedThread = 4;  // P <= 4096
+constexpr uint32_t kSmallDeg = 32;       // rows up to this length: one lane per row
+constexpr uint32_t kChunk = 512;         // longer rows: one wavefront per 512 edges
 constexpr unsigned long long kEmpty = ~0ull;
-constexpr int kOverflowIdx = C_COUNT;  // counters[C_COUNT] = overflow flag
+constexpr int kStepGrid = 2048;          // 8 workgroups per CU for the step kernels
 
 // ------------------------------------------------------------- Philox ----
 
@@ -60,24 +67,25 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint2 k) {
 // One move of a sqrt(c)-walk: at node v (index t of walk k) the walk stops
 // when v has no in-neighbour or Philox word 0 < t_stop; otherwise it goes to
 // in-neighbour floor(r64 * |I(v)| / 2^64) of v's ascending in-row.
-__device__ __forceinline__ int32_t walk_move(int32_t v, uint32_t k, uint32_t t, const QueryDev& q,
-                                             const uint2* __restrict__ in_rows, const int32_t* __restrict__ in_col) {
+__device__ __forceinline__ int32_t walk_move(int32_t v, uint32_t k, uint32_t t, const QueryDev& q) {
   const uint4 w = philox4x32_10(make_uint4(k, t, (uint32_t)q.u, 0u),
                                 make_uint2((uint32_t)q.seed, (uint32_t)(q.seed >> 32)));
-  const uint2 row = in_rows[v];
+  const uint2 row = q.in_rows[v];
   if (row.y == 0u || w.x < q.t_stop) return -1;
   const uint64_t r = ((uint64_t)w.z << 32) | w.y;
   const uint32_t idx = (uint32_t)__umul64hi(r, (uint64_t)row.y);
-  return in_col[row.x + idx];
+  return q.in_col[row.x + idx];
 }
 
-__device__ __forceinline__ int find_query(const QueryDev* __restrict__ qs, int nq, int64_t g) {
-  int lo = 0, hi = nq - 1;
+// Record of global walk g in a walk launch over records lq[0..nl).
+__device__ __forceinline__ int find_record(const QueryDev* __restrict__ qr, const int32_t* __restrict__ lq, int nl,
+                                           int64_t g) {
+  int lo = 0, hi = nl - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (qs[mid].walk_base <= g) lo = mid; else hi = mid - 1;
+    if (qr[lq[mid]].walk_base <= g) lo = mid; else hi = mid - 1;
   }
-  return lo;
+  return lq[lo];
 }
 
 // ------------------------------------------------------ wave utilities ----
@@ -91,7 +99,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
 }
 
 // Reserves one output position per lane with `flag` set; one atomic per wave.
-// Call with every active lane (inactive lanes do not take part).
+// Every lane active at the call takes part.
 __device__ __forceinline__ unsigned long long wave_reserve(bool flag, unsigned long long* counter,
                                                            unsigned long long* leader_total) {
   const unsigned long long mask = __ballot(flag);
@@ -130,18 +138,19 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 
 // ------------------------------------------------------------- walks ----
 
-__global__ void k_walk_bound(const QueryDev* __restrict__ qs, int nq, int64_t total,
-                             const uint2* __restrict__ in_rows, const int32_t* __restrict__ in_col,
-                             unsigned long long* __restrict__ ctr) {
+__global__ void k_walk_bound(const QueryDev* __restrict__ qr, const int32_t* __restrict__ lq, int nl, int64_t total,
+                             unsigned long long* __restrict__ qbound, unsigned long long* __restrict__ ctr) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int r = -1;
   unsigned long long extra = 0, nodes = 0;
   if (g < total) {
-    const QueryDev q = qs[find_query(qs, nq, g)];
+    r = find_record(qr, lq, nl, g);
+    const QueryDev q = qr[r];
     const uint32_t k = (uint32_t)(q.walk_begin + (g - q.walk_base));
     int32_t v = q.u;
     int len = 1;
     for (uint32_t t = 0; len < q.L; ++t) {
-      const int32_t nx = walk_move(v, k, t, q, in_rows, in_col);
+      const int32_t nx = walk_move(v, k, t, q);
       if (nx < 0) break;
       v = nx;
       ++len;
@@ -149,16 +158,20 @@ __global__ void k_walk_bound(const QueryDev* __restrict__ qs, int nq, int64_t to
     extra = (unsigned long long)(len - 1);
     nodes = (unsigned long long)len;
   }
-  extra = wave_sum(extra);
-  nodes = wave_sum(nodes);
-  if (lane_id() == 0) {
-    if (extra) atomicAdd(&ctr[C_TREE_BOUND], extra);
-    atomicAdd(&ctr[C_WALK_NODES], nodes);
+  // one atomic per wavefront when all its walks belong to one query
+  const int r0 = __shfl(r, 0, 64);
+  const bool uniform = __ballot(r != r0 && r >= 0) == 0ull;
+  const unsigned long long wn = wave_sum(nodes);
+  if (uniform) {
+    const unsigned long long we = wave_sum(extra);
+    if (lane_id() == 0 && r0 >= 0 && we) atomicAdd(&qbound[r0], we);
+  } else if (r >= 0 && extra) {
+    atomicAdd(&qbound[r], extra);
   }
+  if (lane_id() == 0 && wn) atomicAdd(&ctr[C_WALK_NODES], wn);
 }
 
-__global__ void k_walk_export(QueryDev q, int64_t k_begin, int64_t count, const uint2* __restrict__ in_rows,
-                              const int32_t* __restrict__ in_col, int32_t* __restrict__ nodes,
+__global__ void k_walk_export(QueryDev q, int64_t k_begin, int64_t count, int32_t* __restrict__ nodes,
                               int32_t* __restrict__ lens) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= count) return;
@@ -168,7 +181,7 @@ __global__ void k_walk_export(QueryDev q, int64_t k_begin, int64_t count, const 
   int len = 1;
   row[0] = v;
   for (uint32_t t = 0; len < q.L; ++t) {
-    const int32_t nx = walk_move(v, k, t, q, in_rows, in_col);
+    const int32_t nx = walk_move(v, k, t, q);
     if (nx < 0) break;
     v = nx;
     row[len++] = v;
@@ -177,76 +190,93 @@ __global__ void k_walk_export(QueryDev q, int64_t k_begin, int64_t count, const 
   for (int i = len; i < q.L; ++i) row[i] = -1;
 }
 
-// Inserts key = (parent tree node << 32 | graph node) with linear probing.
-// The slot index is the tree node id.  The table always has free slots
-// (capacity >= 2 * number of keys), so the probe sequence ends.
-__device__ __forceinline__ uint32_t tree_insert(unsigned long long* __restrict__ keys, uint64_t mask,
+// Inserts key = (parent tree node << 32 | graph node) by linear probing in the
+// region [base, base + mask + 1).  The slot is the tree node id.  A region
+// holds at least twice as many slots as the query has keys, so the probe
+// sequence always ends.
+__device__ __forceinline__ uint32_t tree_insert(unsigned long long* __restrict__ keys, uint64_t base, uint64_t mask,
                                                 unsigned long long key, bool& inserted) {
   uint64_t s = mix64(key) & mask;
   inserted = false;
   while (true) {
-    const unsigned long long cur = keys[s];
-    if (cur == key) return (uint32_t)s;
+    unsigned long long* slot = keys + base + s;
+    const unsigned long long cur = *slot;
+    if (cur == key) return (uint32_t)(base + s);
     if (cur == kEmpty) {
-      const unsigned long long prev = atomicCAS(&keys[s], kEmpty, key);
+      const unsigned long long prev = atomicCAS(slot, kEmpty, key);
       if (prev == kEmpty) {
         inserted = true;
-        return (uint32_t)s;
+        return (uint32_t)(base + s);
       }
-      if (prev == key) return (uint32_t)s;
+      if (prev == key) return (uint32_t)(base + s);
     }
     s = (s + 1) & mask;
   }
 }
 
-// Alg. 3, tree construction: walk k of query q descends from the root of q
-// (tree id cap + q) through one tree node per prefix, creating it on first
-// visit and adding one to its weight.
-__global__ void k_walk_tree(const QueryDev* __restrict__ qs, int nq, int64_t total,
-                            const uint2* __restrict__ in_rows, const int32_t* __restrict__ in_col,
-                            unsigned long long* __restrict__ keys, uint64_t cap,
-                            int32_t* __restrict__ t_parent, int32_t* __restrict__ t_node,
-                            int32_t* __restrict__ t_depth, int32_t* __restrict__ t_query,
-                            int32_t* __restrict__ t_weight, int32_t* __restrict__ probe_list,
-                            unsigned long long* __restrict__ ctr) {
+struct TreeArgs {
+  const QueryDev* qr;
+  const int32_t* lq;
+  int nl;
+  int64_t total;
+  uint64_t root_base;  // tree id of the root of record r is root_base + r
+  unsigned long long* keys;
+  int32_t* t_parent;
+  int32_t* t_node;
+  int32_t* t_depth;
+  int32_t* t_query;
+  int32_t* t_weight;
+  int32_t* ring;
+  uint64_t ring_mask;
+  unsigned long long* remaining;
+  unsigned long long* ctr;
+};
+
+// Alg. 3, tree construction: walk k of query q descends from q's root through
+// one tree node per prefix, creating it on first visit (and queueing its
+// probe) and adding one to its weight.
+__global__ void k_walk_tree(TreeArgs a) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total) return;
-  const int qi = find_query(qs, nq, g);
-  const QueryDev q = qs[qi];
+  if (g >= a.total) return;
+  const int r = find_record(a.qr, a.lq, a.nl, g);
+  const QueryDev q = a.qr[r];
   const uint32_t k = (uint32_t)(q.walk_begin + (g - q.walk_base));
-  uint32_t parent = (uint32_t)(cap + qi);
+  uint32_t parent = (uint32_t)(a.root_base + r);
   int32_t v = q.u;
   int len = 1;
   for (uint32_t t = 0; len < q.L; ++t) {
-    const int32_t nx = walk_move(v, k, t, q, in_rows, in_col);
+    const int32_t nx = walk_move(v, k, t, q);
     if (nx < 0) break;
     v = nx;
     ++len;
     const unsigned long long key = ((unsigned long long)parent << 32) | (uint32_t)v;
     bool inserted;
-    const uint32_t id = tree_insert(keys, cap - 1, key, inserted);
+    const uint32_t id = tree_insert(a.keys, q.tree_base, q.tree_mask, key, inserted);
     if (inserted) {
-      t_parent[id] = (int32_t)parent;
-      t_node[id] = v;
-      t_depth[id] = len;
-      t_query[id] = qi;
-      const unsigned long long pos = atomicAdd(&ctr[C_PROBES], 1ull);
-      probe_list[pos] = (int32_t)id;
-      atomicAdd(&ctr[C_LEVELS], (unsigned long long)(len - 1));
+      a.t_parent[id] = (int32_t)parent;
+      a.t_node[id] = v;
+      a.t_depth[id] = len;
+      a.t_query[id] = r;
+      atomicAdd(&a.remaining[r], 1ull);
+      atomicAdd(&a.ctr[C_LEVELS], (unsigned long long)(len - 1));
+      const unsigned long long pos = atomicAdd(&a.ctr[C_TAIL], 1ull);
+      a.ring[pos & a.ring_mask] = (int32_t)id;
     }
-    atomicAdd(&t_weight[id], 1);
+    atomicAdd(&a.t_weight[id], 1);
     parent = id;
   }
 }
 
-__global__ void k_init_roots(const QueryDev* __restrict__ qs, int nq, uint64_t cap, int32_t* t_parent,
-                             int32_t* t_node, int32_t* t_depth, int32_t* t_query) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  t_parent[cap + q] = -1;
-  t_node[cap + q] = qs[q].u;
-  t_depth[cap + q] = 1;
-  t_query[cap + q] = q;
+__global__ void k_init_roots(const QueryDev* __restrict__ qr, const int32_t* __restrict__ lq, int nl,
+                             uint64_t root_base, int32_t* t_parent, int32_t* t_node, int32_t* t_depth,
+                             int32_t* t_query) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  const int r = lq[i];
+  t_parent[root_base + r] = -1;
+  t_node[root_base + r] = qr[r].u;
+  t_depth[root_base + r] = 1;
+  t_query[root_base + r] = r;
 }
 
 template <typename T>
@@ -266,68 +296,128 @@ __global__ void k_reset_slots(Slot* slots, int32_t* has_next, int P) {
 
 // ------------------------------------------------------- level steps ----
 
-// Advances every slot by one PROBE iteration, or hands it the next probe.
-// A probe ends after its last level (i-2) or when Rule 2 emptied its
-// frontier.  A new probe on (u_1..u_i) starts with H_0 = {u_i: 1}.
-__global__ void k_sched(int P, int32_t n, Slot* __restrict__ slots, int32_t* __restrict__ has_next,
-                        const int32_t* __restrict__ probe_list, const int32_t* __restrict__ t_parent,
-                        const int32_t* __restrict__ t_node, const int32_t* __restrict__ t_depth,
-                        const int32_t* __restrict__ t_query, const int32_t* __restrict__ t_weight,
-                        const QueryDev* __restrict__ qs, const float* __restrict__ thr_tab,
-                        float* __restrict__ dense_cur, int2* __restrict__ list_cur, uint64_t list_cap,
-                        unsigned long long* __restrict__ ctr, int cur) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) {
-    ctr[C_SMALL] = 0;
-    ctr[C_CHUNK] = 0;
-    ctr[C_LIST0 + (cur ^ 1)] = 0;
+struct SchedArgs {
+  int P;
+  int32_t n;
+  int qmax;
+  Slot* slots;
+  int32_t* has_next;
+  const int32_t* ring;
+  uint64_t ring_mask;
+  const int32_t* t_parent;
+  const int32_t* t_node;
+  const int32_t* t_depth;
+  const int32_t* t_query;
+  const int32_t* t_weight;
+  const QueryDev* qr;
+  const float* thr_tab;
+  unsigned long long* remaining;
+  int32_t* done_ring;
+  float* dense_cur;
+  int2* list_cur;
+  uint64_t list_cap;
+  unsigned long long* ctr;
+  int cur;
+};
+
+// One workgroup: advances every slot by one PROBE iteration, retires probes
+// whose last level (i-2) ran or whose frontier Rule 2 emptied, and hands free
+// slots the next pending probes in ring order.  A new probe on (u_1..u_i)
+// starts with H_0 = {u_i: 1}.
+__global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
+  __shared__ uint32_t wave_tot[kSchedThreads / 64];
+  __shared__ unsigned long long s_head, s_avail;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid >> 6;
+  if (tid == 0) {
+    a.ctr[C_SMALL] = 0;
+    a.ctr[C_CHUNK] = 0;
+    a.ctr[C_LIST0 + (a.cur ^ 1)] = 0;
+    s_head = a.ctr[C_HEAD];
+    s_avail = a.ctr[C_TAIL] - s_head;
   }
-  if (s >= P) return;
-  Slot st = slots[s];
-  bool fetch = false;
-  if (st.probe >= 0) {
-    if (st.last || !has_next[s]) {
-      st.probe = -1;
-      fetch = true;
-    } else {
-      st.level++;
-      st.cursor = t_parent[st.cursor];
-    }
-  } else {
-    fetch = true;
-  }
-  has_next[s] = 0;
-  if (fetch) {
-    const unsigned long long p = atomicAdd(&ctr[C_CURSOR], 1ull);
-    if (p < ctr[C_PROBES]) {
-      const int32_t t = probe_list[p];
-      st.probe = t;
-      st.level = 0;
-      st.depth = t_depth[t];
-      st.cursor = t_parent[t];
-      st.query = t_query[t];
-      st.w = (double)t_weight[t];
-      const int32_t x = t_node[t];
-      const unsigned long long pos = atomicAdd(&ctr[C_LIST0 + cur], 1ull);
-      if (pos < list_cap) {
-        dense_cur[(size_t)s * n + x] = 1.0f;
-        list_cur[pos] = make_int2(s, x);
+  __syncthreads();
+  Slot st[kSlotsPerSchedThread];
+  bool need[kSlotsPerSchedThread];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int r = 0; r < kSlotsPerSchedThread; ++r) {
+    const int s = tid * kSlotsPerSchedThread + r;
+    need[r] = false;
+    if (s >= a.P) continue;
+    st[r] = a.slots[s];
+    if (st[r].probe >= 0) {
+      if (st[r].last || !a.has_next[s]) {
+        const int q = st[r].query;
+        if (atomicAdd(&a.remaining[q], ~0ull) == 1ull) {  // last probe of the query
+          const unsigned long long pos = atomicAdd(&a.ctr[C_DONE], 1ull);
+          a.done_ring[pos % (unsigned long long)a.qmax] = q;
+        }
+        st[r].probe = -1;
+        need[r] = true;
       } else {
-        ctr[kOverflowIdx] = 1;
+        st[r].level++;
+        st[r].cursor = a.t_parent[st[r].cursor];
       }
-      atomicAdd(&ctr[C_LEVEL0], 1ull);
     } else {
-      st.probe = -1;
+      need[r] = true;
     }
+    a.has_next[s] = 0;
+    cnt += need[r] ? 1u : 0u;
   }
-  if (st.probe >= 0) {
-    const int e = st.depth - st.level - 1;  // iterations left, i-j-1 >= 1
-    st.thr = thr_tab[st.query * PS_MAX_WALK_LEN + e];
-    st.sc = qs[st.query].sc;
-    st.excl = t_node[st.cursor];
-    st.last = st.level == st.depth - 2;
+  // Exclusive scan of the per-thread counts of free slots.
+  const uint32_t incl = wave_incl_scan(cnt);
+  if (lane == 63) wave_tot[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+  for (int w = 0; w < kSchedThreads / 64; ++w) {
+    if (w < wv) before += wave_tot[w];
+    total += wave_tot[w];
   }
-  slots[s] = st;
+  unsigned long long rank = before + incl - cnt;
+  const unsigned long long head = s_head, avail = s_avail;
+#pragma unroll
+  for (int r = 0; r < kSlotsPerSchedThread; ++r) {
+    const int s = tid * kSlotsPerSchedThread + r;
+    if (s >= a.P) continue;
+    if (need[r]) {
+      if (rank < avail) {
+        const int32_t t = a.ring[(head + rank) & a.ring_mask];
+        const int q = a.t_query[t];
+        const QueryDev& Q = a.qr[q];
+        st[r].probe = t;
+        st[r].level = 0;
+        st[r].depth = a.t_depth[t];
+        st[r].cursor = a.t_parent[t];
+        st[r].query = q;
+        st[r].w = (double)a.t_weight[t];
+        st[r].sc = Q.sc;
+        st[r].out_rows = Q.out_rows;
+        st[r].out_col = Q.out_col;
+        st[r].inv_indeg = Q.inv_indeg;
+        st[r].acc = Q.acc;
+        const int32_t x = a.t_node[t];
+        const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
+        if (pos < a.list_cap) {
+          a.dense_cur[(size_t)s * a.n + x] = 1.0f;
+          a.list_cur[pos] = make_int2(s, x);
+        } else {
+          a.ctr[C_OVERFLOW] = 1;
+        }
+        atomicAdd(&a.ctr[C_LEVEL0], 1ull);
+      }
+      ++rank;
+    }
+    if (st[r].probe >= 0) {
+      const int e = st[r].depth - st[r].level - 1;  // iterations left, i-j-1 >= 1
+      st[r].thr = a.thr_tab[st[r].query * PS_MAX_WALK_LEN + e];
+      st[r].excl = a.t_node[st[r].cursor];
+      st[r].last = st[r].level == st[r].depth - 2;
+    }
+    a.slots[s] = st[r];
+  }
+  if (tid == 0) a.ctr[C_HEAD] = head + (total < avail ? total : avail);
 }
 
 // Reads and clears the scores of the listed entries, applies Rule 2 (remove x
@@ -336,9 +426,8 @@ __global__ void k_sched(int P, int32_t n, Slot* __restrict__ slots, int32_t* __r
 // cut into 512-edge chunks for the wavefront-per-chunk list.
 __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restrict__ slots,
                                                  const int2* __restrict__ list_cur, float* __restrict__ dense_cur,
-                                                 float* __restrict__ item_val, const uint2* __restrict__ out_rows,
-                                                 int32_t* __restrict__ small_list, int2* __restrict__ chunk_list,
-                                                 uint64_t list_cap, uint64_t chunk_cap,
+                                                 float* __restrict__ item_val, int32_t* __restrict__ small_list,
+                                                 int2* __restrict__ chunk_list, uint64_t list_cap, uint64_t chunk_cap,
                                                  unsigned long long* __restrict__ ctr, int cur) {
   // after an overflow the counter runs past the list; never read beyond it
   const unsigned long long cnt = min(ctr[C_LIST0 + cur], (unsigned long long)list_cap);
@@ -358,12 +447,12 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       const Slot& sl = slots[it.x];
       if (val > sl.thr) {
         ++kept;
-        const uint2 row = out_rows[it.y];
-        if (row.y) {
+        const uint32_t deg = sl.out_rows[it.y].y;
+        if (deg) {
           item_val[i] = val * sl.sc;
-          edges += row.y;
-          if (row.y <= kSmallDeg) small = true;
-          else nch = (row.y + kChunk - 1) / kChunk;
+          edges += deg;
+          if (deg <= kSmallDeg) small = true;
+          else nch = (deg + kChunk - 1) / kChunk;
         }
       } else {
         ++pruned;
@@ -381,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       if (first + nch <= chunk_cap) {
         for (uint32_t c = 0; c < nch; ++c) chunk_list[first + c] = make_int2((int32_t)i, (int32_t)c);
       } else if (nch) {
-        ctr[kOverflowIdx] = 1;
+        ctr[C_OVERFLOW] = 1;
       }
     }
   }
@@ -402,11 +491,7 @@ struct ExpandArgs {
   const int32_t* small_list;
   const int2* chunk_list;
   const Slot* slots;
-  const uint2* out_rows;
-  const int32_t* out_col;
-  const float* inv_indeg;
   float* dense_next;
-  double* acc;
   int2* list_next;
   uint64_t list_cap;
   uint64_t chunk_cap;
@@ -421,10 +506,10 @@ __device__ __forceinline__ void visit_edge(const ExpandArgs& a, bool active, int
                                            const Slot& sl, unsigned long long& nfinal, unsigned long long& nnext) {
   bool append = false;
   if (active && v != sl.excl) {
-    const float c = sv * a.inv_indeg[v];
+    const float c = sv * sl.inv_indeg[v];
     if (c >= 1.17549435e-38f) {  // contributions below FLT_MIN are dropped
       if (sl.last) {
-        unsafeAtomicAdd(&a.acc[(size_t)sl.query * a.n + v], (double)c * sl.w);
+        unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
         ++nfinal;
       } else {
         const float old = unsafeAtomicAdd(&a.dense_next[(size_t)s * a.n + v], c);
@@ -439,7 +524,7 @@ __device__ __forceinline__ void visit_edge(const ExpandArgs& a, bool active, int
         a.list_next[pos] = make_int2(s, v);
         a.has_next[s] = 1;
       } else {
-        a.ctr[kOverflowIdx] = 1;
+        a.ctr[C_OVERFLOW] = 1;
       }
     }
   }
@@ -464,11 +549,11 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
       s = it.x;
       sl = a.slots[s];
       sv = a.item_val[i];
-      const uint2 row = a.out_rows[it.y];
+      const uint2 row = sl.out_rows[it.y];
       start = row.x;
       deg = row.y;
     }
-    for (uint32_t t = 0; t < deg; ++t) visit_edge(a, true, s, a.out_col[start + t], sv, sl, nfinal, nnext);
+    for (uint32_t t = 0; t < deg; ++t) visit_edge(a, true, s, sl.out_col[start + t], sv, sl, nfinal, nnext);
   }
   // Long rows: one wavefront per chunk of 512 consecutive out-edges.
   const unsigned long long nchunk = min(a.ctr[C_CHUNK], (unsigned long long)a.chunk_cap);
@@ -478,13 +563,13 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
     const int32_t s = it.x;
     const Slot sl = a.slots[s];
     const float sv = a.item_val[ch.x];
-    const uint2 row = a.out_rows[it.y];
+    const uint2 row = sl.out_rows[it.y];
     const uint32_t b = (uint32_t)ch.y * kChunk;
     const uint32_t e = min(row.y, b + kChunk);
     for (uint32_t t0 = b; t0 < e; t0 += 64) {
       const uint32_t t = t0 + lane;
       const bool act = t < e;
-      const int32_t v = act ? a.out_col[row.x + t] : -1;
+      const int32_t v = act ? sl.out_col[row.x + t] : -1;
       visit_edge(a, act, s, v, sv, sl, nfinal, nnext);
     }
   }
@@ -497,15 +582,10 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
 }
 
 // s^(u, v) = acc / n_r (+ shift for v != u), s^(u, u) = 1.
-__global__ void k_finalize(int32_t n, const QueryDev* __restrict__ qs, int nq, double* __restrict__ acc) {
-  const uint64_t total = (uint64_t)n * nq;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const int q = (int)(i / (uint64_t)n);
-    const int32_t v = (int32_t)(i - (uint64_t)q * n);
-    const QueryDev Q = qs[q];
-    acc[i] = v == Q.u ? 1.0 : acc[i] * Q.inv_nr + Q.shift;
-  }
+__global__ void k_finalize(int32_t n, const QueryDev* __restrict__ qr, int r) {
+  const QueryDev Q = qr[r];
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    Q.acc[v] = v == Q.u ? 1.0 : Q.acc[v] * Q.inv_nr + Q.shift;
 }
 
 // Sort keys for top-k: the estimate, with u itself pushed below every node.
@@ -530,13 +610,41 @@ int grid_for(uint64_t work, int block) {
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 1u << 30));
 }
 
-constexpr int kStepGrid = 2048;  // 8 workgroups per CU for the level-step kernels
-
 ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (!bytes) return PS_OK;
   const hipMemcpyKind kind = ps_is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   PS_HIP(hipMemcpyAsync(dst, src, bytes, kind, st));
   return PS_OK;
+}
+
+bool tree_alloc(Session* s, uint64_t len, uint64_t* start) {
+  for (size_t i = 0; i < s->tree_free.size(); ++i) {
+    auto& f = s->tree_free[i];
+    if (f.second >= len) {
+      *start = f.first;
+      f.first += len;
+      f.second -= len;
+      if (!f.second) s->tree_free.erase(s->tree_free.begin() + (long)i);
+      return true;
+    }
+  }
+  return false;
+}
+
+void tree_release(Session* s, uint64_t start, uint64_t len) {
+  if (!len) return;
+  auto& fl = s->tree_free;
+  auto it = std::lower_bound(fl.begin(), fl.end(), std::make_pair(start, (uint64_t)0));
+  it = fl.insert(it, {start, len});
+  // coalesce with the neighbours
+  if (it + 1 != fl.end() && it->first + it->second == (it + 1)->first) {
+    it->second += (it + 1)->second;
+    fl.erase(it + 1);
+  }
+  if (it != fl.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+    (it - 1)->second += it->second;
+    fl.erase(it);
+  }
 }
 
 }  // namespace
@@ -562,6 +670,366 @@ void devbuf_free(DevBuf& b) {
   b.bytes = 0;
 }
 
+void session_free(Session* s) {
+  if (!s) return;
+  DevBuf* bufs[] = {&s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
+                    &s->item_val, &s->small_list, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
+                    &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->keys,
+                    &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
+                    &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp};
+  for (DevBuf* b : bufs) devbuf_free(*b);
+  if (s->h_ctr) (void)hipHostFree(s->h_ctr);
+  delete s;
+}
+
+// Probe slots: enough concurrent probes to fill the GPU, bounded so that the
+// per-slot buffers (dense scores 8 B, frontier lists 16 B, scaled scores 4 B,
+// bins 12 B per node) stay within a fixed share of HBM and slot * n fits in
+// 31 bits.
+int session_slots_for(int32_t n, int opt) {
+  if (opt > 0) return std::min(opt, kSchedThreads * kSlotsPerSchedThread);
+  const uint64_t budget = 24ull << 30;
+  uint64_t p = budget / (40ull * (uint64_t)n);
+  p = std::min<uint64_t>(p, ((1ull << 31) - 1) / (uint64_t)n);
+  p = std::min<uint64_t>(p, 512);
+  return (int)std::max<uint64_t>(p, 1);
+}
+
+ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax, uint64_t tree_pool,
+                         uint64_t ring_cap) {
+  Session*& s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  ring_cap = next_pow2(std::max<uint64_t>(ring_cap, 1024));
+  tree_pool = std::max<uint64_t>(tree_pool, 1024);
+  if (s && s->n == n && s->P == P && s->qmax >= qmax && s->tree_pool >= tree_pool && s->ring_cap >= ring_cap &&
+      s->chunk_cap >= s->list_cap + ((uint64_t)P * m_cap) / kChunk + 1)
+    return PS_OK;
+  if (s && (int)s->free_recs.size() != s->qmax) return PS_ERR_STATE;  // queries admitted
+  if (!s) s = new Session();
+  const bool shape = s->n != n || s->P != P;
+  s->n = n;
+  s->P = P;
+  s->qmax = std::max(qmax, s->qmax);
+  s->tree_pool = std::max(tree_pool, s->tree_pool);
+  s->ring_cap = std::max(ring_cap, s->ring_cap);
+  // Every (slot, node) pair enters a frontier list at most once per step, so
+  // P * n entries never overflow; chunks add at most m / 512 per slot.
+  s->list_cap = (uint64_t)P * (uint64_t)n;
+  s->chunk_cap = s->list_cap + ((uint64_t)P * m_cap) / kChunk + 1;
+  PS_TRY(devbuf_reserve(s->slots, sizeof(Slot) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->has_next, sizeof(int32_t) * (size_t)P));
+  const bool fresh = !s->dense[0].p || shape;
+  PS_TRY(devbuf_reserve(s->dense[0], sizeof(float) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->dense[1], sizeof(float) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->list[0], sizeof(int2) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->list[1], sizeof(int2) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->item_val, sizeof(float) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->small_list, sizeof(int32_t) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->chunk_list, sizeof(int2) * s->chunk_cap));
+  PS_TRY(devbuf_reserve(s->counters, sizeof(unsigned long long) * C_COUNT));
+  PS_TRY(devbuf_reserve(s->qrec, sizeof(QueryDev) * (size_t)s->qmax));
+  PS_TRY(devbuf_reserve(s->thr, sizeof(float) * (size_t)s->qmax * PS_MAX_WALK_LEN));
+  PS_TRY(devbuf_reserve(s->remaining, sizeof(unsigned long long) * (size_t)s->qmax));
+  PS_TRY(devbuf_reserve(s->done_ring, sizeof(int32_t) * (size_t)s->qmax));
+  PS_TRY(devbuf_reserve(s->qbound, sizeof(unsigned long long) * (size_t)s->qmax));
+  PS_TRY(devbuf_reserve(s->acc, sizeof(double) * (size_t)s->qmax * (size_t)n));
+  PS_TRY(devbuf_reserve(s->lq, sizeof(int32_t) * (size_t)s->qmax));
+  PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
+  PS_TRY(devbuf_reserve(s->t_parent, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+  PS_TRY(devbuf_reserve(s->t_node, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+  PS_TRY(devbuf_reserve(s->t_depth, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+  PS_TRY(devbuf_reserve(s->t_query, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+  PS_TRY(devbuf_reserve(s->t_weight, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+  PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
+  if (!s->h_ctr) PS_HIP(hipHostMalloc((void**)&s->h_ctr, sizeof(uint64_t) * C_COUNT, 0));
+  if (fresh) {
+    PS_HIP(hipMemsetAsync(s->dense[0].p, 0, sizeof(float) * s->list_cap, st));
+    PS_HIP(hipMemsetAsync(s->dense[1].p, 0, sizeof(float) * s->list_cap, st));
+  }
+  PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
+  k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(s->slots.as<Slot>(), s->has_next.as<int32_t>(), P);
+  PS_HIP(hipGetLastError());
+  s->steps = 0;
+  s->free_recs.clear();
+  for (int r = s->qmax - 1; r >= 0; --r) s->free_recs.push_back(r);
+  s->h_rec.assign((size_t)s->qmax, QueryDev{});
+  s->rec_version.assign((size_t)s->qmax, nullptr);
+  s->rec_tree.assign((size_t)s->qmax, {0, 0});
+  s->rec_ring.assign((size_t)s->qmax, 0);
+  s->tree_free.assign(1, {0, s->tree_pool});
+  s->ring_outstanding = 0;
+  PS_HIP(hipStreamSynchronize(st));
+  return PS_OK;
+}
+
+bool session_can_admit(const Session* s, uint64_t bound) {
+  if (!s || s->free_recs.empty()) return false;
+  if (s->ring_outstanding + bound > s->ring_cap) return false;
+  const uint64_t need = next_pow2(std::max<uint64_t>(2 * bound, 64));
+  for (auto& f : s->tree_free)
+    if (f.second >= need) return true;
+  return false;
+}
+
+// Phase 1 of admission: records, walk sampling, tree sizes (one sync).
+ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
+                        std::vector<int>* recs, std::vector<uint64_t>* bounds) {
+  Session* s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  if ((size_t)s->free_recs.size() < qs.size()) return PS_ERR_BUSY;
+  recs->clear();
+  bounds->assign(qs.size(), 0);
+  if (qs.empty()) return PS_OK;
+  // one threshold row per query, alive until the synchronisation below
+  std::vector<float> thr_all(qs.size() * PS_MAX_WALK_LEN, 0.0f);
+  int64_t total = 0;
+  for (const QueryRun& q : qs) {
+    float* thr = thr_all.data() + recs->size() * PS_MAX_WALK_LEN;
+    const int r = s->free_recs.back();
+    s->free_recs.pop_back();
+    recs->push_back(r);
+    QueryDev d{};
+    d.u = q.u;
+    d.L = q.prm.L;
+    d.t_stop = q.prm.t_stop;
+    d.topk = q.k;
+    d.seed = q.seed;
+    d.walk_begin = q.walk_begin;
+    d.walk_count = q.walk_end - q.walk_begin;
+    d.walk_base = total;
+    const double sc = std::sqrt(q.prm.c);
+    d.sc = (float)sc;
+    d.inv_nr = 1.0 / (double)q.prm.n_r;
+    d.shift = q.bias_shift ? q.prm.eps_t / 2.0 : 0.0;
+    d.in_rows = gv->in_rows;
+    d.in_col = gv->in_store->col;
+    d.out_rows = gv->out_rows;
+    d.out_col = gv->out_store->col;
+    d.inv_indeg = gv->inv_indeg;
+    d.acc = s->acc.as<double>() + (size_t)r * (size_t)s->n;
+    total += d.walk_count;
+    s->h_rec[(size_t)r] = d;
+    {
+      std::lock_guard<std::mutex> lk(g->mu);
+      gv->refs++;
+    }
+    s->rec_version[(size_t)r] = gv;
+    // Rule 2 thresholds thr[e] = eps_p / sqrt(c)^e (0 = no pruning)
+    for (int x = 1; x < PS_MAX_WALK_LEN; ++x)
+      thr[x] = q.prm.eps_p > 0.0 ? (float)(q.prm.eps_p / std::pow(sc, (double)x)) : 0.0f;
+    PS_HIP(hipMemcpyAsync(s->thr.as<float>() + (size_t)r * PS_MAX_WALK_LEN, thr, sizeof(float) * PS_MAX_WALK_LEN,
+                          hipMemcpyHostToDevice, st));
+    PS_HIP(hipMemcpyAsync(s->qrec.as<QueryDev>() + r, &s->h_rec[(size_t)r], sizeof(QueryDev), hipMemcpyHostToDevice,
+                          st));
+    PS_HIP(hipMemsetAsync(d.acc, 0, sizeof(double) * (size_t)s->n, st));
+    PS_HIP(hipMemsetAsync(s->qbound.as<unsigned long long>() + r, 0, sizeof(unsigned long long), st));
+    PS_HIP(hipMemsetAsync(s->remaining.as<unsigned long long>() + r, 0, sizeof(unsigned long long), st));
+  }
+  PS_HIP(hipMemcpyAsync(s->lq.p, recs->data(), sizeof(int32_t) * recs->size(), hipMemcpyHostToDevice, st));
+  if (total > 0) {
+    k_walk_bound<<<grid_for((uint64_t)total, kBlock), kBlock, 0, st>>>(
+        s->qrec.as<QueryDev>(), s->lq.as<int32_t>(), (int)recs->size(), total, s->qbound.as<unsigned long long>(),
+        s->counters.as<unsigned long long>());
+    PS_HIP(hipGetLastError());
+  }
+  std::vector<unsigned long long> hb((size_t)s->qmax);
+  PS_HIP(hipMemcpyAsync(hb.data(), s->qbound.p, sizeof(unsigned long long) * (size_t)s->qmax, hipMemcpyDeviceToHost,
+                        st));
+  PS_HIP(hipStreamSynchronize(st));
+  for (size_t i = 0; i < recs->size(); ++i) (*bounds)[i] = hb[(size_t)(*recs)[i]];
+  return PS_OK;
+}
+
+// Phase 2 of admission: tree regions, tree construction, probes queued.
+// Records with bound 0 have no probe and need no tree.
+ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds) {
+  Session* s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  std::vector<int32_t> launch;
+  int64_t total = 0;
+  uint64_t ring_need = 0;
+  for (size_t i = 0; i < recs.size(); ++i) ring_need += bounds[i];
+  if (s->ring_outstanding + ring_need > s->ring_cap) return PS_ERR_BUSY;
+  std::vector<std::pair<int, uint64_t>> got;
+  for (size_t i = 0; i < recs.size(); ++i) {
+    if (!bounds[i]) continue;
+    const int r = recs[i];
+    const uint64_t cap = next_pow2(std::max<uint64_t>(2 * bounds[i], 64));
+    uint64_t start;
+    if (!tree_alloc(s, cap, &start)) {
+      for (auto& gr : got) tree_release(s, s->rec_tree[(size_t)gr.first].first, gr.second);
+      return PS_ERR_BUSY;
+    }
+    got.push_back({r, cap});
+    s->rec_tree[(size_t)r] = {start, cap};
+  }
+  for (size_t i = 0; i < recs.size(); ++i) {
+    if (!bounds[i]) continue;
+    const int r = recs[i];
+    QueryDev& d = s->h_rec[(size_t)r];
+    d.tree_base = s->rec_tree[(size_t)r].first;
+    d.tree_mask = s->rec_tree[(size_t)r].second - 1;
+    d.walk_base = total;
+    total += d.walk_count;
+    s->rec_ring[(size_t)r] = bounds[i];
+    s->ring_outstanding += bounds[i];
+    launch.push_back(r);
+    PS_HIP(hipMemcpyAsync(s->qrec.as<QueryDev>() + r, &d, sizeof(QueryDev), hipMemcpyHostToDevice, st));
+    PS_HIP(hipMemsetAsync(s->keys.as<unsigned long long>() + d.tree_base, 0xFF,
+                          sizeof(unsigned long long) * (d.tree_mask + 1), st));
+    PS_HIP(hipMemsetAsync(s->t_weight.as<int32_t>() + d.tree_base, 0, sizeof(int32_t) * (d.tree_mask + 1), st));
+  }
+  if (launch.empty()) return PS_OK;
+  PS_HIP(hipMemcpyAsync(s->lq.p, launch.data(), sizeof(int32_t) * launch.size(), hipMemcpyHostToDevice, st));
+  k_init_roots<<<grid_for(launch.size(), kBlock), kBlock, 0, st>>>(
+      s->qrec.as<QueryDev>(), s->lq.as<int32_t>(), (int)launch.size(), s->tree_pool, s->t_parent.as<int32_t>(),
+      s->t_node.as<int32_t>(), s->t_depth.as<int32_t>(), s->t_query.as<int32_t>());
+  PS_HIP(hipGetLastError());
+  TreeArgs a{};
+  a.qr = s->qrec.as<QueryDev>();
+  a.lq = s->lq.as<int32_t>();
+  a.nl = (int)launch.size();
+  a.total = total;
+  a.root_base = s->tree_pool;
+  a.keys = s->keys.as<unsigned long long>();
+  a.t_parent = s->t_parent.as<int32_t>();
+  a.t_node = s->t_node.as<int32_t>();
+  a.t_depth = s->t_depth.as<int32_t>();
+  a.t_query = s->t_query.as<int32_t>();
+  a.t_weight = s->t_weight.as<int32_t>();
+  a.ring = s->ring.as<int32_t>();
+  a.ring_mask = s->ring_cap - 1;
+  a.remaining = s->remaining.as<unsigned long long>();
+  a.ctr = s->counters.as<unsigned long long>();
+  if (total > 0) {
+    k_walk_tree<<<grid_for((uint64_t)total, kBlock), kBlock, 0, st>>>(a);
+    PS_HIP(hipGetLastError());
+  }
+  return PS_OK;
+}
+
+ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
+  Session* s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  unsigned long long* ctr = s->counters.as<unsigned long long>();
+  SchedArgs sa{};
+  sa.P = s->P;
+  sa.n = s->n;
+  sa.qmax = s->qmax;
+  sa.slots = s->slots.as<Slot>();
+  sa.has_next = s->has_next.as<int32_t>();
+  sa.ring = s->ring.as<int32_t>();
+  sa.ring_mask = s->ring_cap - 1;
+  sa.t_parent = s->t_parent.as<int32_t>();
+  sa.t_node = s->t_node.as<int32_t>();
+  sa.t_depth = s->t_depth.as<int32_t>();
+  sa.t_query = s->t_query.as<int32_t>();
+  sa.t_weight = s->t_weight.as<int32_t>();
+  sa.qr = s->qrec.as<QueryDev>();
+  sa.thr_tab = s->thr.as<float>();
+  sa.remaining = s->remaining.as<unsigned long long>();
+  sa.done_ring = s->done_ring.as<int32_t>();
+  sa.list_cap = s->list_cap;
+  sa.ctr = ctr;
+  ExpandArgs ea{};
+  ea.n = s->n;
+  ea.item_val = s->item_val.as<float>();
+  ea.small_list = s->small_list.as<int32_t>();
+  ea.chunk_list = s->chunk_list.as<int2>();
+  ea.slots = s->slots.as<Slot>();
+  ea.list_cap = s->list_cap;
+  ea.chunk_cap = s->chunk_cap;
+  ea.has_next = s->has_next.as<int32_t>();
+  ea.ctr = ctr;
+  const bool timing = ctx->timing && expand_ms;
+  if (timing) {
+    while (ctx->ev_pool.size() < 2 * count) {
+      hipEvent_t ev;
+      PS_HIP(hipEventCreate(&ev));
+      ctx->ev_pool.push_back(ev);
+    }
+  }
+  for (uint64_t t = 0; t < count; ++t) {
+    const int cur = (int)(s->steps & 1), nxt = cur ^ 1;
+    sa.dense_cur = s->dense[cur].as<float>();
+    sa.list_cur = s->list[cur].as<int2>();
+    sa.cur = cur;
+    k_sched<<<1, kSchedThreads, 0, st>>>(sa);
+    k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
+                                         s->item_val.as<float>(), s->small_list.as<int32_t>(),
+                                         s->chunk_list.as<int2>(), s->list_cap, s->chunk_cap, ctr, cur);
+    ea.list_cur = s->list[cur].as<int2>();
+    ea.dense_next = s->dense[nxt].as<float>();
+    ea.list_next = s->list[nxt].as<int2>();
+    ea.nxt = nxt;
+    if (timing) PS_HIP(hipEventRecord(ctx->ev_pool[2 * t], st));
+    k_expand<<<kStepGrid, kBlock, 0, st>>>(ea);
+    if (timing) PS_HIP(hipEventRecord(ctx->ev_pool[2 * t + 1], st));
+    s->steps++;
+  }
+  PS_HIP(hipGetLastError());
+  if (timing) {
+    PS_HIP(hipStreamSynchronize(st));
+    double ms = 0.0;
+    for (uint64_t t = 0; t < count; ++t) {
+      float x = 0.0f;
+      PS_HIP(hipEventElapsedTime(&x, ctx->ev_pool[2 * t], ctx->ev_pool[2 * t + 1]));
+      ms += x;
+    }
+    *expand_ms += ms;
+  }
+  return PS_OK;
+}
+
+// Finalises record r and writes its result; frees the record.
+ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, const QueryOut& out) {
+  Session* s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  const int32_t n = s->n;
+  double* acc = s->h_rec[(size_t)r].acc;
+  k_finalize<<<grid_for((uint64_t)n, kBlock) > 4096 ? 4096 : grid_for((uint64_t)n, kBlock), kBlock, 0, st>>>(
+      n, s->qrec.as<QueryDev>(), r);
+  PS_HIP(hipGetLastError());
+  if (q.k <= 0) {
+    PS_TRY(copy_out(out.scores, acc, sizeof(double) * (size_t)n, st));
+  } else {
+    PS_TRY(devbuf_reserve(s->sort_keys[0], sizeof(double) * (size_t)n));
+    PS_TRY(devbuf_reserve(s->sort_keys[1], sizeof(double) * (size_t)n));
+    PS_TRY(devbuf_reserve(s->sort_vals[0], sizeof(int32_t) * (size_t)n));
+    PS_TRY(devbuf_reserve(s->sort_vals[1], sizeof(int32_t) * (size_t)n));
+    k_topk_keys<<<kStepGrid, kBlock, 0, st>>>(n, q.u, acc, s->sort_keys[0].as<double>(), s->sort_vals[0].as<int32_t>());
+    PS_HIP(hipGetLastError());
+    size_t tmp = 0;
+    PS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp, s->sort_keys[0].as<double>(),
+                                                         s->sort_keys[1].as<double>(), s->sort_vals[0].as<int32_t>(),
+                                                         s->sort_vals[1].as<int32_t>(), n, 0, 64, st));
+    PS_TRY(devbuf_reserve(s->sort_tmp, tmp));
+    PS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(s->sort_tmp.p, tmp, s->sort_keys[0].as<double>(),
+                                                         s->sort_keys[1].as<double>(), s->sort_vals[0].as<int32_t>(),
+                                                         s->sort_vals[1].as<int32_t>(), n, 0, 64, st));
+    PS_TRY(copy_out(out.scores, s->sort_keys[1].p, sizeof(double) * (size_t)q.k, st));
+    PS_TRY(copy_out(out.nodes, s->sort_vals[1].p, sizeof(int32_t) * (size_t)q.k, st));
+  }
+  // release the record (later users are ordered after these copies on the stream)
+  auto tr = s->rec_tree[(size_t)r];
+  tree_release(s, tr.first, tr.second);
+  s->rec_tree[(size_t)r] = {0, 0};
+  s->ring_outstanding -= s->rec_ring[(size_t)r];
+  s->rec_ring[(size_t)r] = 0;
+  if (s->rec_version[(size_t)r]) graph_release(g, s->rec_version[(size_t)r]);
+  s->rec_version[(size_t)r] = nullptr;
+  s->free_recs.push_back(r);
+  return PS_OK;
+}
+
+// Releases a record whose tree was never built (admission failed).
+void session_abandon(ps_ctx* ctx, ps_graph* g, int r) {
+  Session* s = ctx->sess;
+  if (s->rec_version[(size_t)r]) graph_release(g, s->rec_version[(size_t)r]);
+  s->rec_version[(size_t)r] = nullptr;
+  s->free_recs.push_back(r);
+}
+
 ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun& q, int64_t k_begin, int64_t count,
                        int32_t* nodes, int32_t* lens) {
   (void)n;
@@ -571,45 +1039,28 @@ ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun&
   d.L = q.prm.L;
   d.t_stop = q.prm.t_stop;
   d.seed = q.seed;
-  Engine& e = ctx->eng;
+  d.in_rows = gv->in_rows;
+  d.in_col = gv->in_store->col;
   const size_t nb = sizeof(int32_t) * (size_t)count * (size_t)d.L;
-  PS_TRY(devbuf_reserve(e.stage, nb + sizeof(int32_t) * (size_t)count + 256));
-  int32_t* dn = e.stage.as<int32_t>();
-  int32_t* dl = dn + (size_t)count * d.L;
+  int32_t* dn = nullptr;
   if (count > 0) {
-    k_walk_export<<<grid_for((uint64_t)count, kBlock), kBlock, 0, st>>>(d, k_begin, count, gv->in_rows,
-                                                                       gv->in_store->col, dn, dl);
+    PS_HIP(hipMalloc(&dn, nb + sizeof(int32_t) * (size_t)count));
+    int32_t* dl = dn + (size_t)count * d.L;
+    k_walk_export<<<grid_for((uint64_t)count, kBlock), kBlock, 0, st>>>(d, k_begin, count, dn, dl);
     PS_HIP(hipGetLastError());
     PS_TRY(copy_out(nodes, dn, nb, st));
     PS_TRY(copy_out(lens, dl, sizeof(int32_t) * (size_t)count, st));
   }
   PS_HIP(hipStreamSynchronize(st));
+  if (dn) (void)hipFree(dn);
   return PS_OK;
 }
 
-namespace {
-
-// Chooses the number of probe slots: enough concurrent probes to fill the
-// GPU, bounded so that the dense per-slot score vectors (2 x 4 B x n each)
-// stay within a fixed share of HBM and slot * n fits in 31 bits.
-int choose_slots(int32_t n, uint64_t levels, int opt) {
-  if (opt > 0) return opt;
-  const uint64_t budget = 16ull << 30;  // bytes for the dense score vectors
-  uint64_t p = budget / (8ull * (uint64_t)n);
-  p = std::min<uint64_t>(p, ((1ull << 31) - 1) / (uint64_t)n);
-  p = std::min<uint64_t>(p, 1024);
-  const uint64_t want = std::max<uint64_t>(64, levels / 8);
-  p = std::min(p, want);
-  return (int)std::max<uint64_t>(p, 1);
-}
-
-}  // namespace
-
-ps_status engine_run(ps_ctx* ctx, GraphVersion* gv, int32_t n, const std::vector<QueryRun>& qs,
+ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
                      const std::vector<QueryOut>& outs, int slots_opt) {
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t st = ctx->stream;
-  Engine& e = ctx->eng;
+  const int32_t n = g->n;
   const int nq = (int)qs.size();
   ps_stats stats{};
   stats.queries = nq;
@@ -617,216 +1068,66 @@ ps_status engine_run(ps_ctx* ctx, GraphVersion* gv, int32_t n, const std::vector
     ctx->last = stats;
     return PS_OK;
   }
-  // Query descriptors and Rule 2 thresholds thr[q][e] = eps_p / sqrt(c)^e.
-  std::vector<QueryDev> qd((size_t)nq);
-  std::vector<float> thr((size_t)nq * PS_MAX_WALK_LEN, 0.0f);
-  int64_t total_walks = 0;
+  const int P = session_slots_for(n, slots_opt);
+  const uint64_t m_cap = std::max<uint64_t>(gv->out_store->cap, 1);
+  Session* s = ctx->sess;
+  PS_TRY(session_ensure(ctx, n, m_cap, P, std::max(nq, s ? s->qmax : 0), s ? s->tree_pool : 0,
+                        s ? s->ring_cap : 0));
+  s = ctx->sess;
+  PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
+  PS_HIP(hipStreamSynchronize(st));
+  std::vector<uint64_t> before(s->h_ctr, s->h_ctr + C_COUNT);
+
+  std::vector<int> recs;
+  std::vector<uint64_t> bounds;
+  PS_TRY(session_begin(ctx, g, gv, qs, &recs, &bounds));
+  uint64_t pool_need = 0, ring_need = 0;
+  for (uint64_t b : bounds) {
+    if (b) pool_need += next_pow2(std::max<uint64_t>(2 * b, 64));
+    ring_need += b;
+  }
+  if (pool_need > s->tree_pool || ring_need > s->ring_cap) {
+    // Grow the tree pool / ring: only this call's records are admitted and
+    // their trees are not built yet, so the buffers can be replaced.
+    s->tree_pool = std::max(pool_need, s->tree_pool);
+    s->ring_cap = next_pow2(std::max(ring_need, s->ring_cap));
+    PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
+    for (DevBuf* b : {&s->t_parent, &s->t_node, &s->t_depth, &s->t_query, &s->t_weight})
+      PS_TRY(devbuf_reserve(*b, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+    PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
+    s->tree_free.assign(1, {0, s->tree_pool});
+  }
+  PS_TRY(session_build(ctx, recs, bounds));
+  PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
+  PS_HIP(hipStreamSynchronize(st));
+  const uint64_t levels = s->h_ctr[C_LEVELS] - before[C_LEVELS];
+  const uint64_t probes = s->h_ctr[C_TAIL] - before[C_TAIL];
   int maxL = 2;
-  for (int i = 0; i < nq; ++i) {
-    const QueryRun& q = qs[(size_t)i];
-    QueryDev& d = qd[(size_t)i];
-    d.u = q.u;
-    d.L = q.prm.L;
-    d.t_stop = q.prm.t_stop;
-    d.topk = q.k;
-    d.seed = q.seed;
-    d.walk_begin = q.walk_begin;
-    d.walk_count = q.walk_end - q.walk_begin;
-    d.walk_base = total_walks;
-    const double sc = std::sqrt(q.prm.c);
-    d.sc = (float)sc;
-    d.inv_nr = 1.0 / (double)q.prm.n_r;
-    d.shift = q.bias_shift ? q.prm.eps_t / 2.0 : 0.0;
-    total_walks += d.walk_count;
-    maxL = std::max(maxL, q.prm.L);
-    for (int x = 1; x < PS_MAX_WALK_LEN; ++x)
-      thr[(size_t)i * PS_MAX_WALK_LEN + x] = q.prm.eps_p > 0.0 ? (float)(q.prm.eps_p / std::pow(sc, (double)x)) : 0.0f;
-  }
-  stats.walks = total_walks;
-  PS_TRY(devbuf_reserve(e.qdesc, sizeof(QueryDev) * (size_t)nq));
-  PS_TRY(devbuf_reserve(e.thr, sizeof(float) * thr.size()));
-  PS_TRY(devbuf_reserve(e.counters, sizeof(unsigned long long) * (C_COUNT + 1)));
-  PS_TRY(devbuf_reserve(e.acc, sizeof(double) * (size_t)nq * (size_t)n));
-  if (!e.h_counters) PS_HIP(hipHostMalloc((void**)&e.h_counters, sizeof(uint64_t) * (C_COUNT + 1), 0));
-  PS_HIP(hipMemcpyAsync(e.qdesc.p, qd.data(), sizeof(QueryDev) * (size_t)nq, hipMemcpyHostToDevice, st));
-  PS_HIP(hipMemcpyAsync(e.thr.p, thr.data(), sizeof(float) * thr.size(), hipMemcpyHostToDevice, st));
-  unsigned long long* ctr = e.counters.as<unsigned long long>();
-  const QueryDev* dq = e.qdesc.as<QueryDev>();
-
-  // 1. Size the tree.
-  PS_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * (C_COUNT + 1), st));
-  if (total_walks > 0) {
-    k_walk_bound<<<grid_for((uint64_t)total_walks, kBlock), kBlock, 0, st>>>(dq, nq, total_walks, gv->in_rows,
-                                                                            gv->in_store->col, ctr);
-    PS_HIP(hipGetLastError());
-  }
-  PS_HIP(hipMemcpyAsync(e.h_counters, ctr, sizeof(uint64_t) * (C_COUNT + 1), hipMemcpyDeviceToHost, st));
+  for (auto& q : qs) maxL = std::max(maxL, q.prm.L);
+  // Greedy list scheduling: every slot is busy while probes are pending, and a
+  // probe holds its slot for depth-1 steps, so this many steps finish them all.
+  const uint64_t steps = probes ? (levels + P - 1) / P + (uint64_t)maxL + 2 : 0;
+  double expand_ms = 0.0;
+  PS_TRY(session_steps(ctx, steps, &expand_ms));
+  for (int i = 0; i < nq; ++i) PS_TRY(session_finish(ctx, g, recs[(size_t)i], qs[(size_t)i], outs[(size_t)i]));
+  PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
-  const uint64_t bound = e.h_counters[C_TREE_BOUND];
-  stats.walk_nodes = (int64_t)e.h_counters[C_WALK_NODES];
-
-  // 2. Build the reverse reachability tree.
-  const uint64_t cap = next_pow2(std::max<uint64_t>(2 * bound, 1024));
-  if (cap + (uint64_t)nq >= (1ull << 31)) return PS_ERR_OOM;
-  PS_TRY(devbuf_reserve(e.keys, sizeof(unsigned long long) * cap));
-  PS_TRY(devbuf_reserve(e.t_parent, sizeof(int32_t) * (cap + nq)));
-  PS_TRY(devbuf_reserve(e.t_node, sizeof(int32_t) * (cap + nq)));
-  PS_TRY(devbuf_reserve(e.t_depth, sizeof(int32_t) * (cap + nq)));
-  PS_TRY(devbuf_reserve(e.t_query, sizeof(int32_t) * (cap + nq)));
-  PS_TRY(devbuf_reserve(e.t_weight, sizeof(int32_t) * (cap + nq)));
-  PS_TRY(devbuf_reserve(e.probe_list, sizeof(int32_t) * std::max<uint64_t>(bound, 1)));
-  PS_HIP(hipMemsetAsync(e.keys.p, 0xFF, sizeof(unsigned long long) * cap, st));
-  PS_HIP(hipMemsetAsync(e.t_weight.p, 0, sizeof(int32_t) * (cap + nq), st));
-  k_init_roots<<<grid_for((uint64_t)nq, kBlock), kBlock, 0, st>>>(dq, nq, cap, e.t_parent.as<int32_t>(),
-                                                                  e.t_node.as<int32_t>(), e.t_depth.as<int32_t>(),
-                                                                  e.t_query.as<int32_t>());
-  PS_HIP(hipGetLastError());
-  if (total_walks > 0) {
-    k_walk_tree<<<grid_for((uint64_t)total_walks, kBlock), kBlock, 0, st>>>(
-        dq, nq, total_walks, gv->in_rows, gv->in_store->col, e.keys.as<unsigned long long>(), cap,
-        e.t_parent.as<int32_t>(), e.t_node.as<int32_t>(), e.t_depth.as<int32_t>(), e.t_query.as<int32_t>(),
-        e.t_weight.as<int32_t>(), e.probe_list.as<int32_t>(), ctr);
-    PS_HIP(hipGetLastError());
-  }
-  PS_HIP(hipMemcpyAsync(e.h_counters, ctr, sizeof(uint64_t) * (C_COUNT + 1), hipMemcpyDeviceToHost, st));
-  PS_HIP(hipStreamSynchronize(st));
-  const uint64_t n_probes = e.h_counters[C_PROBES];
-  const uint64_t levels = e.h_counters[C_LEVELS];
-  stats.tree_nodes = (int64_t)n_probes;
+  const uint64_t* h = s->h_ctr;
+  if (h[C_OVERFLOW]) return PS_ERR_OOM;  // impossible with worst-case capacities; a guard
+  if (h[C_HEAD] != h[C_TAIL]) return PS_ERR_STATE;
+  stats.walks = 0;
+  for (auto& q : qs) stats.walks += q.walk_end - q.walk_begin;
+  stats.walk_nodes = (int64_t)(h[C_WALK_NODES] - before[C_WALK_NODES]);
+  stats.tree_nodes = (int64_t)probes;
   stats.probe_levels = (int64_t)levels;
-
-  // 3. Level steps.
-  const int P = choose_slots(n, levels, slots_opt);
-  uint64_t list_cap = std::min<uint64_t>((uint64_t)P * (uint64_t)n, std::max<uint64_t>(1ull << 24, 8 * levels + (1ull << 22)));
-  list_cap = std::max<uint64_t>(list_cap, e.list_cap);
-  list_cap = std::min<uint64_t>(list_cap, (uint64_t)P * (uint64_t)n);
-  ps_status rs = PS_OK;
-  for (int attempt = 0; attempt < 8; ++attempt) {
-    const uint64_t chunk_cap = list_cap / 2 + (1ull << 20);
-    const bool fresh_dense = e.P != P || e.n != n || !e.dense[0].p;
-    PS_TRY(devbuf_reserve(e.dense[0], sizeof(float) * (size_t)P * n));
-    PS_TRY(devbuf_reserve(e.dense[1], sizeof(float) * (size_t)P * n));
-    PS_TRY(devbuf_reserve(e.list[0], sizeof(int2) * list_cap));
-    PS_TRY(devbuf_reserve(e.list[1], sizeof(int2) * list_cap));
-    PS_TRY(devbuf_reserve(e.item_val, sizeof(float) * list_cap));
-    PS_TRY(devbuf_reserve(e.small_list, sizeof(int32_t) * list_cap));
-    PS_TRY(devbuf_reserve(e.chunk_list, sizeof(int2) * chunk_cap));
-    PS_TRY(devbuf_reserve(e.slots, sizeof(Slot) * (size_t)P));
-    PS_TRY(devbuf_reserve(e.has_next, sizeof(int32_t) * (size_t)P));
-    if (fresh_dense || attempt > 0) {
-      PS_HIP(hipMemsetAsync(e.dense[0].p, 0, sizeof(float) * (size_t)P * n, st));
-      PS_HIP(hipMemsetAsync(e.dense[1].p, 0, sizeof(float) * (size_t)P * n, st));
-    }
-    e.P = P;
-    e.n = n;
-    e.list_cap = list_cap;
-    e.chunk_cap = chunk_cap;
-    PS_HIP(hipMemsetAsync(e.acc.p, 0, sizeof(double) * (size_t)nq * n, st));
-    // keep C_TREE_BOUND .. C_LEVELS; clear the rest
-    PS_HIP(hipMemsetAsync(ctr + C_CURSOR, 0, sizeof(unsigned long long) * (C_COUNT + 1 - C_CURSOR), st));
-    k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(e.slots.as<Slot>(), e.has_next.as<int32_t>(), P);
-    PS_HIP(hipGetLastError());
-
-    const uint64_t steps = (levels + P - 1) / P + (uint64_t)maxL + 2;
-    stats.steps = (int64_t)steps;
-    ExpandArgs a{};
-    a.n = n;
-    a.item_val = e.item_val.as<float>();
-    a.small_list = e.small_list.as<int32_t>();
-    a.chunk_list = e.chunk_list.as<int2>();
-    a.slots = e.slots.as<Slot>();
-    a.out_rows = gv->out_rows;
-    a.out_col = gv->out_store->col;
-    a.inv_indeg = gv->inv_indeg;
-    a.acc = e.acc.as<double>();
-    a.list_cap = list_cap;
-    a.chunk_cap = chunk_cap;
-    a.has_next = e.has_next.as<int32_t>();
-    a.ctr = ctr;
-    std::vector<hipEvent_t> evs;
-    if (ctx->timing) {
-      while (ctx->ev_pool.size() < 2 * steps) {
-        hipEvent_t ev;
-        PS_HIP(hipEventCreate(&ev));
-        ctx->ev_pool.push_back(ev);
-      }
-    }
-    for (uint64_t t = 0; t < steps; ++t) {
-      const int cur = (int)(t & 1), nxt = cur ^ 1;
-      k_sched<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(
-          P, n, e.slots.as<Slot>(), e.has_next.as<int32_t>(), e.probe_list.as<int32_t>(), e.t_parent.as<int32_t>(),
-          e.t_node.as<int32_t>(), e.t_depth.as<int32_t>(), e.t_query.as<int32_t>(), e.t_weight.as<int32_t>(), dq,
-          e.thr.as<float>(), e.dense[cur].as<float>(), e.list[cur].as<int2>(), list_cap, ctr, cur);
-      k_prep<<<kStepGrid, kBlock, 0, st>>>(n, e.slots.as<Slot>(), e.list[cur].as<int2>(), e.dense[cur].as<float>(),
-                                           e.item_val.as<float>(), gv->out_rows, e.small_list.as<int32_t>(),
-                                           e.chunk_list.as<int2>(), list_cap, chunk_cap, ctr, cur);
-      a.list_cur = e.list[cur].as<int2>();
-      a.dense_next = e.dense[nxt].as<float>();
-      a.list_next = e.list[nxt].as<int2>();
-      a.nxt = nxt;
-      if (ctx->timing) PS_HIP(hipEventRecord(ctx->ev_pool[2 * t], st));
-      k_expand<<<kStepGrid, kBlock, 0, st>>>(a);
-      if (ctx->timing) PS_HIP(hipEventRecord(ctx->ev_pool[2 * t + 1], st));
-    }
-    PS_HIP(hipGetLastError());
-    PS_HIP(hipMemcpyAsync(e.h_counters, ctr, sizeof(uint64_t) * (C_COUNT + 1), hipMemcpyDeviceToHost, st));
-    PS_HIP(hipStreamSynchronize(st));
-    stats.expand_launches = (int64_t)steps;
-    if (ctx->timing) {
-      double ms = 0.0;
-      for (uint64_t t = 0; t < steps; ++t) {
-        float x = 0.0f;
-        PS_HIP(hipEventElapsedTime(&x, ctx->ev_pool[2 * t], ctx->ev_pool[2 * t + 1]));
-        ms += x;
-      }
-      stats.expand_ms = ms;
-    }
-    if (!e.h_counters[kOverflowIdx] && e.h_counters[C_CURSOR] >= n_probes) {
-      rs = PS_OK;
-      break;
-    }
-    // A frontier list overflowed (or, impossible by the step bound, probes
-    // were left): grow the lists and run the steps again from clean state.
-    rs = PS_ERR_OOM;
-    if (list_cap >= (uint64_t)P * (uint64_t)n && e.h_counters[kOverflowIdx]) break;
-    list_cap = std::min<uint64_t>(list_cap * 4, (uint64_t)P * (uint64_t)n);
-  }
-  if (rs != PS_OK) return rs;
-  stats.entries_expanded = (int64_t)e.h_counters[C_KEPT];
-  stats.entries_pruned = (int64_t)e.h_counters[C_PRUNED];
-  stats.edges_scanned = (int64_t)e.h_counters[C_EDGES];
-  stats.next_entries = (int64_t)e.h_counters[C_NEXT];
-  stats.final_adds = (int64_t)e.h_counters[C_FINAL];
-
-  // 4. Finalise and write the results.
-  double* acc = e.acc.as<double>();
-  k_finalize<<<kStepGrid, kBlock, 0, st>>>(n, dq, nq, acc);
-  PS_HIP(hipGetLastError());
-  for (int i = 0; i < nq; ++i) {
-    const QueryRun& q = qs[(size_t)i];
-    const double* row = acc + (size_t)i * n;
-    if (q.k <= 0) {
-      PS_TRY(copy_out(outs[(size_t)i].scores, row, sizeof(double) * (size_t)n, st));
-      continue;
-    }
-    PS_TRY(devbuf_reserve(e.sort_keys[0], sizeof(double) * (size_t)n));
-    PS_TRY(devbuf_reserve(e.sort_keys[1], sizeof(double) * (size_t)n));
-    PS_TRY(devbuf_reserve(e.sort_vals[0], sizeof(int32_t) * (size_t)n));
-    PS_TRY(devbuf_reserve(e.sort_vals[1], sizeof(int32_t) * (size_t)n));
-    k_topk_keys<<<kStepGrid, kBlock, 0, st>>>(n, q.u, row, e.sort_keys[0].as<double>(), e.sort_vals[0].as<int32_t>());
-    PS_HIP(hipGetLastError());
-    size_t tmp = 0;
-    PS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp, e.sort_keys[0].as<double>(),
-                                                         e.sort_keys[1].as<double>(), e.sort_vals[0].as<int32_t>(),
-                                                         e.sort_vals[1].as<int32_t>(), n, 0, 64, st));
-    PS_TRY(devbuf_reserve(e.sort_tmp, tmp));
-    PS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(e.sort_tmp.p, tmp, e.sort_keys[0].as<double>(),
-                                                         e.sort_keys[1].as<double>(), e.sort_vals[0].as<int32_t>(),
-                                                         e.sort_vals[1].as<int32_t>(), n, 0, 64, st));
-    PS_TRY(copy_out(outs[(size_t)i].scores, e.sort_keys[1].p, sizeof(double) * (size_t)q.k, st));
-    PS_TRY(copy_out(outs[(size_t)i].nodes, e.sort_vals[1].p, sizeof(int32_t) * (size_t)q.k, st));
-  }
-  PS_HIP(hipStreamSynchronize(st));
+  stats.steps = (int64_t)steps;
+  stats.entries_expanded = (int64_t)(h[C_KEPT] - before[C_KEPT]);
+  stats.entries_pruned = (int64_t)(h[C_PRUNED] - before[C_PRUNED]);
+  stats.edges_scanned = (int64_t)(h[C_EDGES] - before[C_EDGES]);
+  stats.next_entries = (int64_t)(h[C_NEXT] - before[C_NEXT]);
+  stats.final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL]);
+  stats.expand_launches = (int64_t)steps;
+  stats.expand_ms = expand_ms;
   stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   ctx->last = stats;
   return PS_OK;

@@ -38,14 +38,45 @@ ps_status alloc_version_arrays(GraphVersion* v, int32_t n) {
   return PS_OK;
 }
 
+void drop_stores(GraphVersion* v) {
+  if (v->in_store && --v->in_store->refs == 0) (void)hipFree(v->in_store->col);
+  if (v->out_store && --v->out_store->refs == 0) (void)hipFree(v->out_store->col);
+  v->in_store.reset();
+  v->out_store.reset();
+}
+
 void free_version(GraphVersion* v) {
   if (!v) return;
   (void)hipFree(v->in_rows);
   (void)hipFree(v->out_rows);
   (void)hipFree(v->inv_indeg);
-  if (v->in_store && --v->in_store->refs == 0) (void)hipFree(v->in_store->col);
-  if (v->out_store && --v->out_store->refs == 0) (void)hipFree(v->out_store->col);
+  drop_stores(v);
   delete v;
+}
+
+// A superseded version's row arrays are kept for the next update batch
+// (a few at most), which saves an allocation per batch.
+void retire_version(ps_graph* g, GraphVersion* v) {
+  drop_stores(v);
+  if (g->spare.size() < 4) {
+    g->spare.push_back(v);
+  } else {
+    free_version(v);
+  }
+}
+
+GraphVersion* new_version(ps_graph* g) {
+  if (!g->spare.empty()) {
+    GraphVersion* v = g->spare.back();
+    g->spare.pop_back();
+    GraphVersion* fresh = new GraphVersion();
+    fresh->in_rows = v->in_rows;
+    fresh->out_rows = v->out_rows;
+    fresh->inv_indeg = v->inv_indeg;
+    delete v;
+    return fresh;
+  }
+  return new GraphVersion();
 }
 
 // Row of v in the host mirror (rewritten row if any, else the base CSR row).
@@ -136,7 +167,7 @@ void graph_release(ps_graph* g, GraphVersion* v) {
   std::lock_guard<std::mutex> lk(g->mu);
   if (--v->refs == 0) {
     g->retired.erase(std::remove(g->retired.begin(), g->retired.end(), v), g->retired.end());
-    free_version(v);
+    retire_version(g, v);
   }
 }
 
@@ -226,6 +257,7 @@ extern "C" void ps_graph_free(ps_graph* g) {
   (void)hipSetDevice(g->ctx->device);
   (void)hipStreamSynchronize(g->ctx->stream);
   for (auto* v : g->retired) free_version(v);
+  for (auto* v : g->spare) free_version(v);
   free_version(g->cur);
   ps_ctx* ctx = g->ctx;
   delete g;
@@ -308,7 +340,11 @@ ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const 
     hipStream_t st = ctx->stream;
     PS_HIP(hipSetDevice(ctx->device));
     GraphVersion* old = g->cur;
-    auto* v = new GraphVersion();
+    GraphVersion* v;
+    {
+      std::lock_guard<std::mutex> lk(g->mu);
+      v = new_version(g);
+    }
     v->version = old->version + 1;
     v->refs = 1;
     uint64_t need_in = 0, need_out = 0;
@@ -318,13 +354,21 @@ ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const 
                       old->out_store->used + need_out <= old->out_store->cap;
     if (!fits) {
       // Delta region exhausted: compact everything into fresh column stores.
+      if (v->in_rows) {
+        (void)hipFree(v->in_rows);
+        (void)hipFree(v->out_rows);
+        (void)hipFree(v->inv_indeg);
+        v->in_rows = nullptr;
+        v->out_rows = nullptr;
+        v->inv_indeg = nullptr;
+      }
       ps_status s = upload_full(g, v);
       if (s != PS_OK) {
         free_version(v);
         return s;
       }
     } else {
-      PS_TRY(alloc_version_arrays(v, g->n));
+      if (!v->in_rows) PS_TRY(alloc_version_arrays(v, g->n));
       PS_HIP(hipMemcpyAsync(v->in_rows, old->in_rows, sizeof(uint2) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
       PS_HIP(hipMemcpyAsync(v->out_rows, old->out_rows, sizeof(uint2) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
       PS_HIP(hipMemcpyAsync(v->inv_indeg, old->inv_indeg, sizeof(float) * (size_t)g->n, hipMemcpyDeviceToDevice, st));
@@ -368,7 +412,7 @@ ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const 
       std::lock_guard<std::mutex> lk(g->mu);
       g->cur = v;
       if (--old->refs == 0)
-        free_version(old);
+        retire_version(g, old);
       else
         g->retired.push_back(old);
     }

@@ -76,6 +76,7 @@ struct ps_graph {
   std::unordered_map<int32_t, std::vector<int32_t>> mod_in, mod_out;
   GraphVersion* cur = nullptr;
   std::vector<GraphVersion*> retired;  // superseded versions still read by queries
+  std::vector<GraphVersion*> spare;    // freed versions whose row arrays are reused
   std::mutex mu;
 };
 
@@ -90,7 +91,7 @@ ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const 
 
 // ----------------------------------------------------------------- engine --
 
-// Device descriptor of one query in a launch.
+// Device record of one query admitted to a session.
 struct QueryDev {
   int32_t u;
   int32_t L;
@@ -98,15 +99,23 @@ struct QueryDev {
   int32_t topk;
   uint64_t seed;
   int64_t walk_begin;  // first walk index k
-  int64_t walk_count;  // walks of this query in the launch
-  int64_t walk_base;   // offset of this query's walks in the launch's walk space
+  int64_t walk_count;  // walks of this query
+  int64_t walk_base;   // offset of its walks in the current walk launch
   float sc;            // sqrt(c) in FP32 (multiplies probe scores)
-  float pad;
+  int32_t pad;
   double inv_nr;       // 1 / n_r
   double shift;        // eps_t/2 when the bias shift is on, else 0
+  uint64_t tree_base;  // first entry of the query's region in the tree pool
+  uint64_t tree_mask;  // region capacity - 1 (a power of two)
+  const uint2* in_rows;  // graph version the query reads
+  const int32_t* in_col;
+  const uint2* out_rows;
+  const int32_t* out_col;
+  const float* inv_indeg;
+  double* acc;         // n FP64 accumulators, then the estimate
 };
 
-// Host view of a query being run.
+// Host view of a query.
 struct QueryRun {
   int32_t u = 0, k = 0;
   ps_params prm{};
@@ -121,24 +130,28 @@ struct Slot {
   int32_t level;   // PROBE iteration j of the entries currently listed
   int32_t depth;   // i: the probe runs on (u_1..u_i)
   int32_t cursor;  // tree node whose graph node is excluded at this level
-  int32_t query;   // index of the query in the launch
+  int32_t query;   // query record
   int32_t excl;    // graph node u_{i-j-1}, skipped by this level's expansion
   float thr;       // Rule 2: entries with score <= thr are removed
   float sc;        // sqrt(c)
   int32_t last;    // this level's expansion produces the returned score set
   int32_t pad;
   double w;        // number of walks sharing the probed prefix
+  const uint2* out_rows;
+  const int32_t* out_col;
+  const float* inv_indeg;
+  double* acc;
 };
 
 enum CounterIdx {
-  C_TREE_BOUND = 0,  // sum over walks of (len - 1)
-  C_PROBES,          // tree nodes (probes) inserted
-  C_LEVELS,          // sum over probes of (depth - 1)
-  C_CURSOR,          // next probe handed to a slot
-  C_LIST0,           // entries in list 0
-  C_LIST1,           // entries in list 1
-  C_SMALL,           // small-row work items this step
-  C_CHUNK,           // chunk work items this step
+  C_TAIL = 0,    // probes appended to the ring
+  C_HEAD,        // probes handed to slots
+  C_LIST0,       // entries in frontier list 0
+  C_LIST1,       // entries in frontier list 1
+  C_SMALL,       // short-row work items this step
+  C_CHUNK,       // chunk work items this step
+  C_DONE,        // queries completed (entries in the done ring)
+  C_LEVELS,      // sum over inserted probes of (depth - 1)
   C_WALK_NODES,
   C_KEPT,
   C_PRUNED,
@@ -146,21 +159,39 @@ enum CounterIdx {
   C_NEXT,
   C_FINAL,
   C_LEVEL0,
+  C_OVERFLOW,
   C_COUNT
 };
 
-struct Engine {
-  int P = 0;                 // probe slots
-  int32_t n = 0;             // graph nodes the buffers are sized for
-  uint64_t tree_cap = 0;     // hash table capacity (power of two)
-  uint64_t list_cap = 0;     // entries per frontier list
-  uint64_t chunk_cap = 0;
-  int nq_cap = 0;
-  DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, probe_list;
-  DevBuf slots, has_next, dense[2], list[2], item_val, small_list, chunk_list;
-  DevBuf counters, qdesc, thr, acc, stage;
+struct QueryOut {
+  double* scores = nullptr;  // n (single-source) or k (top-k); host or device
+  int32_t* nodes = nullptr;  // k (top-k)
+};
+
+// A persistent set of device buffers that runs the level steps of every
+// admitted query: P probe slots, a ring of pending probes, a pool of tree
+// regions and per-query records with FP64 accumulators.
+struct Session {
+  int32_t n = 0;
+  int P = 0;
+  int qmax = 0;
+  uint64_t list_cap = 0, chunk_cap = 0;
+  uint64_t tree_pool = 0;   // entries
+  uint64_t ring_cap = 0;    // power of two
+  DevBuf slots, has_next, dense[2], list[2], item_val, small_list, chunk_list, counters;
+  DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq;
+  DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp;
-  uint64_t* h_counters = nullptr;  // pinned mirror
+  uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
+  uint64_t steps = 0;         // level steps launched (parity of the lists)
+  // host bookkeeping
+  std::vector<int> free_recs;
+  std::vector<QueryDev> h_rec;
+  std::vector<GraphVersion*> rec_version;
+  std::vector<std::pair<uint64_t, uint64_t>> tree_free;  // [start, len) free regions
+  std::vector<std::pair<uint64_t, uint64_t>> rec_tree;   // region of each record
+  uint64_t ring_outstanding = 0;  // probe bound of admitted, unfinished queries
+  std::vector<uint64_t> rec_ring;
 };
 
 struct ps_ctx {
@@ -169,7 +200,7 @@ struct ps_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool timing = false;
-  Engine eng;
+  Session* sess = nullptr;
   ps_stats last{};
   std::vector<hipEvent_t> ev_pool;
   std::mutex mu;
@@ -178,18 +209,34 @@ struct ps_ctx {
 // Drops one reference; the context is freed with the last one.
 void ctx_release(ps_ctx* c);
 
-// Runs a set of queries on one graph version (all on the device) and writes
-// every result.  Shared by ps_single_source, ps_topk, ps_batch and the
-// server's synchronous fallback.
-struct QueryOut {
-  double* scores = nullptr;  // n (single-source) or k (top-k); host or device
-  int32_t* nodes = nullptr;  // k (top-k)
-};
-ps_status engine_run(ps_ctx* ctx, GraphVersion* gv, int32_t n, const std::vector<QueryRun>& qs,
+// Session lifecycle (engine.hip).  session_ensure (re)allocates when the
+// requested shape exceeds the current one; it must only be called while no
+// query is admitted.
+ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax, uint64_t tree_pool,
+                         uint64_t ring_cap);
+void session_free(Session* s);
+int session_slots_for(int32_t n, int opt);
+// Admits queries (records are assigned by the session); launches their walks
+// and tree construction.  rec[i] receives the record of query i.  Each query
+// reads graph version gv (one reference is taken per query).
+ps_status session_admit(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
+                        std::vector<int>* rec, std::vector<uint64_t>* bound);
+// Launches `count` level steps.
+ps_status session_steps(ps_ctx* ctx, uint64_t count);
+// Finalises record r (divide by n_r, s(u,u) = 1, top-k) and copies its result
+// to `out` on the context stream; then frees the record.
+ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, const QueryOut& out);
+// Tree regions and ring space of admitted queries; for admission control.
+bool session_can_admit(const Session* s, uint64_t bound_hint);
+
+// Runs a set of queries to completion on one graph version and writes every
+// result (ps_single_source, ps_topk, ps_batch).
+ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
                      const std::vector<QueryOut>& outs, int slots_opt);
 
 ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun& q, int64_t k_begin,
                        int64_t count, int32_t* nodes, int32_t* lens);
+
 
 ps_status derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt,
                         ps_params* out);

@@ -1,12 +1,35 @@
-// Serving loop: a host thread that drains a request ring, applies queued edge
-// updates between launches and runs the admitted queries together on the
-// device.
+// Serving loop with continuous batching.
+//
+// A host thread owns the context's session while the server runs.  Each
+// iteration it (1) applies queued edge updates (a new graph version; queries
+// already admitted keep reading theirs), (2) admits waiting queries while
+// query records, tree space and ring space allow -- their walks and trees are
+// built and their probes join the ring behind the probes already pending, so
+// they share the next level steps with the queries already running, (3)
+// launches a few level steps, and (4) collects the queries whose last probe
+// retired (read from the device's done ring one iteration late, so the GPU is
+// never left without queued steps), finalises them and hands their results
+// through pinned staging buffers to a completer thread that copies them to
+// the caller's buffers and wakes ps_wait.
 
 #include <chrono>
+#include <cstring>
 
 #include "ps_internal.h"
 
+// Engine entry points used here (engine.hip).
+ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
+                        std::vector<int>* recs, std::vector<uint64_t>* bounds);
+ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds);
+ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms);
+void session_abandon(ps_ctx* ctx, ps_graph* g, int r);
+ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
+                         const ps_options* opt, QueryRun* q);
+
 namespace {
+
+constexpr int kStepsPerIteration = 4;
+constexpr double kUpdateIntervalMs = 10.0;
 
 struct Request {
   ps_query q;
@@ -19,63 +42,363 @@ struct UpdateBatch {
   std::vector<uint8_t> op;
 };
 
+struct Staging {
+  void* host = nullptr;  // pinned
+  size_t bytes = 0;
+};
+
+struct Completion {
+  hipEvent_t ev;
+  int staging;
+  ps_result* r;
+  int32_t k;      // 0: n scores
+  int32_t count;
+  uint64_t ticket;
+  ps_status status;
+};
+
 }  // namespace
 
 struct ps_server {
   ps_graph* g = nullptr;
   ps_server_cfg cfg{};
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_comp;
   std::deque<Request> ring;
   std::deque<UpdateBatch> updates;
   std::unordered_map<uint64_t, ps_status> finished;
   uint64_t next_ticket = 1;
   bool stopping = false;
-  std::thread th;
+  bool comp_stop = false;
+  std::thread th, comp_th;
+  // completer hand-off
+  std::deque<Completion> comp_q;
+  std::vector<Staging> staging;
+  std::vector<int> staging_free;
+  std::vector<hipEvent_t> ev_free;
+  ps_status fatal = PS_OK;
 };
 
 namespace {
 
-void serve(ps_server* s) {
-  ps_ctx* ctx = s->g->ctx;
-  (void)hipSetDevice(ctx->device);
+struct Admitted {
+  Request req;
+  QueryRun run;
+  uint64_t bound = 0;  // sum over its walks of (len - 1)
+  bool built = false;  // tree built, probes queued
+};
+
+void finish_ticket(ps_server* s, uint64_t ticket, ps_status st) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->finished[ticket] = st;
+  s->cv_done.notify_all();
+}
+
+void completer(ps_server* s) {
   for (;;) {
-    std::vector<Request> batch;
-    std::vector<UpdateBatch> ups;
+    Completion c;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stopping || !s->ring.empty() || !s->updates.empty(); });
-      if (s->ring.empty() && s->updates.empty() && s->stopping) return;
-      while (!s->updates.empty()) {
-        ups.push_back(std::move(s->updates.front()));
-        s->updates.pop_front();
+      s->cv_comp.wait(lk, [&] { return s->comp_stop || !s->comp_q.empty(); });
+      if (s->comp_q.empty()) return;
+      c = s->comp_q.front();
+      s->comp_q.pop_front();
+    }
+    ps_status st = c.status;
+    if (hipEventSynchronize(c.ev) != hipSuccess) st = PS_ERR_DEVICE;
+    if (st == PS_OK && c.staging >= 0) {
+      const Staging& sg = s->staging[(size_t)c.staging];
+      if (c.k > 0) {
+        std::memcpy(c.r->scores, sg.host, sizeof(double) * (size_t)c.k);
+        std::memcpy(c.r->nodes, (const char*)sg.host + sizeof(double) * (size_t)c.k, sizeof(int32_t) * (size_t)c.k);
+      } else {
+        std::memcpy(c.r->scores, sg.host, sizeof(double) * (size_t)c.count);
       }
-      while (!s->ring.empty() && (int)batch.size() < s->cfg.max_inflight) {
-        batch.push_back(s->ring.front());
+    }
+    c.r->status = st;
+    c.r->count = st == PS_OK ? c.count : 0;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (c.staging >= 0) s->staging_free.push_back(c.staging);
+    s->ev_free.push_back(c.ev);
+    s->finished[c.ticket] = st;
+    s->cv_done.notify_all();
+  }
+}
+
+// Takes a free pinned staging buffer (allocating up to a small pool, else
+// waiting for the completer to return one).
+int take_staging(ps_server* s, size_t bytes) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    for (size_t i = 0; i < s->staging_free.size(); ++i) {
+      const int id = s->staging_free[i];
+      if (s->staging[(size_t)id].bytes >= bytes) {
+        s->staging_free.erase(s->staging_free.begin() + (long)i);
+        return id;
+      }
+    }
+    if (s->staging.size() < 16) {
+      Staging sg;
+      if (hipHostMalloc(&sg.host, bytes, 0) != hipSuccess) return -1;
+      sg.bytes = bytes;
+      s->staging.push_back(sg);
+      return (int)s->staging.size() - 1;
+    }
+    if (!s->staging_free.empty()) {
+      // grow the smallest free buffer
+      const int id = s->staging_free.back();
+      s->staging_free.pop_back();
+      Staging& sg = s->staging[(size_t)id];
+      (void)hipHostFree(sg.host);
+      sg.host = nullptr;
+      sg.bytes = 0;
+      if (hipHostMalloc(&sg.host, bytes, 0) != hipSuccess) return -1;
+      sg.bytes = bytes;
+      return id;
+    }
+    s->cv_done.wait(lk);
+  }
+}
+
+hipEvent_t take_event(ps_server* s) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->ev_free.empty()) {
+    hipEvent_t e = s->ev_free.back();
+    s->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  return e;
+}
+
+// Finalises record r on the device and queues its copy-out.
+ps_status complete_record(ps_server* s, int r, Admitted& a) {
+  ps_ctx* ctx = s->g->ctx;
+  Session* ss = ctx->sess;
+  const int32_t n = ss->n;
+  const int32_t k = a.run.k;
+  const size_t bytes = k > 0 ? (sizeof(double) + sizeof(int32_t)) * (size_t)k : sizeof(double) * (size_t)n;
+  const int sid = take_staging(s, bytes);
+  if (sid < 0) return PS_ERR_OOM;
+  QueryOut out;
+  char* host = (char*)s->staging[(size_t)sid].host;
+  out.scores = (double*)host;
+  out.nodes = k > 0 ? (int32_t*)(host + sizeof(double) * (size_t)k) : nullptr;
+  PS_TRY(session_finish(ctx, s->g, r, a.run, out));
+  Completion c;
+  c.ev = take_event(s);
+  PS_HIP(hipEventRecord(c.ev, ctx->stream));
+  c.staging = sid;
+  c.r = a.req.r;
+  c.k = k;
+  c.count = k > 0 ? k : n;
+  c.ticket = a.req.ticket;
+  c.status = PS_OK;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->comp_q.push_back(c);
+  s->cv_comp.notify_one();
+  return PS_OK;
+}
+
+ps_status serve_loop(ps_server* s) {
+  ps_graph* g = s->g;
+  ps_ctx* ctx = g->ctx;
+  PS_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  std::unordered_map<int, Admitted> admitted;  // record -> query
+  std::deque<int> waiting_build;               // records begun, trees not yet built
+  Session* ss = ctx->sess;
+  // done-ring snapshots, two in flight
+  unsigned long long done_seen = 0;
+  unsigned long long* snap[2] = {nullptr, nullptr};
+  int32_t* snap_ring[2] = {nullptr, nullptr};
+  hipEvent_t snap_ev[2];
+  bool snap_live[2] = {false, false};
+  for (int i = 0; i < 2; ++i) {
+    PS_HIP(hipHostMalloc((void**)&snap[i], sizeof(unsigned long long) * C_COUNT, 0));
+    PS_HIP(hipHostMalloc((void**)&snap_ring[i], sizeof(int32_t) * (size_t)ss->qmax, 0));
+    PS_HIP(hipEventCreateWithFlags(&snap_ev[i], hipEventDisableTiming));
+  }
+  int snap_i = 0;
+  // completions of earlier direct calls on this session are not ours
+  PS_HIP(hipMemcpyAsync(snap[0], ss->counters.p, sizeof(unsigned long long) * C_COUNT, hipMemcpyDeviceToHost, st));
+  PS_HIP(hipStreamSynchronize(st));
+  done_seen = snap[0][C_DONE];
+  auto last_update = std::chrono::steady_clock::now();
+  ps_status fatal = PS_OK;
+  for (;;) {
+    std::vector<Request> fresh;
+    std::vector<UpdateBatch> ups;
+    bool stopping;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      auto idle = [&] { return admitted.empty() && waiting_build.empty(); };
+      if (idle() && s->ring.empty() && s->updates.empty())
+        s->cv_work.wait(lk, [&] { return s->stopping || !s->ring.empty() || !s->updates.empty(); });
+      stopping = s->stopping;
+      const double since = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - last_update).count();
+      if (since >= kUpdateIntervalMs || idle()) {
+        while (!s->updates.empty()) {
+          ups.push_back(std::move(s->updates.front()));
+          s->updates.pop_front();
+        }
+      }
+      const int room = s->cfg.max_inflight - (int)admitted.size() - (int)waiting_build.size();
+      while (!s->ring.empty() && (int)fresh.size() < room && (int)fresh.size() < (int)ss->free_recs.size()) {
+        fresh.push_back(s->ring.front());
         s->ring.pop_front();
       }
+      if (stopping && s->ring.empty() && s->updates.empty() && idle() && fresh.empty()) break;
     }
-    for (auto& u : ups) {
-      std::lock_guard<std::mutex> lk(ctx->mu);
-      (void)graph_apply_updates(s->g, (int64_t)u.src.size(), u.src.data(), u.dst.data(), u.op.data(), nullptr, nullptr);
+    // (1) edge updates between level steps
+    if (!ups.empty()) {
+      for (auto& u : ups)
+        (void)graph_apply_updates(g, (int64_t)u.src.size(), u.src.data(), u.dst.data(), u.op.data(), nullptr, nullptr);
+      last_update = std::chrono::steady_clock::now();
     }
-    if (batch.empty()) continue;
-    ps_options opt;
-    ps_options_default(&opt);
-    opt.slots = s->cfg.slots;
-    std::vector<ps_query> qv;
-    std::vector<ps_result> rv;
-    for (auto& rq : batch) {
-      qv.push_back(rq.q);
-      rv.push_back(*rq.r);
+    // (2) admission
+    if (!fresh.empty()) {
+      std::vector<QueryRun> runs;
+      std::vector<Request> ok;
+      for (auto& rq : fresh) {
+        QueryRun qr;
+        ps_options opt;
+        ps_options_default(&opt);
+        ps_status vs = make_query_run(g, rq.q.u, rq.q.k, rq.q.c, rq.q.eps, rq.q.delta, rq.q.seed, &opt, &qr);
+        if (vs == PS_OK && (!rq.r->scores || (rq.q.k > 0 && !rq.r->nodes))) vs = PS_ERR_INVALID_ARG;
+        if (vs != PS_OK) {
+          rq.r->status = vs;
+          rq.r->count = 0;
+          finish_ticket(s, rq.ticket, vs);
+          continue;
+        }
+        runs.push_back(qr);
+        ok.push_back(rq);
+      }
+      if (!runs.empty()) {
+        GraphVersion* gv = graph_acquire(g);
+        std::vector<int> recs;
+        std::vector<uint64_t> bounds;
+        ps_status bs = session_begin(ctx, g, gv, runs, &recs, &bounds);
+        graph_release(g, gv);
+        if (bs != PS_OK) {
+          for (auto& rq : ok) {
+            rq.r->status = bs;
+            finish_ticket(s, rq.ticket, bs);
+          }
+        } else {
+          for (size_t i = 0; i < recs.size(); ++i) {
+            Admitted a;
+            a.req = ok[i];
+            a.run = runs[i];
+            a.bound = bounds[i];
+            admitted[recs[i]] = a;
+            waiting_build.push_back(recs[i]);
+          }
+        }
+      }
     }
-    (void)ps_batch(s->g, (int32_t)qv.size(), qv.data(), &opt, rv.data());
+    // build trees in arrival order while tree/ring space allows
+    while (!waiting_build.empty()) {
+      const int r = waiting_build.front();
+      Admitted& a = admitted[r];
+      ps_status bs = session_build(ctx, {r}, {a.bound});
+      if (bs == PS_ERR_BUSY) {
+        bool any_built = false;
+        for (auto& kv : admitted) any_built |= kv.second.built;
+        if (any_built) break;  // space frees up as running queries finish
+        bs = PS_ERR_OOM;       // the tree does not fit even in an empty session
+        waiting_build.pop_front();
+        session_abandon(ctx, g, r);
+        a.req.r->status = bs;
+        a.req.r->count = 0;
+        finish_ticket(s, a.req.ticket, bs);
+        admitted.erase(r);
+        continue;
+      }
+      waiting_build.pop_front();
+      if (bs != PS_OK) {
+        fatal = bs;
+        break;
+      }
+      a.built = true;
+      if (a.bound == 0) {  // no probe: the estimate is e_u
+        ps_status cs = complete_record(s, r, a);
+        if (cs != PS_OK) fatal = cs;
+        admitted.erase(r);
+      }
+    }
+    if (fatal != PS_OK) break;
+    // (3) level steps for everything admitted
+    bool have_probes = false;
+    for (auto& kv : admitted)
+      if (kv.second.built) have_probes = true;
+    if (have_probes) {
+      ps_status ss_ = session_steps(ctx, kStepsPerIteration, nullptr);
+      if (ss_ != PS_OK) {
+        fatal = ss_;
+        break;
+      }
+      PS_HIP(hipMemcpyAsync(snap[snap_i], ss->counters.p, sizeof(unsigned long long) * C_COUNT, hipMemcpyDeviceToHost,
+                            st));
+      PS_HIP(hipMemcpyAsync(snap_ring[snap_i], ss->done_ring.p, sizeof(int32_t) * (size_t)ss->qmax,
+                            hipMemcpyDeviceToHost, st));
+      PS_HIP(hipEventRecord(snap_ev[snap_i], st));
+      snap_live[snap_i] = true;
+    }
+    // (4) completions seen by the previous iteration's snapshot (or this one
+    // when nothing else is queued)
+    const int prev = snap_i ^ 1;
+    int look = prev;
+    if (!snap_live[prev] && snap_live[snap_i]) look = snap_i;
+    if (snap_live[look]) {
+      PS_HIP(hipEventSynchronize(snap_ev[look]));
+      snap_live[look] = false;
+      const unsigned long long done = snap[look][C_DONE];
+      for (; done_seen < done; ++done_seen) {
+        const int r = snap_ring[look][done_seen % (unsigned long long)ss->qmax];
+        auto it = admitted.find(r);
+        if (it == admitted.end()) continue;
+        ps_status cs = complete_record(s, r, it->second);
+        if (cs != PS_OK) fatal = cs;
+        admitted.erase(it);
+      }
+    }
+    if (fatal != PS_OK) break;
+    snap_i ^= 1;
+  }
+  (void)hipStreamSynchronize(st);
+  for (int i = 0; i < 2; ++i) {
+    (void)hipHostFree(snap[i]);
+    (void)hipHostFree(snap_ring[i]);
+    (void)hipEventDestroy(snap_ev[i]);
+  }
+  if (fatal != PS_OK) {
+    // fail everything still queued or running
+    for (auto& kv : admitted) {
+      kv.second.req.r->status = fatal;
+      finish_ticket(s, kv.second.req.ticket, fatal);
+    }
     std::lock_guard<std::mutex> lk(s->mu);
-    for (size_t i = 0; i < batch.size(); ++i) {
-      *batch[i].r = rv[i];
-      s->finished[batch[i].ticket] = (ps_status)rv[i].status;
+    for (auto& rq : s->ring) {
+      rq.r->status = fatal;
+      s->finished[rq.ticket] = fatal;
     }
+    s->ring.clear();
     s->cv_done.notify_all();
+  }
+  return fatal;
+}
+
+void serve(ps_server* s) {
+  ps_ctx* ctx = s->g->ctx;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  s->fatal = serve_loop(s);
+  {
+    std::lock_guard<std::mutex> lk2(s->mu);
+    s->comp_stop = true;
+    s->cv_comp.notify_all();
   }
 }
 
@@ -83,11 +406,30 @@ void serve(ps_server* s) {
 
 extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_server** out) {
   if (!g || !out) return PS_ERR_INVALID_ARG;
+  *out = nullptr;
+  ps_ctx* ctx = g->ctx;
   auto* s = new ps_server();
   s->g = g;
   if (cfg) s->cfg = *cfg;
   if (s->cfg.ring <= 0) s->cfg.ring = 1024;
   if (s->cfg.max_inflight <= 0) s->cfg.max_inflight = 64;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ps_status st = PS_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) st = PS_ERR_DEVICE;
+    const int P = session_slots_for(g->n, s->cfg.slots);
+    // tree pool / ring sized for max_inflight queries of up to ~1M tree nodes
+    const uint64_t per_q = 1ull << 21;
+    const uint64_t pool = std::max<uint64_t>((uint64_t)s->cfg.max_inflight * per_q, 1ull << 22);
+    if (st == PS_OK)
+      st = session_ensure(ctx, g->n, std::max<uint64_t>(g->cur->out_store->cap, 1), P, s->cfg.max_inflight, pool,
+                          pool / 2);
+    if (st != PS_OK) {
+      delete s;
+      return st;
+    }
+  }
+  s->comp_th = std::thread(completer, s);
   s->th = std::thread(serve, s);
   *out = s;
   return PS_OK;
@@ -140,6 +482,11 @@ extern "C" ps_status ps_server_stop(ps_server* s) {
     s->cv_work.notify_all();
   }
   if (s->th.joinable()) s->th.join();
+  if (s->comp_th.joinable()) s->comp_th.join();
+  for (auto& sg : s->staging)
+    if (sg.host) (void)hipHostFree(sg.host);
+  for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
+  const ps_status st = s->fatal;
   delete s;
-  return PS_OK;
+  return st;
 }
