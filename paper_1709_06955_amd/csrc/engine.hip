@@ -679,6 +679,7 @@ void session_free(Session* s) {
                     &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp};
   for (DevBuf* b : bufs) devbuf_free(*b);
   if (s->h_ctr) (void)hipHostFree(s->h_ctr);
+  if (s->step_pair) (void)hipGraphExecDestroy(s->step_pair);
   delete s;
 }
 
@@ -706,6 +707,10 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
     return PS_OK;
   if (s && (int)s->free_recs.size() != s->qmax) return PS_ERR_STATE;  // queries admitted
   if (!s) s = new Session();
+  if (s->step_pair) {  // captured with the old buffers
+    (void)hipGraphExecDestroy(s->step_pair);
+    s->step_pair = nullptr;
+  }
   const bool shape = s->n != n || s->P != P;
   s->n = n;
   s->P = P;
@@ -908,11 +913,17 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
   return PS_OK;
 }
 
-ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
-  Session* s = ctx->sess;
-  hipStream_t st = ctx->stream;
+namespace {
+
+struct StepKernels {
+  SchedArgs sa;
+  ExpandArgs ea;
+};
+
+StepKernels step_args(Session* s) {
+  StepKernels k{};
   unsigned long long* ctr = s->counters.as<unsigned long long>();
-  SchedArgs sa{};
+  SchedArgs& sa = k.sa;
   sa.P = s->P;
   sa.n = s->n;
   sa.qmax = s->qmax;
@@ -931,7 +942,7 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
   sa.done_ring = s->done_ring.as<int32_t>();
   sa.list_cap = s->list_cap;
   sa.ctr = ctr;
-  ExpandArgs ea{};
+  ExpandArgs& ea = k.ea;
   ea.n = s->n;
   ea.item_val = s->item_val.as<float>();
   ea.small_list = s->small_list.as<int32_t>();
@@ -941,6 +952,37 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
   ea.chunk_cap = s->chunk_cap;
   ea.has_next = s->has_next.as<int32_t>();
   ea.ctr = ctr;
+  return k;
+}
+
+// One level step with the frontier lists of parity `cur`.
+void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const int nxt = cur ^ 1;
+  k.sa.dense_cur = s->dense[cur].as<float>();
+  k.sa.list_cur = s->list[cur].as<int2>();
+  k.sa.cur = cur;
+  k_sched<<<1, kSchedThreads, 0, st>>>(k.sa);
+  k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
+                                       s->item_val.as<float>(), s->small_list.as<int32_t>(), s->chunk_list.as<int2>(),
+                                       s->list_cap, s->chunk_cap, s->counters.as<unsigned long long>(), cur);
+  k.ea.list_cur = s->list[cur].as<int2>();
+  k.ea.dense_next = s->dense[nxt].as<float>();
+  k.ea.list_next = s->list[nxt].as<int2>();
+  k.ea.nxt = nxt;
+  if (ev0) (void)hipEventRecord(ev0, st);
+  k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
+  if (ev1) (void)hipEventRecord(ev1, st);
+}
+
+}  // namespace
+
+// Launches `count` level steps.  Without timing they run as replays of a
+// captured pair of steps (even then odd list parity), one graph launch per
+// pair; with timing every expansion is bracketed by events.
+ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
+  Session* s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  StepKernels k = step_args(s);
   const bool timing = ctx->timing && expand_ms;
   if (timing) {
     while (ctx->ev_pool.size() < 2 * count) {
@@ -948,27 +990,11 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
       PS_HIP(hipEventCreate(&ev));
       ctx->ev_pool.push_back(ev);
     }
-  }
-  for (uint64_t t = 0; t < count; ++t) {
-    const int cur = (int)(s->steps & 1), nxt = cur ^ 1;
-    sa.dense_cur = s->dense[cur].as<float>();
-    sa.list_cur = s->list[cur].as<int2>();
-    sa.cur = cur;
-    k_sched<<<1, kSchedThreads, 0, st>>>(sa);
-    k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
-                                         s->item_val.as<float>(), s->small_list.as<int32_t>(),
-                                         s->chunk_list.as<int2>(), s->list_cap, s->chunk_cap, ctr, cur);
-    ea.list_cur = s->list[cur].as<int2>();
-    ea.dense_next = s->dense[nxt].as<float>();
-    ea.list_next = s->list[nxt].as<int2>();
-    ea.nxt = nxt;
-    if (timing) PS_HIP(hipEventRecord(ctx->ev_pool[2 * t], st));
-    k_expand<<<kStepGrid, kBlock, 0, st>>>(ea);
-    if (timing) PS_HIP(hipEventRecord(ctx->ev_pool[2 * t + 1], st));
-    s->steps++;
-  }
-  PS_HIP(hipGetLastError());
-  if (timing) {
+    for (uint64_t t = 0; t < count; ++t) {
+      launch_step(s, k, (int)(s->steps & 1), st, ctx->ev_pool[2 * t], ctx->ev_pool[2 * t + 1]);
+      s->steps++;
+    }
+    PS_HIP(hipGetLastError());
     PS_HIP(hipStreamSynchronize(st));
     double ms = 0.0;
     for (uint64_t t = 0; t < count; ++t) {
@@ -977,7 +1003,34 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
       ms += x;
     }
     *expand_ms += ms;
+    return PS_OK;
   }
+  if (count >= 4) {
+    if (s->steps & 1) {
+      launch_step(s, k, 1, st, nullptr, nullptr);
+      s->steps++;
+      count--;
+    }
+    if (!s->step_pair) {
+      hipGraph_t graph = nullptr;
+      PS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      launch_step(s, k, 0, st, nullptr, nullptr);
+      launch_step(s, k, 1, st, nullptr, nullptr);
+      PS_HIP(hipStreamEndCapture(st, &graph));
+      const hipError_t e = hipGraphInstantiate(&s->step_pair, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      PS_HIP(e);
+    }
+    for (; count >= 2; count -= 2) {
+      PS_HIP(hipGraphLaunch(s->step_pair, st));
+      s->steps += 2;
+    }
+  }
+  for (; count > 0; --count) {
+    launch_step(s, k, (int)(s->steps & 1), st, nullptr, nullptr);
+    s->steps++;
+  }
+  PS_HIP(hipGetLastError());
   return PS_OK;
 }
 

@@ -184,6 +184,7 @@ struct Session {
   DevBuf sort_keys[2], sort_vals[2], sort_tmp;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)
+  hipGraphExec_t step_pair = nullptr;  // captured even + odd level step
   // host bookkeeping
   std::vector<int> free_recs;
   std::vector<QueryDev> h_rec;
