@@ -66,6 +66,58 @@ def cpu_baseline(n, s, d, q, seconds_target=15.0):
                       f"{spent:.1f} s, scaled by n_r / {walks}"}
 
 
+def served(ps, G, q, n, seconds=8.0, rate_frac=0.5, seed=7):
+    """Continuous-batching server on the same graph and queries: closed-loop
+    saturation throughput X_sat (all queries submitted at once), then
+    open-loop Poisson arrivals at rate_frac * X_sat; latency is submit to
+    result on the host."""
+    import threading
+
+    import numpy as np
+
+    srv = ps.Server(G, max_inflight=32)
+    try:
+        t0 = time.perf_counter()
+        ts = [srv.submit(int(u), C, EPS, DELTA, 1000 + i) for i, u in enumerate(q)]
+        for t in ts:
+            srv.wait(t)
+        x_sat = len(q) / (time.perf_counter() - t0)
+        rate = rate_frac * x_sat
+        rng = np.random.default_rng(seed)
+        count = max(16, int(rate * seconds))
+        gaps = rng.exponential(1.0 / rate, size=count)
+        lat = [None] * count
+        lock = threading.Lock()
+        pending = []
+
+        def waiter(i, ticket, t_sub):
+            srv.wait(ticket)
+            with lock:
+                lat[i] = time.perf_counter() - t_sub
+
+        start = time.perf_counter()
+        due = start
+        for i in range(count):
+            due += gaps[i]
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            u = int(q[i % len(q)])
+            t_sub = time.perf_counter()
+            tk = srv.submit(u, C, EPS, DELTA, 2000 + i)
+            th = threading.Thread(target=waiter, args=(i, tk, t_sub))
+            th.start()
+            pending.append(th)
+        for th in pending:
+            th.join()
+        wall = time.perf_counter() - start
+        l = np.array(lat) * 1e3
+        return {"x_sat_qps": x_sat, "offered_qps": rate, "served_qps": count / wall, "queries": count,
+                "p50_ms": float(np.percentile(l, 50)), "p99_ms": float(np.percentile(l, 99))}
+    finally:
+        srv.stop()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--no-served", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -152,6 +205,8 @@ def main():
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches},
         "work_per_query": {k: acc[k] / queries for k in keys if k not in ("expand_ms",)},
     }
+    if not args.no_served:
+        result["served"] = served(ps, G, q, n)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, s, d, q)
     print(json.dumps(result), flush=True)

@@ -1141,7 +1141,13 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   }
   if (pool_need > s->tree_pool || ring_need > s->ring_cap) {
     // Grow the tree pool / ring: only this call's records are admitted and
-    // their trees are not built yet, so the buffers can be replaced.
+    // their trees are not built yet, so the buffers can be replaced.  The
+    // captured level steps point at the old buffers and are dropped.
+    if (s->step_pair) {
+      PS_HIP(hipStreamSynchronize(st));
+      (void)hipGraphExecDestroy(s->step_pair);
+      s->step_pair = nullptr;
+    }
     s->tree_pool = std::max(pool_need, s->tree_pool);
     s->ring_cap = next_pow2(std::max(ring_need, s->ring_cap));
     PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
