@@ -126,6 +126,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -139,44 +140,50 @@ def main():
     from synth import graphs
 
     n, s, d = graphs.make_workload(WORKLOAD)
-    q = graphs.query_nodes(n, d, NQ)
+    q = graphs.query_nodes(n, d, NQ)[: args.nq]
+    print(f"graph ready: n={n} m={s.size}", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     ctx = ps.Context(0, stream=stream)
     G = ps.Graph(ctx, n, s, d)
     out = torch.empty(n, dtype=torch.float64, device="cuda:0")
     ctx.set_timing(True)
 
-    def plain_step(acc):
+    def plain_step(acc, tag):
         for i, u in enumerate(q):
             ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots)
+            st = ctx.stats()
+            print(f"[{tag}] query {i} u={int(u)}: {st['total_ms']:.1f} ms, expand {st['expand_ms']:.1f} ms in "
+                  f"{st['expand_launches']} steps, tree nodes {st['tree_nodes']}, edges {st['edges_scanned']}, "
+                  f"entries {st['entries_expanded']}, next {st['next_entries']}, final {st['final_adds']}",
+                  file=sys.stderr, flush=True)
             if acc is not None:
-                st = ctx.stats()
                 for k in acc:
                     acc[k] += st[k]
 
     for _ in range(args.warmup):
-        plain_step(None)
+        plain_step(None, "warmup")
     keys = ["expand_ms", "expand_launches", "entries_expanded", "edges_scanned", "next_entries", "final_adds",
             "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned"]
     acc = {k: 0 for k in keys}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plain_step(acc)
+        plain_step(acc, "timed")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    queries = NQ * args.steps
+    queries = len(q) * args.steps
     qps = queries / dt
 
     # Batched: the same 32 queries in one launch.
-    outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in range(NQ)]
+    outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in range(len(q))]
     qlist = [dict(u=int(u), k=0, c=C, eps=EPS, delta=DELTA, seed=3 + i) for i, u in enumerate(q)]
     ps.ps_batch(G, qlist, outs=outs, slots=args.slots)
     torch.cuda.synchronize()
     tb = time.perf_counter()
     ps.ps_batch(G, qlist, outs=outs, slots=args.slots)
     torch.cuda.synchronize()
-    batched_qps = NQ / (time.perf_counter() - tb)
+    batched_qps = len(q) / (time.perf_counter() - tb)
+    print(f"batched: {batched_qps:.2f} queries/s", file=sys.stderr, flush=True)
 
     alg_bytes = expand_bytes(acc)
     launches = max(acc["expand_launches"], 1)
@@ -197,7 +204,7 @@ def main():
         "data": "synthetic (seeded Chung-Lu power-law graph; the paper's SNAP/LAW graphs are not available)",
         "config": {"workload": "Chung-Lu directed power-law graph, 1M nodes, 10M edges, exponent 2.1; "
                                "32 uniform query nodes with in-edges run one at a time; c=0.6, eps=0.05, "
-                               "delta=0.01", "queries_per_step": NQ},
+                               "delta=0.01", "queries_per_step": len(q)},
         "batched_qps": batched_qps,
         "batched_speedup": batched_qps / qps,
         "roofline": {"bound": "hbm", "kernel": "k_expand", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -17,9 +17,10 @@
 //                iteration, retires finished probes (a query is complete when
 //                its last probe retires) and hands free slots the next
 //                pending probes; k_prep reads and clears the scores of the
-//                listed frontier entries, applies Rule 2 and bins the
-//                surviving rows by out-degree; k_expand pushes scores along
-//                out-edges.  Each slot owns a dense FP32 score vector per
+//                listed frontier entries, applies Rule 2 and records the
+//                surviving rows; k_expand pushes scores along out-edges,
+//                load-balanced per edge over tiles of entries (long rows in
+//                fixed-size chunks).  Each slot owns a dense FP32 score vector per
 //                level parity; the atomic add that turns an entry nonzero
 //                appends (slot, node) to the next frontier list, so frontiers
 //                stay sparse lists while the sums stay exact.  A probe's last
@@ -41,8 +42,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kSchedThreads = 1024;
 constexpr int kSlotsPerSchedThread = 4;  // P <= 4096
-constexpr uint32_t kSmallDeg = 32;       // rows up to this length: one lane per row
-constexpr uint32_t kChunk = 512;         // longer rows: one wavefront per 512 edges
+constexpr uint32_t kBigDeg = 1024;       // longer rows: one wavefront per kChunk edges
+constexpr uint32_t kChunk = 512;
+constexpr uint32_t kBigFlag = 0x80000000u;
+constexpr int kTile = 1024;              // listed entries per workgroup tile in k_expand
+constexpr int kWaveBuf = 512;            // staged new frontier entries per wavefront
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kStepGrid = 2048;          // 8 workgroups per CU for the step kernels
 
@@ -420,13 +424,15 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
   if (tid == 0) a.ctr[C_HEAD] = head + (total < avail ? total : avail);
 }
 
-// Reads and clears the scores of the listed entries, applies Rule 2 (remove x
-// when Score(x) * sqrt(c)^(i-j-1) <= eps_p, i.e. Score(x) <= thr) and bins
-// the surviving rows: short rows go to the lane-per-row list, long rows are
-// cut into 512-edge chunks for the wavefront-per-chunk list.
+// Reads and clears the scores of the listed entries and applies Rule 2
+// (remove x when Score(x) * sqrt(c)^(i-j-1) <= eps_p, i.e. Score(x) <= thr).
+// For every surviving entry it records its out-row and sqrt(c) * Score(x);
+// rows longer than kBigDeg are also cut into kChunk-edge chunks for the
+// wavefront-per-chunk part of k_expand (marked with the top bit of the
+// length so that the tile part skips them).  Removed entries get length 0.
 __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restrict__ slots,
                                                  const int2* __restrict__ list_cur, float* __restrict__ dense_cur,
-                                                 float* __restrict__ item_val, int32_t* __restrict__ small_list,
+                                                 float* __restrict__ item_val, uint2* __restrict__ item_row,
                                                  int2* __restrict__ chunk_list, uint64_t list_cap, uint64_t chunk_cap,
                                                  unsigned long long* __restrict__ ctr, int cur) {
   // after an overflow the counter runs past the list; never read beyond it
@@ -437,7 +443,6 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
   unsigned long long kept = 0, pruned = 0, edges = 0;
   for (uint64_t i0 = gtid - lane; i0 < cnt; i0 += stride) {
     const uint64_t i = i0 + lane;
-    bool small = false;
     uint32_t nch = 0;
     if (i < cnt) {
       const int2 it = list_cur[i];
@@ -445,21 +450,21 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       const float val = *d;
       *d = 0.0f;
       const Slot& sl = slots[it.x];
+      uint2 row = make_uint2(0u, 0u);
       if (val > sl.thr) {
         ++kept;
-        const uint32_t deg = sl.out_rows[it.y].y;
-        if (deg) {
-          item_val[i] = val * sl.sc;
-          edges += deg;
-          if (deg <= kSmallDeg) small = true;
-          else nch = (deg + kChunk - 1) / kChunk;
+        row = sl.out_rows[it.y];
+        edges += row.y;
+        item_val[i] = val * sl.sc;
+        if (row.y > kBigDeg) {
+          nch = (row.y + kChunk - 1) / kChunk;
+          row.y |= kBigFlag;
         }
       } else {
         ++pruned;
       }
+      item_row[i] = row;
     }
-    const unsigned long long sp = wave_reserve(small, &ctr[C_SMALL], nullptr);
-    if (small) small_list[sp] = (int32_t)i;
     const uint32_t incl = wave_incl_scan(nch);
     const uint32_t total = __shfl(incl, 63, 64);
     if (total) {
@@ -488,7 +493,7 @@ struct ExpandArgs {
   int32_t n;
   const int2* list_cur;
   const float* item_val;
-  const int32_t* small_list;
+  const uint2* item_row;
   const int2* chunk_list;
   const Slot* slots;
   float* dense_next;
@@ -497,82 +502,178 @@ struct ExpandArgs {
   uint64_t chunk_cap;
   int32_t* has_next;
   unsigned long long* ctr;
+  int cur;
   int nxt;
 };
 
-// One out-edge x -> v of a listed entry: add sqrt(c)/|I(v)| * Score(x) to
-// H_{j+1}[v] unless v is the excluded walk node u_{i-j-1} (Alg. 2).
-__device__ __forceinline__ void visit_edge(const ExpandArgs& a, bool active, int32_t s, int32_t v, float sv,
-                                           const Slot& sl, unsigned long long& nfinal, unsigned long long& nnext) {
-  bool append = false;
-  if (active && v != sl.excl) {
-    const float c = sv * sl.inv_indeg[v];
-    if (c >= 1.17549435e-38f) {  // contributions below FLT_MIN are dropped
-      if (sl.last) {
-        unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
-        ++nfinal;
-      } else {
-        const float old = unsafeAtomicAdd(&a.dense_next[(size_t)s * a.n + v], c);
-        append = old == 0.0f;
-      }
-    }
+// Per-wavefront staging of new frontier entries in LDS: one global atomic per
+// flush instead of one per append.  Every lane of the wavefront must call
+// these together (the callers' loops are wavefront-uniform).
+struct WaveBuf {
+  int2* buf;   // kWaveBuf entries of this wavefront
+  uint32_t n;  // entries staged (same value in every lane)
+};
+
+__device__ __forceinline__ void wave_flush(WaveBuf& wb, const ExpandArgs& a, unsigned long long& nnext) {
+  if (wb.n == 0) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int lane = lane_id();
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(&a.ctr[C_LIST0 + a.nxt], (unsigned long long)wb.n);
+  base = __shfl(base, 0, 64);
+  for (uint32_t k = (uint32_t)lane; k < wb.n; k += 64) {
+    const unsigned long long pos = base + k;
+    if (pos < a.list_cap) a.list_next[pos] = wb.buf[k];
+    else a.ctr[C_OVERFLOW] = 1;
   }
-  if (__ballot(append)) {
-    const unsigned long long pos = wave_reserve(append, &a.ctr[C_LIST0 + a.nxt], &nnext);
-    if (append) {
-      if (pos < a.list_cap) {
-        a.list_next[pos] = make_int2(s, v);
-        a.has_next[s] = 1;
-      } else {
-        a.ctr[C_OVERFLOW] = 1;
-      }
-    }
-  }
+  if (lane == 0) nnext += wb.n;
+  wb.n = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
-__global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
-  const int lane = lane_id();
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  unsigned long long nfinal = 0, nnext = 0;
-  // Short rows: one lane per listed entry.
-  const unsigned long long nsmall = min(a.ctr[C_SMALL], (unsigned long long)a.list_cap);
-  for (uint64_t j0 = wave * 64; j0 < nsmall; j0 += nwaves * 64) {
-    const uint64_t j = j0 + lane;
-    uint32_t deg = 0, start = 0;
-    int32_t s = 0;
-    float sv = 0.0f;
-    Slot sl{};
-    if (j < nsmall) {
-      const int32_t i = a.small_list[j];
-      const int2 it = a.list_cur[i];
-      s = it.x;
-      sl = a.slots[s];
-      sv = a.item_val[i];
-      const uint2 row = sl.out_rows[it.y];
-      start = row.x;
-      deg = row.y;
-    }
-    for (uint32_t t = 0; t < deg; ++t) visit_edge(a, true, s, sl.out_col[start + t], sv, sl, nfinal, nnext);
+__device__ __forceinline__ void wave_append(WaveBuf& wb, bool flag, int32_t s, int32_t v, const ExpandArgs& a,
+                                            unsigned long long& nnext) {
+  const unsigned long long mask = __ballot(flag);
+  if (!mask) return;
+  const uint32_t cnt = (uint32_t)__popcll(mask);
+  if (wb.n + cnt > (uint32_t)kWaveBuf) wave_flush(wb, a, nnext);
+  const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
+  if (flag) wb.buf[wb.n + rank] = make_int2(s, v);
+  wb.n += cnt;
+}
+
+// One out-edge x -> v of a listed entry of slot s: add sqrt(c)/|I(v)| *
+// Score(x) to H_{j+1}[v] unless v is the excluded walk node u_{i-j-1}
+// (Alg. 2).  Returns whether (s, v) became a new frontier entry.
+__device__ __forceinline__ bool visit_edge(const ExpandArgs& a, int32_t s, int32_t v, float sv, const Slot& sl,
+                                           unsigned long long& nfinal) {
+  if (v == sl.excl) return false;
+  const float c = sv * sl.inv_indeg[v];
+  if (!(c >= 1.17549435e-38f)) return false;  // contributions below FLT_MIN are dropped
+  if (sl.last) {
+    unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
+    ++nfinal;
+    return false;
   }
-  // Long rows: one wavefront per chunk of 512 consecutive out-edges.
+  const float old = unsafeAtomicAdd(&a.dense_next[(size_t)s * a.n + v], c);
+  return old == 0.0f;
+}
+
+// PROBE expansion.  Part 1: workgroups take tiles of kTile listed entries,
+// scan their out-degrees in LDS and walk the tile's edges 256 at a time, each
+// lane finding its entry by binary search, so the work per lane is one edge
+// whatever the degree mix.  Part 2: one wavefront per kChunk-edge chunk of the
+// long rows.
+__global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
+  __shared__ uint32_t s_pref[kTile + 1];
+  __shared__ int32_t s_slot[kTile];
+  __shared__ uint32_t s_start[kTile];
+  __shared__ float s_val[kTile];
+  __shared__ int32_t s_flag[kTile];
+  __shared__ uint32_t s_wtot[kBlock / 64];
+  __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid >> 6;
+  WaveBuf wb{s_buf[wv], 0u};
+  unsigned long long nfinal = 0, nnext = 0;
+
+  const unsigned long long cnt = min(a.ctr[C_LIST0 + a.cur], (unsigned long long)a.list_cap);
+  for (uint64_t tile0 = (uint64_t)blockIdx.x * kTile; tile0 < cnt; tile0 += (uint64_t)gridDim.x * kTile) {
+    constexpr int kPer = kTile / kBlock;
+    uint32_t deg[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int j = tid * kPer + r;
+      const uint64_t i = tile0 + j;
+      deg[r] = 0;
+      if (i < cnt) {
+        const uint2 row = a.item_row[i];
+        if (!(row.y & kBigFlag) && row.y) {
+          deg[r] = row.y;
+          s_start[j] = row.x;
+          s_val[j] = a.item_val[i];
+          s_slot[j] = a.list_cur[i].x;
+        }
+      }
+      s_flag[j] = 0;
+      sum += deg[r];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) s_wtot[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      if (w < wv) before += s_wtot[w];
+      total += s_wtot[w];
+    }
+    uint32_t run = before + incl - sum;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      s_pref[tid * kPer + r] = run;
+      run += deg[r];
+    }
+    if (tid == 0) s_pref[kTile] = total;
+    __syncthreads();
+    for (uint32_t e0 = 0; e0 < total; e0 += kBlock) {
+      const uint32_t e = e0 + (uint32_t)tid;
+      bool app = false;
+      int32_t s = 0, v = 0;
+      if (e < total) {
+        int lo = 0, hi = kTile - 1;  // last entry j with s_pref[j] <= e
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pref[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        s = s_slot[lo];
+        const Slot& sl = a.slots[s];
+        v = sl.out_col[s_start[lo] + (e - s_pref[lo])];
+        app = visit_edge(a, s, v, s_val[lo], sl, nfinal);
+        if (app) s_flag[lo] = 1;
+      }
+      wave_append(wb, app, s, v, a, nnext);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int j = tid * kPer + r;
+      if (s_flag[j]) a.has_next[s_slot[j]] = 1;
+    }
+    __syncthreads();
+  }
+
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const unsigned long long nchunk = min(a.ctr[C_CHUNK], (unsigned long long)a.chunk_cap);
   for (uint64_t c = wave; c < nchunk; c += nwaves) {
     const int2 ch = a.chunk_list[c];
-    const int2 it = a.list_cur[ch.x];
-    const int32_t s = it.x;
+    const int32_t s = a.list_cur[ch.x].x;
     const Slot sl = a.slots[s];
     const float sv = a.item_val[ch.x];
-    const uint2 row = sl.out_rows[it.y];
+    const uint2 row = a.item_row[ch.x];
+    const uint32_t len = row.y & ~kBigFlag;
     const uint32_t b = (uint32_t)ch.y * kChunk;
-    const uint32_t e = min(row.y, b + kChunk);
+    const uint32_t e = min(len, b + kChunk);
+    bool any = false;
     for (uint32_t t0 = b; t0 < e; t0 += 64) {
       const uint32_t t = t0 + lane;
-      const bool act = t < e;
-      const int32_t v = act ? sl.out_col[row.x + t] : -1;
-      visit_edge(a, act, s, v, sv, sl, nfinal, nnext);
+      bool app = false;
+      int32_t v = 0;
+      if (t < e) {
+        v = sl.out_col[row.x + t];
+        app = visit_edge(a, s, v, sv, sl, nfinal);
+      }
+      any |= app;
+      wave_append(wb, app, s, v, a, nnext);
     }
+    if (__ballot(any) && lane == 0) a.has_next[s] = 1;
   }
+  wave_flush(wb, a, nnext);
+
   nfinal = wave_sum(nfinal);
   nnext = wave_sum(nnext);
   if (lane == 0) {
@@ -673,7 +774,7 @@ void devbuf_free(DevBuf& b) {
 void session_free(Session* s) {
   if (!s) return;
   DevBuf* bufs[] = {&s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
-                    &s->item_val, &s->small_list, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
+                    &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->keys,
                     &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
                     &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp};
@@ -729,7 +830,7 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->list[0], sizeof(int2) * s->list_cap));
   PS_TRY(devbuf_reserve(s->list[1], sizeof(int2) * s->list_cap));
   PS_TRY(devbuf_reserve(s->item_val, sizeof(float) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->small_list, sizeof(int32_t) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->item_row, sizeof(uint2) * s->list_cap));
   PS_TRY(devbuf_reserve(s->chunk_list, sizeof(int2) * s->chunk_cap));
   PS_TRY(devbuf_reserve(s->counters, sizeof(unsigned long long) * C_COUNT));
   PS_TRY(devbuf_reserve(s->qrec, sizeof(QueryDev) * (size_t)s->qmax));
@@ -945,7 +1046,7 @@ StepKernels step_args(Session* s) {
   ExpandArgs& ea = k.ea;
   ea.n = s->n;
   ea.item_val = s->item_val.as<float>();
-  ea.small_list = s->small_list.as<int32_t>();
+  ea.item_row = s->item_row.as<uint2>();
   ea.chunk_list = s->chunk_list.as<int2>();
   ea.slots = s->slots.as<Slot>();
   ea.list_cap = s->list_cap;
@@ -963,9 +1064,10 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k.sa.cur = cur;
   k_sched<<<1, kSchedThreads, 0, st>>>(k.sa);
   k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
-                                       s->item_val.as<float>(), s->small_list.as<int32_t>(), s->chunk_list.as<int2>(),
+                                       s->item_val.as<float>(), s->item_row.as<uint2>(), s->chunk_list.as<int2>(),
                                        s->list_cap, s->chunk_cap, s->counters.as<unsigned long long>(), cur);
   k.ea.list_cur = s->list[cur].as<int2>();
+  k.ea.cur = cur;
   k.ea.dense_next = s->dense[nxt].as<float>();
   k.ea.list_next = s->list[nxt].as<int2>();
   k.ea.nxt = nxt;

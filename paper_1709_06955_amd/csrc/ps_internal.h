@@ -178,7 +178,7 @@ struct Session {
   uint64_t list_cap = 0, chunk_cap = 0;
   uint64_t tree_pool = 0;   // entries
   uint64_t ring_cap = 0;    // power of two
-  DevBuf slots, has_next, dense[2], list[2], item_val, small_list, chunk_list, counters;
+  DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters;
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp;
