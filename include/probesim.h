@@ -116,6 +116,10 @@ typedef struct ps_options {
                          (still divided by the full n_r), so shards add up. */
   int32_t slots;      /* concurrent probes on the device; 0: automatic */
   int32_t reserved;
+  int64_t pull_edges; /* a probe level whose kept entries have at least this many
+                         out-edges is computed by pulling along in-edges over
+                         all nodes instead of pushing along its out-edges (same
+                         sums, other order); 0: automatic, < 0: never */
 } ps_options;
 
 #define PS_MAX_WALK_LEN 64
@@ -203,8 +207,11 @@ typedef struct ps_stats {
   int64_t edges_scanned;    /* out-edges of expanded entries */
   int64_t next_entries;     /* distinct (probe, node) entries created in inner levels */
   int64_t final_adds;       /* contributions added into estimates */
-  int64_t expand_launches;  /* PROBE expansion kernel launches */
-  double expand_ms;         /* their summed duration (timing enabled) */
+  int64_t expand_launches;  /* PROBE expansion (push) kernel launches */
+  int64_t pull_levels;      /* probe levels computed by pulling */
+  int64_t pull_edges;       /* in-edges read by those pulls */
+  double expand_ms;         /* summed duration of the push launches (timing enabled) */
+  double pull_ms;           /* summed duration of the pull launches (timing enabled) */
   double total_ms;          /* wall time of the call */
 } ps_stats;
 

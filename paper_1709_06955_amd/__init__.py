@@ -47,6 +47,7 @@ class Options(C.Structure):
         ("max_len", C.c_int32), ("bias_shift", C.c_int32),
         ("walk_begin", C.c_int64), ("walk_end", C.c_int64),
         ("slots", C.c_int32), ("reserved", C.c_int32),
+        ("pull_edges", C.c_int64),
     ]
 
 
@@ -61,8 +62,8 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "queries", "walks", "walk_nodes", "tree_nodes", "probe_levels", "steps", "entries_expanded",
-        "entries_pruned", "edges_scanned", "next_entries", "final_adds", "expand_launches")] + [
-        ("expand_ms", C.c_double), ("total_ms", C.c_double)]
+        "entries_pruned", "edges_scanned", "next_entries", "final_adds", "expand_launches", "pull_levels",
+        "pull_edges")] + [("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -140,12 +140,13 @@ ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, doub
 
 namespace {
 
-ps_status run_locked(ps_graph* g, const std::vector<QueryRun>& qs, const std::vector<QueryOut>& outs, int slots) {
+ps_status run_locked(ps_graph* g, const std::vector<QueryRun>& qs, const std::vector<QueryOut>& outs,
+                     const ps_options* opt) {
   ps_ctx* ctx = g->ctx;
   std::lock_guard<std::mutex> lk(ctx->mu);
   PS_HIP(hipSetDevice(ctx->device));
   GraphVersion* gv = graph_acquire(g);
-  ps_status s = engine_run(ctx, g, gv, qs, outs, slots);
+  ps_status s = engine_run(ctx, g, gv, qs, outs, opt ? opt->slots : 0, opt ? opt->pull_edges : 0);
   graph_release(g, gv);
   return s;
 }
@@ -174,7 +175,7 @@ extern "C" ps_status ps_single_source(ps_graph* g, int32_t u, double c, double e
   PS_TRY(make_query_run(g, u, 0, c, eps, delta, seed, opt, &q));
   QueryOut o;
   o.scores = out;
-  return run_locked(g, {q}, {o}, opt ? opt->slots : 0);
+  return run_locked(g, {q}, {o}, opt);
 }
 
 extern "C" ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
@@ -185,7 +186,7 @@ extern "C" ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double
   QueryOut o;
   o.scores = scores;
   o.nodes = nodes;
-  return run_locked(g, {q}, {o}, opt ? opt->slots : 0);
+  return run_locked(g, {q}, {o}, opt);
 }
 
 extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const ps_options* opt, ps_result* r) {
@@ -208,7 +209,7 @@ extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const
     outs.push_back(o);
     which.push_back(i);
   }
-  ps_status s = run_locked(g, qs, outs, opt ? opt->slots : 0);
+  ps_status s = run_locked(g, qs, outs, opt);
   for (size_t j = 0; j < which.size(); ++j) {
     ps_result& rr = r[which[j]];
     rr.status = s;

@@ -289,6 +289,8 @@ __global__ void k_fill(T* p, T v, uint64_t cnt) {
     p[i] = v;
 }
 
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
 __global__ void k_reset_slots(Slot* slots, int32_t* has_next, int P) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= P) return;
@@ -320,6 +322,7 @@ struct SchedArgs {
   float* dense_cur;
   int2* list_cur;
   uint64_t list_cap;
+  unsigned long long* slot_edges;
   unsigned long long* ctr;
   int cur;
 };
@@ -368,6 +371,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
       need[r] = true;
     }
     a.has_next[s] = 0;
+    a.slot_edges[s] = 0;
     cnt += need[r] ? 1u : 0u;
   }
   // Exclusive scan of the per-thread counts of free slots.
@@ -401,6 +405,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         st[r].out_col = Q.out_col;
         st[r].inv_indeg = Q.inv_indeg;
         st[r].acc = Q.acc;
+        st[r].in_rows = Q.in_rows;
+        st[r].in_col = Q.in_col;
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
@@ -424,16 +430,20 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
   if (tid == 0) a.ctr[C_HEAD] = head + (total < avail ? total : avail);
 }
 
-// Reads and clears the scores of the listed entries and applies Rule 2
-// (remove x when Score(x) * sqrt(c)^(i-j-1) <= eps_p, i.e. Score(x) <= thr).
-// For every surviving entry it records its out-row and sqrt(c) * Score(x);
-// rows longer than kBigDeg are also cut into kChunk-edge chunks for the
-// wavefront-per-chunk part of k_expand (marked with the top bit of the
-// length so that the tile part skips them).  Removed entries get length 0.
+// Reads the scores of the listed entries and applies Rule 2 (remove x when
+// Score(x) * sqrt(c)^(i-j-1) <= eps_p, i.e. Score(x) <= thr).  Removed
+// entries and entries without out-edges are cleared at once; the others keep
+// their score in the dense vector (a pulled slot reads it there) and get
+// their out-row and sqrt(c) * Score(x) recorded.  Rows longer than kBigDeg are
+// also cut into kChunk-edge chunks for the wavefront-per-chunk part of
+// k_expand (marked with the top bit of the length so that the tile part skips
+// them).  Per slot, the out-degrees of its kept entries are summed: that
+// decides between pushing and pulling the slot's level.
 __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restrict__ slots,
                                                  const int2* __restrict__ list_cur, float* __restrict__ dense_cur,
                                                  float* __restrict__ item_val, uint2* __restrict__ item_row,
                                                  int2* __restrict__ chunk_list, uint64_t list_cap, uint64_t chunk_cap,
+                                                 unsigned long long* __restrict__ slot_edges,
                                                  unsigned long long* __restrict__ ctr, int cur) {
   // after an overflow the counter runs past the list; never read beyond it
   const unsigned long long cnt = min(ctr[C_LIST0 + cur], (unsigned long long)list_cap);
@@ -444,11 +454,12 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
   for (uint64_t i0 = gtid - lane; i0 < cnt; i0 += stride) {
     const uint64_t i = i0 + lane;
     uint32_t nch = 0;
+    int32_t myslot = -1;
+    unsigned long long mydeg = 0;
     if (i < cnt) {
       const int2 it = list_cur[i];
       float* d = dense_cur + (size_t)it.x * n + it.y;
       const float val = *d;
-      *d = 0.0f;
       const Slot& sl = slots[it.x];
       uint2 row = make_uint2(0u, 0u);
       if (val > sl.thr) {
@@ -456,6 +467,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
         row = sl.out_rows[it.y];
         edges += row.y;
         item_val[i] = val * sl.sc;
+        myslot = it.x;
+        mydeg = row.y;
         if (row.y > kBigDeg) {
           nch = (row.y + kChunk - 1) / kChunk;
           row.y |= kBigFlag;
@@ -463,7 +476,19 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       } else {
         ++pruned;
       }
+      if (!row.y) *d = 0.0f;
       item_row[i] = row;
+    }
+    // segmented sum of out-degrees per slot over the wavefront
+    for (;;) {
+      const unsigned long long live = __ballot(myslot >= 0 && mydeg > 0);
+      if (!live) break;
+      const int leader = __ffsll((long long)live) - 1;
+      const int32_t s0 = __shfl(myslot, leader, 64);
+      const bool mine = myslot == s0;
+      const unsigned long long sum = wave_sum(mine ? mydeg : 0ull);
+      if (lane == leader) atomicAdd(&slot_edges[s0], sum);
+      if (mine) myslot = -1;
     }
     const uint32_t incl = wave_incl_scan(nch);
     const uint32_t total = __shfl(incl, 63, 64);
@@ -489,8 +514,33 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
   }
 }
 
+// One workgroup: marks the slots whose kept entries have at least
+// ctr[C_PULL_T] out-edges; their level is computed by k_pull.
+__global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned long long* __restrict__ slot_edges,
+                                                         int32_t* __restrict__ pull_flag,
+                                                         int32_t* __restrict__ pull_list,
+                                                         unsigned long long* __restrict__ ctr) {
+  __shared__ uint32_t s_n;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const unsigned long long T = ctr[C_PULL_T];
+  for (int s = threadIdx.x; s < P; s += blockDim.x) {
+    const unsigned long long e = slot_edges[s];
+    const bool pull = e > 0 && e >= T;
+    pull_flag[s] = pull ? 1 : 0;
+    if (pull) pull_list[atomicAdd(&s_n, 1u)] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ctr[C_NPULL] = s_n;
+    if (s_n) atomicAdd(&ctr[C_PULLS], (unsigned long long)s_n);
+  }
+}
+
 struct ExpandArgs {
   int32_t n;
+  float* dense_cur;
+  const int32_t* pull_flag;
   const int2* list_cur;
   const float* item_val;
   const uint2* item_row;
@@ -592,11 +642,17 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
       deg[r] = 0;
       if (i < cnt) {
         const uint2 row = a.item_row[i];
-        if (!(row.y & kBigFlag) && row.y) {
-          deg[r] = row.y;
-          s_start[j] = row.x;
-          s_val[j] = a.item_val[i];
-          s_slot[j] = a.list_cur[i].x;
+        if (row.y) {
+          const int2 it = a.list_cur[i];
+          if (!a.pull_flag[it.x]) {  // pushed: its score is consumed here
+            a.dense_cur[(size_t)it.x * a.n + it.y] = 0.0f;
+            if (!(row.y & kBigFlag)) {
+              deg[r] = row.y;
+              s_start[j] = row.x;
+              s_val[j] = a.item_val[i];
+              s_slot[j] = it.x;
+            }
+          }
         }
       }
       s_flag[j] = 0;
@@ -652,6 +708,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
   for (uint64_t c = wave; c < nchunk; c += nwaves) {
     const int2 ch = a.chunk_list[c];
     const int32_t s = a.list_cur[ch.x].x;
+    if (a.pull_flag[s]) continue;
     const Slot sl = a.slots[s];
     const float sv = a.item_val[ch.x];
     const uint2 row = a.item_row[ch.x];
@@ -679,6 +736,71 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
   if (lane == 0) {
     if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
     if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
+  }
+}
+
+// Dense level by pulling (the same sums as Alg. 2, accumulated per target):
+// for a slot marked by k_pick, H_{j+1}[v] = sqrt(c)/|I(v)| * sum over
+// in-neighbours x of v of H_j[x], for every v other than the excluded walk
+// node.  H_j is the slot's dense score vector, holding exactly the kept
+// entries.  Each target is written by one lane, so no atomics are needed
+// except the FP64 estimate on a last level.
+__global__ void __launch_bounds__(kBlock) k_pull(ExpandArgs a, const int32_t* __restrict__ pull_list) {
+  __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid >> 6;
+  WaveBuf wb{s_buf[wv], 0u};
+  unsigned long long nfinal = 0, nnext = 0, inedges = 0;
+  const unsigned long long npull = a.ctr[C_NPULL];
+  const uint64_t tiles_per_slot = ((uint64_t)a.n + kBlock - 1) / kBlock;
+  const uint64_t tiles = npull * tiles_per_slot;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int32_t s = pull_list[t / tiles_per_slot];
+    const int64_t v = (int64_t)(t % tiles_per_slot) * kBlock + tid;
+    const Slot& sl = a.slots[s];
+    const float* h = a.dense_cur + (size_t)s * a.n;
+    bool app = false;
+    if (v < a.n && (int32_t)v != sl.excl) {
+      const uint2 row = sl.in_rows[v];
+      float sum = 0.0f;
+      for (uint32_t k = 0; k < row.y; ++k) sum += h[sl.in_col[row.x + k]];
+      inedges += row.y;
+      if (sum > 0.0f) {
+        const float c = sum * sl.sc * sl.inv_indeg[v];
+        if (c >= 1.17549435e-38f) {
+          if (sl.last) {
+            unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
+            ++nfinal;
+          } else {
+            a.dense_next[(size_t)s * a.n + v] = c;
+            app = true;
+          }
+        }
+      }
+    }
+    if (__ballot(app) && lane == 0) a.has_next[s] = 1;
+    wave_append(wb, app, s, (int32_t)v, a, nnext);
+  }
+  wave_flush(wb, a, nnext);
+  nfinal = wave_sum(nfinal);
+  nnext = wave_sum(nnext);
+  inedges = wave_sum(inedges);
+  if (lane == 0) {
+    if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
+    if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
+    if (inedges) atomicAdd(&a.ctr[C_PULL_EDGES], inedges);
+  }
+}
+
+// Zeroes the dense score vectors of the slots pulled this step.
+__global__ void k_clear_pulled(int32_t n, float* __restrict__ dense_cur, const int32_t* __restrict__ pull_list,
+                               const unsigned long long* __restrict__ ctr) {
+  const unsigned long long npull = ctr[C_NPULL];
+  const uint64_t total = npull * (uint64_t)n;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t s = pull_list[i / (uint64_t)n];
+    dense_cur[(size_t)s * n + (i % (uint64_t)n)] = 0.0f;
   }
 }
 
@@ -773,7 +895,7 @@ void devbuf_free(DevBuf& b) {
 
 void session_free(Session* s) {
   if (!s) return;
-  DevBuf* bufs[] = {&s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
+  DevBuf* bufs[] = {&s->slot_edges, &s->pull_list, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
                     &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->keys,
                     &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
@@ -824,6 +946,9 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   s->chunk_cap = s->list_cap + ((uint64_t)P * m_cap) / kChunk + 1;
   PS_TRY(devbuf_reserve(s->slots, sizeof(Slot) * (size_t)P));
   PS_TRY(devbuf_reserve(s->has_next, sizeof(int32_t) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->slot_edges, sizeof(unsigned long long) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->pull_list, sizeof(int32_t) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->pull_flag, sizeof(int32_t) * (size_t)P));
   const bool fresh = !s->dense[0].p || shape;
   PS_TRY(devbuf_reserve(s->dense[0], sizeof(float) * s->list_cap));
   PS_TRY(devbuf_reserve(s->dense[1], sizeof(float) * s->list_cap));
@@ -866,15 +991,6 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   s->ring_outstanding = 0;
   PS_HIP(hipStreamSynchronize(st));
   return PS_OK;
-}
-
-bool session_can_admit(const Session* s, uint64_t bound) {
-  if (!s || s->free_recs.empty()) return false;
-  if (s->ring_outstanding + bound > s->ring_cap) return false;
-  const uint64_t need = next_pow2(std::max<uint64_t>(2 * bound, 64));
-  for (auto& f : s->tree_free)
-    if (f.second >= need) return true;
-  return false;
 }
 
 // Phase 1 of admission: records, walk sampling, tree sizes (one sync).
@@ -1042,8 +1158,10 @@ StepKernels step_args(Session* s) {
   sa.remaining = s->remaining.as<unsigned long long>();
   sa.done_ring = s->done_ring.as<int32_t>();
   sa.list_cap = s->list_cap;
+  sa.slot_edges = s->slot_edges.as<unsigned long long>();
   sa.ctr = ctr;
   ExpandArgs& ea = k.ea;
+  ea.pull_flag = s->pull_flag.as<int32_t>();
   ea.n = s->n;
   ea.item_val = s->item_val.as<float>();
   ea.item_row = s->item_row.as<uint2>();
@@ -1057,23 +1175,31 @@ StepKernels step_args(Session* s) {
 }
 
 // One level step with the frontier lists of parity `cur`.
-void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                 hipEvent_t ev2) {
   const int nxt = cur ^ 1;
+  unsigned long long* ctr = s->counters.as<unsigned long long>();
   k.sa.dense_cur = s->dense[cur].as<float>();
   k.sa.list_cur = s->list[cur].as<int2>();
   k.sa.cur = cur;
   k_sched<<<1, kSchedThreads, 0, st>>>(k.sa);
   k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
                                        s->item_val.as<float>(), s->item_row.as<uint2>(), s->chunk_list.as<int2>(),
-                                       s->list_cap, s->chunk_cap, s->counters.as<unsigned long long>(), cur);
+                                       s->list_cap, s->chunk_cap, s->slot_edges.as<unsigned long long>(), ctr, cur);
+  k_pick<<<1, kSchedThreads, 0, st>>>(s->P, s->slot_edges.as<unsigned long long>(), s->pull_flag.as<int32_t>(),
+                                      s->pull_list.as<int32_t>(), ctr);
   k.ea.list_cur = s->list[cur].as<int2>();
   k.ea.cur = cur;
+  k.ea.dense_cur = s->dense[cur].as<float>();
   k.ea.dense_next = s->dense[nxt].as<float>();
   k.ea.list_next = s->list[nxt].as<int2>();
   k.ea.nxt = nxt;
   if (ev0) (void)hipEventRecord(ev0, st);
   k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
   if (ev1) (void)hipEventRecord(ev1, st);
+  k_pull<<<kStepGrid, kBlock, 0, st>>>(k.ea, s->pull_list.as<int32_t>());
+  if (ev2) (void)hipEventRecord(ev2, st);
+  k_clear_pulled<<<kStepGrid, kBlock, 0, st>>>(s->n, s->dense[cur].as<float>(), s->pull_list.as<int32_t>(), ctr);
 }
 
 }  // namespace
@@ -1081,43 +1207,47 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
 // Launches `count` level steps.  Without timing they run as replays of a
 // captured pair of steps (even then odd list parity), one graph launch per
 // pair; with timing every expansion is bracketed by events.
-ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
+ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* pull_ms) {
   Session* s = ctx->sess;
   hipStream_t st = ctx->stream;
   StepKernels k = step_args(s);
   const bool timing = ctx->timing && expand_ms;
   if (timing) {
-    while (ctx->ev_pool.size() < 2 * count) {
+    while (ctx->ev_pool.size() < 3 * count) {
       hipEvent_t ev;
       PS_HIP(hipEventCreate(&ev));
       ctx->ev_pool.push_back(ev);
     }
     for (uint64_t t = 0; t < count; ++t) {
-      launch_step(s, k, (int)(s->steps & 1), st, ctx->ev_pool[2 * t], ctx->ev_pool[2 * t + 1]);
+      launch_step(s, k, (int)(s->steps & 1), st, ctx->ev_pool[3 * t], ctx->ev_pool[3 * t + 1],
+                  ctx->ev_pool[3 * t + 2]);
       s->steps++;
     }
     PS_HIP(hipGetLastError());
     PS_HIP(hipStreamSynchronize(st));
-    double ms = 0.0;
+    double ms = 0.0, pms = 0.0;
     for (uint64_t t = 0; t < count; ++t) {
-      float x = 0.0f;
-      PS_HIP(hipEventElapsedTime(&x, ctx->ev_pool[2 * t], ctx->ev_pool[2 * t + 1]));
+      float x = 0.0f, y = 0.0f;
+      PS_HIP(hipEventElapsedTime(&x, ctx->ev_pool[3 * t], ctx->ev_pool[3 * t + 1]));
+      PS_HIP(hipEventElapsedTime(&y, ctx->ev_pool[3 * t + 1], ctx->ev_pool[3 * t + 2]));
       ms += x;
+      pms += y;
     }
     *expand_ms += ms;
+    if (pull_ms) *pull_ms += pms;
     return PS_OK;
   }
   if (count >= 4) {
     if (s->steps & 1) {
-      launch_step(s, k, 1, st, nullptr, nullptr);
+      launch_step(s, k, 1, st, nullptr, nullptr, nullptr);
       s->steps++;
       count--;
     }
     if (!s->step_pair) {
       hipGraph_t graph = nullptr;
       PS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      launch_step(s, k, 0, st, nullptr, nullptr);
-      launch_step(s, k, 1, st, nullptr, nullptr);
+      launch_step(s, k, 0, st, nullptr, nullptr, nullptr);
+      launch_step(s, k, 1, st, nullptr, nullptr, nullptr);
       PS_HIP(hipStreamEndCapture(st, &graph));
       const hipError_t e = hipGraphInstantiate(&s->step_pair, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
@@ -1129,7 +1259,7 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms) {
     }
   }
   for (; count > 0; --count) {
-    launch_step(s, k, (int)(s->steps & 1), st, nullptr, nullptr);
+    launch_step(s, k, (int)(s->steps & 1), st, nullptr, nullptr, nullptr);
     s->steps++;
   }
   PS_HIP(hipGetLastError());
@@ -1211,8 +1341,25 @@ ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun&
   return PS_OK;
 }
 
+// Pull threshold in out-edges of a slot's kept entries: a pull reads every
+// in-edge of the graph once, so it pays off when the level would push along
+// a sizable share of them.
+uint64_t pull_threshold(int64_t m, int64_t opt) {
+  if (opt < 0) return ~0ull;
+  if (opt > 0) return (uint64_t)opt;
+  return std::max<uint64_t>((uint64_t)m / 8, 4096);
+}
+
+ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold) {
+  Session* s = ctx->sess;
+  k_set_u64<<<1, 1, 0, ctx->stream>>>(s->counters.as<unsigned long long>() + C_PULL_T,
+                                      (unsigned long long)threshold);
+  PS_HIP(hipGetLastError());
+  return PS_OK;
+}
+
 ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                     const std::vector<QueryOut>& outs, int slots_opt) {
+                     const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt) {
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t st = ctx->stream;
   const int32_t n = g->n;
@@ -1268,8 +1415,9 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   // Greedy list scheduling: every slot is busy while probes are pending, and a
   // probe holds its slot for depth-1 steps, so this many steps finish them all.
   const uint64_t steps = probes ? (levels + P - 1) / P + (uint64_t)maxL + 2 : 0;
-  double expand_ms = 0.0;
-  PS_TRY(session_steps(ctx, steps, &expand_ms));
+  double expand_ms = 0.0, pull_ms = 0.0;
+  PS_TRY(session_set_pull(ctx, pull_threshold(g->m, pull_opt)));
+  PS_TRY(session_steps(ctx, steps, &expand_ms, &pull_ms));
   for (int i = 0; i < nq; ++i) PS_TRY(session_finish(ctx, g, recs[(size_t)i], qs[(size_t)i], outs[(size_t)i]));
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
@@ -1288,7 +1436,10 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   stats.next_entries = (int64_t)(h[C_NEXT] - before[C_NEXT]);
   stats.final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL]);
   stats.expand_launches = (int64_t)steps;
+  stats.pull_levels = (int64_t)(h[C_PULLS] - before[C_PULLS]);
+  stats.pull_edges = (int64_t)(h[C_PULL_EDGES] - before[C_PULL_EDGES]);
   stats.expand_ms = expand_ms;
+  stats.pull_ms = pull_ms;
   stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   ctx->last = stats;
   return PS_OK;

@@ -141,6 +141,8 @@ struct Slot {
   const int32_t* out_col;
   const float* inv_indeg;
   double* acc;
+  const uint2* in_rows;  // for levels computed by pulling
+  const int32_t* in_col;
 };
 
 enum CounterIdx {
@@ -160,6 +162,10 @@ enum CounterIdx {
   C_FINAL,
   C_LEVEL0,
   C_OVERFLOW,
+  C_NPULL,       // slots pulled this step
+  C_PULLS,       // probe levels computed by pulling
+  C_PULL_EDGES,  // in-edges read by pulls
+  C_PULL_T,      // pull threshold in out-edges (set by the host)
   C_COUNT
 };
 
@@ -178,7 +184,7 @@ struct Session {
   uint64_t list_cap = 0, chunk_cap = 0;
   uint64_t tree_pool = 0;   // entries
   uint64_t ring_cap = 0;    // power of two
-  DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters;
+  DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_list, pull_flag;
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp;
@@ -211,29 +217,35 @@ struct ps_ctx {
 void ctx_release(ps_ctx* c);
 
 // Session lifecycle (engine.hip).  session_ensure (re)allocates when the
-// requested shape exceeds the current one; it must only be called while no
-// query is admitted.
+// requested shape exceeds the current one; only while no query is admitted.
 ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax, uint64_t tree_pool,
                          uint64_t ring_cap);
 void session_free(Session* s);
 int session_slots_for(int32_t n, int opt);
-// Admits queries (records are assigned by the session); launches their walks
-// and tree construction.  rec[i] receives the record of query i.  Each query
-// reads graph version gv (one reference is taken per query).
-ps_status session_admit(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                        std::vector<int>* rec, std::vector<uint64_t>* bound);
-// Launches `count` level steps.
-ps_status session_steps(ps_ctx* ctx, uint64_t count);
-// Finalises record r (divide by n_r, s(u,u) = 1, top-k) and copies its result
-// to `out` on the context stream; then frees the record.
+// Admission, phase 1: takes records for the queries (all reading graph
+// version gv), samples their walks once and returns each tree's size bound.
+ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
+                        std::vector<int>* recs, std::vector<uint64_t>* bounds);
+// Admission, phase 2: tree regions, tree construction, probes queued.
+// PS_ERR_BUSY when tree or ring space is short.
+ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds);
+// Releases a record whose tree was never built.
+void session_abandon(ps_ctx* ctx, ps_graph* g, int r);
+// Launches `count` level steps (timings added when the pointers are given
+// and the context times launches).
+ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* pull_ms);
+// Finalises record r (divide by n_r, s(u,u) = 1, top-k), copies its result
+// to `out` on the context stream and frees the record.
 ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, const QueryOut& out);
-// Tree regions and ring space of admitted queries; for admission control.
-bool session_can_admit(const Session* s, uint64_t bound_hint);
+ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta,
+                         uint64_t seed, const ps_options* opt, QueryRun* q);
 
 // Runs a set of queries to completion on one graph version and writes every
 // result (ps_single_source, ps_topk, ps_batch).
 ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                     const std::vector<QueryOut>& outs, int slots_opt);
+                     const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt);
+uint64_t pull_threshold(int64_t m, int64_t opt);
+ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold);
 
 ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun& q, int64_t k_begin,
                        int64_t count, int32_t* nodes, int32_t* lens);

@@ -17,15 +17,6 @@
 
 #include "ps_internal.h"
 
-// Engine entry points used here (engine.hip).
-ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                        std::vector<int>* recs, std::vector<uint64_t>* bounds);
-ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds);
-ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms);
-void session_abandon(ps_ctx* ctx, ps_graph* g, int r);
-ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
-                         const ps_options* opt, QueryRun* q);
-
 namespace {
 
 constexpr int kStepsPerIteration = 4;
@@ -335,7 +326,7 @@ ps_status serve_loop(ps_server* s) {
     for (auto& kv : admitted)
       if (kv.second.built) have_probes = true;
     if (have_probes) {
-      ps_status ss_ = session_steps(ctx, kStepsPerIteration, nullptr);
+      ps_status ss_ = session_steps(ctx, kStepsPerIteration, nullptr, nullptr);
       if (ss_ != PS_OK) {
         fatal = ss_;
         break;
@@ -424,6 +415,7 @@ extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_s
     if (st == PS_OK)
       st = session_ensure(ctx, g->n, std::max<uint64_t>(g->cur->out_store->cap, 1), P, s->cfg.max_inflight, pool,
                           pool / 2);
+    if (st == PS_OK) st = session_set_pull(ctx, pull_threshold(g->m, 0));
     if (st != PS_OK) {
       delete s;
       return st;

@@ -340,3 +340,19 @@ def test_server_busy_and_stop(ps, ctx):
     finally:
         srv.stop()
     assert got_busy or len(tickets) == 50
+
+
+@pytest.mark.parametrize("pull", [1, -1, 0])
+def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
+    # pull_edges=1 computes every level by pulling along in-edges, -1 never
+    # does, 0 picks per level; all must give the oracle's estimates.
+    n, s, d, G, O = cl20k
+    u = int(graphs.query_nodes(n, d, 1, seed=15)[0])
+    gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 11, pull_edges=pull)
+    st = ctx.stats()
+    if pull == 1:
+        assert st["pull_levels"] > 0 and st["pull_edges"] > 0
+    if pull == -1:
+        assert st["pull_levels"] == 0
+    ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11)
+    _parity(gpu, ref, ost, f"pull_edges={pull}")
