@@ -127,6 +127,7 @@ def main():
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
+    ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -150,11 +151,12 @@ def main():
 
     def plain_step(acc, tag):
         for i, u in enumerate(q):
-            ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots)
+            ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots, pull_edges=args.pull)
             st = ctx.stats()
-            print(f"[{tag}] query {i} u={int(u)}: {st['total_ms']:.1f} ms, expand {st['expand_ms']:.1f} ms in "
-                  f"{st['expand_launches']} steps, tree nodes {st['tree_nodes']}, edges {st['edges_scanned']}, "
-                  f"entries {st['entries_expanded']}, next {st['next_entries']}, final {st['final_adds']}",
+            print(f"[{tag}] query {i} u={int(u)}: {st['total_ms']:.1f} ms, push {st['expand_ms']:.1f} ms + pull "
+                  f"{st['pull_ms']:.1f} ms in {st['expand_launches']} steps, tree nodes {st['tree_nodes']}, "
+                  f"edges {st['edges_scanned']}, entries {st['entries_expanded']}, next {st['next_entries']}, "
+                  f"final {st['final_adds']}, pulled levels {st['pull_levels']} ({st['pull_edges']} in-edges)",
                   file=sys.stderr, flush=True)
             if acc is not None:
                 for k in acc:
@@ -162,7 +164,7 @@ def main():
 
     for _ in range(args.warmup):
         plain_step(None, "warmup")
-    keys = ["expand_ms", "expand_launches", "entries_expanded", "edges_scanned", "next_entries", "final_adds",
+    keys = ["expand_ms", "pull_ms", "pull_levels", "pull_edges", "expand_launches", "entries_expanded", "edges_scanned", "next_entries", "final_adds",
             "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned"]
     acc = {k: 0 for k in keys}
     torch.cuda.synchronize()
@@ -177,10 +179,10 @@ def main():
     # Batched: the same 32 queries in one launch.
     outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in range(len(q))]
     qlist = [dict(u=int(u), k=0, c=C, eps=EPS, delta=DELTA, seed=3 + i) for i, u in enumerate(q)]
-    ps.ps_batch(G, qlist, outs=outs, slots=args.slots)
+    ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    ps.ps_batch(G, qlist, outs=outs, slots=args.slots)
+    ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
     torch.cuda.synchronize()
     batched_qps = len(q) / (time.perf_counter() - tb)
     print(f"batched: {batched_qps:.2f} queries/s", file=sys.stderr, flush=True)

@@ -407,6 +407,9 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         st[r].acc = Q.acc;
         st[r].in_rows = Q.in_rows;
         st[r].in_col = Q.in_col;
+        st[r].heavy_nodes = Q.heavy_nodes;
+        st[r].heavy_chunks = Q.heavy_chunks;
+        st[r].heavy_cnt = Q.heavy_cnt;
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
@@ -743,8 +746,27 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
 // for a slot marked by k_pick, H_{j+1}[v] = sqrt(c)/|I(v)| * sum over
 // in-neighbours x of v of H_j[x], for every v other than the excluded walk
 // node.  H_j is the slot's dense score vector, holding exactly the kept
-// entries.  Each target is written by one lane, so no atomics are needed
-// except the FP64 estimate on a last level.
+// entries.  Part 1: one lane per target with at most kPullLane in-neighbours
+// sums its in-row and finishes the target (one writer per target, no
+// atomics but the FP64 estimate on a last level).  Part 2: longer in-rows
+// come in kPullChunk-edge chunks; one wavefront sums a chunk and adds it to
+// the target's raw sum in the next dense vector, finished by k_pull_fin.
+
+// Writes the finished value of target v of slot s (c = scaled sum).
+__device__ __forceinline__ bool pull_finish(const ExpandArgs& a, int32_t s, int32_t v, float sum, const Slot& sl,
+                                            unsigned long long& nfinal) {
+  float* dn = a.dense_next + (size_t)s * a.n + v;
+  const float c = sum * sl.sc * sl.inv_indeg[v];
+  if (!(c >= 1.17549435e-38f)) return false;
+  if (sl.last) {
+    unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
+    ++nfinal;
+    return false;
+  }
+  *dn = c;
+  return true;
+}
+
 __global__ void __launch_bounds__(kBlock) k_pull(ExpandArgs a, const int32_t* __restrict__ pull_list) {
   __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
   const int tid = threadIdx.x;
@@ -753,6 +775,7 @@ __global__ void __launch_bounds__(kBlock) k_pull(ExpandArgs a, const int32_t* __
   WaveBuf wb{s_buf[wv], 0u};
   unsigned long long nfinal = 0, nnext = 0, inedges = 0;
   const unsigned long long npull = a.ctr[C_NPULL];
+  // Part 1: light targets, one lane each.
   const uint64_t tiles_per_slot = ((uint64_t)a.n + kBlock - 1) / kBlock;
   const uint64_t tiles = npull * tiles_per_slot;
   for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
@@ -763,26 +786,50 @@ __global__ void __launch_bounds__(kBlock) k_pull(ExpandArgs a, const int32_t* __
     bool app = false;
     if (v < a.n && (int32_t)v != sl.excl) {
       const uint2 row = sl.in_rows[v];
-      float sum = 0.0f;
-      for (uint32_t k = 0; k < row.y; ++k) sum += h[sl.in_col[row.x + k]];
-      inedges += row.y;
-      if (sum > 0.0f) {
-        const float c = sum * sl.sc * sl.inv_indeg[v];
-        if (c >= 1.17549435e-38f) {
-          if (sl.last) {
-            unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
-            ++nfinal;
-          } else {
-            a.dense_next[(size_t)s * a.n + v] = c;
-            app = true;
-          }
+      if (row.y <= kPullLane) {
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+        uint32_t k = 0;
+        for (; k + 4 <= row.y; k += 4) {
+          const int32_t x0 = sl.in_col[row.x + k], x1 = sl.in_col[row.x + k + 1];
+          const int32_t x2 = sl.in_col[row.x + k + 2], x3 = sl.in_col[row.x + k + 3];
+          s0 += h[x0];
+          s1 += h[x1];
+          s2 += h[x2];
+          s3 += h[x3];
         }
+        for (; k < row.y; ++k) s0 += h[sl.in_col[row.x + k]];
+        const float sum = (s0 + s1) + (s2 + s3);
+        inedges += row.y;
+        if (sum > 0.0f) app = pull_finish(a, s, (int32_t)v, sum, sl, nfinal);
       }
     }
     if (__ballot(app) && lane == 0) a.has_next[s] = 1;
     wave_append(wb, app, s, (int32_t)v, a, nnext);
   }
   wave_flush(wb, a, nnext);
+  // Part 2: chunks of long in-rows, one wavefront each; raw partial sums.
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t pi = 0; pi < npull; ++pi) {
+    const int32_t s = pull_list[pi];
+    const Slot& sl = a.slots[s];
+    const float* h = a.dense_cur + (size_t)s * a.n;
+    const unsigned long long nch = sl.heavy_cnt[1];
+    for (uint64_t c = wave; c < nch; c += nwaves) {
+      const int2 ch = sl.heavy_chunks[c];
+      if (ch.x == sl.excl) continue;
+      const uint2 row = sl.in_rows[ch.x];
+      const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
+      float part = 0.0f;
+      for (uint32_t k = (uint32_t)ch.y + lane; k < e; k += 64) part += h[sl.in_col[row.x + k]];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      if (lane == 0) {
+        inedges += e - (uint32_t)ch.y;
+        if (part > 0.0f) unsafeAtomicAdd(&a.dense_next[(size_t)s * a.n + ch.x], part);
+      }
+    }
+  }
   nfinal = wave_sum(nfinal);
   nnext = wave_sum(nnext);
   inedges = wave_sum(inedges);
@@ -790,6 +837,44 @@ __global__ void __launch_bounds__(kBlock) k_pull(ExpandArgs a, const int32_t* __
     if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
     if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
     if (inedges) atomicAdd(&a.ctr[C_PULL_EDGES], inedges);
+  }
+}
+
+// Finishes the long-row targets of the pulled slots from their raw sums.
+__global__ void __launch_bounds__(kBlock) k_pull_fin(ExpandArgs a, const int32_t* __restrict__ pull_list) {
+  __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  WaveBuf wb{s_buf[tid >> 6], 0u};
+  unsigned long long nfinal = 0, nnext = 0;
+  const unsigned long long npull = a.ctr[C_NPULL];
+  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + tid;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t pi = 0; pi < npull; ++pi) {
+    const int32_t s = pull_list[pi];
+    const Slot& sl = a.slots[s];
+    const unsigned long long nh = sl.heavy_cnt[0];
+    for (uint64_t i0 = gtid - lane; i0 < nh; i0 += stride) {
+      const uint64_t i = i0 + lane;
+      bool app = false;
+      int32_t v = 0;
+      if (i < nh) {
+        v = sl.heavy_nodes[i];
+        float* dn = a.dense_next + (size_t)s * a.n + v;
+        const float sum = *dn;
+        *dn = 0.0f;
+        if (sum > 0.0f && v != sl.excl) app = pull_finish(a, s, v, sum, sl, nfinal);
+      }
+      if (__ballot(app) && lane == 0) a.has_next[s] = 1;
+      wave_append(wb, app, s, v, a, nnext);
+    }
+  }
+  wave_flush(wb, a, nnext);
+  nfinal = wave_sum(nfinal);
+  nnext = wave_sum(nnext);
+  if (lane == 0) {
+    if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
+    if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
   }
 }
 
@@ -1028,6 +1113,9 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     d.out_rows = gv->out_rows;
     d.out_col = gv->out_store->col;
     d.inv_indeg = gv->inv_indeg;
+    d.heavy_nodes = gv->heavy_nodes;
+    d.heavy_chunks = gv->heavy_chunks;
+    d.heavy_cnt = gv->heavy_cnt;
     d.acc = s->acc.as<double>() + (size_t)r * (size_t)s->n;
     total += d.walk_count;
     s->h_rec[(size_t)r] = d;
@@ -1198,6 +1286,7 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
   if (ev1) (void)hipEventRecord(ev1, st);
   k_pull<<<kStepGrid, kBlock, 0, st>>>(k.ea, s->pull_list.as<int32_t>());
+  k_pull_fin<<<kStepGrid / 4, kBlock, 0, st>>>(k.ea, s->pull_list.as<int32_t>());
   if (ev2) (void)hipEventRecord(ev2, st);
   k_clear_pulled<<<kStepGrid, kBlock, 0, st>>>(s->n, s->dense[cur].as<float>(), s->pull_list.as<int32_t>(), ctr);
 }

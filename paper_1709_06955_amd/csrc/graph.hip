@@ -31,10 +31,38 @@ __global__ void k_patch_rows(const int32_t* __restrict__ node, const uint2* __re
   if (inv_indeg) inv_indeg[v] = row[i].y ? 1.0f / (float)row[i].y : 0.0f;
 }
 
+// Lists the nodes with more than kPullLane in-neighbours and cuts their
+// in-rows into kPullChunk-edge chunks (order of the lists is irrelevant).
+__global__ void k_heavy(int32_t n, const uint2* __restrict__ in_rows, int32_t* __restrict__ nodes,
+                        int2* __restrict__ chunks, unsigned long long* __restrict__ cnt) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t d = in_rows[v].y;
+  if (d <= kPullLane) return;
+  nodes[atomicAdd(&cnt[0], 1ull)] = (int32_t)v;
+  const uint32_t nch = (d + kPullChunk - 1) / kPullChunk;
+  const unsigned long long base = atomicAdd(&cnt[1], (unsigned long long)nch);
+  for (uint32_t c = 0; c < nch; ++c) chunks[base + c] = make_int2((int32_t)v, (int32_t)(c * kPullChunk));
+}
+
 ps_status alloc_version_arrays(GraphVersion* v, int32_t n) {
   PS_HIP(hipMalloc(&v->in_rows, sizeof(uint2) * (size_t)n));
   PS_HIP(hipMalloc(&v->out_rows, sizeof(uint2) * (size_t)n));
   PS_HIP(hipMalloc(&v->inv_indeg, sizeof(float) * (size_t)n));
+  return PS_OK;
+}
+
+// (Re)builds the heavy in-row lists of a version from its in_rows.  Chunks
+// are bounded by m / kPullChunk + (nodes with long rows) <= m_cap / kPullChunk + n.
+ps_status build_heavy(GraphVersion* v, int32_t n, uint64_t m_cap, hipStream_t st) {
+  if (!v->heavy_nodes) {
+    PS_HIP(hipMalloc(&v->heavy_nodes, sizeof(int32_t) * (size_t)n));
+    PS_HIP(hipMalloc(&v->heavy_chunks, sizeof(int2) * (m_cap / kPullChunk + (size_t)n + 1)));
+    PS_HIP(hipMalloc(&v->heavy_cnt, sizeof(unsigned long long) * 2));
+  }
+  PS_HIP(hipMemsetAsync(v->heavy_cnt, 0, sizeof(unsigned long long) * 2, st));
+  k_heavy<<<(n + 255) / 256, 256, 0, st>>>(n, v->in_rows, v->heavy_nodes, v->heavy_chunks, v->heavy_cnt);
+  PS_HIP(hipGetLastError());
   return PS_OK;
 }
 
@@ -45,11 +73,21 @@ void drop_stores(GraphVersion* v) {
   v->out_store.reset();
 }
 
+void free_heavy(GraphVersion* v) {
+  (void)hipFree(v->heavy_nodes);
+  (void)hipFree(v->heavy_chunks);
+  (void)hipFree(v->heavy_cnt);
+  v->heavy_nodes = nullptr;
+  v->heavy_chunks = nullptr;
+  v->heavy_cnt = nullptr;
+}
+
 void free_version(GraphVersion* v) {
   if (!v) return;
   (void)hipFree(v->in_rows);
   (void)hipFree(v->out_rows);
   (void)hipFree(v->inv_indeg);
+  free_heavy(v);
   drop_stores(v);
   delete v;
 }
@@ -73,6 +111,7 @@ GraphVersion* new_version(ps_graph* g) {
     fresh->in_rows = v->in_rows;
     fresh->out_rows = v->out_rows;
     fresh->inv_indeg = v->inv_indeg;
+    free_heavy(v);
     delete v;
     return fresh;
   }
@@ -137,6 +176,7 @@ ps_status upload_full(ps_graph* g, GraphVersion* v) {
   PS_HIP(hipMemcpyAsync(v->in_rows, in_rows.data(), sizeof(uint2) * (size_t)n, hipMemcpyHostToDevice, st));
   PS_HIP(hipMemcpyAsync(v->out_rows, out_rows.data(), sizeof(uint2) * (size_t)n, hipMemcpyHostToDevice, st));
   PS_HIP(hipMemcpyAsync(v->inv_indeg, inv.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, st));
+  PS_TRY(build_heavy(v, n, in_store->cap, st));
   PS_HIP(hipStreamSynchronize(st));
   in_store->refs = out_store->refs = 1;
   v->in_store = in_store;
@@ -407,6 +447,8 @@ ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const 
       };
       PS_TRY(stage(touched_in, g->mod_in, v->in_store.get(), v->in_rows, v->inv_indeg));
       PS_TRY(stage(touched_out, g->mod_out, v->out_store.get(), v->out_rows, nullptr));
+      PS_TRY(build_heavy(v, g->n, v->in_store->cap, st));
+      PS_HIP(hipStreamSynchronize(st));
     }
     {
       std::lock_guard<std::mutex> lk(g->mu);

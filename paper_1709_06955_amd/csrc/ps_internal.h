@@ -62,6 +62,12 @@ struct GraphVersion {
   uint2* in_rows = nullptr;   // (start, len) of each node's in-row in in_store->col
   uint2* out_rows = nullptr;  // (start, len) of each node's out-row in out_store->col
   float* inv_indeg = nullptr; // 1/|I(v)| (0 when I(v) is empty)
+  // Nodes whose in-row is longer than a lane should sum alone, and their
+  // in-rows cut into fixed chunks, for levels computed by pulling.  Counts
+  // (nodes, chunks) live on the device.
+  int32_t* heavy_nodes = nullptr;
+  int2* heavy_chunks = nullptr;          // (node, first in-row offset)
+  unsigned long long* heavy_cnt = nullptr;
   std::shared_ptr<ColStore> in_store, out_store;
   int refs = 0;               // queries reading this version + 1 while current
 };
@@ -85,6 +91,10 @@ GraphVersion* graph_acquire(ps_graph* g);
 void graph_release(ps_graph* g, GraphVersion* v);
 // In-degree of v in the current host mirror.
 int64_t graph_host_indeg(const ps_graph* g, int32_t v);
+// In-degree cut-offs of the pull path: in-rows up to kPullLane edges are
+// summed by one lane, longer ones in chunks of kPullChunk edges.
+constexpr uint32_t kPullLane = 64;
+constexpr uint32_t kPullChunk = 256;
 // Applies a batch of updates (shared by ps_graph_update and the server).
 ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const int32_t* dst,
                               const uint8_t* op, int32_t* per_edge, uint64_t* version);
@@ -113,6 +123,9 @@ struct QueryDev {
   const int32_t* out_col;
   const float* inv_indeg;
   double* acc;         // n FP64 accumulators, then the estimate
+  const int32_t* heavy_nodes;
+  const int2* heavy_chunks;
+  const unsigned long long* heavy_cnt;
 };
 
 // Host view of a query.
@@ -143,6 +156,9 @@ struct Slot {
   double* acc;
   const uint2* in_rows;  // for levels computed by pulling
   const int32_t* in_col;
+  const int32_t* heavy_nodes;
+  const int2* heavy_chunks;
+  const unsigned long long* heavy_cnt;
 };
 
 enum CounterIdx {
