@@ -158,6 +158,11 @@ def main():
                   f"edges {st['edges_scanned']}, entries {st['entries_expanded']}, next {st['next_entries']}, "
                   f"final {st['final_adds']}, pulled levels {st['pull_levels']} ({st['pull_edges']} in-edges)",
                   file=sys.stderr, flush=True)
+            if i == 0 and tag != "warmup":
+                tot = max(sum(st["level_hist_edges"]), 1)
+                rows = [f"2^{b}:{c}/{100.0 * e / tot:.1f}%" for b, (c, e) in
+                        enumerate(zip(st["level_hist_count"], st["level_hist_edges"])) if c]
+                print("  level sizes (levels/edge share):", " ".join(rows), file=sys.stderr, flush=True)
             if acc is not None:
                 for k in acc:
                     acc[k] += st[k]

@@ -213,6 +213,10 @@ typedef struct ps_stats {
   double expand_ms;         /* summed duration of the push launches (timing enabled) */
   double pull_ms;           /* summed duration of the pull launches (timing enabled) */
   double total_ms;          /* wall time of the call */
+  /* probe levels by the out-edge count E of their kept entries: bin b holds
+     levels with 2^b <= E < 2^(b+1) (count, and the sum of E) */
+  int64_t level_hist_count[32];
+  int64_t level_hist_edges[32];
 } ps_stats;
 
 ps_status ps_get_stats(ps_ctx* ctx, ps_stats* out);

@@ -63,10 +63,15 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "queries", "walks", "walk_nodes", "tree_nodes", "probe_levels", "steps", "entries_expanded",
         "entries_pruned", "edges_scanned", "next_entries", "final_adds", "expand_launches", "pull_levels",
-        "pull_edges")] + [("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double)]
+        "pull_edges")] + [("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double),
+                          ("level_hist_count", C.c_int64 * 32), ("level_hist_edges", C.c_int64 * 32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k.startswith("level_hist") else v
+        return d
 
 
 class Query(C.Structure):

@@ -530,6 +530,11 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned lo
   for (int s = threadIdx.x; s < P; s += blockDim.x) {
     const unsigned long long e = slot_edges[s];
     const bool pull = e > 0 && e >= T;
+    if (e) {
+      const int b = 63 - __clzll((long long)e);
+      atomicAdd(&ctr[C_HIST_N + b], 1ull);
+      atomicAdd(&ctr[C_HIST_E + b], e);
+    }
     pull_flag[s] = pull ? 1 : 0;
     if (pull) pull_list[atomicAdd(&s_n, 1u)] = s;
   }
@@ -1529,6 +1534,10 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   stats.pull_edges = (int64_t)(h[C_PULL_EDGES] - before[C_PULL_EDGES]);
   stats.expand_ms = expand_ms;
   stats.pull_ms = pull_ms;
+  for (int b = 0; b < 32; ++b) {
+    stats.level_hist_count[b] = (int64_t)(h[C_HIST_N + b] - before[C_HIST_N + b]);
+    stats.level_hist_edges[b] = (int64_t)(h[C_HIST_E + b] - before[C_HIST_E + b]);
+  }
   stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   ctx->last = stats;
   return PS_OK;

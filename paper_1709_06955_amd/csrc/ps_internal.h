@@ -182,7 +182,9 @@ enum CounterIdx {
   C_PULLS,       // probe levels computed by pulling
   C_PULL_EDGES,  // in-edges read by pulls
   C_PULL_T,      // pull threshold in out-edges (set by the host)
-  C_COUNT
+  C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
+  C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
+  C_COUNT = C_HIST_E + 32
 };
 
 struct QueryOut {
