@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
     ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="also run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -219,6 +221,12 @@ def main():
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches},
         "work_per_query": {k: acc[k] / queries for k in keys if k not in ("expand_ms",)},
     }
+    if args.calib_copy:
+        a = torch.empty(args.calib_copy << 18, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written", file=sys.stderr)
     if not args.no_served:
         result["served"] = served(ps, G, q, n)
     if not args.no_cpu_baseline:

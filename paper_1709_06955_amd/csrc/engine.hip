@@ -996,16 +996,16 @@ void session_free(Session* s) {
   delete s;
 }
 
-// Probe slots: enough concurrent probes to fill the GPU, bounded so that the
-// per-slot buffers (dense scores 8 B, frontier lists 16 B, scaled scores 4 B,
-// bins 12 B per node) stay within a fixed share of HBM and slot * n fits in
-// 31 bits.
+// Probe slots: enough concurrent probes to fill the GPU (more slots also
+// mean fewer level steps), bounded so that the per-slot buffers (dense
+// scores 8 B, frontier lists 16 B, scaled scores 4 B, rows 8 B, chunks 8 B
+// per node) stay within a fixed share of HBM and slot * n fits in 31 bits.
 int session_slots_for(int32_t n, int opt) {
   if (opt > 0) return std::min(opt, kSchedThreads * kSlotsPerSchedThread);
-  const uint64_t budget = 24ull << 30;
-  uint64_t p = budget / (40ull * (uint64_t)n);
+  const uint64_t budget = 48ull << 30;
+  uint64_t p = budget / (44ull * (uint64_t)n);
   p = std::min<uint64_t>(p, ((1ull << 31) - 1) / (uint64_t)n);
-  p = std::min<uint64_t>(p, 512);
+  p = std::min<uint64_t>(p, 1024);
   return (int)std::max<uint64_t>(p, 1);
 }
 
