@@ -47,6 +47,7 @@ constexpr uint32_t kChunk = 512;
 constexpr uint32_t kBigFlag = 0x80000000u;
 constexpr int kTile = 1024;              // listed entries per workgroup tile in k_expand
 constexpr int kWaveBuf = 512;            // staged new frontier entries per wavefront
+constexpr int kLanes = 64;               // dense frontier columns (one wavefront lane each)
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr int kStepGrid = 2048;          // 8 workgroups per CU for the step kernels
 
@@ -296,8 +297,23 @@ __global__ void k_reset_slots(Slot* slots, int32_t* has_next, int P) {
   if (s >= P) return;
   Slot st{};
   st.probe = -1;
+  st.lane = -1;
   slots[s] = st;
   has_next[s] = 0;
+}
+
+// Graph version whose in-rows the dense pass reads (all dense lanes share it).
+struct DenseVer {
+  const uint2* in_rows;
+  const int32_t* in_col;
+  const float* inv_indeg;
+  const int32_t* heavy_nodes;
+  const int2* heavy_chunks;
+  const unsigned long long* heavy_cnt;
+};
+
+__global__ void k_reset_lanes(int32_t* lane_slot) {
+  if (threadIdx.x < kLanes) lane_slot[threadIdx.x] = -1;
 }
 
 // ------------------------------------------------------- level steps ----
@@ -323,6 +339,7 @@ struct SchedArgs {
   int2* list_cur;
   uint64_t list_cap;
   unsigned long long* slot_edges;
+  int32_t* lane_slot;
   unsigned long long* ctr;
   int cur;
 };
@@ -361,7 +378,9 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
           const unsigned long long pos = atomicAdd(&a.ctr[C_DONE], 1ull);
           a.done_ring[pos % (unsigned long long)a.qmax] = q;
         }
+        if (st[r].lane >= 0) a.lane_slot[st[r].lane] = -1;  // dense column free again
         st[r].probe = -1;
+        st[r].lane = -1;
         need[r] = true;
       } else {
         st[r].level++;
@@ -395,6 +414,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         const int q = a.t_query[t];
         const QueryDev& Q = a.qr[q];
         st[r].probe = t;
+        st[r].lane = -1;
         st[r].level = 0;
         st[r].depth = a.t_depth[t];
         st[r].cursor = a.t_parent[t];
@@ -517,37 +537,90 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
   }
 }
 
-// One workgroup: marks the slots whose kept entries have at least
-// ctr[C_PULL_T] out-edges; their level is computed by k_pull.
+// One workgroup: moves sparse slots whose kept entries have at least
+// ctr[C_PULL_T] out-edges into free dense columns, as long as they read the
+// graph version the dense pass uses (fixed by the columns already active, or
+// by the first slot moved).  Their entries are scattered into the dense
+// matrix by k_expand this step.  Also sets the column range of this step's
+// dense pass and records the version's arrays for it.
 __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned long long* __restrict__ slot_edges,
-                                                         int32_t* __restrict__ pull_flag,
-                                                         int32_t* __restrict__ pull_list,
+                                                         Slot* __restrict__ slots, int32_t* __restrict__ pull_flag,
+                                                         int32_t* __restrict__ lane_slot, DenseVer* __restrict__ dv,
                                                          unsigned long long* __restrict__ ctr) {
-  __shared__ uint32_t s_n;
-  if (threadIdx.x == 0) s_n = 0;
+  __shared__ int32_t s_free[kLanes];
+  __shared__ uint32_t s_nfree, s_ncand, s_hi, s_active;
+  __shared__ unsigned long long s_ver;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_nfree = 0;
+    s_ncand = 0;
+    s_hi = 0;
+    s_active = 0;
+    s_ver = 0ull;
+  }
+  __syncthreads();
+  if (tid < kLanes) {
+    const int32_t ls = lane_slot[tid];
+    if (ls < 0) s_free[atomicAdd(&s_nfree, 1u)] = tid;
+    else s_ver = (unsigned long long)slots[ls].in_rows;  // all active columns share it
+  }
   __syncthreads();
   const unsigned long long T = ctr[C_PULL_T];
-  for (int s = threadIdx.x; s < P; s += blockDim.x) {
+  for (int s = tid; s < P; s += blockDim.x) {
     const unsigned long long e = slot_edges[s];
-    const bool pull = e > 0 && e >= T;
+    int32_t flag = 0;
     if (e) {
       const int b = 63 - __clzll((long long)e);
       atomicAdd(&ctr[C_HIST_N + b], 1ull);
       atomicAdd(&ctr[C_HIST_E + b], e);
+      if (e >= T && slots[s].lane < 0) {
+        const unsigned long long ver = (unsigned long long)slots[s].in_rows;
+        const unsigned long long old = atomicCAS(&s_ver, 0ull, ver);
+        if ((old == 0ull ? ver : old) == ver) {
+          const uint32_t k = atomicAdd(&s_ncand, 1u);
+          if (k < s_nfree) {
+            const int32_t lane = s_free[k];
+            slots[s].lane = lane;
+            lane_slot[lane] = s;
+            flag = 1;
+          }
+        }
+      }
     }
-    pull_flag[s] = pull ? 1 : 0;
-    if (pull) pull_list[atomicAdd(&s_n, 1u)] = s;
+    pull_flag[s] = flag;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ctr[C_NPULL] = s_n;
-    if (s_n) atomicAdd(&ctr[C_PULLS], (unsigned long long)s_n);
+  if (tid < kLanes && lane_slot[tid] >= 0) {
+    atomicMax(&s_hi, (uint32_t)tid + 1u);
+    atomicAdd(&s_active, 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned long long hi = s_hi;
+    const unsigned long long prev = ctr[C_GPREV];
+    ctr[C_GHI] = hi;
+    ctr[C_GW] = hi > prev ? hi : prev;
+    ctr[C_GPREV] = hi;
+    if (s_active) atomicAdd(&ctr[C_PULLS], (unsigned long long)s_active);
+    for (int g = 0; g < kLanes; ++g) {
+      const int32_t ls = lane_slot[g];
+      if (ls < 0) continue;
+      const Slot& sl = slots[ls];
+      dv->in_rows = sl.in_rows;
+      dv->in_col = sl.in_col;
+      dv->inv_indeg = sl.inv_indeg;
+      dv->heavy_nodes = sl.heavy_nodes;
+      dv->heavy_chunks = sl.heavy_chunks;
+      dv->heavy_cnt = sl.heavy_cnt;
+      break;
+    }
   }
 }
 
 struct ExpandArgs {
   int32_t n;
   float* dense_cur;
+  float* mat_cur;  // dense frontier matrix (n x kLanes) of this step
   const int32_t* pull_flag;
   const int2* list_cur;
   const float* item_val;
@@ -652,8 +725,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
         const uint2 row = a.item_row[i];
         if (row.y) {
           const int2 it = a.list_cur[i];
-          if (!a.pull_flag[it.x]) {  // pushed: its score is consumed here
-            a.dense_cur[(size_t)it.x * a.n + it.y] = 0.0f;
+          float* dc = a.dense_cur + (size_t)it.x * a.n + it.y;
+          if (a.pull_flag[it.x]) {  // slot moved to a dense column: scatter
+            a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = *dc;
+            *dc = 0.0f;
+          } else {  // pushed: its score is consumed here
+            *dc = 0.0f;
             if (!(row.y & kBigFlag)) {
               deg[r] = row.y;
               s_start[j] = row.x;
@@ -747,151 +824,178 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
   }
 }
 
-// Dense level by pulling (the same sums as Alg. 2, accumulated per target):
-// for a slot marked by k_pick, H_{j+1}[v] = sqrt(c)/|I(v)| * sum over
-// in-neighbours x of v of H_j[x], for every v other than the excluded walk
-// node.  H_j is the slot's dense score vector, holding exactly the kept
-// entries.  Part 1: one lane per target with at most kPullLane in-neighbours
-// sums its in-row and finishes the target (one writer per target, no
-// atomics but the FP64 estimate on a last level).  Part 2: longer in-rows
-// come in kPullChunk-edge chunks; one wavefront sums a chunk and adds it to
-// the target's raw sum in the next dense vector, finished by k_pull_fin.
+// Dense levels.  Up to kLanes slots keep their frontier as a column of a
+// node-major matrix M (n x kLanes FP32, one 256-byte row per node).  One pass
+// per step advances all of them together, by pulling: for every target v,
+//   H_{j+1}[v] = sqrt(c)/|I(v)| * sum over in-neighbours x of v of H_j[x],
+// with Rule 2 applied to H_j[x] as it is read (values <= thr count as 0) and
+// the excluded walk node skipped (the same sums as Alg. 2, accumulated per
+// target).  A wavefront handles one target and its 64 lanes the 64 columns,
+// so each in-neighbour costs one contiguous row read; the row of v in the
+// next matrix is written whole.  In-rows longer than kPullLane edges are
+// summed in kPullChunk-edge chunks into raw partial sums, finished by
+// k_dense_fin.  On a probe's last level the value goes into the FP64
+// estimate instead (one add per target, not per edge).
 
-// Writes the finished value of target v of slot s (c = scaled sum).
-__device__ __forceinline__ bool pull_finish(const ExpandArgs& a, int32_t s, int32_t v, float sum, const Slot& sl,
-                                            unsigned long long& nfinal) {
-  float* dn = a.dense_next + (size_t)s * a.n + v;
-  const float c = sum * sl.sc * sl.inv_indeg[v];
-  if (!(c >= 1.17549435e-38f)) return false;
-  if (sl.last) {
-    unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
-    ++nfinal;
-    return false;
+struct DenseArgs {
+  int32_t n;
+  const Slot* slots;
+  const int32_t* lane_slot;
+  const DenseVer* dv;
+  const float* mat_cur;
+  float* mat_next;
+  float* npart;  // n x kLanes raw sums of long in-rows
+  int32_t* has_next;
+  unsigned long long* ctr;
+};
+
+struct LaneInfo {
+  bool active;
+  bool last;
+  float thr, sc;
+  int32_t excl;
+  double w;
+  double* acc;
+};
+
+__device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigned long long ghi) {
+  LaneInfo li{};
+  li.active = false;
+  if ((unsigned long long)g < ghi) {
+    const int32_t s = a.lane_slot[g];
+    if (s >= 0) {
+      const Slot& sl = a.slots[s];
+      li.active = true;
+      li.last = sl.last != 0;
+      li.thr = sl.thr;
+      li.sc = sl.sc;
+      li.excl = sl.excl;
+      li.w = sl.w;
+      li.acc = sl.acc;
+    }
   }
-  *dn = c;
-  return true;
+  return li;
 }
 
-__global__ void __launch_bounds__(kBlock) k_pull(ExpandArgs a, const int32_t* __restrict__ pull_list) {
-  __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wv = tid >> 6;
-  WaveBuf wb{s_buf[wv], 0u};
-  unsigned long long nfinal = 0, nnext = 0, inedges = 0;
-  const unsigned long long npull = a.ctr[C_NPULL];
-  // Part 1: light targets, one lane each.
-  const uint64_t tiles_per_slot = ((uint64_t)a.n + kBlock - 1) / kBlock;
-  const uint64_t tiles = npull * tiles_per_slot;
-  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    const int32_t s = pull_list[t / tiles_per_slot];
-    const int64_t v = (int64_t)(t % tiles_per_slot) * kBlock + tid;
-    const Slot& sl = a.slots[s];
-    const float* h = a.dense_cur + (size_t)s * a.n;
-    bool app = false;
-    if (v < a.n && (int32_t)v != sl.excl) {
-      const uint2 row = sl.in_rows[v];
-      if (row.y <= kPullLane) {
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-        uint32_t k = 0;
-        for (; k + 4 <= row.y; k += 4) {
-          const int32_t x0 = sl.in_col[row.x + k], x1 = sl.in_col[row.x + k + 1];
-          const int32_t x2 = sl.in_col[row.x + k + 2], x3 = sl.in_col[row.x + k + 3];
-          s0 += h[x0];
-          s1 += h[x1];
-          s2 += h[x2];
-          s3 += h[x3];
-        }
-        for (; k < row.y; ++k) s0 += h[sl.in_col[row.x + k]];
-        const float sum = (s0 + s1) + (s2 + s3);
-        inedges += row.y;
-        if (sum > 0.0f) app = pull_finish(a, s, (int32_t)v, sum, sl, nfinal);
+__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, int32_t v, float sum,
+                                             float inv, unsigned long long gw, unsigned long long& nfinal) {
+  float out = 0.0f;
+  bool nz = false;
+  if (li.active && v != li.excl && sum > 0.0f) {
+    const float c = sum * li.sc * inv;
+    if (c >= 1.17549435e-38f) {
+      if (li.last) {
+        unsafeAtomicAdd(&li.acc[v], (double)c * li.w);
+        ++nfinal;
+      } else {
+        out = c;
+        nz = true;
       }
     }
-    if (__ballot(app) && lane == 0) a.has_next[s] = 1;
-    wave_append(wb, app, s, (int32_t)v, a, nnext);
   }
-  wave_flush(wb, a, nnext);
-  // Part 2: chunks of long in-rows, one wavefront each; raw partial sums.
+  if ((unsigned long long)g < gw) a.mat_next[(size_t)v * kLanes + g] = out;
+  return nz;
+}
+
+__device__ __forceinline__ float pruned(float x, float thr) { return x > thr ? x : 0.0f; }
+
+__global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
+  __shared__ unsigned long long s_nz;
+  const unsigned long long ghi = a.ctr[C_GHI], gw = a.ctr[C_GW];
+  if (gw == 0) return;
+  const int tid = threadIdx.x;
+  const int g = lane_id();
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t pi = 0; pi < npull; ++pi) {
-    const int32_t s = pull_list[pi];
-    const Slot& sl = a.slots[s];
-    const float* h = a.dense_cur + (size_t)s * a.n;
-    const unsigned long long nch = sl.heavy_cnt[1];
-    for (uint64_t c = wave; c < nch; c += nwaves) {
-      const int2 ch = sl.heavy_chunks[c];
-      if (ch.x == sl.excl) continue;
-      const uint2 row = sl.in_rows[ch.x];
-      const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
-      float part = 0.0f;
-      for (uint32_t k = (uint32_t)ch.y + lane; k < e; k += 64) part += h[sl.in_col[row.x + k]];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-      if (lane == 0) {
-        inedges += e - (uint32_t)ch.y;
-        if (part > 0.0f) unsafeAtomicAdd(&a.dense_next[(size_t)s * a.n + ch.x], part);
-      }
-    }
+  if (ghi == 0) {  // no column in use: clear the columns used last step
+    for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves)
+      if ((unsigned long long)g < gw) a.mat_next[v * kLanes + g] = 0.0f;
+    return;
   }
+  if (tid == 0) s_nz = 0ull;
+  __syncthreads();
+  const LaneInfo li = lane_info(a, g, ghi);
+  const DenseVer dv = *a.dv;
+  const float* m = a.mat_cur + g;
+  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0;
+  for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
+    const uint2 row = dv.in_rows[v];
+    if (row.y > kPullLane) continue;  // long in-row: chunks + k_dense_fin
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    if (li.active) {
+      uint32_t k = 0;
+      for (; k + 4 <= row.y; k += 4) {
+        const int32_t x0 = dv.in_col[row.x + k], x1 = dv.in_col[row.x + k + 1];
+        const int32_t x2 = dv.in_col[row.x + k + 2], x3 = dv.in_col[row.x + k + 3];
+        s0 += pruned(m[(size_t)x0 * kLanes], li.thr);
+        s1 += pruned(m[(size_t)x1 * kLanes], li.thr);
+        s2 += pruned(m[(size_t)x2 * kLanes], li.thr);
+        s3 += pruned(m[(size_t)x3 * kLanes], li.thr);
+      }
+      for (; k < row.y; ++k) s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
+    }
+    inedges += row.y;
+    const bool nz = dense_finish(a, li, g, (int32_t)v, (s0 + s1) + (s2 + s3), dv.inv_indeg[v], gw, nfinal);
+    nz_mask |= __ballot(nz);
+  }
+  const unsigned long long nch = dv.heavy_cnt[1];
+  for (uint64_t c = wave; c < nch; c += nwaves) {
+    const int2 ch = dv.heavy_chunks[c];
+    const uint2 row = dv.in_rows[ch.x];
+    const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
+    inedges += e - (uint32_t)ch.y;
+    if (!li.active) continue;
+    float s0 = 0.0f, s1 = 0.0f;
+    uint32_t k = (uint32_t)ch.y;
+    for (; k + 2 <= e; k += 2) {
+      s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
+      s1 += pruned(m[(size_t)dv.in_col[row.x + k + 1] * kLanes], li.thr);
+    }
+    if (k < e) s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
+    const float part = s0 + s1;
+    if (part > 0.0f) unsafeAtomicAdd(&a.npart[(size_t)ch.x * kLanes + g], part);
+  }
+  if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
-  nnext = wave_sum(nnext);
-  inedges = wave_sum(inedges);
-  if (lane == 0) {
+  if (g == 0) {
     if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
-    if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
     if (inedges) atomicAdd(&a.ctr[C_PULL_EDGES], inedges);
   }
+  __syncthreads();
+  if (tid < kLanes && ((s_nz >> tid) & 1ull)) a.has_next[a.lane_slot[tid]] = 1;
 }
 
-// Finishes the long-row targets of the pulled slots from their raw sums.
-__global__ void __launch_bounds__(kBlock) k_pull_fin(ExpandArgs a, const int32_t* __restrict__ pull_list) {
-  __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
+// Finishes the targets with long in-rows from their raw partial sums.
+__global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
+  __shared__ unsigned long long s_nz;
+  const unsigned long long ghi = a.ctr[C_GHI], gw = a.ctr[C_GW];
+  if (ghi == 0) return;
   const int tid = threadIdx.x;
-  const int lane = lane_id();
-  WaveBuf wb{s_buf[tid >> 6], 0u};
-  unsigned long long nfinal = 0, nnext = 0;
-  const unsigned long long npull = a.ctr[C_NPULL];
-  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + tid;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t pi = 0; pi < npull; ++pi) {
-    const int32_t s = pull_list[pi];
-    const Slot& sl = a.slots[s];
-    const unsigned long long nh = sl.heavy_cnt[0];
-    for (uint64_t i0 = gtid - lane; i0 < nh; i0 += stride) {
-      const uint64_t i = i0 + lane;
-      bool app = false;
-      int32_t v = 0;
-      if (i < nh) {
-        v = sl.heavy_nodes[i];
-        float* dn = a.dense_next + (size_t)s * a.n + v;
-        const float sum = *dn;
-        *dn = 0.0f;
-        if (sum > 0.0f && v != sl.excl) app = pull_finish(a, s, v, sum, sl, nfinal);
-      }
-      if (__ballot(app) && lane == 0) a.has_next[s] = 1;
-      wave_append(wb, app, s, v, a, nnext);
+  const int g = lane_id();
+  if (tid == 0) s_nz = 0ull;
+  __syncthreads();
+  const LaneInfo li = lane_info(a, g, ghi);
+  const DenseVer dv = *a.dv;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  unsigned long long nz_mask = 0, nfinal = 0;
+  const unsigned long long nh = dv.heavy_cnt[0];
+  for (uint64_t i = wave; i < nh; i += nwaves) {
+    const int32_t v = dv.heavy_nodes[i];
+    float sum = 0.0f;
+    if (li.active) {
+      float* p = a.npart + (size_t)v * kLanes + g;
+      sum = *p;
+      *p = 0.0f;
     }
+    const bool nz = dense_finish(a, li, g, v, sum, dv.inv_indeg[v], gw, nfinal);
+    nz_mask |= __ballot(nz);
   }
-  wave_flush(wb, a, nnext);
+  if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
-  nnext = wave_sum(nnext);
-  if (lane == 0) {
-    if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
-    if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
-  }
-}
-
-// Zeroes the dense score vectors of the slots pulled this step.
-__global__ void k_clear_pulled(int32_t n, float* __restrict__ dense_cur, const int32_t* __restrict__ pull_list,
-                               const unsigned long long* __restrict__ ctr) {
-  const unsigned long long npull = ctr[C_NPULL];
-  const uint64_t total = npull * (uint64_t)n;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (uint64_t)gridDim.x * blockDim.x) {
-    const int32_t s = pull_list[i / (uint64_t)n];
-    dense_cur[(size_t)s * n + (i % (uint64_t)n)] = 0.0f;
-  }
+  if (g == 0 && nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
+  __syncthreads();
+  if (tid < kLanes && ((s_nz >> tid) & 1ull)) a.has_next[a.lane_slot[tid]] = 1;
 }
 
 // s^(u, v) = acc / n_r (+ shift for v != u), s^(u, u) = 1.
@@ -985,7 +1089,7 @@ void devbuf_free(DevBuf& b) {
 
 void session_free(Session* s) {
   if (!s) return;
-  DevBuf* bufs[] = {&s->slot_edges, &s->pull_list, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
+  DevBuf* bufs[] = {&s->mat[0], &s->mat[1], &s->npart, &s->lane_slot, &s->dense_ver, &s->slot_edges, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
                     &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->keys,
                     &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
@@ -1037,8 +1141,12 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->slots, sizeof(Slot) * (size_t)P));
   PS_TRY(devbuf_reserve(s->has_next, sizeof(int32_t) * (size_t)P));
   PS_TRY(devbuf_reserve(s->slot_edges, sizeof(unsigned long long) * (size_t)P));
-  PS_TRY(devbuf_reserve(s->pull_list, sizeof(int32_t) * (size_t)P));
   PS_TRY(devbuf_reserve(s->pull_flag, sizeof(int32_t) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->mat[0], sizeof(float) * (size_t)n * kLanes));
+  PS_TRY(devbuf_reserve(s->mat[1], sizeof(float) * (size_t)n * kLanes));
+  PS_TRY(devbuf_reserve(s->npart, sizeof(float) * (size_t)n * kLanes));
+  PS_TRY(devbuf_reserve(s->lane_slot, sizeof(int32_t) * kLanes));
+  PS_TRY(devbuf_reserve(s->dense_ver, sizeof(DenseVer)));
   const bool fresh = !s->dense[0].p || shape;
   PS_TRY(devbuf_reserve(s->dense[0], sizeof(float) * s->list_cap));
   PS_TRY(devbuf_reserve(s->dense[1], sizeof(float) * s->list_cap));
@@ -1067,6 +1175,9 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
     PS_HIP(hipMemsetAsync(s->dense[0].p, 0, sizeof(float) * s->list_cap, st));
     PS_HIP(hipMemsetAsync(s->dense[1].p, 0, sizeof(float) * s->list_cap, st));
   }
+  for (DevBuf* b : {&s->mat[0], &s->mat[1], &s->npart})
+    PS_HIP(hipMemsetAsync(b->p, 0, sizeof(float) * (size_t)n * kLanes, st));
+  k_reset_lanes<<<1, kLanes, 0, st>>>(s->lane_slot.as<int32_t>());
   PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
   k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(s->slots.as<Slot>(), s->has_next.as<int32_t>(), P);
   PS_HIP(hipGetLastError());
@@ -1252,6 +1363,7 @@ StepKernels step_args(Session* s) {
   sa.done_ring = s->done_ring.as<int32_t>();
   sa.list_cap = s->list_cap;
   sa.slot_edges = s->slot_edges.as<unsigned long long>();
+  sa.lane_slot = s->lane_slot.as<int32_t>();
   sa.ctr = ctr;
   ExpandArgs& ea = k.ea;
   ea.pull_flag = s->pull_flag.as<int32_t>();
@@ -1279,21 +1391,32 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
                                        s->item_val.as<float>(), s->item_row.as<uint2>(), s->chunk_list.as<int2>(),
                                        s->list_cap, s->chunk_cap, s->slot_edges.as<unsigned long long>(), ctr, cur);
-  k_pick<<<1, kSchedThreads, 0, st>>>(s->P, s->slot_edges.as<unsigned long long>(), s->pull_flag.as<int32_t>(),
-                                      s->pull_list.as<int32_t>(), ctr);
+  k_pick<<<1, kSchedThreads, 0, st>>>(s->P, s->slot_edges.as<unsigned long long>(), s->slots.as<Slot>(),
+                                      s->pull_flag.as<int32_t>(), s->lane_slot.as<int32_t>(),
+                                      s->dense_ver.as<DenseVer>(), ctr);
   k.ea.list_cur = s->list[cur].as<int2>();
   k.ea.cur = cur;
   k.ea.dense_cur = s->dense[cur].as<float>();
+  k.ea.mat_cur = s->mat[cur].as<float>();
   k.ea.dense_next = s->dense[nxt].as<float>();
   k.ea.list_next = s->list[nxt].as<int2>();
   k.ea.nxt = nxt;
   if (ev0) (void)hipEventRecord(ev0, st);
   k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
   if (ev1) (void)hipEventRecord(ev1, st);
-  k_pull<<<kStepGrid, kBlock, 0, st>>>(k.ea, s->pull_list.as<int32_t>());
-  k_pull_fin<<<kStepGrid / 4, kBlock, 0, st>>>(k.ea, s->pull_list.as<int32_t>());
+  DenseArgs da{};
+  da.n = s->n;
+  da.slots = s->slots.as<Slot>();
+  da.lane_slot = s->lane_slot.as<int32_t>();
+  da.dv = s->dense_ver.as<DenseVer>();
+  da.mat_cur = s->mat[cur].as<float>();
+  da.mat_next = s->mat[nxt].as<float>();
+  da.npart = s->npart.as<float>();
+  da.has_next = s->has_next.as<int32_t>();
+  da.ctr = ctr;
+  k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
+  k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
   if (ev2) (void)hipEventRecord(ev2, st);
-  k_clear_pulled<<<kStepGrid, kBlock, 0, st>>>(s->n, s->dense[cur].as<float>(), s->pull_list.as<int32_t>(), ctr);
 }
 
 }  // namespace
@@ -1441,7 +1564,7 @@ ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun&
 uint64_t pull_threshold(int64_t m, int64_t opt) {
   if (opt < 0) return ~0ull;
   if (opt > 0) return (uint64_t)opt;
-  return std::max<uint64_t>((uint64_t)m / 4, 4096);
+  return std::max<uint64_t>((uint64_t)m / 64, 4096);
 }
 
 ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold) {

@@ -148,7 +148,7 @@ struct Slot {
   float thr;       // Rule 2: entries with score <= thr are removed
   float sc;        // sqrt(c)
   int32_t last;    // this level's expansion produces the returned score set
-  int32_t pad;
+  int32_t lane;    // column of the dense frontier matrix, -1 for a sparse frontier
   double w;        // number of walks sharing the probed prefix
   const uint2* out_rows;
   const int32_t* out_col;
@@ -178,10 +178,12 @@ enum CounterIdx {
   C_FINAL,
   C_LEVEL0,
   C_OVERFLOW,
-  C_NPULL,       // slots pulled this step
-  C_PULLS,       // probe levels computed by pulling
-  C_PULL_EDGES,  // in-edges read by pulls
-  C_PULL_T,      // pull threshold in out-edges (set by the host)
+  C_GHI,         // dense lanes in use this step: 1 + highest active lane
+  C_GW,          // dense columns written this step (covers lanes freed last step)
+  C_GPREV,       // C_GHI of the previous step
+  C_PULLS,       // probe levels computed by the dense pass
+  C_PULL_EDGES,  // in-edges read by dense passes
+  C_PULL_T,      // dense threshold in out-edges (set by the host)
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
   C_COUNT = C_HIST_E + 32
@@ -202,7 +204,8 @@ struct Session {
   uint64_t list_cap = 0, chunk_cap = 0;
   uint64_t tree_pool = 0;   // entries
   uint64_t ring_cap = 0;    // power of two
-  DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_list, pull_flag;
+  DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_flag;
+  DevBuf mat[2], npart, lane_slot, dense_ver;  // dense frontier lanes
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp;
