@@ -1574,7 +1574,7 @@ ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun&
 uint64_t pull_threshold(int64_t m, int64_t opt) {
   if (opt < 0) return ~0ull;
   if (opt > 0) return (uint64_t)opt;
-  return std::max<uint64_t>((uint64_t)m / 64, 4096);
+  return std::max<uint64_t>((uint64_t)m / 20, 4096);
 }
 
 ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold) {
