@@ -918,35 +918,25 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   const DenseVer dv = *a.dv;
   const float* m = a.mat_cur + g;
   unsigned long long nz_mask = 0, nfinal = 0, inedges = 0;
-  // Four consecutive targets per wavefront at a time: four independent
-  // load chains keep more rows in flight than one target would.
-  constexpr int kV = 4;
-  for (uint64_t v0 = wave * kV; v0 < (uint64_t)a.n; v0 += nwaves * kV) {
-    uint2 row[kV];
-    float sum[kV];
-    uint32_t kmax = 0;
-#pragma unroll
-    for (int i = 0; i < kV; ++i) {
-      row[i] = v0 + i < (uint64_t)a.n ? dv.in_rows[v0 + i] : make_uint2(0u, 0u);
-      if (row[i].y > kPullLane) row[i].y = kBigFlag;  // long in-row: chunks + k_dense_fin
-      sum[i] = 0.0f;
-      if (row[i].y != kBigFlag) kmax = max(kmax, row[i].y);
-    }
+  for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
+    const uint2 row = dv.in_rows[v];
+    if (row.y > kPullLane) continue;  // long in-row: chunks + k_dense_fin
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
     if (li.active) {
-      for (uint32_t k = 0; k < kmax; ++k) {
-#pragma unroll
-        for (int i = 0; i < kV; ++i)
-          if (k < row[i].y && row[i].y != kBigFlag)
-            sum[i] += pruned(m[(size_t)dv.in_col[row[i].x + k] * kLanes], li.thr);
+      uint32_t k = 0;
+      for (; k + 4 <= row.y; k += 4) {
+        const int32_t x0 = dv.in_col[row.x + k], x1 = dv.in_col[row.x + k + 1];
+        const int32_t x2 = dv.in_col[row.x + k + 2], x3 = dv.in_col[row.x + k + 3];
+        s0 += pruned(m[(size_t)x0 * kLanes], li.thr);
+        s1 += pruned(m[(size_t)x1 * kLanes], li.thr);
+        s2 += pruned(m[(size_t)x2 * kLanes], li.thr);
+        s3 += pruned(m[(size_t)x3 * kLanes], li.thr);
       }
+      for (; k < row.y; ++k) s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
     }
-#pragma unroll
-    for (int i = 0; i < kV; ++i) {
-      if (v0 + i >= (uint64_t)a.n || row[i].y == kBigFlag) continue;
-      inedges += row[i].y;
-      const bool nz = dense_finish(a, li, g, (int32_t)(v0 + i), sum[i], dv.inv_indeg[v0 + i], gw, nfinal);
-      nz_mask |= __ballot(nz);
-    }
+    inedges += row.y;
+    const bool nz = dense_finish(a, li, g, (int32_t)v, (s0 + s1) + (s2 + s3), dv.inv_indeg[v], gw, nfinal);
+    nz_mask |= __ballot(nz);
   }
   const unsigned long long nch = dv.heavy_cnt[1];
   for (uint64_t c = wave; c < nch; c += nwaves) {
