@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
     ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,6 +150,13 @@ def main():
     ctx = ps.Context(0, stream=stream)
     G = ps.Graph(ctx, n, s, d)
     out = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    tune = None
+    if not args.no_autotune and not args.slots and not args.pull:
+        # launch settings only (results do not depend on them); outside the timed region
+        t0 = time.perf_counter()
+        tune = ps.ps_autotune(G, graphs.query_nodes(n, d, 2, seed=99), C, EPS, DELTA)
+        tune["seconds"] = time.perf_counter() - t0
+        print(f"autotune: {tune}", file=sys.stderr, flush=True)
     ctx.set_timing(True)
 
     def plain_step(acc, tag):
@@ -214,6 +222,7 @@ def main():
         "config": {"workload": "Chung-Lu directed power-law graph, 1M nodes, 10M edges, exponent 2.1; "
                                "32 uniform query nodes with in-edges run one at a time; c=0.6, eps=0.05, "
                                "delta=0.01", "queries_per_step": len(q)},
+        "autotune": tune,
         "batched_qps": batched_qps,
         "batched_speedup": batched_qps / qps,
         "roofline": {"bound": "hbm", "kernel": "k_expand", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -194,6 +194,27 @@ typedef struct ps_result {
  * argument errors are reported in r[i].status and do not stop the others. */
 ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* q, const ps_options* opt, ps_result* r);
 
+/* ------------------------------------------------------------ tuning -- */
+
+typedef struct ps_tune {
+  int32_t slots;       /* probe slots chosen */
+  int32_t from_cache;  /* 1 when read from the cache file */
+  int64_t dense_edges; /* dense-level threshold chosen (< 0: never) */
+  double ms_per_query; /* measured time of the chosen setting */
+} ps_tune;
+
+/* Autotuner of the launch settings that do not change results (beyond
+ * floating-point summation order): the number of probe slots and the
+ * out-edge threshold above which a probe level moves to the dense pass.  It
+ * times the nsample query nodes `nodes` (host array) as plain single-source
+ * queries under each candidate setting (one untimed run first) and keeps the
+ * fastest as this context's automatic setting (ps_options fields left at 0).
+ * With cache_path non-NULL the choice is looked up in / appended to that text
+ * file, keyed by the graph's n and m and the query's eps.  The context must
+ * not have a running server. */
+ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double c, double eps, double delta,
+                      const char* cache_path, ps_tune* out);
+
 /* Work counters and timings of the last query call on this context. */
 typedef struct ps_stats {
   int64_t queries;

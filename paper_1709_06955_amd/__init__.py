@@ -31,7 +31,7 @@ EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
     "ps_graph_free", "ps_graph_info", "ps_graph_update", "ps_graph_edges", "ps_options_default",
     "ps_derive_params", "ps_walks", "ps_single_source", "ps_topk", "ps_batch", "ps_get_stats",
-    "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop",
+    "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
 ]
 
 
@@ -81,6 +81,11 @@ class Query(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("scores", C.c_void_p), ("nodes", C.c_void_p), ("status", C.c_int32), ("count", C.c_int32)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("from_cache", C.c_int32), ("dense_edges", C.c_int64),
+                ("ms_per_query", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -143,6 +148,7 @@ def load_library(path: str = LIB_PATH):
         "ps_wait": ([vp, C.c_uint64, C.c_int64], C.c_int),
         "ps_server_update": ([vp, C.c_int64, vp, vp, vp], C.c_int),
         "ps_server_stop": ([vp], C.c_int),
+        "ps_autotune": ([vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, C.c_char_p, P(Tune)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -292,6 +298,16 @@ def ps_topk(g: Graph, u, k, c, eps, delta, seed, out_nodes=None, out_scores=None
     _check(load_library().ps_topk(g._h, int(u), int(k), c, eps, delta, C.c_uint64(seed), C.byref(o),
                                   _ptr(nodes), _ptr(scores)), "ps_topk")
     return nodes, scores
+
+
+def ps_autotune(g: Graph, nodes, c, eps, delta, cache_path=None) -> dict:
+    """Times sample queries under candidate slot counts and dense thresholds
+    and keeps the fastest as the context's automatic setting."""
+    nd = np.ascontiguousarray(nodes, dtype=np.int32)
+    t = Tune()
+    _check(load_library().ps_autotune(g._h, int(nd.size), nd.ctypes.data, c, eps, delta,
+                                      cache_path.encode() if cache_path else None, C.byref(t)), "ps_autotune")
+    return {k: getattr(t, k) for k, _ in t._fields_}
 
 
 def ps_batch(g: Graph, queries, outs=None, **opt):

@@ -1,5 +1,6 @@
 // C ABI entry points: contexts, parameters, queries, statistics.
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -146,7 +147,11 @@ ps_status run_locked(ps_graph* g, const std::vector<QueryRun>& qs, const std::ve
   std::lock_guard<std::mutex> lk(ctx->mu);
   PS_HIP(hipSetDevice(ctx->device));
   GraphVersion* gv = graph_acquire(g);
-  ps_status s = engine_run(ctx, g, gv, qs, outs, opt ? opt->slots : 0, opt ? opt->pull_edges : 0);
+  int slots = opt ? opt->slots : 0;
+  int64_t dense = opt ? opt->pull_edges : 0;
+  if (slots == 0) slots = ctx->tuned_slots;
+  if (dense == 0) dense = ctx->tuned_dense;
+  ps_status s = engine_run(ctx, g, gv, qs, outs, slots, dense);
   graph_release(g, gv);
   return s;
 }
@@ -221,5 +226,102 @@ extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const
 extern "C" ps_status ps_get_stats(ps_ctx* c, ps_stats* out) {
   if (!c || !out) return PS_ERR_INVALID_ARG;
   *out = c->last;
+  return PS_OK;
+}
+
+// ------------------------------------------------------------ autotuner --
+
+namespace {
+
+bool cache_lookup(const char* path, int32_t n, int64_t m, double eps, ps_tune* out) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  long long cn, cm, cd;
+  int cs;
+  double ce, cms;
+  bool hit = false;
+  while (fscanf(f, "%lld %lld %lf %d %lld %lf", &cn, &cm, &ce, &cs, &cd, &cms) == 6) {
+    if (cn == n && cm == m && std::fabs(ce - eps) < 1e-12) {
+      out->slots = cs;
+      out->dense_edges = cd;
+      out->ms_per_query = cms;
+      hit = true;
+    }
+  }
+  fclose(f);
+  return hit;
+}
+
+}  // namespace
+
+extern "C" ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double c, double eps,
+                                 double delta, const char* cache_path, ps_tune* out) {
+  if (!g || nsample <= 0 || !nodes || !out) return PS_ERR_INVALID_ARG;
+  ps_ctx* ctx = g->ctx;
+  memset(out, 0, sizeof(*out));
+  if (cache_path && cache_lookup(cache_path, g->n, g->m, eps, out)) {
+    ctx->tuned_slots = out->slots;
+    ctx->tuned_dense = out->dense_edges;
+    out->from_cache = 1;
+    return PS_OK;
+  }
+  std::vector<QueryRun> qs;
+  for (int32_t i = 0; i < nsample; ++i) {
+    QueryRun q;
+    PS_TRY(make_query_run(g, nodes[i], 0, c, eps, delta, (uint64_t)(7 + i), nullptr, &q));
+    qs.push_back(q);
+  }
+  double* dout = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    PS_HIP(hipSetDevice(ctx->device));
+    PS_HIP(hipMalloc(&dout, sizeof(double) * (size_t)g->n));
+  }
+  const int max_slots = session_slots_for(g->n, 0);
+  std::vector<int> slot_c = {max_slots};
+  if (max_slots >= 1024) slot_c.push_back(512);
+  const int64_t m = std::max<int64_t>(g->m, 1);
+  const std::vector<int64_t> dense_c = {m / 40, m / 20, m / 10, -1};
+  double best = 1e300;
+  ps_status st = PS_OK;
+  for (int sl : slot_c) {
+    for (int64_t de : dense_c) {
+      if (de == 0) continue;
+      double ms = 0.0;
+      for (int rep = 0; rep < 2 && st == PS_OK; ++rep) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (auto& q : qs) {
+          QueryOut o;
+          o.scores = dout;
+          std::lock_guard<std::mutex> lk(ctx->mu);
+          GraphVersion* gv = graph_acquire(g);
+          st = engine_run(ctx, g, gv, {q}, {o}, sl, de);
+          graph_release(g, gv);
+          if (st != PS_OK) break;
+        }
+        if (rep == 1)
+          ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / nsample;
+      }
+      if (st != PS_OK) break;
+      if (ms < best) {
+        best = ms;
+        out->slots = sl;
+        out->dense_edges = de;
+        out->ms_per_query = ms;
+      }
+    }
+  }
+  (void)hipFree(dout);
+  if (st != PS_OK) return st;
+  ctx->tuned_slots = out->slots;
+  ctx->tuned_dense = out->dense_edges;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%d %lld %.17g %d %lld %.6f\n", g->n, (long long)g->m, eps, out->slots, (long long)out->dense_edges,
+              out->ms_per_query);
+      fclose(f);
+    }
+  }
   return PS_OK;
 }

@@ -229,6 +229,8 @@ struct ps_ctx {
   bool own_stream = false;
   bool timing = false;
   Session* sess = nullptr;
+  int tuned_slots = 0;        // autotuned probe slots (0: none)
+  int64_t tuned_dense = 0;    // autotuned dense threshold (0: none)
   ps_stats last{};
   std::vector<hipEvent_t> ev_pool;
   std::mutex mu;

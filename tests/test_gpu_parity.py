@@ -356,3 +356,18 @@ def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
         assert st["pull_levels"] == 0
     ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11)
     _parity(gpu, ref, ost, f"pull_edges={pull}")
+
+
+def test_autotune_keeps_results(ps, ctx, cl20k, orc, tmp_path):
+    # The autotuner only picks launch settings; estimates must not change.
+    n, s, d, G, O = cl20k
+    qn = graphs.query_nodes(n, d, 2, seed=47)
+    cache = str(tmp_path / "tune.txt")
+    t = ps.ps_autotune(G, qn, 0.6, 0.1, 0.01, cache_path=cache)
+    assert t["slots"] > 0 and t["dense_edges"] != 0 and t["from_cache"] == 0
+    t2 = ps.ps_autotune(G, qn, 0.6, 0.1, 0.01, cache_path=cache)
+    assert t2["from_cache"] == 1 and t2["slots"] == t["slots"] and t2["dense_edges"] == t["dense_edges"]
+    u = int(qn[0])
+    gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 19)
+    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19)
+    _parity(gpu, ref, st, f"autotuned {t}")
