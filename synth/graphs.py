@@ -58,11 +58,12 @@ def chung_lu_weights(n: int, m: int, gamma: float) -> np.ndarray:
     return w
 
 
-def chung_lu(n: int, m: int, gamma: float, seed: int = 1, batch: int = 1 << 24):
+def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
     """Directed Chung-Lu graph: src ~ w_out, dst ~ w_in with independent
     seeded permutations of the same power-law weights; self-loops and
-    duplicates rejected, topped up to exactly m edges.  Returns (src, dst)
-    int32 arrays sorted by (src, dst)."""
+    duplicates rejected.  Draws about 10% more pairs than needed, keeps the
+    distinct non-loop ones, tops up if short and keeps a seeded uniform subset
+    of exactly m.  Returns (src, dst) int32 arrays sorted by (src, dst)."""
     rng = _rng(seed, 2)
     w = chung_lu_weights(n, m, gamma)
     w_out = np.empty(n)
@@ -73,17 +74,33 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1, batch: int = 1 << 24):
     cdf_out /= cdf_out[-1]
     cdf_in = np.cumsum(w_in)
     cdf_in /= cdf_in[-1]
-    keys = np.empty(0, dtype=np.int64)
+    del w_out, w_in
+
+    def draw(count):
+        # Sorted uniforms make the inverse-CDF searches sequential; pairing the
+        # sorted sources with a random permutation of the targets gives the
+        # same distribution as independent pairs.
+        keys = np.empty(count, dtype=np.int64)
+        step = 1 << 24
+        for a in range(0, count, step):
+            b = min(count, a + step)
+            src = np.searchsorted(cdf_out, np.sort(rng.random(b - a)), side="right")
+            dst = np.searchsorted(cdf_in, np.sort(rng.random(b - a)), side="right")[rng.permutation(b - a)]
+            np.minimum(src, n - 1, out=src)
+            np.minimum(dst, n - 1, out=dst)
+            k = src.astype(np.int64) * n + dst
+            k[src == dst] = -1
+            keys[a:b] = k
+        return keys
+
+    keys = np.unique(draw(int(m * 1.1) + 1024))
+    keys = keys[keys >= 0]
     while keys.size < m:
-        need = m - keys.size
-        draw = min(batch, max(4096, int(need * 1.3) + 64))
-        s = np.searchsorted(cdf_out, rng.random(draw), side="right").astype(np.int64)
-        d = np.searchsorted(cdf_in, rng.random(draw), side="right").astype(np.int64)
-        np.minimum(s, n - 1, out=s)
-        np.minimum(d, n - 1, out=d)
-        ok = s != d
-        keys = _unique_in_draw_order(np.concatenate([keys, s[ok] * n + d[ok]]))
-    keys = np.sort(keys[:m])
+        more = draw(int((m - keys.size) * 2) + 1024)
+        keys = np.unique(np.concatenate([keys, more[more >= 0]]))
+    if keys.size > m:
+        keep = np.sort(rng.choice(keys.size, size=m, replace=False))
+        keys = keys[keep]
     return (keys // n).astype(np.int32), (keys % n).astype(np.int32)
 
 
