@@ -114,7 +114,10 @@ typedef struct ps_options {
   int64_t walk_end;   /* one past the last walk index; < 0: n_r.  A sub-range
                          returns that range's share of the sum over walks
                          (still divided by the full n_r), so shards add up. */
-  int32_t slots;      /* concurrent probes on the device; 0: automatic */
+  int32_t slots;      /* concurrent probes on the device; 0: the graph's autotuned
+                         setting, else automatic (up to 1024).  Clamped so that
+                         the per-slot buffers (44 B per slot and node) fit in
+                         48 GiB. */
   int32_t reserved;
   int64_t pull_edges; /* a probe level whose kept entries have at least this many
                          out-edges is computed by pulling along in-edges over
@@ -185,6 +188,12 @@ typedef struct ps_result {
   int32_t* nodes; /* k node ids for top-k; unused for single-source */
   int32_t status; /* ps_status of this query */
   int32_t count;  /* entries written */
+  double flip_allowance; /* how far FP32 rounding may move an estimate through
+                            Rule 2: the sum, over pruning tests whose score fell
+                            within 1e-5 relative of the threshold, of
+                            eps_p * (walks sharing the probe) / n_r.  A run
+                            and the FP64 definition agree within 1e-5 plus it;
+                            two runs within 1e-5 plus both allowances. */
 } ps_result;
 
 /* Runs nq queries together: all their walks, trees and probes share the
@@ -208,7 +217,8 @@ typedef struct ps_tune {
  * out-edge threshold above which a probe level moves to the dense pass.  It
  * times the nsample query nodes `nodes` (host array) as plain single-source
  * queries under each candidate setting (one untimed run first) and keeps the
- * fastest as this context's automatic setting (ps_options fields left at 0).
+ * fastest as this graph's automatic setting (ps_options fields left at 0,
+ * and servers started on it afterwards).
  * With cache_path non-NULL the choice is looked up in / appended to that text
  * file, keyed by the graph's n and m and the query's eps.  The context must
  * not have a running server. */
@@ -231,6 +241,8 @@ typedef struct ps_stats {
   int64_t expand_launches;  /* PROBE expansion (push) kernel launches */
   int64_t pull_levels;      /* probe levels computed by pulling */
   int64_t pull_edges;       /* in-edges read by those pulls */
+  int64_t near_threshold;   /* Rule 2 tests within 1e-5 relative of the threshold */
+  double flip_allowance;    /* largest per-query allowance of the call (ps_result) */
   double expand_ms;         /* summed duration of the push launches (timing enabled) */
   double pull_ms;           /* summed duration of the pull launches (timing enabled) */
   double total_ms;          /* wall time of the call */
@@ -247,7 +259,7 @@ ps_status ps_get_stats(ps_ctx* ctx, ps_stats* out);
 typedef struct ps_server_cfg {
   int32_t ring;           /* request ring capacity (0: 1024) */
   int32_t max_inflight;   /* queries admitted on the device at once (0: 64) */
-  int32_t slots;          /* probe slots (0: automatic) */
+  int32_t slots;          /* probe slots (0: the graph's autotuned setting, else automatic) */
   int32_t reserved;
   int64_t frontier_bytes; /* device memory budget for admitted queries (0: automatic) */
 } ps_server_cfg;
@@ -270,8 +282,10 @@ ps_status ps_submit(ps_server* s, const ps_query* q, ps_result* r, uint64_t* tic
 ps_status ps_wait(ps_server* s, uint64_t ticket, int64_t timeout_us);
 
 /* Queues edge updates (as ps_graph_update); they are applied between level
- * steps.  A query sees the graph version current when it was admitted.
- * Thread-safe; the arrays are copied. */
+ * steps.  A query reads exactly the edge set left by the updates submitted
+ * before it (submission order is the order in which ps_submit and
+ * ps_server_update calls take the server's lock); queries already running
+ * keep their version.  Thread-safe; the arrays are copied. */
 ps_status ps_server_update(ps_server* s, int64_t k, const int32_t* src, const int32_t* dst,
                            const uint8_t* op);
 

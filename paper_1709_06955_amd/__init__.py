@@ -63,8 +63,9 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "queries", "walks", "walk_nodes", "tree_nodes", "probe_levels", "steps", "entries_expanded",
         "entries_pruned", "edges_scanned", "next_entries", "final_adds", "expand_launches", "pull_levels",
-        "pull_edges")] + [("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double),
-                          ("level_hist_count", C.c_int64 * 32), ("level_hist_edges", C.c_int64 * 32)]
+        "pull_edges", "near_threshold")] + [
+        ("flip_allowance", C.c_double), ("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double),
+        ("level_hist_count", C.c_int64 * 32), ("level_hist_edges", C.c_int64 * 32)]
 
     def as_dict(self):
         d = {}
@@ -80,7 +81,8 @@ class Query(C.Structure):
 
 
 class Result(C.Structure):
-    _fields_ = [("scores", C.c_void_p), ("nodes", C.c_void_p), ("status", C.c_int32), ("count", C.c_int32)]
+    _fields_ = [("scores", C.c_void_p), ("nodes", C.c_void_p), ("status", C.c_int32), ("count", C.c_int32),
+                ("flip_allowance", C.c_double)]
 
 
 class Tune(C.Structure):
@@ -302,7 +304,7 @@ def ps_topk(g: Graph, u, k, c, eps, delta, seed, out_nodes=None, out_scores=None
 
 def ps_autotune(g: Graph, nodes, c, eps, delta, cache_path=None) -> dict:
     """Times sample queries under candidate slot counts and dense thresholds
-    and keeps the fastest as the context's automatic setting."""
+    and keeps the fastest as the graph's automatic setting."""
     nd = np.ascontiguousarray(nodes, dtype=np.int32)
     t = Tune()
     _check(load_library().ps_autotune(g._h, int(nd.size), nd.ctypes.data, c, eps, delta,
@@ -310,9 +312,17 @@ def ps_autotune(g: Graph, nodes, c, eps, delta, cache_path=None) -> dict:
     return {k: getattr(t, k) for k, _ in t._fields_}
 
 
+class BatchResults(list):
+    """Per-query results of ps_batch; `flip_allowance[i]` is query i's
+    Rule-2 near-threshold allowance (ps_result.flip_allowance)."""
+
+    flip_allowance: list
+
+
 def ps_batch(g: Graph, queries, outs=None, **opt):
     """queries: list of dicts (u, k, c, eps, delta, seed).  Returns a list of
-    score arrays (single-source) or (nodes, scores) pairs (top-k)."""
+    score arrays (single-source) or (nodes, scores) pairs (top-k), with the
+    per-query allowances in its `flip_allowance` attribute."""
     nq = len(queries)
     qa = (Query * max(nq, 1))()
     ra = (Result * max(nq, 1))()
@@ -330,10 +340,12 @@ def ps_batch(g: Graph, queries, outs=None, **opt):
         ra[i].nodes = _ptr(nd) if nd is not None else None
     o = options(**opt)
     _check(load_library().ps_batch(g._h, nq, qa, C.byref(o), ra), "ps_batch")
-    res = []
+    res = BatchResults()
+    res.flip_allowance = []
     for i, (sc, nd) in enumerate(keep):
         _check(ra[i].status, f"query {i}")
         res.append(sc if nd is None else (nd, sc))
+        res.flip_allowance.append(ra[i].flip_allowance)
     return res
 
 
@@ -354,7 +366,7 @@ class Server:
             sc, nd = np.zeros(k, np.float64), np.zeros(k, np.int32)
         else:
             sc, nd = np.zeros(self.g.n, np.float64), None
-        r = Result(sc.ctypes.data, nd.ctypes.data if nd is not None else None, 0, 0)
+        r = Result(sc.ctypes.data, nd.ctypes.data if nd is not None else None, 0, 0, 0.0)
         t = C.c_uint64()
         code = load_library().ps_submit(self._h, C.byref(q), C.byref(r), C.byref(t))
         if code != PS_OK:
@@ -362,13 +374,16 @@ class Server:
         self._pending[t.value] = (q, r, sc, nd)
         return t.value
 
-    def wait(self, ticket, timeout_us=-1):
+    def wait(self, ticket, timeout_us=-1, allowance=False):
+        """The query's result; with allowance=True also its Rule-2
+        near-threshold allowance (ps_result.flip_allowance)."""
         code = load_library().ps_wait(self._h, C.c_uint64(ticket), int(timeout_us))
         if code == 9:
             raise TimeoutError(ticket)
         q, r, sc, nd = self._pending.pop(ticket)
         _check(code, f"ticket {ticket}")
-        return sc if nd is None else (nd, sc)
+        out = sc if nd is None else (nd, sc)
+        return (out, r.flip_allowance) if allowance else out
 
     def update(self, src, dst, op):
         s = np.ascontiguousarray(src, dtype=np.int32)

@@ -149,8 +149,8 @@ ps_status run_locked(ps_graph* g, const std::vector<QueryRun>& qs, const std::ve
   GraphVersion* gv = graph_acquire(g);
   int slots = opt ? opt->slots : 0;
   int64_t dense = opt ? opt->pull_edges : 0;
-  if (slots == 0) slots = ctx->tuned_slots;
-  if (dense == 0) dense = ctx->tuned_dense;
+  if (slots == 0) slots = g->tuned_slots;
+  if (dense == 0) dense = g->tuned_dense;
   ps_status s = engine_run(ctx, g, gv, qs, outs, slots, dense);
   graph_release(g, gv);
   return s;
@@ -206,10 +206,12 @@ extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const
     if (s == PS_OK && (!r[i].scores || (qv[i].k > 0 && !r[i].nodes))) s = PS_ERR_INVALID_ARG;
     r[i].status = s;
     r[i].count = 0;
+    r[i].flip_allowance = 0.0;
     if (s != PS_OK) continue;
     QueryOut o;
     o.scores = r[i].scores;
     o.nodes = r[i].nodes;
+    o.flip = &r[i].flip_allowance;
     qs.push_back(q);
     outs.push_back(o);
     which.push_back(i);
@@ -260,8 +262,8 @@ extern "C" ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* no
   ps_ctx* ctx = g->ctx;
   memset(out, 0, sizeof(*out));
   if (cache_path && cache_lookup(cache_path, g->n, g->m, eps, out)) {
-    ctx->tuned_slots = out->slots;
-    ctx->tuned_dense = out->dense_edges;
+    g->tuned_slots = out->slots;
+    g->tuned_dense = out->dense_edges;
     out->from_cache = 1;
     return PS_OK;
   }
@@ -313,8 +315,8 @@ extern "C" ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* no
   }
   (void)hipFree(dout);
   if (st != PS_OK) return st;
-  ctx->tuned_slots = out->slots;
-  ctx->tuned_dense = out->dense_edges;
+  g->tuned_slots = out->slots;
+  g->tuned_dense = out->dense_edges;
   if (cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {

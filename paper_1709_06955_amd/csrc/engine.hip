@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "ps_internal.h"
@@ -430,13 +431,15 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         st[r].heavy_nodes = Q.heavy_nodes;
         st[r].heavy_chunks = Q.heavy_chunks;
         st[r].heavy_cnt = Q.heavy_cnt;
+        st[r].flip = Q.flip;
+        st[r].flip_unit = Q.flip_unit * st[r].w;
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
           a.dense_cur[(size_t)s * a.n + x] = 1.0f;
           a.list_cur[pos] = make_int2(s, x);
         } else {
-          a.ctr[C_OVERFLOW] = 1;
+          atomicOr(&a.ctr[C_OVERFLOW], 1ull);
         }
         atomicAdd(&a.ctr[C_LEVEL0], 1ull);
       }
@@ -473,7 +476,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
   const int lane = lane_id();
   const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  unsigned long long kept = 0, pruned = 0, edges = 0;
+  unsigned long long kept = 0, pruned = 0, edges = 0, near = 0;
   for (uint64_t i0 = gtid - lane; i0 < cnt; i0 += stride) {
     const uint64_t i = i0 + lane;
     uint32_t nch = 0;
@@ -485,6 +488,10 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       const float val = *d;
       const Slot& sl = slots[it.x];
       uint2 row = make_uint2(0u, 0u);
+      if (fabsf(val - sl.thr) <= 1e-5f * sl.thr) {  // FP32 rounding may decide this test
+        ++near;
+        unsafeAtomicAdd(sl.flip, sl.flip_unit);
+      }
       if (val > sl.thr) {
         ++kept;
         row = sl.out_rows[it.y];
@@ -523,14 +530,16 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       if (first + nch <= chunk_cap) {
         for (uint32_t c = 0; c < nch; ++c) chunk_list[first + c] = make_int2((int32_t)i, (int32_t)c);
       } else if (nch) {
-        ctr[C_OVERFLOW] = 1;
+        atomicOr(&ctr[C_OVERFLOW], 2ull);
       }
     }
   }
   kept = wave_sum(kept);
   pruned = wave_sum(pruned);
   edges = wave_sum(edges);
+  near = wave_sum(near);
   if (lane == 0) {
+    if (near) atomicAdd(&ctr[C_NEAR], near);
     if (kept) atomicAdd(&ctr[C_KEPT], kept);
     if (pruned) atomicAdd(&ctr[C_PRUNED], pruned);
     if (edges) atomicAdd(&ctr[C_EDGES], edges);
@@ -656,7 +665,7 @@ __device__ __forceinline__ void wave_flush(WaveBuf& wb, const ExpandArgs& a, uns
   for (uint32_t k = (uint32_t)lane; k < wb.n; k += 64) {
     const unsigned long long pos = base + k;
     if (pos < a.list_cap) a.list_next[pos] = wb.buf[k];
-    else a.ctr[C_OVERFLOW] = 1;
+    else atomicOr(&a.ctr[C_OVERFLOW], 4ull);
   }
   if (lane == 0) nnext += wb.n;
   wb.n = 0;
@@ -856,6 +865,8 @@ struct LaneInfo {
   int32_t excl;
   double w;
   double* acc;
+  double* flip;
+  double flip_unit;
 };
 
 __device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigned long long ghi) {
@@ -872,6 +883,8 @@ __device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigne
       li.excl = sl.excl;
       li.w = sl.w;
       li.acc = sl.acc;
+      li.flip = sl.flip;
+      li.flip_unit = sl.flip_unit;
     }
   }
   return li;
@@ -890,6 +903,9 @@ __device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo&
       } else {
         out = c;
         nz = true;
+        // the next level tests this value against thr * sqrt(c)
+        const float t = li.thr * li.sc;
+        if (fabsf(c - t) <= 1e-5f * t) unsafeAtomicAdd(li.flip, li.flip_unit);
       }
     }
   }
@@ -1066,6 +1082,19 @@ void tree_release(Session* s, uint64_t start, uint64_t len) {
 
 }  // namespace
 
+void report_overflow(const Session* s, const uint64_t* h) {
+  std::fprintf(stderr,
+               "probesim: frontier capacity guard tripped (sites 0x%llx: 1 roots, 2 chunks, 4 next level); "
+               "P %d n %d list cap %llu (lists %llu, %llu) chunk cap %llu (chunks %llu)\n",
+               (unsigned long long)h[C_OVERFLOW], s->P, s->n, (unsigned long long)s->list_cap,
+               (unsigned long long)h[C_LIST0], (unsigned long long)h[C_LIST1], (unsigned long long)s->chunk_cap,
+               (unsigned long long)h[C_CHUNK]);
+}
+
+void session_clear_guard(Session* s, hipStream_t st) {
+  k_set_u64<<<1, 1, 0, st>>>(s->counters.as<unsigned long long>() + C_OVERFLOW, 0ull);
+}
+
 ps_status devbuf_reserve(DevBuf& b, size_t bytes) {
   if (bytes <= b.bytes && b.p) return PS_OK;
   if (b.p) (void)hipFree(b.p);
@@ -1074,6 +1103,7 @@ ps_status devbuf_reserve(DevBuf& b, size_t bytes) {
   const size_t want = std::max<size_t>(bytes, 256);
   if (hipMalloc(&b.p, want) != hipSuccess) {
     (void)hipGetLastError();
+    std::fprintf(stderr, "probesim: device allocation of %zu bytes failed\n", want);
     b.p = nullptr;
     return PS_ERR_OOM;
   }
@@ -1091,7 +1121,8 @@ void session_free(Session* s) {
   if (!s) return;
   DevBuf* bufs[] = {&s->mat[0], &s->mat[1], &s->npart, &s->lane_slot, &s->dense_ver, &s->slot_edges, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
                     &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
-                    &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->keys,
+                    &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
+                    &s->keys,
                     &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
                     &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp};
   for (DevBuf* b : bufs) devbuf_free(*b);
@@ -1101,15 +1132,15 @@ void session_free(Session* s) {
 }
 
 // Probe slots: enough concurrent probes to fill the GPU (more slots also
-// mean fewer level steps), bounded so that the per-slot buffers (dense
-// scores 8 B, frontier lists 16 B, scaled scores 4 B, rows 8 B, chunks 8 B
-// per node) stay within a fixed share of HBM and slot * n fits in 31 bits.
+// mean fewer level steps), at most 1024 by default, and never more than the
+// per-slot buffers (dense scores 8 B, frontier lists 16 B, scaled scores 4 B,
+// rows 8 B, chunks 8 B per node) fit in a fixed share of HBM, with slot * n
+// within 31 bits.  An explicit request is clamped the same way.
 int session_slots_for(int32_t n, int opt) {
-  if (opt > 0) return std::min(opt, kSchedThreads * kSlotsPerSchedThread);
   const uint64_t budget = 48ull << 30;
   uint64_t p = budget / (44ull * (uint64_t)n);
   p = std::min<uint64_t>(p, ((1ull << 31) - 1) / (uint64_t)n);
-  p = std::min<uint64_t>(p, 1024);
+  p = std::min<uint64_t>(p, opt > 0 ? (uint64_t)std::min(opt, kSchedThreads * kSlotsPerSchedThread) : 1024ull);
   return (int)std::max<uint64_t>(p, 1);
 }
 
@@ -1163,6 +1194,7 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->qbound, sizeof(unsigned long long) * (size_t)s->qmax));
   PS_TRY(devbuf_reserve(s->acc, sizeof(double) * (size_t)s->qmax * (size_t)n));
   PS_TRY(devbuf_reserve(s->lq, sizeof(int32_t) * (size_t)s->qmax));
+  PS_TRY(devbuf_reserve(s->flip, sizeof(double) * (size_t)s->qmax));
   PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
   PS_TRY(devbuf_reserve(s->t_parent, sizeof(int32_t) * (s->tree_pool + s->qmax)));
   PS_TRY(devbuf_reserve(s->t_node, sizeof(int32_t) * (s->tree_pool + s->qmax)));
@@ -1233,6 +1265,10 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     d.heavy_chunks = gv->heavy_chunks;
     d.heavy_cnt = gv->heavy_cnt;
     d.acc = s->acc.as<double>() + (size_t)r * (size_t)s->n;
+    d.flip = s->flip.as<double>() + r;
+    // one flip moves an estimate by at most Score * sqrt(c)^e ~ eps_p per
+    // walk sharing the probe (the near band is 1e-5 relative wide)
+    d.flip_unit = q.prm.eps_p * (1.0 + 1e-4) / (double)q.prm.n_r;
     total += d.walk_count;
     s->h_rec[(size_t)r] = d;
     {
@@ -1250,6 +1286,7 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     PS_HIP(hipMemsetAsync(d.acc, 0, sizeof(double) * (size_t)s->n, st));
     PS_HIP(hipMemsetAsync(s->qbound.as<unsigned long long>() + r, 0, sizeof(unsigned long long), st));
     PS_HIP(hipMemsetAsync(s->remaining.as<unsigned long long>() + r, 0, sizeof(unsigned long long), st));
+    PS_HIP(hipMemsetAsync(d.flip, 0, sizeof(double), st));
   }
   PS_HIP(hipMemcpyAsync(s->lq.p, recs->data(), sizeof(int32_t) * recs->size(), hipMemcpyHostToDevice, st));
   if (total > 0) {
@@ -1512,6 +1549,7 @@ ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, con
     PS_TRY(copy_out(out.scores, s->sort_keys[1].p, sizeof(double) * (size_t)q.k, st));
     PS_TRY(copy_out(out.nodes, s->sort_vals[1].p, sizeof(int32_t) * (size_t)q.k, st));
   }
+  if (out.flip) PS_TRY(copy_out(out.flip, s->flip.as<double>() + r, sizeof(double), st));
   // release the record (later users are ordered after these copies on the stream)
   auto tr = s->rec_tree[(size_t)r];
   tree_release(s, tr.first, tr.second);
@@ -1593,6 +1631,7 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   PS_TRY(session_ensure(ctx, n, m_cap, P, std::max(nq, s ? s->qmax : 0), s ? s->tree_pool : 0,
                         s ? s->ring_cap : 0));
   s = ctx->sess;
+  session_clear_guard(s, st);
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
   std::vector<uint64_t> before(s->h_ctr, s->h_ctr + C_COUNT);
@@ -1635,11 +1674,24 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   double expand_ms = 0.0, pull_ms = 0.0;
   PS_TRY(session_set_pull(ctx, pull_threshold(g->m, pull_opt)));
   PS_TRY(session_steps(ctx, steps, &expand_ms, &pull_ms));
-  for (int i = 0; i < nq; ++i) PS_TRY(session_finish(ctx, g, recs[(size_t)i], qs[(size_t)i], outs[(size_t)i]));
+  std::vector<double> flips((size_t)nq, 0.0);
+  for (int i = 0; i < nq; ++i) {
+    QueryOut o = outs[(size_t)i];
+    if (!o.flip) o.flip = &flips[(size_t)i];
+    PS_TRY(session_finish(ctx, g, recs[(size_t)i], qs[(size_t)i], o));
+  }
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < nq; ++i) {
+    const double f = outs[(size_t)i].flip && !ps_is_device_ptr(outs[(size_t)i].flip) ? *outs[(size_t)i].flip
+                                                                                       : flips[(size_t)i];
+    stats.flip_allowance = std::max(stats.flip_allowance, f);
+  }
   const uint64_t* h = s->h_ctr;
-  if (h[C_OVERFLOW]) return PS_ERR_OOM;  // impossible with worst-case capacities; a guard
+  if (h[C_OVERFLOW]) {  // impossible with worst-case capacities; a guard
+    report_overflow(s, h);
+    return PS_ERR_OOM;
+  }
   if (h[C_HEAD] != h[C_TAIL]) return PS_ERR_STATE;
   stats.walks = 0;
   for (auto& q : qs) stats.walks += q.walk_end - q.walk_begin;
@@ -1655,6 +1707,7 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   stats.expand_launches = (int64_t)steps;
   stats.pull_levels = (int64_t)(h[C_PULLS] - before[C_PULLS]);
   stats.pull_edges = (int64_t)(h[C_PULL_EDGES] - before[C_PULL_EDGES]);
+  stats.near_threshold = (int64_t)(h[C_NEAR] - before[C_NEAR]);
   stats.expand_ms = expand_ms;
   stats.pull_ms = pull_ms;
   for (int b = 0; b < 32; ++b) {

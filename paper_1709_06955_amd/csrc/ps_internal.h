@@ -83,6 +83,8 @@ struct ps_graph {
   GraphVersion* cur = nullptr;
   std::vector<GraphVersion*> retired;  // superseded versions still read by queries
   std::vector<GraphVersion*> spare;    // freed versions whose row arrays are reused
+  int tuned_slots = 0;                 // autotuned probe slots (0: none)
+  int64_t tuned_dense = 0;             // autotuned dense threshold (0: none)
   std::mutex mu;
 };
 
@@ -126,6 +128,8 @@ struct QueryDev {
   const int32_t* heavy_nodes;
   const int2* heavy_chunks;
   const unsigned long long* heavy_cnt;
+  double* flip;        // Rule-2 near-threshold allowance of the query
+  double flip_unit;    // eps_p / n_r (times a walk count when charged)
 };
 
 // Host view of a query.
@@ -159,6 +163,8 @@ struct Slot {
   const int32_t* heavy_nodes;
   const int2* heavy_chunks;
   const unsigned long long* heavy_cnt;
+  double* flip;      // the query's near-threshold allowance
+  double flip_unit;  // eps_p * w / n_r: what one Rule-2 flip can move an estimate by
 };
 
 enum CounterIdx {
@@ -184,6 +190,7 @@ enum CounterIdx {
   C_PULLS,       // probe levels computed by the dense pass
   C_PULL_EDGES,  // in-edges read by dense passes
   C_PULL_T,      // dense threshold in out-edges (set by the host)
+  C_NEAR,        // Rule 2 tests within 1e-5 relative of the threshold
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
   C_COUNT = C_HIST_E + 32
@@ -192,6 +199,7 @@ enum CounterIdx {
 struct QueryOut {
   double* scores = nullptr;  // n (single-source) or k (top-k); host or device
   int32_t* nodes = nullptr;  // k (top-k)
+  double* flip = nullptr;    // the query's near-threshold allowance (host or device)
 };
 
 // A persistent set of device buffers that runs the level steps of every
@@ -206,7 +214,7 @@ struct Session {
   uint64_t ring_cap = 0;    // power of two
   DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_flag;
   DevBuf mat[2], npart, lane_slot, dense_ver;  // dense frontier lanes
-  DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq;
+  DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
@@ -229,8 +237,6 @@ struct ps_ctx {
   bool own_stream = false;
   bool timing = false;
   Session* sess = nullptr;
-  int tuned_slots = 0;        // autotuned probe slots (0: none)
-  int64_t tuned_dense = 0;    // autotuned dense threshold (0: none)
   ps_stats last{};
   std::vector<hipEvent_t> ev_pool;
   std::mutex mu;
@@ -243,6 +249,10 @@ void ctx_release(ps_ctx* c);
 // requested shape exceeds the current one; only while no query is admitted.
 ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax, uint64_t tree_pool,
                          uint64_t ring_cap);
+// Prints which frontier capacity guard tripped (counters as read back).
+void report_overflow(const Session* s, const uint64_t* h);
+// Clears the capacity-guard flag (stream-ordered).
+void session_clear_guard(Session* s, hipStream_t st);
 void session_free(Session* s);
 int session_slots_for(int32_t n, int opt);
 // Admission, phase 1: takes records for the queries (all reading graph

@@ -12,6 +12,7 @@
 // through pinned staging buffers to a completer thread that copies them to
 // the caller's buffers and wakes ps_wait.
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 
@@ -26,11 +27,13 @@ struct Request {
   ps_query q;
   ps_result* r;
   uint64_t ticket;
+  uint64_t seq;  // submission order among requests and update batches
 };
 
 struct UpdateBatch {
   std::vector<int32_t> src, dst;
   std::vector<uint8_t> op;
+  uint64_t seq;
 };
 
 struct Staging {
@@ -59,6 +62,7 @@ struct ps_server {
   std::deque<UpdateBatch> updates;
   std::unordered_map<uint64_t, ps_status> finished;
   uint64_t next_ticket = 1;
+  uint64_t next_seq = 1;
   bool stopping = false;
   bool comp_stop = false;
   std::thread th, comp_th;
@@ -99,11 +103,13 @@ void completer(ps_server* s) {
     if (hipEventSynchronize(c.ev) != hipSuccess) st = PS_ERR_DEVICE;
     if (st == PS_OK && c.staging >= 0) {
       const Staging& sg = s->staging[(size_t)c.staging];
+      const char* host = (const char*)sg.host;
+      std::memcpy(&c.r->flip_allowance, host, sizeof(double));
       if (c.k > 0) {
-        std::memcpy(c.r->scores, sg.host, sizeof(double) * (size_t)c.k);
-        std::memcpy(c.r->nodes, (const char*)sg.host + sizeof(double) * (size_t)c.k, sizeof(int32_t) * (size_t)c.k);
+        std::memcpy(c.r->scores, host + sizeof(double), sizeof(double) * (size_t)c.k);
+        std::memcpy(c.r->nodes, host + sizeof(double) * (1 + (size_t)c.k), sizeof(int32_t) * (size_t)c.k);
       } else {
-        std::memcpy(c.r->scores, sg.host, sizeof(double) * (size_t)c.count);
+        std::memcpy(c.r->scores, host + sizeof(double), sizeof(double) * (size_t)c.count);
       }
     }
     c.r->status = st;
@@ -169,13 +175,16 @@ ps_status complete_record(ps_server* s, int r, Admitted& a) {
   Session* ss = ctx->sess;
   const int32_t n = ss->n;
   const int32_t k = a.run.k;
-  const size_t bytes = k > 0 ? (sizeof(double) + sizeof(int32_t)) * (size_t)k : sizeof(double) * (size_t)n;
+  // staging layout: allowance, scores, node ids
+  const size_t bytes =
+      sizeof(double) + (k > 0 ? (sizeof(double) + sizeof(int32_t)) * (size_t)k : sizeof(double) * (size_t)n);
   const int sid = take_staging(s, bytes);
   if (sid < 0) return PS_ERR_OOM;
   QueryOut out;
   char* host = (char*)s->staging[(size_t)sid].host;
-  out.scores = (double*)host;
-  out.nodes = k > 0 ? (int32_t*)(host + sizeof(double) * (size_t)k) : nullptr;
+  out.flip = (double*)host;
+  out.scores = (double*)(host + sizeof(double));
+  out.nodes = k > 0 ? (int32_t*)(host + sizeof(double) * (1 + (size_t)k)) : nullptr;
   PS_TRY(session_finish(ctx, s->g, r, a.run, out));
   Completion c;
   c.ev = take_event(s);
@@ -213,6 +222,7 @@ ps_status serve_loop(ps_server* s) {
   }
   int snap_i = 0;
   // completions of earlier direct calls on this session are not ours
+  session_clear_guard(ss, st);
   PS_HIP(hipMemcpyAsync(snap[0], ss->counters.p, sizeof(unsigned long long) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
   done_seen = snap[0][C_DONE];
@@ -228,15 +238,24 @@ ps_status serve_loop(ps_server* s) {
       if (idle() && s->ring.empty() && s->updates.empty())
         s->cv_work.wait(lk, [&] { return s->stopping || !s->ring.empty() || !s->updates.empty(); });
       stopping = s->stopping;
+      // A query reads exactly the edge set left by the updates submitted
+      // before it.  Updates older than the oldest waiting query may be
+      // applied at any time (they are coalesced for kUpdateIntervalMs);
+      // before that query is admitted they must be.  Admission stops at the
+      // next update in submission order, which a later iteration applies.
+      const int room = std::min(s->cfg.max_inflight - (int)admitted.size() - (int)waiting_build.size(),
+                                (int)ss->free_recs.size());
+      const bool admit = !s->ring.empty() && room > 0;
+      const uint64_t oldest = s->ring.empty() ? ~0ull : s->ring.front().seq;
       const double since = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - last_update).count();
-      if (since >= kUpdateIntervalMs || idle()) {
-        while (!s->updates.empty()) {
+      if (admit || since >= kUpdateIntervalMs || idle()) {
+        while (!s->updates.empty() && s->updates.front().seq < oldest) {
           ups.push_back(std::move(s->updates.front()));
           s->updates.pop_front();
         }
       }
-      const int room = s->cfg.max_inflight - (int)admitted.size() - (int)waiting_build.size();
-      while (!s->ring.empty() && (int)fresh.size() < room && (int)fresh.size() < (int)ss->free_recs.size()) {
+      while (admit && !s->ring.empty() && (int)fresh.size() < room &&
+             (s->updates.empty() || s->ring.front().seq < s->updates.front().seq)) {
         fresh.push_back(s->ring.front());
         s->ring.pop_front();
       }
@@ -346,6 +365,11 @@ ps_status serve_loop(ps_server* s) {
     if (snap_live[look]) {
       PS_HIP(hipEventSynchronize(snap_ev[look]));
       snap_live[look] = false;
+      if (snap[look][C_OVERFLOW]) {  // a capacity guard dropped frontier entries
+        report_overflow(ss, reinterpret_cast<const uint64_t*>(snap[look]));
+        fatal = PS_ERR_OOM;
+        break;
+      }
       const unsigned long long done = snap[look][C_DONE];
       for (; done_seen < done; ++done_seen) {
         const int r = snap_ring[look][done_seen % (unsigned long long)ss->qmax];
@@ -408,14 +432,14 @@ extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_s
     std::lock_guard<std::mutex> lk(ctx->mu);
     ps_status st = PS_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) st = PS_ERR_DEVICE;
-    const int P = session_slots_for(g->n, s->cfg.slots);
+    const int P = session_slots_for(g->n, s->cfg.slots ? s->cfg.slots : g->tuned_slots);
     // tree pool / ring sized for max_inflight queries of up to ~1M tree nodes
     const uint64_t per_q = 1ull << 21;
     const uint64_t pool = std::max<uint64_t>((uint64_t)s->cfg.max_inflight * per_q, 1ull << 22);
     if (st == PS_OK)
       st = session_ensure(ctx, g->n, std::max<uint64_t>(g->cur->out_store->cap, 1), P, s->cfg.max_inflight, pool,
                           pool / 2);
-    if (st == PS_OK) st = session_set_pull(ctx, pull_threshold(g->m, 0));
+    if (st == PS_OK) st = session_set_pull(ctx, pull_threshold(g->m, g->tuned_dense));
     if (st != PS_OK) {
       delete s;
       return st;
@@ -433,7 +457,7 @@ extern "C" ps_status ps_submit(ps_server* s, const ps_query* q, ps_result* r, ui
   if (s->stopping) return PS_ERR_STATE;
   if ((int)s->ring.size() >= s->cfg.ring) return PS_ERR_BUSY;
   *ticket = s->next_ticket++;
-  s->ring.push_back(Request{*q, r, *ticket});
+  s->ring.push_back(Request{*q, r, *ticket, s->next_seq++});
   s->cv_work.notify_one();
   return PS_OK;
 }
@@ -461,6 +485,7 @@ extern "C" ps_status ps_server_update(ps_server* s, int64_t k, const int32_t* sr
   b.op.assign(op, op + k);
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) return PS_ERR_STATE;
+  b.seq = s->next_seq++;
   s->updates.push_back(std::move(b));
   s->cv_work.notify_one();
   return PS_OK;

@@ -14,6 +14,9 @@ nodes drawn uniformly from the nodes of nonzero in-degree as in Section 5.1.
 
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 
@@ -62,8 +65,13 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
     """Directed Chung-Lu graph: src ~ w_out, dst ~ w_in with independent
     seeded permutations of the same power-law weights; self-loops and
     duplicates rejected.  Draws about 10% more pairs than needed, keeps the
-    distinct non-loop ones, tops up if short and keeps a seeded uniform subset
-    of exactly m.  Returns (src, dst) int32 arrays sorted by (src, dst)."""
+    distinct non-loop ones, tops up if short and drops a seeded uniform subset
+    of the surplus to keep exactly m.  Returns (src, dst) int32 arrays sorted
+    by (src, dst).
+
+    Pairs are drawn in chunks of 2^22, each from its own Philox stream, so the
+    chunks run on worker threads and the result does not depend on how many
+    there are."""
     rng = _rng(seed, 2)
     w = chung_lu_weights(n, m, gamma)
     w_out = np.empty(n)
@@ -75,32 +83,38 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
     cdf_in = np.cumsum(w_in)
     cdf_in /= cdf_in[-1]
     del w_out, w_in
+    step = 1 << 22
 
-    def draw(count):
+    def chunk(index, count):
         # Sorted uniforms make the inverse-CDF searches sequential; pairing the
         # sorted sources with a random permutation of the targets gives the
         # same distribution as independent pairs.
-        keys = np.empty(count, dtype=np.int64)
-        step = 1 << 24
-        for a in range(0, count, step):
-            b = min(count, a + step)
-            src = np.searchsorted(cdf_out, np.sort(rng.random(b - a)), side="right")
-            dst = np.searchsorted(cdf_in, np.sort(rng.random(b - a)), side="right")[rng.permutation(b - a)]
-            np.minimum(src, n - 1, out=src)
-            np.minimum(dst, n - 1, out=dst)
-            k = src.astype(np.int64) * n + dst
-            k[src == dst] = -1
-            keys[a:b] = k
-        return keys
+        r = _rng(seed, (1 << 20) + index)
+        src = np.searchsorted(cdf_out, np.sort(r.random(count)), side="right")
+        dst = np.searchsorted(cdf_in, np.sort(r.random(count)), side="right")[r.permutation(count)]
+        np.minimum(src, n - 1, out=src)
+        np.minimum(dst, n - 1, out=dst)
+        k = src.astype(np.int64) * n + dst
+        return k[src != dst]
+
+    next_chunk = 0
+
+    def draw(count):
+        nonlocal next_chunk
+        sizes = [min(step, count - a) for a in range(0, count, step)]
+        ids = range(next_chunk, next_chunk + len(sizes))
+        next_chunk += len(sizes)
+        workers = max(1, min(16, os.cpu_count() or 1, len(sizes)))
+        with ThreadPoolExecutor(workers) as ex:
+            return np.concatenate(list(ex.map(chunk, ids, sizes)))
 
     keys = np.unique(draw(int(m * 1.1) + 1024))
-    keys = keys[keys >= 0]
     while keys.size < m:
-        more = draw(int((m - keys.size) * 2) + 1024)
-        keys = np.unique(np.concatenate([keys, more[more >= 0]]))
+        keys = np.unique(np.concatenate([keys, draw(int((m - keys.size) * 2) + 1024)]))
     if keys.size > m:
-        keep = np.sort(rng.choice(keys.size, size=m, replace=False))
-        keys = keys[keep]
+        drop = np.ones(keys.size, dtype=bool)
+        drop[rng.choice(keys.size, size=keys.size - m, replace=False)] = False
+        keys = keys[drop]
     return (keys // n).astype(np.int32), (keys % n).astype(np.int32)
 
 
@@ -143,12 +157,21 @@ def stratified_query_nodes(n: int, dst: np.ndarray, count: int, seed: int = 2) -
 
 def update_stream(n: int, src: np.ndarray, dst: np.ndarray, count: int, seed: int = 5):
     """Edge updates: half uniform inserts of absent non-self-loop edges, half
-    deletes of live edges, interleaved in a seeded order.  Each update is
-    valid against the edge set produced by the updates before it.
+    deletes of live edges (uniform over the live set), interleaved in a
+    seeded order.  Each update is valid against the edge set produced by the
+    updates before it.  Membership in the base graph is a binary search of its
+    sorted keys, so the cost does not grow with m beyond one sort.
     Returns (src, dst, op) with op 0 = insert, 1 = delete."""
     rng = _rng(seed, 5)
-    live = set((src.astype(np.int64) * n + dst.astype(np.int64)).tolist())
-    live_list = list(live)
+    base = np.sort(src.astype(np.int64) * n + dst.astype(np.int64))
+
+    def in_base(key):
+        i = int(np.searchsorted(base, key))
+        return i < base.size and int(base[i]) == key
+
+    deleted = set()  # base edges deleted so far
+    added = []  # inserted edges, in insertion order
+    added_live = {}  # live inserted edge -> its position in added
     ops = rng.permutation(np.repeat(np.array([0, 1], dtype=np.uint8), [count - count // 2, count // 2]))
     us = np.empty(count, np.int32)
     ud = np.empty(count, np.int32)
@@ -157,19 +180,26 @@ def update_stream(n: int, src: np.ndarray, dst: np.ndarray, count: int, seed: in
             while True:
                 a, b = (int(x) for x in rng.integers(0, n, size=2))
                 key = a * n + b
-                if a != b and key not in live:
+                if a != b and key not in added_live and (key in deleted or not in_base(key)):
                     break
-            live.add(key)
-            live_list.append(key)
+            deleted.discard(key)
+            added_live[key] = len(added)
+            added.append(key)
         else:
             while True:
-                pos = int(rng.integers(0, len(live_list)))
-                key = live_list[pos]
-                live_list[pos] = live_list[-1]
-                live_list.pop()
-                if key in live:
-                    break
-            live.discard(key)
+                pos = int(rng.integers(0, base.size + len(added)))
+                if pos < base.size:
+                    key = int(base[pos])
+                    if key not in deleted and key not in added_live:
+                        deleted.add(key)
+                        break
+                else:
+                    key = added[pos - base.size]
+                    if added_live.get(key) == pos - base.size:
+                        del added_live[key]
+                        if in_base(key):
+                            deleted.add(key)
+                        break
         us[t] = key // n
         ud[t] = key % n
     return us, ud, ops

@@ -59,3 +59,39 @@ def test_params_agree_with_oracle(orc):
         b = orc.params(n, c, eps, delta)
         assert (a.n_r, a.L, a.t_stop) == (b.n_r, b.L, b.t_stop)
         assert a.eps_p == b.eps_p and a.eps_s == b.eps_s and a.eps_t == b.eps_t
+
+
+STRUCTS = {"ps_options": "Options", "ps_params": "Params", "ps_stats": "Stats", "ps_query": "Query",
+           "ps_result": "Result", "ps_tune": "Tune", "ps_server_cfg": "ServerCfg"}
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    # The binding's ctypes mirrors must have the header's field offsets and
+    # sizes: a C program built from the header prints them.
+    import shutil
+    import subprocess
+
+    import paper_1709_06955_amd as ps
+
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "probesim.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(ps, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        a, b, v = line.split()
+        got[(a, b)] = int(v)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(ps, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)

@@ -9,6 +9,7 @@ sqrt(c)^(levels left), weighted by walks/n_r).  Walks must agree bit for bit.
 """
 
 import os
+import time
 
 import numpy as np
 import pytest
@@ -35,13 +36,35 @@ def ctx(ps):
     c.close()
 
 
-def _parity(gpu, ref, stats, what):
-    tol = TOL + stats["flip_allowance"]
+def _parity(gpu, ref, stats, what, gpu_flip=0.0):
+    tol = TOL + stats["flip_allowance"] + gpu_flip
     err = np.abs(gpu - ref)
     worst = int(np.argmax(err))
     print(f"{what}: max|gpu-oracle| = {err.max():.3e} at {worst} (tol {tol:.3e}, near-threshold {stats['near_threshold']})",
           flush=True)
     assert err.max() <= tol, what
+
+
+def _alone(ps, G, q):
+    """The query run alone, and its Rule-2 near-threshold allowance."""
+    if q.get("k", 0):
+        r = ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"])
+    else:
+        r = ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"])
+    return r, G.ctx.stats()["flip_allowance"]
+
+
+def _same_query(a, fa, b, fb, what):
+    """Two runs of one query: equal within TOL plus both allowances (FP32
+    summation order differs; a Rule-2 test that FP32 rounding may decide
+    either way is covered by the allowances)."""
+    x = a[1] if isinstance(a, tuple) else a
+    y = b[1] if isinstance(b, tuple) else b
+    err = float(np.abs(x - y).max())
+    tol = TOL + fa + fb
+    print(f"{what}: max|a-b| = {err:.3e} (tol {tol:.3e})", flush=True)
+    assert err <= tol, what
+    return err
 
 
 @pytest.fixture(scope="module")
@@ -117,13 +140,16 @@ def test_walk_range_shards_add_up(ps, cl20k, orc):
     u = int(graphs.query_nodes(n, d, 1, seed=9)[0])
     p = orc.params(n, 0.6, 0.1, 0.01)
     full = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 5)
-    parts = [ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 5, walk_begin=a, walk_end=b)
-             for a, b in ((0, 1000), (1000, 1001), (1001, p.n_r))]
+    ff = G.ctx.stats()["flip_allowance"]
+    parts, flips = [], []
+    for a, b in ((0, 1000), (1000, 1001), (1001, p.n_r)):
+        parts.append(ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 5, walk_begin=a, walk_end=b))
+        flips.append(G.ctx.stats()["flip_allowance"])
     tot = sum(parts)
     tot[u] = 1.0
-    assert np.abs(tot - full).max() <= TOL
+    _same_query(tot, sum(flips), full, ff, "walk shards vs whole")
     ref, st = orc.batch(O, u, p, 5, 1000, 1001)
-    _parity(parts[1], ref, st, "single-walk shard")
+    _parity(parts[1], ref, st, "single-walk shard", flips[1])
 
 
 def test_bias_shift(ps, er, orc):
@@ -174,9 +200,10 @@ def test_topk_matches_oracle(ps, cl20k, orc):
     u = int(graphs.query_nodes(n, d, 1, seed=12)[0])
     k = 50
     nodes, vals = ps.ps_topk(G, u, k, 0.6, 0.05, 0.01, 21)
+    fg = G.ctx.stats()["flip_allowance"]
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 21)
     rn, rv = orc.topk(ref, u, k)
-    tol = TOL + st["flip_allowance"]
+    tol = TOL + st["flip_allowance"] + fg
     assert u not in nodes.tolist()
     assert np.all(np.diff(vals) <= 0)
     # same set except among entries within 2 tol of the k-th score
@@ -194,13 +221,9 @@ def test_batch_equals_alone(ps, cl20k):
     qs = [dict(u=int(u), k=(0 if i % 2 == 0 else 20), c=0.6, eps=[0.1, 0.05, 0.2][i % 3], delta=0.01, seed=40 + i)
           for i, u in enumerate(qn)]
     res = ps.ps_batch(G, qs)
-    for q, r in zip(qs, res):
-        if q["k"] == 0:
-            alone = ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"])
-            assert np.abs(r - alone).max() <= TOL  # FP32 sums in another atomic order
-        else:
-            an, av = ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"])
-            assert np.abs(r[1] - av).max() <= TOL
+    for q, r, f in zip(qs, res, res.flip_allowance):
+        a, fa = _alone(ps, G, q)
+        _same_query(r, f, a, fa, f"batch vs alone u={q['u']} k={q['k']}")
 
 
 def test_device_output_tensor(ps, er, orc):
@@ -229,12 +252,13 @@ def test_dynamic_graph_equals_rebuilt(ps, ctx, orc):
     a_nodes, a_lens = ps.ps_walks(G, u, 0.6, 0.1, 0.01, 5, 0, 4000)
     b_nodes, b_lens = ps.ps_walks(R, u, 0.6, 0.1, 0.01, 5, 0, 4000)
     assert (a_nodes == b_nodes).all() and (a_lens == b_lens).all()
-    a = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 5)
-    b = ps.ps_single_source(R, u, 0.6, 0.1, 0.01, 5)
+    q = dict(u=u, k=0, c=0.6, eps=0.1, delta=0.01, seed=5)
+    a, fa = _alone(ps, G, q)
+    b, fb = _alone(ps, R, q)
     O = orc.Graph(n, es, ed)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5)
-    _parity(a, ref, st, "updated graph vs oracle")
-    assert np.abs(a - b).max() <= 2 * TOL
+    _parity(a, ref, st, "updated graph vs oracle", fa)
+    _same_query(a, fa, b, fb, "updated vs rebuilt graph")
     # invalid updates are reported per edge and skipped
     pe, _ = G.update([es[0], 1, 2], [ed[0], 1, (ed[0] + 1) % n], [0, 0, 1])
     assert pe[0] == 4 and pe[1] == 3
@@ -274,21 +298,13 @@ def test_server_equals_alone_with_continuous_admission(ps, ctx):
     qn = graphs.query_nodes(n, d, 10, seed=29)
     qs = [dict(u=int(u), k=(0 if i % 3 else 30), c=0.6, eps=[0.1, 0.05][i % 2], delta=0.01, seed=60 + i)
           for i, u in enumerate(qn)]
-    alone = []
-    for q in qs:
-        if q["k"]:
-            alone.append(ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"]))
-        else:
-            alone.append(ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"]))
+    alone = [_alone(ps, G, q) for q in qs]
     srv = ps.Server(G, max_inflight=3)
     try:
         tickets = [srv.submit(q["u"], q["c"], q["eps"], q["delta"], q["seed"], k=q["k"]) for q in qs]
-        for q, t, a in zip(qs, tickets, alone):
-            r = srv.wait(t, timeout_us=60_000_000)
-            if q["k"]:
-                assert np.abs(r[1] - a[1]).max() <= TOL
-            else:
-                assert np.abs(r - a).max() <= TOL, q
+        for q, t, (a, fa) in zip(qs, tickets, alone):
+            r, fr = srv.wait(t, timeout_us=60_000_000, allowance=True)
+            _same_query(r, fr, a, fa, f"served vs alone u={q['u']} k={q['k']}")
     finally:
         srv.stop()
 
@@ -299,15 +315,15 @@ def test_server_interleaves_updates(ps, ctx):
     G = ps.Graph(ctx, n, s, d)
     us, ud, op = graphs.update_stream(n, s, d, 300, seed=37)
     u = int(graphs.query_nodes(n, d, 1, seed=41)[0])
-    before = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 9)
+    q = dict(u=u, k=0, c=0.6, eps=0.1, delta=0.01, seed=9)
+    before, fb = _alone(ps, G, q)
     srv = ps.Server(G, max_inflight=4)
     try:
         t1 = srv.submit(u, 0.6, 0.1, 0.01, 9)
         srv.update(us, ud, op)
-        r1 = srv.wait(t1, timeout_us=60_000_000)
-        # a query submitted after the update has been waited for sees it
         t2 = srv.submit(u, 0.6, 0.1, 0.01, 9)
-        r2 = srv.wait(t2, timeout_us=60_000_000)
+        r1, f1 = srv.wait(t1, timeout_us=60_000_000, allowance=True)
+        r2, f2 = srv.wait(t2, timeout_us=60_000_000, allowance=True)
     finally:
         srv.stop()
     es, ed = G.edges()
@@ -315,9 +331,10 @@ def test_server_interleaves_updates(ps, ctx):
     for a, b, o in zip(us.tolist(), ud.tolist(), op.tolist()):
         (ref.add if o == 0 else ref.discard)((a, b))
     assert set(zip(es.tolist(), ed.tolist())) == ref
-    after = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 9)
-    assert np.abs(r1 - before).max() <= TOL or np.abs(r1 - after).max() <= TOL
-    assert np.abs(r2 - after).max() <= TOL
+    after, fa = _alone(ps, G, q)
+    # each query reads exactly the updates submitted before it
+    _same_query(r1, f1, before, fb, "submitted before the update")
+    _same_query(r2, f2, after, fa, "submitted after the update")
 
 
 def test_server_busy_and_stop(ps, ctx):
@@ -371,3 +388,127 @@ def test_autotune_keeps_results(ps, ctx, cl20k, orc, tmp_path):
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 19)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19)
     _parity(gpu, ref, st, f"autotuned {t}")
+
+
+_T0 = time.perf_counter()
+
+
+def _say(msg):
+    print(f"[{time.perf_counter() - _T0:7.1f} s] {msg}", flush=True)
+
+
+def _walks_match(ps, G, O, orc, u, eps, seed, count, every):
+    p = orc.params(O.n, 0.6, eps, 0.01)
+    nodes, lens = ps.ps_walks(G, u, 0.6, eps, 0.01, seed, 0, count)
+    for k in range(0, count, every):
+        w = orc.walk(O, u, k, seed, p)
+        assert lens[k] == len(w) and (nodes[k, : len(w)] == w).all(), (u, k)
+
+
+@pytest.mark.skipif(os.environ.get("PS_SKIP_FULL") == "1", reason="full-size case skipped")
+def test_full_size_batched_mixed_eps(ps, ctx, orc):
+    # 5M nodes / 50M edges; degree-stratified query nodes with eps cycling
+    # over {0.1, 0.05, 0.02} run together in one batch.  Every result equals
+    # the query alone; the oracle checks walks bit for bit and a walk-range
+    # shard of one query per eps.  PS_FULL_BATCH=<count> runs that many of
+    # the 256 stratified queries in the batch (default 6).
+    n, s, d = graphs.make_workload("cl_5m_50m")
+    G = ps.Graph(ctx, n, s, d)
+    _say("cl5m loaded")
+    qn = graphs.stratified_query_nodes(n, d, 256)
+    count = int(os.environ.get("PS_FULL_BATCH", "6"))
+    qs = [dict(u=int(qn[i]), k=0, c=0.6, eps=(0.1, 0.05, 0.02)[i % 3], delta=0.01, seed=100 + i)
+          for i in range(count)]
+    res = ps.ps_batch(G, qs)
+    _say(f"cl5m batch of {count} done")
+    for i in range(0, count, max(1, count // 6)):
+        q = qs[i]
+        alone, fa = _alone(ps, G, q)
+        _same_query(res[i], res.flip_allowance[i], alone, fa, f"cl5m batch vs alone {i} u={q['u']} eps={q['eps']}")
+        assert res[i][q["u"]] == 1.0 and res[i].min() >= 0.0
+    del res
+    O = orc.Graph(n, s, d)
+    for q in qs[:3]:
+        p = orc.params(n, 0.6, q["eps"], 0.01)
+        _walks_match(ps, G, O, orc, q["u"], q["eps"], q["seed"], 400, 8)
+        gpu = ps.ps_single_source(G, q["u"], 0.6, q["eps"], 0.01, q["seed"], walk_begin=0, walk_end=40)
+        fg = G.ctx.stats()["flip_allowance"]
+        ref, st = orc.single_source(O, q["u"], p, q["seed"], 0, 40)
+        _parity(gpu, ref, st, f"cl5m u={q['u']} eps={q['eps']} walks [0,40)", fg)
+
+
+@pytest.mark.skipif(os.environ.get("PS_SKIP_FULL") == "1", reason="full-size case skipped")
+def test_full_size_served_dynamic_graph(ps, ctx):
+    # 10M nodes / 200M edges served with edge updates interleaved between
+    # queries (half inserts, half deletes); single-source and top-k (k = 50)
+    # queries.  Each served result equals the query run alone on a second
+    # copy of the graph that replays the updates in submission order.  On
+    # this graph a query at eps = 0.05 scans about 10^11 edges and one at
+    # 0.02 about 10^12, so the mix stays at eps 0.1 and 0.05 here; the
+    # 5M-node case covers 0.02 against the oracle.
+    n, s, d = graphs.make_workload("cl_10m_200m")
+    _say("cl10m generated")
+    G = ps.Graph(ctx, n, s, d)
+    R = ps.Graph(ctx, n, s, d)
+    _say("cl10m loaded twice")
+    us, ud, op = graphs.update_stream(n, s, d, 1000, seed=5)
+    _say("update stream ready")
+    qn = graphs.query_nodes(n, d, 4, seed=43)
+    del s, d
+    eps = (0.1, 0.05, 0.1, 0.1)
+    qs = [dict(u=int(u), k=(50 if i == 2 else 0), c=0.6, eps=eps[i], delta=0.01, seed=200 + i)
+          for i, u in enumerate(qn)]
+    plan = []
+    for i, q in enumerate(qs):
+        plan.append(("q", q))
+        b = i * 250
+        plan.append(("u", (us[b:b + 250], ud[b:b + 250], op[b:b + 250])))
+    srv = ps.Server(G, max_inflight=4)
+    try:
+        tickets = []
+        for kind, x in plan:
+            if kind == "q":
+                tickets.append(srv.submit(x["u"], x["c"], x["eps"], x["delta"], x["seed"], k=x["k"]))
+            else:
+                srv.update(*x)
+        served = []
+        for t in tickets:
+            served.append(srv.wait(t, timeout_us=300_000_000, allowance=True))
+            _say(f"served result {len(served)}")
+    finally:
+        srv.stop()
+    i = 0
+    for kind, x in plan:
+        if kind == "u":
+            pe, _ = R.update(*x)
+            assert (pe == 0).all()
+            continue
+        r, fr = served[i]
+        a, fa = _alone(ps, R, x)
+        _same_query(r, fr, a, fa, f"cl10m served vs alone {i} u={x['u']} eps={x['eps']} k={x['k']}")
+        _say(f"query {i} checked (allowances {fr:.2e}, {fa:.2e})")
+        i += 1
+    es, ed = G.edges()
+    fs, fd = R.edges()
+    assert es.size == fs.size and (es == fs).all() and (ed == fd).all()
+
+
+@pytest.mark.skipif(os.environ.get("PS_FULL_BILLION") != "1", reason="billion-edge case runs with PS_FULL_BILLION=1")
+def test_full_size_billion_edge_topk(ps, ctx, orc):
+    # 40M nodes / 1.4B edges, exponent 2.0: a batch of top-k queries (k = 50,
+    # eps = 0.025) equals the queries alone; walks match the oracle.
+    n, s, d = graphs.make_workload("cl_40m_1400m")
+    _say("cl40m generated")
+    G = ps.Graph(ctx, n, s, d)
+    _say("cl40m loaded")
+    qn = graphs.query_nodes(n, d, int(os.environ.get("PS_FULL_BATCH", "8")), seed=47)
+    qs = [dict(u=int(u), k=50, c=0.6, eps=0.025, delta=0.01, seed=300 + i) for i, u in enumerate(qn)]
+    res = ps.ps_batch(G, qs)
+    _say(f"cl40m batch of {len(qs)} done")
+    for i in (0, len(qs) - 1):
+        q = qs[i]
+        a, fa = _alone(ps, G, q)
+        _same_query(res[i], res.flip_allowance[i], a, fa, f"cl40m top-k batch vs alone {i} u={q['u']}")
+    O = orc.Graph(n, s, d)
+    del s, d
+    _walks_match(ps, G, O, orc, qs[0]["u"], 0.025, qs[0]["seed"], 400, 8)
