@@ -25,7 +25,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.check_call(
-            ["g++", "-O3", "-std=c++17", "-shared", "-fPIC", "-Wall", "-Wextra", "-o", tmp, _SRC]
+            ["g++", "-O3", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC", "-Wall", "-Wextra", "-o", tmp,
+             _SRC]
         )
         os.replace(tmp, _SO)
     return _SO
@@ -70,9 +71,10 @@ def lib():
         L.orc_philox4x32_10.restype = None
         L.orc_walk.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, P(Params), P(C.c_int32)]
         L.orc_walk.restype = C.c_int32
-        L.orc_probe.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_double, C.c_double, P(C.c_double)]
+        L.orc_probe.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_double, C.c_double, C.c_int,
+                                P(C.c_double)]
         for f in (L.orc_single_source, L.orc_batch):
-            f.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int,
+            f.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int,
                           P(C.c_double), P(Stats)]
         L.orc_topk.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_double)]
         _lib = L
@@ -127,35 +129,49 @@ def walk(g: Graph, u: int, k: int, seed: int, p: Params) -> np.ndarray:
     return buf[:ln].copy()
 
 
-def probe(g: Graph, path, c: float, eps_p: float = 0.0) -> np.ndarray:
+PRECISIONS = ("f64", "f32")
+
+
+def _f32(precision: str) -> int:
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {PRECISIONS}")
+    return int(precision == "f32")
+
+
+def probe(g: Graph, path, c: float, eps_p: float = 0.0, precision: str = "f64") -> np.ndarray:
+    """Alg. 2 scores of PROBE(path); precision "f64" evaluates the plain
+    definition, "f32" the FP32 score model (Rule 2 decided in FP32)."""
     pa, pp = _i32(path)
     out = np.zeros(g.n, dtype=np.float64)
-    rc = lib().orc_probe(g._h, pp, int(pa.size), c, eps_p, out.ctypes.data_as(C.POINTER(C.c_double)))
+    rc = lib().orc_probe(g._h, pp, int(pa.size), c, eps_p, _f32(precision),
+                         out.ctypes.data_as(C.POINTER(C.c_double)))
     if rc != ORC_OK:
         raise ValueError(f"probe failed with code {rc}")
     return out
 
 
-def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift):
+def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision):
     out = np.zeros(g.n, dtype=np.float64)
     st = Stats()
     kb = 0 if k_begin is None else int(k_begin)
     ke = int(p.n_r) if k_end is None else int(k_end)
-    rc = fn(g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift),
+    rc = fn(g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift), _f32(precision),
             out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
     if rc != ORC_OK:
         raise ValueError(f"query failed with code {rc}")
     return out, st.as_dict()
 
 
-def single_source(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False):
+def single_source(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False,
+                  precision: str = "f64"):
     """Alg. 1 estimate s^(u, .) over walks [k_begin, k_end) (default all n_r)."""
-    return _run(lib().orc_single_source, g, u, p, seed, k_begin, k_end, bias_shift)
+    return _run(lib().orc_single_source, g, u, p, seed, k_begin, k_end, bias_shift, precision)
 
 
-def batch(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False):
+def batch(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False,
+          precision: str = "f64"):
     """Alg. 3 (reverse reachability tree) estimate; equal to Alg. 1 up to rounding."""
-    return _run(lib().orc_batch, g, u, p, seed, k_begin, k_end, bias_shift)
+    return _run(lib().orc_batch, g, u, p, seed, k_begin, k_end, bias_shift, precision)
 
 
 def topk(scores: np.ndarray, u: int, k: int):

@@ -15,7 +15,8 @@
 //                       the random source open; parity unpinned against an
 //                       external known-answer table, which is not available)
 //   orc_walk            Definition of the sqrt(c)-walk (Section 2.2)
-//   orc_probe           Alg. 2 (deterministic PROBE) with Pruning Rule 2
+//   orc_probe           Alg. 2 (deterministic PROBE) with Pruning Rule 2, in
+//                       FP64 or in the FP32 score model below
 //   orc_single_source   Alg. 1 (basic ProbeSim) with Pruning Rules 1 and 2
 //   orc_batch           Alg. 3 (reverse reachability tree), same estimate
 //   orc_topk            Definition 2 (top-k by sorting the estimates)
@@ -25,6 +26,16 @@
 // visited node including u_1 and a node with no in-neighbour ends the walk;
 // Rule 2 removes x when Score(x) * sqrt(c)^(i-j-1) <= eps_p, for levels
 // j = 0..i-2 only (never the returned level); the estimate of u itself is 1.
+//
+// Precision.  Rule 2 turns a floating-point comparison into a keep/remove
+// decision, so besides the plain FP64 evaluation the oracle offers the FP32
+// score model, in which that decision is taken in FP32: every probe score of
+// an inner level is an FP32 number, each contribution of Alg. 2 is
+// fl32(fl32(Score(x) * fl32(sqrt c)) * fl32(1/|I(v)|)), contributions are
+// summed exactly on the grid 2^-62 (each rounded to nearest-even there
+// first), a level's score is that sum rounded to FP32, Rule 2 compares it
+// with fl32(eps_p / sqrt(c)^(i-j-1)), and the returned level keeps the exact
+// sum.  Estimates are summed over walks in FP64 in both modes.
 
 #include <cmath>
 #include <cstdint>
@@ -284,16 +295,102 @@ static void probe(const orc_graph* g, const int32_t* path, int32_t i, double sc,
   }
 }
 
+// Exact sums on the grid 2^-62 for the FP32 score model: one 64-bit integer
+// per present node (scores never exceed 1, so sums stay below 2^63).
+struct FixSet {
+  std::vector<int64_t> sum;
+  std::vector<int32_t> keys;
+  explicit FixSet(int32_t n) : sum((size_t)n, 0) {}
+  void add(int32_t v, int64_t q) {
+    if (sum[v] == 0) keys.push_back(v);
+    sum[v] += q;
+  }
+  void clear() {
+    for (int32_t v : keys) sum[v] = 0;
+    keys.clear();
+  }
+};
+
+static const double kGrid = 4611686018427387904.0;  // 2^62
+
+// fl32 of an exact grid sum
+static inline float grid_to_f32(int64_t q) { return (float)q * (float)(1.0 / kGrid); }
+
+// Alg. 2 with Rule 2 in the FP32 score model (see the header).  The returned
+// set H_{i-1} keeps the exact grid sums.
+static void probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p, double n_r,
+                      FixSet& cur, FixSet& nxt, orc_stats* st) {
+  const float sig = (float)std::sqrt(c);
+  cur.clear();
+  cur.add(path[i - 1], (int64_t)kGrid);  // H_0 = {u_i: 1}
+  for (int32_t j = 0; j <= i - 2; ++j) {
+    const int32_t excl = path[i - j - 2];  // u_{i-j-1}
+    const float thr = eps_p > 0.0 ? (float)(eps_p / std::pow(std::sqrt(c), (double)(i - j - 1))) : 0.0f;
+    nxt.clear();
+    for (int32_t x : cur.keys) {
+      const float h = grid_to_f32(cur.sum[x]);
+      if (eps_p > 0.0) {
+        if (st && std::fabs((double)h - (double)thr) <= 1e-5 * (double)thr) {
+          st->near_threshold++;
+          st->flip_allowance += eps_p / n_r;
+        }
+        if (!(h > thr)) {
+          if (st) st->entries_pruned++;
+          continue;
+        }
+      }
+      if (st) st->entries_expanded++;
+      const float a = h * sig;
+      for (int64_t e = g->out_ptr[x]; e < g->out_ptr[x + 1]; ++e) {
+        const int32_t v = g->out_col[e];
+        if (st) st->edges_scanned++;
+        if (v == excl) continue;
+        const float inv = 1.0f / (float)indeg(g, v);
+        const float contrib = a * inv;
+        const int64_t q = std::llrint((double)contrib * kGrid);
+        if (q != 0) nxt.add(v, q);
+      }
+    }
+    if (st && j < i - 2) st->next_entries += (int64_t)nxt.keys.size();
+    std::swap(cur.sum, nxt.sum);
+    std::swap(cur.keys, nxt.keys);
+  }
+  if (st) {
+    st->probes++;
+    st->final_entries += (int64_t)cur.keys.size();
+  }
+}
+
+// One probe in either precision; adds weight * Score(v) to acc.
+struct Prober {
+  const orc_graph* g;
+  bool f32;
+  ScoreSet cur, nxt;
+  FixSet fcur, fnxt;
+  Prober(const orc_graph* g_, bool f) : g(g_), f32(f), cur(f ? 1 : g_->n), nxt(f ? 1 : g_->n),
+                                        fcur(f ? g_->n : 1), fnxt(f ? g_->n : 1) {}
+  void run(const int32_t* path, int32_t i, double c, double eps_p, double n_r_over_w, double w,
+           std::vector<double>& acc, orc_stats* st) {
+    if (f32) {
+      probe_f32(g, path, i, c, eps_p, n_r_over_w, fcur, fnxt, st);
+      for (int32_t v : fcur.keys) acc[v] += w * ((double)fcur.sum[v] / kGrid);
+    } else {
+      probe(g, path, i, std::sqrt(c), eps_p, n_r_over_w, cur, nxt, st);
+      for (int32_t v : cur.keys) acc[v] += w * cur.val[v];
+    }
+  }
+};
+
 // Alg. 2 alone, for tests: dense scores of PROBE((u_1..u_i)).
-int orc_probe(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p,
+int orc_probe(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p, int f32,
               double* out) {
   if (i < 2) return ORC_EINVAL;
   for (int32_t t = 0; t < i; ++t)
     if (path[t] < 0 || path[t] >= g->n) return ORC_ERANGE;
-  ScoreSet cur(g->n), nxt(g->n);
-  probe(g, path, i, std::sqrt(c), eps_p, 1.0, cur, nxt, nullptr);
-  std::fill(out, out + g->n, 0.0);
-  for (int32_t v : cur.keys) out[v] = cur.val[v];
+  std::vector<double> acc((size_t)g->n, 0.0);
+  Prober pr(g, f32 != 0);
+  pr.run(path, i, c, eps_p, 1.0, 1.0, acc, nullptr);
+  std::copy(acc.begin(), acc.end(), out);
   return ORC_OK;
 }
 
@@ -311,21 +408,17 @@ static void finish(const orc_graph* g, int32_t u, const orc_params* p, int bias_
 // walks divided by n_r (the running average of Alg. 1 is the same number).
 // A sub-range of walks gives that range's share of the sum.
 int orc_single_source(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
-                      int64_t k_begin, int64_t k_end, int bias_shift, double* out, orc_stats* st) {
+                      int64_t k_begin, int64_t k_end, int bias_shift, int f32, double* out, orc_stats* st) {
   if (u < 0 || u >= g->n) return ORC_ERANGE;
   if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
   if (st) memset(st, 0, sizeof(*st));
-  const double sc = std::sqrt(p->c);
   std::vector<double> acc((size_t)g->n, 0.0);
   std::vector<int32_t> walk((size_t)p->L);
-  ScoreSet cur(g->n), nxt(g->n);
+  Prober pr(g, f32 != 0);
   for (int64_t k = k_begin; k < k_end; ++k) {
     const int32_t len = orc_walk(g, u, k, seed, p, walk.data());
     if (st) st->walk_nodes += len;
-    for (int32_t i = 2; i <= len; ++i) {
-      probe(g, walk.data(), i, sc, p->eps_p, (double)p->n_r, cur, nxt, st);
-      for (int32_t v : cur.keys) acc[v] += cur.val[v];
-    }
+    for (int32_t i = 2; i <= len; ++i) pr.run(walk.data(), i, p->c, p->eps_p, (double)p->n_r, 1.0, acc, st);
   }
   finish(g, u, p, bias_shift, acc, out);
   return ORC_OK;
@@ -335,7 +428,7 @@ int orc_single_source(const orc_graph* g, int32_t u, const orc_params* p, uint64
 // distinct prefix (u_1..u_q), q >= 2, weighted by the number of walks sharing
 // it), PROBE every tree node once and add weight/n_r * Score.
 int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
-              int64_t k_end, int bias_shift, double* out, orc_stats* st) {
+              int64_t k_end, int bias_shift, int f32, double* out, orc_stats* st) {
   if (u < 0 || u >= g->n) return ORC_ERANGE;
   if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
   if (st) memset(st, 0, sizeof(*st));
@@ -364,17 +457,15 @@ int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
     }
   }
   if (st) st->tree_nodes = (int64_t)tree.size() - 1;
-  const double sc = std::sqrt(p->c);
   std::vector<double> acc((size_t)g->n, 0.0);
   std::vector<int32_t> path;
-  ScoreSet cur(g->n), nxt(g->n);
+  Prober pr(g, f32 != 0);
   for (size_t q = 1; q < tree.size(); ++q) {
     const int32_t i = tree[q].depth;
     path.assign((size_t)i, 0);
     for (int64_t a = (int64_t)q; a >= 0; a = tree[a].parent) path[tree[a].depth - 1] = tree[a].node;
-    probe(g, path.data(), i, sc, p->eps_p, (double)p->n_r / (double)tree[q].weight, cur, nxt, st);
     const double w = (double)tree[q].weight;
-    for (int32_t v : cur.keys) acc[v] += w * cur.val[v];
+    pr.run(path.data(), i, p->c, p->eps_p, (double)p->n_r / w, w, acc, st);
   }
   finish(g, u, p, bias_shift, acc, out);
   return ORC_OK;

@@ -394,3 +394,70 @@ def test_topk_order_and_ties(orc):
     assert nodes.tolist() == [0, 3, 2, 5, 4]
     with pytest.raises(ValueError):
         orc.topk(s, 0, 6)
+
+
+# ----------------------------------------------------------- FP32 score model
+#
+# The FP32 score model takes Rule 2's keep/remove decision in FP32 (the GPU
+# kernels' precision).  Its pins: without pruning it stays within the
+# rounding bound of the FP64 evaluation (itself pinned above by brute force),
+# its sums are exact so node order cannot change a single bit, and a full
+# query stays within 1e-5 plus the Rule-2 near-threshold allowances of the
+# FP64 query.
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_f32_model_within_rounding_bound_without_pruning(orc, seed):
+    # Per level: sqrt(c), the two products, 1/|I(v)| and the final rounding
+    # to FP32 each add at most 2^-24 relative error; the grid adds 2^-63 per
+    # contribution.
+    rng = np.random.default_rng(200 + seed)
+    n = 30
+    src, dst = refs.random_graph(n, 0.2, seed)
+    G = orc.Graph(n, src, dst)
+    for _ in range(6):
+        i = int(rng.integers(2, 9))
+        path = [int(x) for x in rng.integers(0, n, size=i)]
+        c = float(rng.choice([0.25, 0.6, 0.8]))
+        a = orc.probe(G, path, c, 0.0, precision="f64")
+        b = orc.probe(G, path, c, 0.0, precision="f32")
+        bound = 6 * (i - 1) * 2.0**-24 * a + n * (i - 1) * 2.0**-62
+        assert np.all(np.abs(a - b) <= bound), (path, c)
+        assert np.all((a > 0) == (b > 0))
+
+
+def test_f32_model_sums_do_not_depend_on_node_order(orc):
+    # Relabelling the nodes changes every adjacency order; exact sums keep
+    # the FP32 model's scores bit for bit.
+    rng = np.random.default_rng(7)
+    n = 40
+    src, dst = refs.random_graph(n, 0.25, 3)
+    perm = rng.permutation(n).astype(np.int32)
+    G = orc.Graph(n, src, dst)
+    H = orc.Graph(n, perm[src], perm[dst])
+    for _ in range(10):
+        i = int(rng.integers(2, 8))
+        path = np.array(rng.integers(0, n, size=i), np.int32)
+        for eps_p in (0.0, 0.003, 0.02):
+            a = orc.probe(G, path, 0.6, eps_p, precision="f32")
+            b = orc.probe(H, perm[path], 0.6, eps_p, precision="f32")
+            assert np.array_equal(a, b[perm]), (path, eps_p)
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.05])
+def test_f32_model_query_within_allowance_of_f64(orc, eps):
+    from synth.graphs import chung_lu
+
+    n = 3000
+    s_, d_ = chung_lu(n, 24_000, 2.1, seed=11)
+    G = orc.Graph(n, s_, d_)
+    p = orc.params(n, 0.6, eps, 0.01)
+    for u in (3, 1700):
+        a, sa = orc.batch(G, u, p, 5, precision="f64")
+        b, sb = orc.batch(G, u, p, 5, precision="f32")
+        tol = 1e-5 + sa["flip_allowance"] + sb["flip_allowance"]
+        assert np.abs(a - b).max() <= tol
+        # Alg. 1 and Alg. 3 agree in the FP32 model too
+        c1, _ = orc.single_source(G, u, p, 5, 0, 300, precision="f32")
+        c3, _ = orc.batch(G, u, p, 5, 0, 300, precision="f32")
+        assert np.abs(c1 - c3).max() <= 1e-13
