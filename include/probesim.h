@@ -22,6 +22,18 @@
  *    of y (x in I(y)); walks follow in-edges, PROBE follows out-edges.
  *  - Calls on one context are not thread-safe unless stated otherwise; the
  *    server (ps_server_*) is the thread-safe entry.
+ *
+ * Precision.  Probe scores (Alg. 2) are FP32 numbers: a contribution is
+ * fl32(fl32(Score(x) * fl32(sqrt c)) * fl32(1/|I(v)|)) (fl32: nearest FP32
+ * number), the contributions to a node are summed exactly as 64-bit integers
+ * on the grid 2^-62, an inner level's score is that sum rounded to FP32 and
+ * Pruning Rule 2 compares it with fl32(eps_p / sqrt(c)^(i-j-1)).  Estimates
+ * are accumulated in FP64.  So a query's result does not depend on the
+ * order of the device's atomic adds, on the batch or server mix it runs in,
+ * on the number of probe slots or on pushing versus pulling: only the order
+ * of the FP64 additions varies.  Against the plain FP64 evaluation of the
+ * method a result differs by FP32 rounding (about 1e-7 relative) and by the
+ * Rule-2 tests that rounding decides, which ps_result.flip_allowance bounds.
  */
 #ifndef PROBESIM_H
 #define PROBESIM_H
@@ -116,8 +128,8 @@ typedef struct ps_options {
                          (still divided by the full n_r), so shards add up. */
   int32_t slots;      /* concurrent probes on the device; 0: the graph's autotuned
                          setting, else automatic (up to 1024).  Clamped so that
-                         the per-slot buffers (44 B per slot and node) fit in
-                         48 GiB. */
+                         the per-slot buffers (52 B per slot and node) fit in
+                         56 GiB. */
   int32_t reserved;
   int64_t pull_edges; /* a probe level whose kept entries have at least this many
                          out-edges is computed by pulling along in-edges over
@@ -164,9 +176,10 @@ ps_status ps_walks(ps_graph* g, int32_t u, double c, double eps, double delta, u
  * out[v] = estimate of s(u, v), out[u] = 1.  Samples n_r sqrt(c)-walks
  * from u, merges them into the reverse reachability tree (Alg. 3), runs
  * deterministic PROBE (Alg. 2) once per tree node with Rule 2 pruning and
- * adds weight/n_r * Score to the estimate.  Probe scores are FP32, the
- * estimate is accumulated in FP64.  Deterministic for fixed (graph version,
- * u, c, eps, delta, seed, options) up to floating-point summation order. */
+ * adds weight/n_r * Score to the estimate.  Probe scores are FP32 with exact
+ * sums, the estimate is accumulated in FP64 (see Precision above).
+ * Deterministic for fixed (graph version, u, c, eps, delta, seed, walk
+ * range) up to the order of the FP64 additions. */
 ps_status ps_single_source(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
                            const ps_options* opt, double* out);
 
@@ -188,17 +201,17 @@ typedef struct ps_result {
   int32_t* nodes; /* k node ids for top-k; unused for single-source */
   int32_t status; /* ps_status of this query */
   int32_t count;  /* entries written */
-  double flip_allowance; /* how far FP32 rounding may move an estimate through
-                            Rule 2: the sum, over pruning tests whose score fell
-                            within 1e-5 relative of the threshold, of
-                            eps_p * (walks sharing the probe) / n_r.  A run
-                            and the FP64 definition agree within 1e-5 plus it;
-                            two runs within 1e-5 plus both allowances. */
+  double flip_allowance; /* how far the FP32 scores may move an estimate away
+                            from the plain FP64 evaluation through Rule 2: the
+                            sum, over pruning tests whose score fell within
+                            1e-5 relative of the threshold, of eps_p * (walks
+                            sharing the probe) / n_r.  The stated error
+                            against the FP64 evaluation is 1e-5 plus this. */
 } ps_result;
 
 /* Runs nq queries together: all their walks, trees and probes share the
  * device's probe slots and one level-synchronous launch sequence.  Each
- * result equals the same query run alone (up to summation order).  opt
+ * result equals the same query run alone (up to FP64 summation order).  opt
  * applies to every query (its walk range must be the default).  Per-query
  * argument errors are reported in r[i].status and do not stop the others. */
 ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* q, const ps_options* opt, ps_result* r);
@@ -213,7 +226,7 @@ typedef struct ps_tune {
 } ps_tune;
 
 /* Autotuner of the launch settings that do not change results (beyond
- * floating-point summation order): the number of probe slots and the
+ * the order of FP64 additions): the number of probe slots and the
  * out-edge threshold above which a probe level moves to the dense pass.  It
  * times the nsample query nodes `nodes` (host array) as plain single-source
  * queries under each candidate setting (one untimed run first) and keeps the

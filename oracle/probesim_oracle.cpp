@@ -31,11 +31,12 @@
 // decision, so besides the plain FP64 evaluation the oracle offers the FP32
 // score model, in which that decision is taken in FP32: every probe score of
 // an inner level is an FP32 number, each contribution of Alg. 2 is
-// fl32(fl32(Score(x) * fl32(sqrt c)) * fl32(1/|I(v)|)), contributions are
-// summed exactly on the grid 2^-62 (each rounded to nearest-even there
-// first), a level's score is that sum rounded to FP32, Rule 2 compares it
-// with fl32(eps_p / sqrt(c)^(i-j-1)), and the returned level keeps the exact
-// sum.  Estimates are summed over walks in FP64 in both modes.
+// fl32(fl32(Score(x) * fl32(sqrt c)) * fl32(1/|I(v)|)), where fl32 is the
+// nearest FP32 number; contributions are summed exactly on the grid 2^-62
+// (each rounded to nearest-even there first), a level's score is that sum
+// rounded to FP32, Rule 2 compares it with fl32(eps_p / sqrt(c)^(i-j-1)),
+// and the returned level keeps the exact sum.  Estimates are summed over
+// walks in FP64 in both modes.
 
 #include <cmath>
 #include <cstdint>
@@ -313,13 +314,42 @@ struct FixSet {
 
 static const double kGrid = 4611686018427387904.0;  // 2^62
 
+// fl32(1/d) for d >= 1: of the FP32 numbers next to the double quotient, the
+// one nearest to 1/d, distances |1 - r*d| compared exactly in 128-bit
+// integers (r = m * 2^e with an integer mantissa m).
+static float recip_f32(int64_t d) {
+  const float r0 = (float)(1.0 / (double)d);
+  const float cand[3] = {std::nextafter(r0, 0.0f), r0, std::nextafter(r0, 2.0f)};
+  int64_t m[3];
+  int e[3], emin = 0;
+  for (int t = 0; t < 3; ++t) {
+    const float f = std::frexp(cand[t], &e[t]);
+    m[t] = (int64_t)std::ldexp(f, 24);
+    e[t] -= 24;
+    emin = std::min(emin, e[t]);
+  }
+  float best = r0;
+  __int128 best_d = -1;
+  for (int t = 0; t < 3; ++t) {
+    // |1 - m d 2^e| * 2^-emin = |2^-emin - m d 2^(e-emin)|
+    const __int128 one = (__int128)1 << (-emin);
+    __int128 dist = one - ((__int128)m[t] * d << (e[t] - emin));
+    if (dist < 0) dist = -dist;
+    if (best_d < 0 || dist < best_d) {
+      best_d = dist;
+      best = cand[t];
+    }
+  }
+  return best;
+}
+
 // fl32 of an exact grid sum
 static inline float grid_to_f32(int64_t q) { return (float)q * (float)(1.0 / kGrid); }
 
 // Alg. 2 with Rule 2 in the FP32 score model (see the header).  The returned
 // set H_{i-1} keeps the exact grid sums.
 static void probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p, double n_r,
-                      FixSet& cur, FixSet& nxt, orc_stats* st) {
+                      const std::vector<float>& inv_indeg, FixSet& cur, FixSet& nxt, orc_stats* st) {
   const float sig = (float)std::sqrt(c);
   cur.clear();
   cur.add(path[i - 1], (int64_t)kGrid);  // H_0 = {u_i: 1}
@@ -345,8 +375,7 @@ static void probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double
         const int32_t v = g->out_col[e];
         if (st) st->edges_scanned++;
         if (v == excl) continue;
-        const float inv = 1.0f / (float)indeg(g, v);
-        const float contrib = a * inv;
+        const float contrib = a * inv_indeg[v];
         const int64_t q = std::llrint((double)contrib * kGrid);
         if (q != 0) nxt.add(v, q);
       }
@@ -367,12 +396,19 @@ struct Prober {
   bool f32;
   ScoreSet cur, nxt;
   FixSet fcur, fnxt;
+  std::vector<float> inv;  // fl32(1/|I(v)|), FP32 model only
   Prober(const orc_graph* g_, bool f) : g(g_), f32(f), cur(f ? 1 : g_->n), nxt(f ? 1 : g_->n),
-                                        fcur(f ? g_->n : 1), fnxt(f ? g_->n : 1) {}
+                                        fcur(f ? g_->n : 1), fnxt(f ? g_->n : 1) {
+    if (f32) {
+      inv.assign((size_t)g->n, 0.0f);
+      for (int32_t v = 0; v < g->n; ++v)
+        if (indeg(g, v) > 0) inv[v] = recip_f32(indeg(g, v));
+    }
+  }
   void run(const int32_t* path, int32_t i, double c, double eps_p, double n_r_over_w, double w,
            std::vector<double>& acc, orc_stats* st) {
     if (f32) {
-      probe_f32(g, path, i, c, eps_p, n_r_over_w, fcur, fnxt, st);
+      probe_f32(g, path, i, c, eps_p, n_r_over_w, inv, fcur, fnxt, st);
       for (int32_t v : fcur.keys) acc[v] += w * ((double)fcur.sum[v] / kGrid);
     } else {
       probe(g, path, i, std::sqrt(c), eps_p, n_r_over_w, cur, nxt, st);

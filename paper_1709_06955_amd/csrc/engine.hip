@@ -20,12 +20,13 @@
 //                listed frontier entries, applies Rule 2 and records the
 //                surviving rows; k_expand pushes scores along out-edges,
 //                load-balanced per edge over tiles of entries (long rows in
-//                fixed-size chunks).  Each slot owns a dense FP32 score vector per
-//                level parity; the atomic add that turns an entry nonzero
-//                appends (slot, node) to the next frontier list, so frontiers
-//                stay sparse lists while the sums stay exact.  A probe's last
-//                level adds weight * score straight into the query's FP64
-//                estimate.
+//                fixed-size chunks).  Each slot owns a dense vector of exact
+//                score sums (64-bit integers on the grid 2^-62) per level
+//                parity; the atomic add that turns an entry nonzero appends
+//                (slot, node) to the next frontier list, so frontiers stay
+//                sparse lists while the sums stay exact and independent of
+//                the order of the adds.  A probe's last level adds weight *
+//                score straight into the query's FP64 estimate.
 //   finish       k_finalize divides by n_r and sets s(u,u) = 1; top-k sorts.
 
 #include <hipcub/hipcub.hpp>
@@ -319,6 +320,17 @@ __global__ void k_reset_lanes(int32_t* lane_slot) {
 
 // ------------------------------------------------------- level steps ----
 
+// Probe scores.  The scores of inner levels are FP32 numbers.  The
+// contributions that make up a level are summed exactly, as 64-bit integers
+// on the grid 2^-62 (a level's scores never exceed 1), so no order of atomic
+// adds changes a bit; a level's FP32 score is its sum rounded to nearest.
+// Rule 2 then compares FP32 numbers only, and the same query gives the same
+// result alone, in a batch, pushed or pulled.
+__device__ __forceinline__ long long to_grid(float c) { return __float2ll_rn(c * 0x1p62f); }
+__device__ __forceinline__ float grid_f32(long long q) { return __ll2float_rn(q) * 0x1p-62f; }
+__device__ __forceinline__ double grid_f64(long long q) { return (double)q * 0x1p-62; }
+constexpr long long kGridOne = 1ll << 62;
+
 struct SchedArgs {
   int P;
   int32_t n;
@@ -336,7 +348,7 @@ struct SchedArgs {
   const float* thr_tab;
   unsigned long long* remaining;
   int32_t* done_ring;
-  float* dense_cur;
+  long long* dense_cur;
   int2* list_cur;
   uint64_t list_cap;
   unsigned long long* slot_edges;
@@ -436,7 +448,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
-          a.dense_cur[(size_t)s * a.n + x] = 1.0f;
+          a.dense_cur[(size_t)s * a.n + x] = kGridOne;  // H_0 = {u_i: 1}
           a.list_cur[pos] = make_int2(s, x);
         } else {
           atomicOr(&a.ctr[C_OVERFLOW], 1ull);
@@ -466,7 +478,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
 // them).  Per slot, the out-degrees of its kept entries are summed: that
 // decides between pushing and pulling the slot's level.
 __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restrict__ slots,
-                                                 const int2* __restrict__ list_cur, float* __restrict__ dense_cur,
+                                                 const int2* __restrict__ list_cur, long long* __restrict__ dense_cur,
                                                  float* __restrict__ item_val, uint2* __restrict__ item_row,
                                                  int2* __restrict__ chunk_list, uint64_t list_cap, uint64_t chunk_cap,
                                                  unsigned long long* __restrict__ slot_edges,
@@ -484,8 +496,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
     unsigned long long mydeg = 0;
     if (i < cnt) {
       const int2 it = list_cur[i];
-      float* d = dense_cur + (size_t)it.x * n + it.y;
-      const float val = *d;
+      long long* d = dense_cur + (size_t)it.x * n + it.y;
+      const float val = grid_f32(*d);
       const Slot& sl = slots[it.x];
       uint2 row = make_uint2(0u, 0u);
       if (fabsf(val - sl.thr) <= 1e-5f * sl.thr) {  // FP32 rounding may decide this test
@@ -506,7 +518,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       } else {
         ++pruned;
       }
-      if (!row.y) *d = 0.0f;
+      if (!row.y) *d = 0;
       item_row[i] = row;
     }
     // segmented sum of out-degrees per slot over the wavefront
@@ -628,7 +640,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned lo
 
 struct ExpandArgs {
   int32_t n;
-  float* dense_cur;
+  long long* dense_cur;
   float* mat_cur;  // dense frontier matrix (n x kLanes) of this step
   const int32_t* pull_flag;
   const int2* list_cur;
@@ -636,7 +648,7 @@ struct ExpandArgs {
   const uint2* item_row;
   const int2* chunk_list;
   const Slot* slots;
-  float* dense_next;
+  long long* dense_next;
   int2* list_next;
   uint64_t list_cap;
   uint64_t chunk_cap;
@@ -686,19 +698,22 @@ __device__ __forceinline__ void wave_append(WaveBuf& wb, bool flag, int32_t s, i
 
 // One out-edge x -> v of a listed entry of slot s: add sqrt(c)/|I(v)| *
 // Score(x) to H_{j+1}[v] unless v is the excluded walk node u_{i-j-1}
-// (Alg. 2).  Returns whether (s, v) became a new frontier entry.
+// (Alg. 2); sv = fl32(Score(x) * sqrt(c)).  Returns whether (s, v) became a
+// new frontier entry.
 __device__ __forceinline__ bool visit_edge(const ExpandArgs& a, int32_t s, int32_t v, float sv, const Slot& sl,
                                            unsigned long long& nfinal) {
   if (v == sl.excl) return false;
   const float c = sv * sl.inv_indeg[v];
-  if (!(c >= 1.17549435e-38f)) return false;  // contributions below FLT_MIN are dropped
+  const long long q = to_grid(c);
+  if (q == 0) return false;  // below the grid
   if (sl.last) {
     unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
     ++nfinal;
     return false;
   }
-  const float old = unsafeAtomicAdd(&a.dense_next[(size_t)s * a.n + v], c);
-  return old == 0.0f;
+  const unsigned long long old =
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.dense_next[(size_t)s * a.n + v]), (unsigned long long)q);
+  return old == 0ull;
 }
 
 // PROBE expansion.  Part 1: workgroups take tiles of kTile listed entries,
@@ -734,12 +749,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
         const uint2 row = a.item_row[i];
         if (row.y) {
           const int2 it = a.list_cur[i];
-          float* dc = a.dense_cur + (size_t)it.x * a.n + it.y;
+          long long* dc = a.dense_cur + (size_t)it.x * a.n + it.y;
           if (a.pull_flag[it.x]) {  // slot moved to a dense column: scatter
-            a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = *dc;
-            *dc = 0.0f;
+            a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = grid_f32(*dc);
+            *dc = 0;
           } else {  // pushed: its score is consumed here
-            *dc = 0.0f;
+            *dc = 0;
             if (!(row.y & kBigFlag)) {
               deg[r] = row.y;
               s_start[j] = row.x;
@@ -834,17 +849,17 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
 }
 
 // Dense levels.  Up to kLanes slots keep their frontier as a column of a
-// node-major matrix M (n x kLanes FP32, one 256-byte row per node).  One pass
-// per step advances all of them together, by pulling: for every target v,
-//   H_{j+1}[v] = sqrt(c)/|I(v)| * sum over in-neighbours x of v of H_j[x],
-// with Rule 2 applied to H_j[x] as it is read (values <= thr count as 0) and
-// the excluded walk node skipped (the same sums as Alg. 2, accumulated per
-// target).  A wavefront handles one target and its 64 lanes the 64 columns,
-// so each in-neighbour costs one contiguous row read; the row of v in the
-// next matrix is written whole.  In-rows longer than kPullLane edges are
-// summed in kPullChunk-edge chunks into raw partial sums, finished by
-// k_dense_fin.  On a probe's last level the value goes into the FP64
-// estimate instead (one add per target, not per edge).
+// node-major matrix M (n x kLanes FP32 scores, one 256-byte row per node).
+// One pass per step advances all of them together, by pulling: for every
+// target v, H_{j+1}[v] is the grid sum over in-neighbours x of v of the same
+// per-edge contributions the push path adds, with Rule 2 applied to H_j[x]
+// as it is read and the excluded walk node skipped (Alg. 2 accumulated per
+// target; exact sums make it equal to pushing).  A wavefront handles one
+// target and its 64 lanes the 64 columns, so each in-neighbour costs one
+// contiguous row read; the row of v in the next matrix is written whole.
+// In-rows longer than kPullLane edges are summed in kPullChunk-edge chunks
+// into partial grid sums, finished by k_dense_fin.  On a probe's last level
+// the value goes into the FP64 estimate instead (one add per target).
 
 struct DenseArgs {
   int32_t n;
@@ -853,7 +868,7 @@ struct DenseArgs {
   const DenseVer* dv;
   const float* mat_cur;
   float* mat_next;
-  float* npart;  // n x kLanes raw sums of long in-rows
+  long long* npart;  // n x kLanes partial grid sums of long in-rows
   int32_t* has_next;
   unsigned long long* ctr;
 };
@@ -890,30 +905,33 @@ __device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigne
   return li;
 }
 
-__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, int32_t v, float sum,
-                                             float inv, unsigned long long gw, unsigned long long& nfinal) {
+// Target v of lane g with grid sum q of its contributions: the FP64
+// estimate on a probe's last level, else the next level's FP32 score.
+__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, int32_t v, long long q,
+                                             unsigned long long gw, unsigned long long& nfinal) {
   float out = 0.0f;
   bool nz = false;
-  if (li.active && v != li.excl && sum > 0.0f) {
-    const float c = sum * li.sc * inv;
-    if (c >= 1.17549435e-38f) {
-      if (li.last) {
-        unsafeAtomicAdd(&li.acc[v], (double)c * li.w);
-        ++nfinal;
-      } else {
-        out = c;
-        nz = true;
-        // the next level tests this value against thr * sqrt(c)
-        const float t = li.thr * li.sc;
-        if (fabsf(c - t) <= 1e-5f * t) unsafeAtomicAdd(li.flip, li.flip_unit);
-      }
+  if (li.active && v != li.excl && q > 0) {
+    if (li.last) {
+      unsafeAtomicAdd(&li.acc[v], grid_f64(q) * li.w);
+      ++nfinal;
+    } else {
+      out = grid_f32(q);
+      nz = true;
+      // the next level tests this value against thr * sqrt(c)
+      const float t = li.thr * li.sc;
+      if (fabsf(out - t) <= 1e-5f * t) unsafeAtomicAdd(li.flip, li.flip_unit);
     }
   }
   if ((unsigned long long)g < gw) a.mat_next[(size_t)v * kLanes + g] = out;
   return nz;
 }
 
-__device__ __forceinline__ float pruned(float x, float thr) { return x > thr ? x : 0.0f; }
+// Grid value of the contribution of in-neighbour score h to target v (the
+// push path's fl32(fl32(h * sqrt c) * 1/|I(v)|)); 0 when Rule 2 removes h.
+__device__ __forceinline__ long long pull_term(float h, float thr, float sc, float inv) {
+  return h > thr ? to_grid((h * sc) * inv) : 0ll;
+}
 
 __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   __shared__ unsigned long long s_nz;
@@ -937,21 +955,22 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
     const uint2 row = dv.in_rows[v];
     if (row.y > kPullLane) continue;  // long in-row: chunks + k_dense_fin
-    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     if (li.active) {
+      const float inv = dv.inv_indeg[v];
       uint32_t k = 0;
       for (; k + 4 <= row.y; k += 4) {
         const int32_t x0 = dv.in_col[row.x + k], x1 = dv.in_col[row.x + k + 1];
         const int32_t x2 = dv.in_col[row.x + k + 2], x3 = dv.in_col[row.x + k + 3];
-        s0 += pruned(m[(size_t)x0 * kLanes], li.thr);
-        s1 += pruned(m[(size_t)x1 * kLanes], li.thr);
-        s2 += pruned(m[(size_t)x2 * kLanes], li.thr);
-        s3 += pruned(m[(size_t)x3 * kLanes], li.thr);
+        s0 += pull_term(m[(size_t)x0 * kLanes], li.thr, li.sc, inv);
+        s1 += pull_term(m[(size_t)x1 * kLanes], li.thr, li.sc, inv);
+        s2 += pull_term(m[(size_t)x2 * kLanes], li.thr, li.sc, inv);
+        s3 += pull_term(m[(size_t)x3 * kLanes], li.thr, li.sc, inv);
       }
-      for (; k < row.y; ++k) s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
+      for (; k < row.y; ++k) s0 += pull_term(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr, li.sc, inv);
     }
     inedges += row.y;
-    const bool nz = dense_finish(a, li, g, (int32_t)v, (s0 + s1) + (s2 + s3), dv.inv_indeg[v], gw, nfinal);
+    const bool nz = dense_finish(a, li, g, (int32_t)v, (s0 + s1) + (s2 + s3), gw, nfinal);
     nz_mask |= __ballot(nz);
   }
   const unsigned long long nch = dv.heavy_cnt[1];
@@ -961,15 +980,17 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
     const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
     inedges += e - (uint32_t)ch.y;
     if (!li.active) continue;
-    float s0 = 0.0f, s1 = 0.0f;
+    const float inv = dv.inv_indeg[ch.x];
+    long long s0 = 0, s1 = 0;
     uint32_t k = (uint32_t)ch.y;
     for (; k + 2 <= e; k += 2) {
-      s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
-      s1 += pruned(m[(size_t)dv.in_col[row.x + k + 1] * kLanes], li.thr);
+      s0 += pull_term(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr, li.sc, inv);
+      s1 += pull_term(m[(size_t)dv.in_col[row.x + k + 1] * kLanes], li.thr, li.sc, inv);
     }
-    if (k < e) s0 += pruned(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr);
-    const float part = s0 + s1;
-    if (part > 0.0f) unsafeAtomicAdd(&a.npart[(size_t)ch.x * kLanes + g], part);
+    if (k < e) s0 += pull_term(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr, li.sc, inv);
+    const long long part = s0 + s1;
+    if (part > 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.npart[(size_t)ch.x * kLanes + g]), (unsigned long long)part);
   }
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
@@ -998,13 +1019,13 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   const unsigned long long nh = dv.heavy_cnt[0];
   for (uint64_t i = wave; i < nh; i += nwaves) {
     const int32_t v = dv.heavy_nodes[i];
-    float sum = 0.0f;
+    long long sum = 0;
     if (li.active) {
-      float* p = a.npart + (size_t)v * kLanes + g;
+      long long* p = a.npart + (size_t)v * kLanes + g;
       sum = *p;
-      *p = 0.0f;
+      *p = 0;
     }
-    const bool nz = dense_finish(a, li, g, v, sum, dv.inv_indeg[v], gw, nfinal);
+    const bool nz = dense_finish(a, li, g, v, sum, gw, nfinal);
     nz_mask |= __ballot(nz);
   }
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
@@ -1133,12 +1154,12 @@ void session_free(Session* s) {
 
 // Probe slots: enough concurrent probes to fill the GPU (more slots also
 // mean fewer level steps), at most 1024 by default, and never more than the
-// per-slot buffers (dense scores 8 B, frontier lists 16 B, scaled scores 4 B,
+// per-slot buffers (grid sums 16 B, frontier lists 16 B, scaled scores 4 B,
 // rows 8 B, chunks 8 B per node) fit in a fixed share of HBM, with slot * n
 // within 31 bits.  An explicit request is clamped the same way.
 int session_slots_for(int32_t n, int opt) {
-  const uint64_t budget = 48ull << 30;
-  uint64_t p = budget / (44ull * (uint64_t)n);
+  const uint64_t budget = 56ull << 30;
+  uint64_t p = budget / (52ull * (uint64_t)n);
   p = std::min<uint64_t>(p, ((1ull << 31) - 1) / (uint64_t)n);
   p = std::min<uint64_t>(p, opt > 0 ? (uint64_t)std::min(opt, kSchedThreads * kSlotsPerSchedThread) : 1024ull);
   return (int)std::max<uint64_t>(p, 1);
@@ -1175,12 +1196,12 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->pull_flag, sizeof(int32_t) * (size_t)P));
   PS_TRY(devbuf_reserve(s->mat[0], sizeof(float) * (size_t)n * kLanes));
   PS_TRY(devbuf_reserve(s->mat[1], sizeof(float) * (size_t)n * kLanes));
-  PS_TRY(devbuf_reserve(s->npart, sizeof(float) * (size_t)n * kLanes));
+  PS_TRY(devbuf_reserve(s->npart, sizeof(long long) * (size_t)n * kLanes));
   PS_TRY(devbuf_reserve(s->lane_slot, sizeof(int32_t) * kLanes));
   PS_TRY(devbuf_reserve(s->dense_ver, sizeof(DenseVer)));
   const bool fresh = !s->dense[0].p || shape;
-  PS_TRY(devbuf_reserve(s->dense[0], sizeof(float) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->dense[1], sizeof(float) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->dense[0], sizeof(long long) * s->list_cap));
+  PS_TRY(devbuf_reserve(s->dense[1], sizeof(long long) * s->list_cap));
   PS_TRY(devbuf_reserve(s->list[0], sizeof(int2) * s->list_cap));
   PS_TRY(devbuf_reserve(s->list[1], sizeof(int2) * s->list_cap));
   PS_TRY(devbuf_reserve(s->item_val, sizeof(float) * s->list_cap));
@@ -1204,11 +1225,11 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
   if (!s->h_ctr) PS_HIP(hipHostMalloc((void**)&s->h_ctr, sizeof(uint64_t) * C_COUNT, 0));
   if (fresh) {
-    PS_HIP(hipMemsetAsync(s->dense[0].p, 0, sizeof(float) * s->list_cap, st));
-    PS_HIP(hipMemsetAsync(s->dense[1].p, 0, sizeof(float) * s->list_cap, st));
+    PS_HIP(hipMemsetAsync(s->dense[0].p, 0, sizeof(long long) * s->list_cap, st));
+    PS_HIP(hipMemsetAsync(s->dense[1].p, 0, sizeof(long long) * s->list_cap, st));
   }
-  for (DevBuf* b : {&s->mat[0], &s->mat[1], &s->npart})
-    PS_HIP(hipMemsetAsync(b->p, 0, sizeof(float) * (size_t)n * kLanes, st));
+  for (DevBuf* b : {&s->mat[0], &s->mat[1]}) PS_HIP(hipMemsetAsync(b->p, 0, sizeof(float) * (size_t)n * kLanes, st));
+  PS_HIP(hipMemsetAsync(s->npart.p, 0, sizeof(long long) * (size_t)n * kLanes, st));
   k_reset_lanes<<<1, kLanes, 0, st>>>(s->lane_slot.as<int32_t>());
   PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
   k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(s->slots.as<Slot>(), s->has_next.as<int32_t>(), P);
@@ -1421,11 +1442,11 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
                  hipEvent_t ev2) {
   const int nxt = cur ^ 1;
   unsigned long long* ctr = s->counters.as<unsigned long long>();
-  k.sa.dense_cur = s->dense[cur].as<float>();
+  k.sa.dense_cur = s->dense[cur].as<long long>();
   k.sa.list_cur = s->list[cur].as<int2>();
   k.sa.cur = cur;
   k_sched<<<1, kSchedThreads, 0, st>>>(k.sa);
-  k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<float>(),
+  k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<long long>(),
                                        s->item_val.as<float>(), s->item_row.as<uint2>(), s->chunk_list.as<int2>(),
                                        s->list_cap, s->chunk_cap, s->slot_edges.as<unsigned long long>(), ctr, cur);
   k_pick<<<1, kSchedThreads, 0, st>>>(s->P, s->slot_edges.as<unsigned long long>(), s->slots.as<Slot>(),
@@ -1433,9 +1454,9 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
                                       s->dense_ver.as<DenseVer>(), ctr);
   k.ea.list_cur = s->list[cur].as<int2>();
   k.ea.cur = cur;
-  k.ea.dense_cur = s->dense[cur].as<float>();
+  k.ea.dense_cur = s->dense[cur].as<long long>();
   k.ea.mat_cur = s->mat[cur].as<float>();
-  k.ea.dense_next = s->dense[nxt].as<float>();
+  k.ea.dense_next = s->dense[nxt].as<long long>();
   k.ea.list_next = s->list[nxt].as<int2>();
   k.ea.nxt = nxt;
   if (ev0) (void)hipEventRecord(ev0, st);
@@ -1448,7 +1469,7 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   da.dv = s->dense_ver.as<DenseVer>();
   da.mat_cur = s->mat[cur].as<float>();
   da.mat_next = s->mat[nxt].as<float>();
-  da.npart = s->npart.as<float>();
+  da.npart = s->npart.as<long long>();
   da.has_next = s->has_next.as<int32_t>();
   da.ctr = ctr;
   k_dense<<<kStepGrid, kBlock, 0, st>>>(da);

@@ -22,13 +22,24 @@ namespace {
 
 constexpr uint64_t kMinSlack = 1ull << 20;
 
+// 1/d rounded to the nearest FP32 number, in integer arithmetic so that it
+// does not depend on how the compiler divides: with 2^k <= d < 2^(k+1) and d
+// not a power of two, 1/d lies in (2^-(k+1), 2^-k), its 24-bit mantissa is
+// round(2^(24+k) / d) (never a tie) and the value is that times 2^-(24+k).
+__host__ __device__ float recip_rn(uint32_t d) {
+  const int k = 31 - __builtin_clz(d);
+  if ((d & (d - 1)) == 0) return ldexpf(1.0f, -k);
+  const uint64_t mant = ((1ull << (24 + k)) + (d >> 1)) / d;
+  return ldexpf((float)mant, -(24 + k));
+}
+
 __global__ void k_patch_rows(const int32_t* __restrict__ node, const uint2* __restrict__ row, int32_t cnt,
                              uint2* __restrict__ rows, float* __restrict__ inv_indeg) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   const int32_t v = node[i];
   rows[v] = row[i];
-  if (inv_indeg) inv_indeg[v] = row[i].y ? 1.0f / (float)row[i].y : 0.0f;
+  if (inv_indeg) inv_indeg[v] = row[i].y ? recip_rn(row[i].y) : 0.0f;
 }
 
 // Lists the nodes with more than kPullLane in-neighbours and cuts their
@@ -163,7 +174,7 @@ ps_status upload_full(ps_graph* g, GraphVersion* v) {
     out_rows[x] = make_uint2((uint32_t)out_col.size(), (uint32_t)lo);
     in_col.insert(in_col.end(), ri, ri + li);
     out_col.insert(out_col.end(), ro, ro + lo);
-    inv[x] = li ? 1.0f / (float)li : 0.0f;
+    inv[x] = li ? recip_rn((uint32_t)li) : 0.0f;
   }
   in_store->used = in_col.size();
   out_store->used = out_col.size();

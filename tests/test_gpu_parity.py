@@ -1,11 +1,16 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
-Tolerance (stated per result): probe scores are FP32 on the GPU and FP64 in
-the oracle; estimates are accumulated in FP64 on both.  Every estimate must
-agree within 1e-5 absolute plus the oracle's Rule-2 flip allowance: the sum,
-over pruning tests that landed within 1e-5 relative of eps_p, of the largest
-share of the estimate such an entry can carry (its score times
-sqrt(c)^(levels left), weighted by walks/n_r).  Walks must agree bit for bit.
+Tolerances.  The kernels compute probe scores in the FP32 score model: FP32
+scores, every contribution fl32(fl32(Score * fl32(sqrt c)) * fl32(1/|I(v)|)),
+exact sums on the grid 2^-62, Rule 2 decided on the FP32 score.  The oracle's
+FP32 model computes the same numbers on the CPU, so the only difference left
+is the order of the FP64 additions into the estimates: GPU and oracle (and
+two GPU runs of one query, alone or in any mix) agree within TOL_MODEL = 1e-12.
+Against the oracle's plain FP64 evaluation the stated error is 1e-5 plus the
+Rule-2 near-threshold allowances (ps_result.flip_allowance and the oracle's
+own): the sum, over pruning tests whose score fell within 1e-5 relative of
+the threshold, of eps_p times the walks sharing the probe over n_r.  Walks
+must agree bit for bit.
 """
 
 import os
@@ -18,7 +23,8 @@ from synth import graphs
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
+TOL = 1e-5          # GPU vs the FP64 definition, plus allowances
+TOL_MODEL = 1e-12   # GPU vs the FP32 score model / GPU vs GPU: FP64 summation order only
 
 
 @pytest.fixture(scope="module")
@@ -36,12 +42,20 @@ def ctx(ps):
     c.close()
 
 
-def _parity(gpu, ref, stats, what, gpu_flip=0.0):
-    tol = TOL + stats["flip_allowance"] + gpu_flip
+def _parity(gpu, ref, stats, what):
+    """GPU result against the oracle's FP32 score model."""
     err = np.abs(gpu - ref)
     worst = int(np.argmax(err))
-    print(f"{what}: max|gpu-oracle| = {err.max():.3e} at {worst} (tol {tol:.3e}, near-threshold {stats['near_threshold']})",
-          flush=True)
+    print(f"{what}: max|gpu-oracle32| = {err.max():.3e} at {worst} (tol {TOL_MODEL:.1e}, "
+          f"near-threshold tests {stats['near_threshold']})", flush=True)
+    assert err.max() <= TOL_MODEL, what
+
+
+def _parity64(gpu, ref, stats, what, gpu_flip):
+    """GPU result against the FP64 definition: 1e-5 plus both allowances."""
+    tol = TOL + stats["flip_allowance"] + gpu_flip
+    err = np.abs(gpu - ref)
+    print(f"{what}: max|gpu-oracle64| = {err.max():.3e} (tol {tol:.3e})", flush=True)
     assert err.max() <= tol, what
 
 
@@ -55,15 +69,13 @@ def _alone(ps, G, q):
 
 
 def _same_query(a, fa, b, fb, what):
-    """Two runs of one query: equal within TOL plus both allowances (FP32
-    summation order differs; a Rule-2 test that FP32 rounding may decide
-    either way is covered by the allowances)."""
+    """Two runs of one query (alone, batched, served, shards): the same FP32
+    scores, so equal up to FP64 summation order; the allowances are equal."""
     x = a[1] if isinstance(a, tuple) else a
     y = b[1] if isinstance(b, tuple) else b
     err = float(np.abs(x - y).max())
-    tol = TOL + fa + fb
-    print(f"{what}: max|a-b| = {err:.3e} (tol {tol:.3e})", flush=True)
-    assert err <= tol, what
+    print(f"{what}: max|a-b| = {err:.3e} (tol {TOL_MODEL:.1e}; allowances {fa:.2e} {fb:.2e})", flush=True)
+    assert err <= TOL_MODEL, what
     return err
 
 
@@ -104,7 +116,7 @@ def test_single_source_er_workload(ps, er, orc):
     # eps = 0.1, delta = 0.01, query node 0, seed 1.
     n, s, d, G, O = er
     gpu = ps.ps_single_source(G, 0, 0.6, 0.1, 0.01, 1)
-    ref, st = orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1)
+    ref, st = orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1, precision="f32")
     _parity(gpu, ref, st, "er u=0")
     assert gpu[0] == 1.0
 
@@ -114,7 +126,7 @@ def test_single_source_power_law(ps, cl20k, orc, eps):
     n, s, d, G, O = cl20k
     for i, u in enumerate(graphs.query_nodes(n, d, 3, seed=11)):
         gpu = ps.ps_single_source(G, int(u), 0.6, eps, 0.01, 3 + i)
-        ref, st = orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i)
+        ref, st = orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i, precision="f32")
         _parity(gpu, ref, st, f"cl20k u={u} eps={eps}")
 
 
@@ -123,7 +135,7 @@ def test_single_source_small_slot_count(ps, cl20k, orc):
     n, s, d, G, O = cl20k
     u = int(graphs.query_nodes(n, d, 1, seed=5)[0])
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 8, slots=3)
-    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8)
+    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8, precision="f32")
     _parity(gpu, ref, st, "cl20k slots=3")
 
 
@@ -131,7 +143,7 @@ def test_no_pruning_and_walk_cap(ps, cl20k, orc):
     n, s, d, G, O = cl20k
     u = int(graphs.query_nodes(n, d, 1, seed=6)[0])
     gpu = ps.ps_single_source(G, u, 0.6, 0.2, 0.01, 4, eps_p=0.0, max_len=6)
-    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4)
+    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4, precision="f32")
     _parity(gpu, ref, st, "no pruning L=6")
 
 
@@ -148,14 +160,14 @@ def test_walk_range_shards_add_up(ps, cl20k, orc):
     tot = sum(parts)
     tot[u] = 1.0
     _same_query(tot, sum(flips), full, ff, "walk shards vs whole")
-    ref, st = orc.batch(O, u, p, 5, 1000, 1001)
-    _parity(parts[1], ref, st, "single-walk shard", flips[1])
+    ref, st = orc.batch(O, u, p, 5, 1000, 1001, precision="f32")
+    _parity(parts[1], ref, st, "single-walk shard")
 
 
 def test_bias_shift(ps, er, orc):
     n, s, d, G, O = er
     gpu = ps.ps_single_source(G, 3, 0.6, 0.1, 0.01, 2, bias_shift=1)
-    ref, st = orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True)
+    ref, st = orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True, precision="f32")
     _parity(gpu, ref, st, "bias shift")
 
 
@@ -200,10 +212,9 @@ def test_topk_matches_oracle(ps, cl20k, orc):
     u = int(graphs.query_nodes(n, d, 1, seed=12)[0])
     k = 50
     nodes, vals = ps.ps_topk(G, u, k, 0.6, 0.05, 0.01, 21)
-    fg = G.ctx.stats()["flip_allowance"]
-    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 21)
+    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 21, precision="f32")
     rn, rv = orc.topk(ref, u, k)
-    tol = TOL + st["flip_allowance"] + fg
+    tol = TOL_MODEL
     assert u not in nodes.tolist()
     assert np.all(np.diff(vals) <= 0)
     # same set except among entries within 2 tol of the k-th score
@@ -213,6 +224,18 @@ def test_topk_matches_oracle(ps, cl20k, orc):
     for v, x in zip(nodes.tolist(), vals.tolist()):
         assert abs(x - ref[v]) <= tol
         assert ref[v] >= kth - 2 * tol
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.05])
+def test_error_against_fp64_definition_is_stated(ps, cl20k, orc, eps):
+    # The stated per-result error: against the plain FP64 evaluation the GPU
+    # is within 1e-5 plus its own and the oracle's near-threshold allowances.
+    n, s, d, G, O = cl20k
+    for i, u in enumerate(graphs.query_nodes(n, d, 2, seed=31)):
+        gpu = ps.ps_single_source(G, int(u), 0.6, eps, 0.01, 50 + i)
+        fg = G.ctx.stats()["flip_allowance"]
+        ref, st = orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 50 + i, precision="f64")
+        _parity64(gpu, ref, st, f"cl20k u={int(u)} eps={eps} vs FP64", fg)
 
 
 def test_batch_equals_alone(ps, cl20k):
@@ -233,7 +256,7 @@ def test_device_output_tensor(ps, er, orc):
     out = torch.zeros(n, dtype=torch.float64, device="cuda:0")
     ps.ps_single_source(G, 7, 0.6, 0.1, 0.01, 3, out=out)
     torch.cuda.synchronize()
-    ref, st = orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3)
+    ref, st = orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3, precision="f32")
     _parity(out.cpu().numpy(), ref, st, "device output")
 
 
@@ -256,8 +279,8 @@ def test_dynamic_graph_equals_rebuilt(ps, ctx, orc):
     a, fa = _alone(ps, G, q)
     b, fb = _alone(ps, R, q)
     O = orc.Graph(n, es, ed)
-    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5)
-    _parity(a, ref, st, "updated graph vs oracle", fa)
+    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5, precision="f32")
+    _parity(a, ref, st, "updated graph vs oracle")
     _same_query(a, fa, b, fb, "updated vs rebuilt graph")
     # invalid updates are reported per edge and skipped
     pe, _ = G.update([es[0], 1, 2], [ed[0], 1, (ed[0] + 1) % n], [0, 0, 1])
@@ -281,7 +304,7 @@ def test_full_size_power_law_walk_shards(ps, ctx, orc):
             w = orc.walk(O, u, k, 3 + i, p)
             assert lens[k] == len(w) and (nodes[k, : len(w)] == w).all()
         gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3 + i, walk_begin=0, walk_end=120)
-        ref, st = orc.single_source(O, u, p, 3 + i, 0, 120)
+        ref, st = orc.single_source(O, u, p, 3 + i, 0, 120, precision="f32")
         _parity(gpu, ref, st, f"cl1m u={u} walks [0,120)")
     full = ps.ps_single_source(G, int(q[0]), 0.6, 0.05, 0.01, 3)
     assert full[int(q[0])] == 1.0 and full.min() >= 0.0
@@ -371,7 +394,7 @@ def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
         assert st["pull_levels"] > 0 and st["pull_edges"] > 0
     if pull == -1:
         assert st["pull_levels"] == 0
-    ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11)
+    ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f32")
     _parity(gpu, ref, ost, f"pull_edges={pull}")
 
 
@@ -386,7 +409,7 @@ def test_autotune_keeps_results(ps, ctx, cl20k, orc, tmp_path):
     assert t2["from_cache"] == 1 and t2["slots"] == t["slots"] and t2["dense_edges"] == t["dense_edges"]
     u = int(qn[0])
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 19)
-    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19)
+    ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19, precision="f32")
     _parity(gpu, ref, st, f"autotuned {t}")
 
 
@@ -433,8 +456,8 @@ def test_full_size_batched_mixed_eps(ps, ctx, orc):
         _walks_match(ps, G, O, orc, q["u"], q["eps"], q["seed"], 400, 8)
         gpu = ps.ps_single_source(G, q["u"], 0.6, q["eps"], 0.01, q["seed"], walk_begin=0, walk_end=40)
         fg = G.ctx.stats()["flip_allowance"]
-        ref, st = orc.single_source(O, q["u"], p, q["seed"], 0, 40)
-        _parity(gpu, ref, st, f"cl5m u={q['u']} eps={q['eps']} walks [0,40)", fg)
+        ref, st = orc.single_source(O, q["u"], p, q["seed"], 0, 40, precision="f32")
+        _parity(gpu, ref, st, f"cl5m u={q['u']} eps={q['eps']} walks [0,40)")
 
 
 @pytest.mark.skipif(os.environ.get("PS_SKIP_FULL") == "1", reason="full-size case skipped")
