@@ -32,15 +32,16 @@ NQ = 32
 
 def expand_bytes(st: dict) -> float:
     """Algorithmic bytes moved by k_expand for the given work counters:
-    20 B per expanded entry (list entry 8, score 4, row start/len 8),
+    28 B per expanded entry (list entry 8, scaled score 4, row start/len 8,
+    clearing its 8-byte grid sum),
     8 B per scanned out-edge (neighbour id 4, 1/|I(v)| 4),
-    8 B per inner-level contribution (FP32 score read-modify-write),
+    16 B per inner-level contribution (64-bit grid sum read-modify-write),
     8 B per new next-level entry (list write),
     16 B per final contribution (FP64 estimate read-modify-write)."""
     F, E = st["entries_expanded"], st["edges_scanned"]
     N, Fin = st["next_entries"], st["final_adds"]
     inner = max(E - Fin, 0)
-    return 20.0 * F + 8.0 * E + 8.0 * inner + 8.0 * N + 16.0 * Fin
+    return 28.0 * F + 8.0 * E + 16.0 * inner + 8.0 * N + 16.0 * Fin
 
 
 def cpu_baseline(n, s, d, q, seconds_target=15.0):

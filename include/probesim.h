@@ -183,6 +183,16 @@ ps_status ps_walks(ps_graph* g, int32_t u, double c, double eps, double delta, u
 ps_status ps_single_source(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
                            const ps_options* opt, double* out);
 
+/* The same query as ps_single_source, returned sparsely: the nodes with a
+ * nonzero estimate (u included, with 1) in ascending id order, with their
+ * estimates.  Writes min(total, cap) pairs to nodes/scores (host or device)
+ * and the total to *count (host).  Returns PS_ERR_INVALID_ARG when total >
+ * cap (the first cap pairs are still written), so a caller can retry with
+ * cap = *count.  With bias_shift every node is nonzero. */
+ps_status ps_single_source_sparse(ps_graph* g, int32_t u, double c, double eps, double delta, uint64_t seed,
+                                  const ps_options* opt, int64_t cap, int32_t* nodes, double* scores,
+                                  int64_t* count);
+
 /* Approximate top-k query (Definition 2): the k nodes v != u with the largest
  * estimates, ties broken by ascending node id, written to nodes[k] and their
  * estimates to scores[k].  k must lie in [1, n-1]. */

@@ -30,7 +30,8 @@ PS_MAX_WALK_LEN = 64
 EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
     "ps_graph_free", "ps_graph_info", "ps_graph_update", "ps_graph_edges", "ps_options_default",
-    "ps_derive_params", "ps_walks", "ps_single_source", "ps_topk", "ps_batch", "ps_get_stats",
+    "ps_derive_params", "ps_walks", "ps_single_source", "ps_single_source_sparse", "ps_topk", "ps_batch",
+    "ps_get_stats",
     "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
 ]
 
@@ -141,6 +142,8 @@ def load_library(path: str = LIB_PATH):
                       C.c_int64, vp, vp], C.c_int),
         "ps_single_source": ([vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), vp],
                              C.c_int),
+        "ps_single_source_sparse": ([vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options),
+                                     C.c_int64, vp, vp, P(C.c_int64)], C.c_int),
         "ps_topk": ([vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), vp,
                      vp], C.c_int),
         "ps_batch": ([vp, C.c_int32, P(Query), P(Options), P(Result)], C.c_int),
@@ -291,6 +294,24 @@ def ps_single_source(g: Graph, u, c, eps, delta, seed, out=None, **opt):
     _check(load_library().ps_single_source(g._h, int(u), c, eps, delta, C.c_uint64(seed), C.byref(o), _ptr(out)),
            "ps_single_source")
     return out
+
+
+def ps_single_source_sparse(g: Graph, u, c, eps, delta, seed, cap=None, out_nodes=None, out_scores=None, **opt):
+    """Nonzero estimates as (nodes ascending, scores); cap defaults to n.  A
+    cap below the number of nonzero entries raises ProbeSimError with the
+    needed count in its `count` attribute."""
+    cap = g.n if cap is None else int(cap)
+    nodes = out_nodes if out_nodes is not None else np.zeros(max(cap, 1), np.int32)
+    scores = out_scores if out_scores is not None else np.zeros(max(cap, 1), np.float64)
+    cnt = C.c_int64(0)
+    o = options(**opt)
+    code = load_library().ps_single_source_sparse(g._h, int(u), c, eps, delta, C.c_uint64(seed), C.byref(o), cap,
+                                                  _ptr(nodes), _ptr(scores), C.byref(cnt))
+    if code != PS_OK:
+        err = ProbeSimError(code, "ps_single_source_sparse")
+        err.count = cnt.value
+        raise err
+    return nodes[: cnt.value], scores[: cnt.value]
 
 
 def ps_topk(g: Graph, u, k, c, eps, delta, seed, out_nodes=None, out_scores=None, **opt):

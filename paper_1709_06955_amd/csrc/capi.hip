@@ -183,6 +183,22 @@ extern "C" ps_status ps_single_source(ps_graph* g, int32_t u, double c, double e
   return run_locked(g, {q}, {o}, opt);
 }
 
+extern "C" ps_status ps_single_source_sparse(ps_graph* g, int32_t u, double c, double eps, double delta,
+                                             uint64_t seed, const ps_options* opt, int64_t cap, int32_t* nodes,
+                                             double* scores, int64_t* count) {
+  if (!g || cap < 0 || !count || (cap > 0 && (!nodes || !scores))) return PS_ERR_INVALID_ARG;
+  QueryRun q;
+  PS_TRY(make_query_run(g, u, 0, c, eps, delta, seed, opt, &q));
+  QueryOut o;
+  o.scores = scores;
+  o.nodes = nodes;
+  o.cap = cap;
+  o.count = count;
+  *count = 0;
+  PS_TRY(run_locked(g, {q}, {o}, opt));
+  return *count > cap ? PS_ERR_INVALID_ARG : PS_OK;
+}
+
 extern "C" ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
                              const ps_options* opt, int32_t* nodes, double* scores) {
   if (!g || !nodes || !scores || k < 1) return PS_ERR_INVALID_ARG;

@@ -1051,6 +1051,17 @@ __global__ void k_topk_keys(int32_t n, int32_t u, const double* __restrict__ s, 
   }
 }
 
+struct NonZero {
+  const double* acc;
+  __device__ bool operator()(int32_t v) const { return acc[v] != 0.0; }
+};
+
+__global__ void k_gather_scores(const double* __restrict__ acc, const int32_t* __restrict__ ids, int64_t cnt,
+                                double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) out[i] = acc[ids[i]];
+}
+
 // ------------------------------------------------------------- host side ----
 
 uint64_t next_pow2(uint64_t x) {
@@ -1145,7 +1156,8 @@ void session_free(Session* s) {
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
                     &s->keys,
                     &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
-                    &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp};
+                    &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp,
+                    &s->sel_count};
   for (DevBuf* b : bufs) devbuf_free(*b);
   if (s->h_ctr) (void)hipHostFree(s->h_ctr);
   if (s->step_pair) (void)hipGraphExecDestroy(s->step_pair);
@@ -1550,7 +1562,32 @@ ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, con
   k_finalize<<<grid_for((uint64_t)n, kBlock) > 4096 ? 4096 : grid_for((uint64_t)n, kBlock), kBlock, 0, st>>>(
       n, s->qrec.as<QueryDev>(), r);
   PS_HIP(hipGetLastError());
-  if (q.k <= 0) {
+  if (out.cap >= 0) {
+    // nonzero estimates in ascending node order (stable selection)
+    PS_TRY(devbuf_reserve(s->sort_vals[0], sizeof(int32_t) * (size_t)n));
+    PS_TRY(devbuf_reserve(s->sort_keys[0], sizeof(double) * (size_t)n));
+    PS_TRY(devbuf_reserve(s->sel_count, sizeof(int64_t)));
+    const NonZero pred{acc};
+    const hipcub::CountingInputIterator<int32_t> ids(0);
+    size_t tmp = 0;
+    PS_HIP(hipcub::DeviceSelect::If(nullptr, tmp, ids, s->sort_vals[0].as<int32_t>(), s->sel_count.as<int64_t>(), n,
+                                    pred, st));
+    PS_TRY(devbuf_reserve(s->sort_tmp, tmp));
+    PS_HIP(hipcub::DeviceSelect::If(s->sort_tmp.p, tmp, ids, s->sort_vals[0].as<int32_t>(), s->sel_count.as<int64_t>(),
+                                    n, pred, st));
+    int64_t total = 0;
+    PS_HIP(hipMemcpyAsync(&total, s->sel_count.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PS_HIP(hipStreamSynchronize(st));
+    const int64_t w = std::min(total, out.cap);
+    if (w > 0) {
+      k_gather_scores<<<grid_for((uint64_t)w, kBlock), kBlock, 0, st>>>(acc, s->sort_vals[0].as<int32_t>(), w,
+                                                                         s->sort_keys[0].as<double>());
+      PS_HIP(hipGetLastError());
+      PS_TRY(copy_out(out.nodes, s->sort_vals[0].p, sizeof(int32_t) * (size_t)w, st));
+      PS_TRY(copy_out(out.scores, s->sort_keys[0].p, sizeof(double) * (size_t)w, st));
+    }
+    *out.count = total;
+  } else if (q.k <= 0) {
     PS_TRY(copy_out(out.scores, acc, sizeof(double) * (size_t)n, st));
   } else {
     PS_TRY(devbuf_reserve(s->sort_keys[0], sizeof(double) * (size_t)n));

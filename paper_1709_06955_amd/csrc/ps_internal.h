@@ -200,6 +200,9 @@ struct QueryOut {
   double* scores = nullptr;  // n (single-source) or k (top-k); host or device
   int32_t* nodes = nullptr;  // k (top-k)
   double* flip = nullptr;    // the query's near-threshold allowance (host or device)
+  // sparse single-source output (cap >= 0): ascending nonzero entries
+  int64_t cap = -1;
+  int64_t* count = nullptr;  // host
 };
 
 // A persistent set of device buffers that runs the level steps of every
@@ -216,7 +219,7 @@ struct Session {
   DevBuf mat[2], npart, lane_slot, dense_ver;  // dense frontier lanes
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
-  DevBuf sort_keys[2], sort_vals[2], sort_tmp;
+  DevBuf sort_keys[2], sort_vals[2], sort_tmp, sel_count;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)
   hipGraphExec_t step_pair = nullptr;  // captured even + odd level step

@@ -249,6 +249,30 @@ def test_batch_equals_alone(ps, cl20k):
         _same_query(r, f, a, fa, f"batch vs alone u={q['u']} k={q['k']}")
 
 
+def test_sparse_output_equals_dense(ps, cl20k):
+    import torch
+
+    n, s, d, G, O = cl20k
+    u = int(graphs.query_nodes(n, d, 1, seed=77)[0])
+    dense = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 8)
+    nodes, vals = ps.ps_single_source_sparse(G, u, 0.6, 0.05, 0.01, 8)
+    nz = np.nonzero(dense)[0]
+    assert np.array_equal(nodes, nz) and u in nodes.tolist()
+    assert np.abs(vals - dense[nz]).max() <= TOL_MODEL
+    # too small a cap: an error that reports the size needed, prefix written
+    small_n, small_v = np.zeros(10, np.int32), np.zeros(10, np.float64)
+    with pytest.raises(ps.ProbeSimError) as e:
+        ps.ps_single_source_sparse(G, u, 0.6, 0.05, 0.01, 8, cap=10, out_nodes=small_n, out_scores=small_v)
+    assert e.value.code == 1 and e.value.count == nz.size
+    assert np.array_equal(small_n, nz[:10])
+    # device outputs
+    dn = torch.zeros(nz.size, dtype=torch.int32, device="cuda:0")
+    dv = torch.zeros(nz.size, dtype=torch.float64, device="cuda:0")
+    ps.ps_single_source_sparse(G, u, 0.6, 0.05, 0.01, 8, cap=nz.size, out_nodes=dn, out_scores=dv)
+    torch.cuda.synchronize()
+    assert np.array_equal(dn.cpu().numpy(), nz) and np.abs(dv.cpu().numpy() - dense[nz]).max() <= TOL_MODEL
+
+
 def test_device_output_tensor(ps, er, orc):
     import torch
 
