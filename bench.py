@@ -44,6 +44,25 @@ def expand_bytes(st: dict) -> float:
     return 28.0 * F + 8.0 * E + 16.0 * inner + 8.0 * N + 16.0 * Fin
 
 
+def measured_traffic(avg_ms):
+    """HBM bytes per k_expand dispatch from the committed rocprofv3 counter
+    runs (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration),
+    used only while the kernel source is the one they were taken on; as GB/s
+    over this run's average launch time.  None otherwise."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_expand_cl_1m_10m_traffic.json")
+    if not os.path.exists(path) or avg_ms <= 0:
+        return None, None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None, None
+    b = rec["hbm_bytes_per_dispatch"]
+    return b / (avg_ms * 1e-3) / 1e9, b
+
+
 def cpu_baseline(n, s, d, q, seconds_target=15.0):
     """The oracle (Alg. 1, FP64, one thread) on a bounded sample: the first
     walks of the first query, scaled to queries/s by n_r (Alg. 1's cost is a
@@ -207,6 +226,7 @@ def main():
     launches = max(acc["expand_launches"], 1)
     avg_ms = acc["expand_ms"] / launches
     achieved = (alg_bytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic, traffic_bytes = measured_traffic(avg_ms)
     result = {
         "metric": "single-source queries/s at eps=0.05 (plain, one query at a time)",
         "value": qps,
@@ -227,8 +247,9 @@ def main():
         "batched_qps": batched_qps,
         "batched_speedup": batched_qps / qps,
         "roofline": {"bound": "hbm", "kernel": "k_expand", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches,
+                     "hbm_bytes_per_launch": traffic_bytes},
         "work_per_query": {k: acc[k] / queries for k in keys if k not in ("expand_ms",)},
     }
     if args.calib_copy:
