@@ -371,6 +371,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
     a.ctr[C_SMALL] = 0;
     a.ctr[C_CHUNK] = 0;
     a.ctr[C_LIST0 + (a.cur ^ 1)] = 0;
+    a.ctr[C_NZROWS0 + (a.cur ^ 1)] = 0;  // k_dense rewrites that matrix this step
     s_head = a.ctr[C_HEAD];
     s_avail = a.ctr[C_TAIL] - s_head;
   }
@@ -642,6 +643,7 @@ struct ExpandArgs {
   int32_t n;
   long long* dense_cur;
   float* mat_cur;  // dense frontier matrix (n x kLanes) of this step
+  uint8_t* map_cur;  // its row map (rows given a score here are flagged)
   const int32_t* pull_flag;
   const int2* list_cur;
   const float* item_val;
@@ -733,7 +735,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
   const int lane = lane_id();
   const int wv = tid >> 6;
   WaveBuf wb{s_buf[wv], 0u};
-  unsigned long long nfinal = 0, nnext = 0;
+  unsigned long long nfinal = 0, nnext = 0, nconv = 0;
 
   const unsigned long long cnt = min(a.ctr[C_LIST0 + a.cur], (unsigned long long)a.list_cap);
   for (uint64_t tile0 = (uint64_t)blockIdx.x * kTile; tile0 < cnt; tile0 += (uint64_t)gridDim.x * kTile) {
@@ -752,6 +754,8 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
           long long* dc = a.dense_cur + (size_t)it.x * a.n + it.y;
           if (a.pull_flag[it.x]) {  // slot moved to a dense column: scatter
             a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = grid_f32(*dc);
+            a.map_cur[it.y] = 1;
+            ++nconv;
             *dc = 0;
           } else {  // pushed: its score is consumed here
             *dc = 0;
@@ -842,9 +846,11 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
 
   nfinal = wave_sum(nfinal);
   nnext = wave_sum(nnext);
+  nconv = wave_sum(nconv);
   if (lane == 0) {
     if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
     if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
+    if (nconv) atomicAdd(&a.ctr[C_NZROWS0 + a.cur], nconv);  // rows given scores in the dense matrix
   }
 }
 
@@ -868,9 +874,12 @@ struct DenseArgs {
   const DenseVer* dv;
   const float* mat_cur;
   float* mat_next;
+  const uint8_t* map_cur;  // per node: its row of mat_cur may hold a nonzero score
+  uint8_t* map_next;       // the same for mat_next, written with it
   long long* npart;  // n x kLanes partial grid sums of long in-rows
   int32_t* has_next;
   unsigned long long* ctr;
+  int cur;
 };
 
 struct LaneInfo {
@@ -905,13 +914,15 @@ __device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigne
   return li;
 }
 
-// Target v of lane g with grid sum q of its contributions: the FP64
-// estimate on a probe's last level, else the next level's FP32 score.
-__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, int32_t v, long long q,
-                                             unsigned long long gw, unsigned long long& nfinal) {
+// Target v of column g with grid sum q of its contributions: the FP64
+// estimate on a probe's last level, else the next level's FP32 score.  Only
+// writer lanes (one per column) act; every lane of the wavefront calls it.
+__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, bool writer, int32_t v,
+                                             long long q, unsigned long long gw, unsigned long long& nfinal,
+                                             unsigned long long& nzrows) {
   float out = 0.0f;
   bool nz = false;
-  if (li.active && v != li.excl && q > 0) {
+  if (writer && li.active && v != li.excl && q > 0) {
     if (li.last) {
       unsafeAtomicAdd(&li.acc[v], grid_f64(q) * li.w);
       ++nfinal;
@@ -923,7 +934,10 @@ __device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo&
       if (fabsf(out - t) <= 1e-5f * t) unsafeAtomicAdd(li.flip, li.flip_unit);
     }
   }
-  if ((unsigned long long)g < gw) a.mat_next[(size_t)v * kLanes + g] = out;
+  if (writer && (unsigned long long)g < gw) a.mat_next[(size_t)v * kLanes + g] = out;
+  const bool any = __ballot(nz) != 0ull;  // the whole row is rewritten: its flag too
+  if (lane_id() == 0) a.map_next[v] = any ? 1 : 0;
+  nzrows += any ? 1ull : 0ull;
   return nz;
 }
 
@@ -931,6 +945,74 @@ __device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo&
 // push path's fl32(fl32(h * sqrt c) * 1/|I(v)|)); 0 when Rule 2 removes h.
 __device__ __forceinline__ long long pull_term(float h, float thr, float sc, float inv) {
   return h > thr ? to_grid((h * sc) * inv) : 0ll;
+}
+
+// Score of in-neighbour x in this lane's column.  With kMap the row is read
+// only when the row map says it may be nonzero (all lanes of a wavefront
+// share x); that saves the gathers of a sparse matrix and costs a dependent
+// load on a dense one.
+template <bool kMap>
+__device__ __forceinline__ float lane_score(const DenseArgs& a, const float* m, int32_t x) {
+  if (kMap && !a.map_cur[x]) return 0.0f;
+  return m[(size_t)x * kLanes];
+}
+
+// The pulls of one pass.  A wavefront works on one target at a time; its 64
+// lanes form 64/L groups of L lanes (L = the power of two covering the
+// columns in use), lane g handling column g % L of every L-th in-edge, so few
+// columns still keep the whole wavefront busy.  Group sums are combined by
+// shuffles.  Short in-rows are finished per target, long in-rows summed in
+// kPullChunk-edge chunks into partial sums.
+template <bool kMap>
+__device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& li, const DenseVer& dv, int col,
+                                           int grp, int L, uint64_t wave, uint64_t nwaves, unsigned long long gw,
+                                           unsigned long long& nz_mask, unsigned long long& nfinal,
+                                           unsigned long long& inedges, unsigned long long& nzrows) {
+  const float* m = a.mat_cur + col;
+  const uint32_t T = 64u / (uint32_t)L;
+  const bool writer = grp == 0;
+  for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
+    const uint2 row = dv.in_rows[v];
+    if (row.y > kPullLane) continue;  // long in-row: chunks + k_dense_fin
+    long long s0 = 0, s1 = 0;
+    if (li.active) {
+      const float inv = dv.inv_indeg[v];
+      uint32_t k = (uint32_t)grp;
+      for (; k + T < row.y; k += 2 * T) {
+        const int32_t x0 = dv.in_col[row.x + k], x1 = dv.in_col[row.x + k + T];
+        s0 += pull_term(lane_score<kMap>(a, m, x0), li.thr, li.sc, inv);
+        s1 += pull_term(lane_score<kMap>(a, m, x1), li.thr, li.sc, inv);
+      }
+      if (k < row.y) s0 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k]), li.thr, li.sc, inv);
+    }
+    long long q = s0 + s1;
+    for (int off = L; off < 64; off <<= 1) q += __shfl_xor(q, off, 64);
+    inedges += row.y;
+    const bool nz = dense_finish(a, li, col, writer, (int32_t)v, q, gw, nfinal, nzrows);
+    nz_mask |= __ballot(nz);
+  }
+  const unsigned long long nch = dv.heavy_cnt[1];
+  for (uint64_t c = wave; c < nch; c += nwaves) {
+    const int2 ch = dv.heavy_chunks[c];
+    const uint2 row = dv.in_rows[ch.x];
+    const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
+    inedges += e - (uint32_t)ch.y;
+    long long s0 = 0, s1 = 0;
+    if (li.active) {
+      const float inv = dv.inv_indeg[ch.x];
+      uint32_t k = (uint32_t)ch.y + (uint32_t)grp;
+      for (; k + T < e; k += 2 * T) {
+        s0 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k]), li.thr, li.sc, inv);
+        s1 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k + T]), li.thr, li.sc, inv);
+      }
+      if (k < e) s0 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k]), li.thr, li.sc, inv);
+    }
+    long long part = s0 + s1;
+    for (int off = L; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
+    if (writer && li.active && part > 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.npart[(size_t)ch.x * kLanes + col]),
+                (unsigned long long)part);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
@@ -942,56 +1024,26 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   if (ghi == 0) {  // no column in use: clear the columns used last step
-    for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves)
+    for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
       if ((unsigned long long)g < gw) a.mat_next[v * kLanes + g] = 0.0f;
+      if (g == 0) a.map_next[v] = 0;
+    }
     return;
   }
   if (tid == 0) s_nz = 0ull;
   __syncthreads();
-  const LaneInfo li = lane_info(a, g, ghi);
+  int L = 1;  // lanes per group: the power of two covering the columns to write
+  while ((unsigned long long)L < gw) L <<= 1;
+  const int col = g & (L - 1), grp = g / L;
+  const LaneInfo li = lane_info(a, col, ghi);
   const DenseVer dv = *a.dv;
-  const float* m = a.mat_cur + g;
-  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0;
-  for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
-    const uint2 row = dv.in_rows[v];
-    if (row.y > kPullLane) continue;  // long in-row: chunks + k_dense_fin
-    long long s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    if (li.active) {
-      const float inv = dv.inv_indeg[v];
-      uint32_t k = 0;
-      for (; k + 4 <= row.y; k += 4) {
-        const int32_t x0 = dv.in_col[row.x + k], x1 = dv.in_col[row.x + k + 1];
-        const int32_t x2 = dv.in_col[row.x + k + 2], x3 = dv.in_col[row.x + k + 3];
-        s0 += pull_term(m[(size_t)x0 * kLanes], li.thr, li.sc, inv);
-        s1 += pull_term(m[(size_t)x1 * kLanes], li.thr, li.sc, inv);
-        s2 += pull_term(m[(size_t)x2 * kLanes], li.thr, li.sc, inv);
-        s3 += pull_term(m[(size_t)x3 * kLanes], li.thr, li.sc, inv);
-      }
-      for (; k < row.y; ++k) s0 += pull_term(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr, li.sc, inv);
-    }
-    inedges += row.y;
-    const bool nz = dense_finish(a, li, g, (int32_t)v, (s0 + s1) + (s2 + s3), gw, nfinal);
-    nz_mask |= __ballot(nz);
-  }
-  const unsigned long long nch = dv.heavy_cnt[1];
-  for (uint64_t c = wave; c < nch; c += nwaves) {
-    const int2 ch = dv.heavy_chunks[c];
-    const uint2 row = dv.in_rows[ch.x];
-    const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
-    inedges += e - (uint32_t)ch.y;
-    if (!li.active) continue;
-    const float inv = dv.inv_indeg[ch.x];
-    long long s0 = 0, s1 = 0;
-    uint32_t k = (uint32_t)ch.y;
-    for (; k + 2 <= e; k += 2) {
-      s0 += pull_term(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr, li.sc, inv);
-      s1 += pull_term(m[(size_t)dv.in_col[row.x + k + 1] * kLanes], li.thr, li.sc, inv);
-    }
-    if (k < e) s0 += pull_term(m[(size_t)dv.in_col[row.x + k] * kLanes], li.thr, li.sc, inv);
-    const long long part = s0 + s1;
-    if (part > 0)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&a.npart[(size_t)ch.x * kLanes + g]), (unsigned long long)part);
-  }
+  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0, nzrows = 0;
+  // the row map pays off when fewer than half of the rows may be nonzero
+  if (2ull * a.ctr[C_NZROWS0 + a.cur] < (unsigned long long)a.n)
+    dense_rows<true>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows);
+  else
+    dense_rows<false>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows);
+  if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
   if (g == 0) {
@@ -1015,7 +1067,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   const DenseVer dv = *a.dv;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  unsigned long long nz_mask = 0, nfinal = 0;
+  unsigned long long nz_mask = 0, nfinal = 0, nzrows = 0;
   const unsigned long long nh = dv.heavy_cnt[0];
   for (uint64_t i = wave; i < nh; i += nwaves) {
     const int32_t v = dv.heavy_nodes[i];
@@ -1025,10 +1077,11 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
       sum = *p;
       *p = 0;
     }
-    const bool nz = dense_finish(a, li, g, v, sum, gw, nfinal);
+    const bool nz = dense_finish(a, li, g, true, v, sum, gw, nfinal, nzrows);
     nz_mask |= __ballot(nz);
   }
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
+  if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
   nfinal = wave_sum(nfinal);
   if (g == 0 && nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
   __syncthreads();
@@ -1151,7 +1204,7 @@ void devbuf_free(DevBuf& b) {
 
 void session_free(Session* s) {
   if (!s) return;
-  DevBuf* bufs[] = {&s->mat[0], &s->mat[1], &s->npart, &s->lane_slot, &s->dense_ver, &s->slot_edges, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
+  DevBuf* bufs[] = {&s->mat[0], &s->mat[1], &s->rowmap[0], &s->rowmap[1], &s->npart, &s->lane_slot, &s->dense_ver, &s->slot_edges, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
                     &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
                     &s->keys,
@@ -1209,6 +1262,8 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->mat[0], sizeof(float) * (size_t)n * kLanes));
   PS_TRY(devbuf_reserve(s->mat[1], sizeof(float) * (size_t)n * kLanes));
   PS_TRY(devbuf_reserve(s->npart, sizeof(long long) * (size_t)n * kLanes));
+  PS_TRY(devbuf_reserve(s->rowmap[0], (size_t)n));
+  PS_TRY(devbuf_reserve(s->rowmap[1], (size_t)n));
   PS_TRY(devbuf_reserve(s->lane_slot, sizeof(int32_t) * kLanes));
   PS_TRY(devbuf_reserve(s->dense_ver, sizeof(DenseVer)));
   const bool fresh = !s->dense[0].p || shape;
@@ -1242,6 +1297,7 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   }
   for (DevBuf* b : {&s->mat[0], &s->mat[1]}) PS_HIP(hipMemsetAsync(b->p, 0, sizeof(float) * (size_t)n * kLanes, st));
   PS_HIP(hipMemsetAsync(s->npart.p, 0, sizeof(long long) * (size_t)n * kLanes, st));
+  for (DevBuf* b : {&s->rowmap[0], &s->rowmap[1]}) PS_HIP(hipMemsetAsync(b->p, 0, (size_t)n, st));
   k_reset_lanes<<<1, kLanes, 0, st>>>(s->lane_slot.as<int32_t>());
   PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
   k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(s->slots.as<Slot>(), s->has_next.as<int32_t>(), P);
@@ -1468,6 +1524,7 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k.ea.cur = cur;
   k.ea.dense_cur = s->dense[cur].as<long long>();
   k.ea.mat_cur = s->mat[cur].as<float>();
+  k.ea.map_cur = s->rowmap[cur].as<uint8_t>();
   k.ea.dense_next = s->dense[nxt].as<long long>();
   k.ea.list_next = s->list[nxt].as<int2>();
   k.ea.nxt = nxt;
@@ -1481,9 +1538,12 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   da.dv = s->dense_ver.as<DenseVer>();
   da.mat_cur = s->mat[cur].as<float>();
   da.mat_next = s->mat[nxt].as<float>();
+  da.map_cur = s->rowmap[cur].as<uint8_t>();
+  da.map_next = s->rowmap[nxt].as<uint8_t>();
   da.npart = s->npart.as<long long>();
   da.has_next = s->has_next.as<int32_t>();
   da.ctr = ctr;
+  da.cur = cur;
   k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
   k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
   if (ev2) (void)hipEventRecord(ev2, st);

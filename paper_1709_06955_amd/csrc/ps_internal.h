@@ -191,6 +191,8 @@ enum CounterIdx {
   C_PULL_EDGES,  // in-edges read by dense passes
   C_PULL_T,      // dense threshold in out-edges (set by the host)
   C_NEAR,        // Rule 2 tests within 1e-5 relative of the threshold
+  C_NZROWS0,     // rows of dense matrix 0 that may hold a nonzero score
+  C_NZROWS1,     // the same for matrix 1
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
   C_COUNT = C_HIST_E + 32
@@ -216,7 +218,7 @@ struct Session {
   uint64_t tree_pool = 0;   // entries
   uint64_t ring_cap = 0;    // power of two
   DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_flag;
-  DevBuf mat[2], npart, lane_slot, dense_ver;  // dense frontier lanes
+  DevBuf mat[2], rowmap[2], npart, lane_slot, dense_ver;  // dense frontier lanes
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp, sel_count;
