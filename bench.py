@@ -10,7 +10,7 @@ are also timed as one ps_batch launch (batched mode).
 
 Prints one JSON line.  The roofline entry covers the PROBE expansion kernel
 (k_expand), timed with HIP events on the stream it runs on; its algorithmic
-bytes per launch come from the kernel's own work counters.
+bytes per launch come from the kernel's own work counters (expand_bytes).
 """
 
 from __future__ import annotations
@@ -153,8 +153,8 @@ def main():
                     help="also run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(queries shard across GPUs by data parallelism, see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(queries would shard across GPUs by data parallelism over a replicated graph)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
