@@ -73,6 +73,8 @@ def lib():
         L.orc_walk.restype = C.c_int32
         L.orc_probe.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_double, C.c_double, C.c_int,
                                 P(C.c_double)]
+        L.orc_rprobe.argtypes = [C.c_void_p, P(C.c_int32), C.c_int32, C.c_double, C.c_uint64, C.c_int64,
+                                 P(C.c_double)]
         for f in (L.orc_single_source, L.orc_batch):
             f.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int,
                           P(C.c_double), P(Stats)]
@@ -150,12 +152,30 @@ def probe(g: Graph, path, c: float, eps_p: float = 0.0, precision: str = "f64") 
     return out
 
 
-def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision):
+PROBES = ("deterministic", "randomized")
+
+
+def rprobe(g: Graph, path, c: float, seed: int, k: int) -> np.ndarray:
+    """Alg. 4 (randomized PROBE) on `path` as the probe of that prefix of walk
+    k: 1.0 for the nodes it returns, else 0."""
+    pa, pp = _i32(path)
+    out = np.zeros(g.n, dtype=np.float64)
+    rc = lib().orc_rprobe(g._h, pp, int(pa.size), c, C.c_uint64(seed), int(k),
+                          out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != ORC_OK:
+        raise ValueError(f"rprobe failed with code {rc}")
+    return out
+
+
+def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe="deterministic"):
+    if probe not in PROBES:
+        raise ValueError(f"probe must be one of {PROBES}")
     out = np.zeros(g.n, dtype=np.float64)
     st = Stats()
     kb = 0 if k_begin is None else int(k_begin)
     ke = int(p.n_r) if k_end is None else int(k_end)
-    rc = fn(g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift), _f32(precision),
+    mode = _f32(precision) | (2 if probe == "randomized" else 0)
+    rc = fn(g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift), mode,
             out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
     if rc != ORC_OK:
         raise ValueError(f"query failed with code {rc}")
@@ -163,9 +183,10 @@ def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision):
 
 
 def single_source(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False,
-                  precision: str = "f64"):
-    """Alg. 1 estimate s^(u, .) over walks [k_begin, k_end) (default all n_r)."""
-    return _run(lib().orc_single_source, g, u, p, seed, k_begin, k_end, bias_shift, precision)
+                  precision: str = "f64", probe: str = "deterministic"):
+    """Alg. 1 estimate s^(u, .) over walks [k_begin, k_end) (default all n_r),
+    with deterministic (Alg. 2) or randomized (Alg. 4) probes."""
+    return _run(lib().orc_single_source, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe)
 
 
 def batch(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False,

@@ -17,7 +17,9 @@
 //   orc_walk            Definition of the sqrt(c)-walk (Section 2.2)
 //   orc_probe           Alg. 2 (deterministic PROBE) with Pruning Rule 2, in
 //                       FP64 or in the FP32 score model below
-//   orc_single_source   Alg. 1 (basic ProbeSim) with Pruning Rules 1 and 2
+//   orc_rprobe          Alg. 4 (randomized PROBE), one run
+//   orc_single_source   Alg. 1 (basic ProbeSim) with Pruning Rules 1 and 2, or
+//                       with randomized PROBE (Section 4.3)
 //   orc_batch           Alg. 3 (reverse reachability tree), same estimate
 //   orc_topk            Definition 2 (top-k by sorting the estimates)
 //
@@ -37,6 +39,14 @@
 // rounded to FP32, Rule 2 compares it with fl32(eps_p / sqrt(c)^(i-j-1)),
 // and the returned level keeps the exact sum.  Estimates are summed over
 // walks in FP64 in both modes.
+//
+// Randomized PROBE (Alg. 4) needs random numbers the paper leaves open:
+// candidate v at iteration j of the probe of prefix (u_1..u_i) of walk k
+// draws Philox4x32-10 with key (seed_lo, seed_hi ^ 0x9E3779B9) and counter
+// (k, i * 2^16 + j, v, 1); words 1:0 pick its in-neighbour (as walks do) and
+// word 2 < floor(sqrt(c) * 2^32) is the sqrt(c) coin.  Rule 2 does not apply
+// to it (Alg. 4 has none), and each walk's probes run on their own: sharing a
+// prefix saves nothing for randomized probes (Section 4.4).
 
 #include <cmath>
 #include <cstdint>
@@ -417,6 +427,64 @@ struct Prober {
   }
 };
 
+// Alg. 4 on the partial walk path[0..i-1] = (u_1..u_i) of walk k: returns
+// H_{i-1} as the list `cur` (membership flags in `in`, cleared on return).
+static void rprobe(const orc_graph* g, const int32_t* path, int32_t i, double c, uint64_t seed, int64_t k,
+                   std::vector<int32_t>& cur, std::vector<int32_t>& cand, std::vector<char>& in,
+                   std::vector<char>& seen, orc_stats* st) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ 0x9E3779B9u};
+  const uint32_t t_sc = (uint32_t)std::floor(std::sqrt(c) * 4294967296.0);
+  cur.assign(1, path[i - 1]);
+  in[path[i - 1]] = 1;
+  std::vector<int32_t> nxt;
+  for (int32_t j = 0; j <= i - 2; ++j) {
+    const int32_t excl = path[i - j - 2];  // u_{i-j-1}
+    cand.clear();
+    for (int32_t x : cur)
+      for (int64_t e = g->out_ptr[x]; e < g->out_ptr[x + 1]; ++e) {
+        const int32_t v = g->out_col[e];
+        if (st) st->edges_scanned++;
+        if (v == excl || seen[v]) continue;
+        seen[v] = 1;
+        cand.push_back(v);
+      }
+    nxt.clear();
+    for (int32_t v : cand) {
+      seen[v] = 0;
+      const uint32_t ctr[4] = {(uint32_t)k, ((uint32_t)i << 16) | (uint32_t)j, (uint32_t)v, 1u};
+      uint32_t w[4];
+      orc_philox4x32_10(ctr, key, w);
+      const uint64_t r = ((uint64_t)w[1] << 32) | w[0];
+      const int64_t d = indeg(g, v);  // >= 1: v has an in-neighbour in cur
+      const int32_t x = g->in_col[g->in_ptr[v] + (int64_t)(((unsigned __int128)r * (uint64_t)d) >> 64)];
+      if (in[x] && w[2] < t_sc) nxt.push_back(v);
+    }
+    for (int32_t x : cur) in[x] = 0;
+    cur.swap(nxt);
+    for (int32_t x : cur) in[x] = 1;
+    if (st) st->next_entries += (int64_t)cur.size();
+  }
+  for (int32_t x : cur) in[x] = 0;
+  if (st) {
+    st->probes++;
+    st->final_entries += (int64_t)cur.size();
+  }
+}
+
+// Alg. 4 alone, for tests: 1 for the nodes of H_{i-1}, else 0.
+int orc_rprobe(const orc_graph* g, const int32_t* path, int32_t i, double c, uint64_t seed, int64_t k,
+               double* out) {
+  if (i < 2) return ORC_EINVAL;
+  for (int32_t t = 0; t < i; ++t)
+    if (path[t] < 0 || path[t] >= g->n) return ORC_ERANGE;
+  std::vector<int32_t> cur, cand;
+  std::vector<char> in((size_t)g->n, 0), seen((size_t)g->n, 0);
+  rprobe(g, path, i, c, seed, k, cur, cand, in, seen, nullptr);
+  std::fill(out, out + g->n, 0.0);
+  for (int32_t v : cur) out[v] = 1.0;
+  return ORC_OK;
+}
+
 // Alg. 2 alone, for tests: dense scores of PROBE((u_1..u_i)).
 int orc_probe(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p, int f32,
               double* out) {
@@ -443,14 +511,29 @@ static void finish(const orc_graph* g, int32_t u, const orc_params* p, int bias_
 // (u_1..u_i), i = 2..len, and sum the scores; the estimate is the sum over
 // walks divided by n_r (the running average of Alg. 1 is the same number).
 // A sub-range of walks gives that range's share of the sum.
+// mode: bit 0 the FP32 score model, bit 1 randomized PROBE (Alg. 4).
 int orc_single_source(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
-                      int64_t k_begin, int64_t k_end, int bias_shift, int f32, double* out, orc_stats* st) {
+                      int64_t k_begin, int64_t k_end, int bias_shift, int mode, double* out, orc_stats* st) {
   if (u < 0 || u >= g->n) return ORC_ERANGE;
   if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
   if (st) memset(st, 0, sizeof(*st));
   std::vector<double> acc((size_t)g->n, 0.0);
   std::vector<int32_t> walk((size_t)p->L);
-  Prober pr(g, f32 != 0);
+  if (mode & 2) {
+    std::vector<int32_t> cur, cand;
+    std::vector<char> in((size_t)g->n, 0), seen((size_t)g->n, 0);
+    for (int64_t k = k_begin; k < k_end; ++k) {
+      const int32_t len = orc_walk(g, u, k, seed, p, walk.data());
+      if (st) st->walk_nodes += len;
+      for (int32_t i = 2; i <= len; ++i) {
+        rprobe(g, walk.data(), i, p->c, seed, k, cur, cand, in, seen, st);
+        for (int32_t v : cur) acc[v] += 1.0;
+      }
+    }
+    finish(g, u, p, bias_shift, acc, out);
+    return ORC_OK;
+  }
+  Prober pr(g, (mode & 1) != 0);
   for (int64_t k = k_begin; k < k_end; ++k) {
     const int32_t len = orc_walk(g, u, k, seed, p, walk.data());
     if (st) st->walk_nodes += len;
@@ -465,6 +548,8 @@ int orc_single_source(const orc_graph* g, int32_t u, const orc_params* p, uint64
 // it), PROBE every tree node once and add weight/n_r * Score.
 int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
               int64_t k_end, int bias_shift, int f32, double* out, orc_stats* st) {
+  if (f32 & 2)  // randomized probes are per walk: the tree changes nothing
+    return orc_single_source(g, u, p, seed, k_begin, k_end, bias_shift, f32, out, st);
   if (u < 0 || u >= g->n) return ORC_ERANGE;
   if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
   if (st) memset(st, 0, sizeof(*st));
@@ -495,7 +580,7 @@ int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
   if (st) st->tree_nodes = (int64_t)tree.size() - 1;
   std::vector<double> acc((size_t)g->n, 0.0);
   std::vector<int32_t> path;
-  Prober pr(g, f32 != 0);
+  Prober pr(g, (f32 & 1) != 0);
   for (size_t q = 1; q < tree.size(); ++q) {
     const int32_t i = tree[q].depth;
     path.assign((size_t)i, 0);

@@ -461,3 +461,48 @@ def test_f32_model_query_within_allowance_of_f64(orc, eps):
         c1, _ = orc.single_source(G, u, p, 5, 0, 300, precision="f32")
         c3, _ = orc.batch(G, u, p, 5, 0, 300, precision="f32")
         assert np.abs(c1 - c3).max() <= 1e-13
+
+
+# ----------------------------------------------------------- randomized PROBE
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_randomized_probe_is_unbiased_for_the_probe_scores(orc, seed):
+    # Section 4.3: a node is in the set returned by Alg. 4 with probability
+    # equal to its Alg. 2 score (no pruning).  Averaging many independent runs
+    # (distinct walk indices draw independent numbers) must reproduce the
+    # deterministic scores, themselves pinned by brute force above; a node
+    # with score 0 is never returned.
+    rng = np.random.default_rng(300 + seed)
+    n = 25
+    src, dst = refs.random_graph(n, 0.25, 10 + seed)
+    G = orc.Graph(n, src, dst)
+    runs = 6000
+    for _ in range(2):
+        i = int(rng.integers(2, 6))
+        path = [int(x) for x in rng.integers(0, n, size=i)]
+        score = orc.probe(G, path, 0.6, 0.0)
+        hits = np.zeros(n)
+        for k in range(runs):
+            hits += orc.rprobe(G, path, 0.6, 77 + seed, k)
+        mean = hits / runs
+        assert np.all(mean[score == 0.0] == 0.0)
+        sd = np.sqrt(np.maximum(score * (1 - score), 1e-12) / runs)
+        assert np.all(np.abs(mean - score) <= 5 * sd + 1e-9), (path, np.abs(mean - score).max())
+
+
+def test_randomized_probe_guarantee_against_power_method(orc):
+    # Theorem 3: Alg. 1 with randomized PROBE keeps max_v |s^ - s| <= eps_a.
+    from synth.graphs import erdos_renyi
+
+    n = 1000
+    s_, d_ = erdos_renyi(n, 10000, seed=1)
+    S = refs.power_method(n, s_, d_, 0.6, iters=55)
+    G = orc.Graph(n, s_, d_)
+    p = orc.params(n, 0.6, 0.1, 0.01)
+    for seed in range(2):
+        est, _ = orc.single_source(G, 0, p, seed, probe="randomized")
+        assert est[0] == 1.0
+        assert np.abs(est - S[0]).max() <= 0.1
+        # each estimate is a count of returned nodes over n_r
+        assert np.allclose(est[1:] * p.n_r, np.round(est[1:] * p.n_r), atol=1e-6)
