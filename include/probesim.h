@@ -130,7 +130,15 @@ typedef struct ps_options {
                          setting, else automatic (up to 1024).  Clamped so that
                          the per-slot buffers (52 B per slot and node) fit in
                          56 GiB. */
-  int32_t reserved;
+  int32_t probe_mode; /* PS_PROBE_DETERMINISTIC (Alg. 2 with Rule 2, the
+                         default) or PS_PROBE_RANDOMIZED (Alg. 4, Section 4.3:
+                         one randomized probe per walk and prefix, no Rule 2;
+                         candidate v of iteration j of the probe of prefix
+                         (u_1..u_i) of walk k draws Philox4x32-10 with key
+                         (seed_lo, seed_hi ^ 0x9E3779B9) and counter
+                         (k, i * 2^16 + j, v, 1): words 1:0 pick its
+                         in-neighbour as walks do, word 2 < floor(sqrt(c) *
+                         2^32) is the sqrt(c) coin) */
   int64_t pull_edges; /* a probe level whose kept entries have at least this many
                          out-edges is computed by pulling along in-edges over
                          all nodes instead of pushing along its out-edges (same
@@ -138,6 +146,8 @@ typedef struct ps_options {
 } ps_options;
 
 #define PS_MAX_WALK_LEN 64
+#define PS_PROBE_DETERMINISTIC 0
+#define PS_PROBE_RANDOMIZED 1
 
 /* Fills the defaults above. */
 void ps_options_default(ps_options* opt);
@@ -204,6 +214,8 @@ typedef struct ps_query {
   int32_t k; /* 0: single-source (n scores); > 0: top-k */
   double c, eps, delta;
   uint64_t seed;
+  int32_t probe_mode; /* as ps_options.probe_mode */
+  int32_t pad;
 } ps_query;
 
 typedef struct ps_result {
@@ -222,7 +234,8 @@ typedef struct ps_result {
 /* Runs nq queries together: all their walks, trees and probes share the
  * device's probe slots and one level-synchronous launch sequence.  Each
  * result equals the same query run alone (up to FP64 summation order).  opt
- * applies to every query (its walk range must be the default).  Per-query
+ * applies to every query (its walk range must be the default); a query's
+ * nonzero probe_mode overrides opt's.  Per-query
  * argument errors are reported in r[i].status and do not stop the others. */
 ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* q, const ps_options* opt, ps_result* r);
 

@@ -27,6 +27,8 @@ PS_LOAD_DROP_SELF_LOOPS = 2
 PS_MAX_WALK_LEN = 64
 
 # Every entry point declared in include/probesim.h.
+PROBE_DETERMINISTIC, PROBE_RANDOMIZED = 0, 1
+
 EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
     "ps_graph_free", "ps_graph_info", "ps_graph_update", "ps_graph_edges", "ps_options_default",
@@ -47,7 +49,7 @@ class Options(C.Structure):
         ("eps_s", C.c_double), ("eps_t", C.c_double), ("eps_p", C.c_double),
         ("max_len", C.c_int32), ("bias_shift", C.c_int32),
         ("walk_begin", C.c_int64), ("walk_end", C.c_int64),
-        ("slots", C.c_int32), ("reserved", C.c_int32),
+        ("slots", C.c_int32), ("probe_mode", C.c_int32),
         ("pull_edges", C.c_int64),
     ]
 
@@ -78,7 +80,7 @@ class Stats(C.Structure):
 
 class Query(C.Structure):
     _fields_ = [("u", C.c_int32), ("k", C.c_int32), ("c", C.c_double), ("eps", C.c_double),
-                ("delta", C.c_double), ("seed", C.c_uint64)]
+                ("delta", C.c_double), ("seed", C.c_uint64), ("probe_mode", C.c_int32), ("pad", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -349,7 +351,8 @@ def ps_batch(g: Graph, queries, outs=None, **opt):
     ra = (Result * max(nq, 1))()
     keep = []
     for i, q in enumerate(queries):
-        qa[i] = Query(int(q["u"]), int(q.get("k", 0)), q["c"], q["eps"], q["delta"], int(q["seed"]))
+        qa[i] = Query(int(q["u"]), int(q.get("k", 0)), q["c"], q["eps"], q["delta"], int(q["seed"]),
+                      int(q.get("probe_mode", 0)), 0)
         if outs is not None:
             sc, nd = outs[i]
         elif q.get("k", 0) > 0:
@@ -381,8 +384,8 @@ class Server:
         self.g = g
         self._pending = {}
 
-    def submit(self, u, c, eps, delta, seed, k=0):
-        q = Query(int(u), int(k), c, eps, delta, int(seed))
+    def submit(self, u, c, eps, delta, seed, k=0, probe_mode=0):
+        q = Query(int(u), int(k), c, eps, delta, int(seed), int(probe_mode), 0)
         if k > 0:
             sc, nd = np.zeros(k, np.float64), np.zeros(k, np.int32)
         else:

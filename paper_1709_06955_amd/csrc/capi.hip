@@ -135,6 +135,8 @@ ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, doub
   q->walk_begin = opt ? opt->walk_begin : 0;
   q->walk_end = (opt && opt->walk_end >= 0) ? opt->walk_end : q->prm.n_r;
   q->bias_shift = opt ? opt->bias_shift : 0;
+  q->randomized = opt ? opt->probe_mode : 0;
+  if (q->randomized != 0 && q->randomized != 1) return PS_ERR_INVALID_ARG;
   if (q->walk_begin < 0 || q->walk_end > q->prm.n_r || q->walk_begin > q->walk_end) return PS_ERR_INVALID_ARG;
   return PS_OK;
 }
@@ -218,7 +220,11 @@ extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const
   std::vector<int32_t> which;
   for (int32_t i = 0; i < nq; ++i) {
     QueryRun q;
-    ps_status s = make_query_run(g, qv[i].u, qv[i].k, qv[i].c, qv[i].eps, qv[i].delta, qv[i].seed, opt, &q);
+    ps_options qo;
+    if (opt) qo = *opt;
+    else ps_options_default(&qo);
+    if (qv[i].probe_mode) qo.probe_mode = qv[i].probe_mode;
+    ps_status s = make_query_run(g, qv[i].u, qv[i].k, qv[i].c, qv[i].eps, qv[i].delta, qv[i].seed, &qo, &q);
     if (s == PS_OK && (!r[i].scores || (qv[i].k > 0 && !r[i].nodes))) s = PS_ERR_INVALID_ARG;
     r[i].status = s;
     r[i].count = 0;

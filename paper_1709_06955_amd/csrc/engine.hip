@@ -234,6 +234,7 @@ struct TreeArgs {
   int32_t* t_query;
   int32_t* t_weight;
   int32_t* ring;
+  int32_t* ring_k;  // walk index of each pending probe (randomized queries)
   uint64_t ring_mask;
   unsigned long long* remaining;
   unsigned long long* ctr;
@@ -264,10 +265,15 @@ __global__ void k_walk_tree(TreeArgs a) {
       a.t_node[id] = v;
       a.t_depth[id] = len;
       a.t_query[id] = r;
+    }
+    // a deterministic probe per tree node; a randomized one per walk and
+    // prefix (their draws differ per walk, so sharing saves nothing)
+    if (inserted || q.randomized) {
       atomicAdd(&a.remaining[r], 1ull);
       atomicAdd(&a.ctr[C_LEVELS], (unsigned long long)(len - 1));
       const unsigned long long pos = atomicAdd(&a.ctr[C_TAIL], 1ull);
       a.ring[pos & a.ring_mask] = (int32_t)id;
+      a.ring_k[pos & a.ring_mask] = (int32_t)k;
     }
     atomicAdd(&a.t_weight[id], 1);
     parent = id;
@@ -338,6 +344,7 @@ struct SchedArgs {
   Slot* slots;
   int32_t* has_next;
   const int32_t* ring;
+  const int32_t* ring_k;
   uint64_t ring_mask;
   const int32_t* t_parent;
   const int32_t* t_node;
@@ -372,6 +379,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
     a.ctr[C_CHUNK] = 0;
     a.ctr[C_LIST0 + (a.cur ^ 1)] = 0;
     a.ctr[C_NZROWS0 + (a.cur ^ 1)] = 0;  // k_dense rewrites that matrix this step
+    a.ctr[C_RAND] = 0;
+    a.ctr[C_RCLEAR] = 0;
     s_head = a.ctr[C_HEAD];
     s_avail = a.ctr[C_TAIL] - s_head;
   }
@@ -433,7 +442,11 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         st[r].depth = a.t_depth[t];
         st[r].cursor = a.t_parent[t];
         st[r].query = q;
-        st[r].w = (double)a.t_weight[t];
+        st[r].mode = Q.randomized;
+        st[r].wk = (uint32_t)a.ring_k[(head + rank) & a.ring_mask];
+        st[r].t_sc = Q.t_sc;
+        st[r].key2 = Q.key2;
+        st[r].w = Q.randomized ? 1.0 : (double)a.t_weight[t];
         st[r].sc = Q.sc;
         st[r].out_rows = Q.out_rows;
         st[r].out_col = Q.out_col;
@@ -449,7 +462,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
-          a.dense_cur[(size_t)s * a.n + x] = kGridOne;  // H_0 = {u_i: 1}
+          // H_0 = {u_i: 1}; a randomized probe's members are marked 2
+          a.dense_cur[(size_t)s * a.n + x] = Q.randomized ? 2ll : kGridOne;
           a.list_cur[pos] = make_int2(s, x);
         } else {
           atomicOr(&a.ctr[C_OVERFLOW], 1ull);
@@ -458,6 +472,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
       }
       ++rank;
     }
+    if (st[r].probe >= 0 && st[r].mode) atomicAdd(&a.ctr[C_RAND], 1ull);
     if (st[r].probe >= 0) {
       const int e = st[r].depth - st[r].level - 1;  // iterations left, i-j-1 >= 1
       st[r].thr = a.thr_tab[st[r].query * PS_MAX_WALK_LEN + e];
@@ -498,14 +513,21 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
     if (i < cnt) {
       const int2 it = list_cur[i];
       long long* d = dense_cur + (size_t)it.x * n + it.y;
-      const float val = grid_f32(*d);
+      const long long raw = *d;
+      const float val = grid_f32(raw);
       const Slot& sl = slots[it.x];
       uint2 row = make_uint2(0u, 0u);
-      if (fabsf(val - sl.thr) <= 1e-5f * sl.thr) {  // FP32 rounding may decide this test
-        ++near;
-        unsafeAtomicAdd(sl.flip, sl.flip_unit);
+      bool keep;
+      if (sl.mode) {  // Alg. 4: listed candidates are kept iff they were selected
+        keep = raw == 2;
+      } else {
+        if (fabsf(val - sl.thr) <= 1e-5f * sl.thr) {  // FP32 rounding may decide this test
+          ++near;
+          unsafeAtomicAdd(sl.flip, sl.flip_unit);
+        }
+        keep = val > sl.thr;
       }
-      if (val > sl.thr) {
+      if (keep) {
         ++kept;
         row = sl.out_rows[it.y];
         edges += row.y;
@@ -519,7 +541,8 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       } else {
         ++pruned;
       }
-      if (!row.y) *d = 0;
+      // members of a randomized probe stay marked until the step's end
+      if (sl.mode ? !keep : !row.y) *d = 0;
       item_row[i] = row;
     }
     // segmented sum of out-degrees per slot over the wavefront
@@ -595,7 +618,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned lo
       const int b = 63 - __clzll((long long)e);
       atomicAdd(&ctr[C_HIST_N + b], 1ull);
       atomicAdd(&ctr[C_HIST_E + b], e);
-      if (e >= T && slots[s].lane < 0) {
+      if (e >= T && slots[s].lane < 0 && !slots[s].mode) {
         const unsigned long long ver = (unsigned long long)slots[s].in_rows;
         const unsigned long long old = atomicCAS(&s_ver, 0ull, ver);
         if ((old == 0ull ? ver : old) == ver) {
@@ -652,6 +675,7 @@ struct ExpandArgs {
   const Slot* slots;
   long long* dense_next;
   int2* list_next;
+  int2* rclear;  // last-level candidate marks of randomized probes
   uint64_t list_cap;
   uint64_t chunk_cap;
   int32_t* has_next;
@@ -718,6 +742,51 @@ __device__ __forceinline__ bool visit_edge(const ExpandArgs& a, int32_t s, int32
   return old == 0ull;
 }
 
+// One out-edge x -> v of a member x of randomized probe slot s (Alg. 4):
+// v is a candidate of the next set unless it is the excluded walk node.  The
+// first visitor of v (a compare-and-swap marks it) draws v's in-neighbour and
+// coin from Philox with counter (walk, i * 2^16 + j, v, 1); v joins the next
+// set (mark 2) when the drawn in-neighbour is a member and the coin falls
+// below sqrt(c).  On the probe's last level a member adds 1 to the estimate
+// and the mark is recorded for clearing at the step's end.  Returns whether v
+// is listed for the next level.
+__device__ __forceinline__ bool visit_random(const ExpandArgs& a, int32_t s, int32_t v, const Slot& sl,
+                                             unsigned long long& nfinal, bool& mark) {
+  if (v == sl.excl) return false;
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(&a.dense_next[(size_t)s * a.n + v]);
+  if (atomicCAS(p, 0ull, 1ull) != 0ull) return false;
+  const uint4 w = philox4x32_10(make_uint4(sl.wk, ((uint32_t)sl.depth << 16) | (uint32_t)sl.level, (uint32_t)v, 1u),
+                                sl.key2);
+  const uint2 row = sl.in_rows[v];  // |I(v)| >= 1: a member is an in-neighbour
+  const uint64_t r = ((uint64_t)w.y << 32) | w.x;
+  const int32_t x = sl.in_col[row.x + (uint32_t)__umul64hi(r, (uint64_t)row.y)];
+  const bool sel = a.dense_cur[(size_t)s * a.n + x] == 2ll && w.z < sl.t_sc;
+  if (sl.last) {
+    mark = true;
+    if (sel) {
+      unsafeAtomicAdd(&sl.acc[v], sl.w);
+      ++nfinal;
+    }
+    return false;
+  }
+  if (sel) *p = 2ull;
+  return true;
+}
+
+// Appends the marked (slot, node) pairs of a wavefront to the clearing list.
+__device__ __forceinline__ void mark_append(const ExpandArgs& a, bool flag, int32_t s, int32_t v) {
+  const unsigned long long mask = __ballot(flag);
+  if (!mask) return;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(&a.ctr[C_RCLEAR], (unsigned long long)__popcll(mask));
+  base = __shfl(base, 0, 64);
+  if (flag) {
+    const unsigned long long pos = base + (unsigned long long)__popcll(mask & ((1ull << lane_id()) - 1ull));
+    if (pos < a.list_cap) a.rclear[pos] = make_int2(s, v);
+    else atomicOr(&a.ctr[C_OVERFLOW], 8ull);
+  }
+}
+
 // PROBE expansion.  Part 1: workgroups take tiles of kTile listed entries,
 // scan their out-degrees in LDS and walk the tile's edges 256 at a time, each
 // lane finding its entry by binary search, so the work per lane is one edge
@@ -757,8 +826,9 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
             a.map_cur[it.y] = 1;
             ++nconv;
             *dc = 0;
-          } else {  // pushed: its score is consumed here
-            *dc = 0;
+          } else {  // pushed: its score is consumed here (members of a
+                    // randomized probe are read again, cleared at the step's end)
+            if (!a.slots[it.x].mode) *dc = 0;
             if (!(row.y & kBigFlag)) {
               deg[r] = row.y;
               s_start[j] = row.x;
@@ -790,7 +860,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
     __syncthreads();
     for (uint32_t e0 = 0; e0 < total; e0 += kBlock) {
       const uint32_t e = e0 + (uint32_t)tid;
-      bool app = false;
+      bool app = false, mark = false;
       int32_t s = 0, v = 0;
       if (e < total) {
         int lo = 0, hi = kTile - 1;  // last entry j with s_pref[j] <= e
@@ -801,10 +871,11 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
         s = s_slot[lo];
         const Slot& sl = a.slots[s];
         v = sl.out_col[s_start[lo] + (e - s_pref[lo])];
-        app = visit_edge(a, s, v, s_val[lo], sl, nfinal);
+        app = sl.mode ? visit_random(a, s, v, sl, nfinal, mark) : visit_edge(a, s, v, s_val[lo], sl, nfinal);
         if (app) s_flag[lo] = 1;
       }
       wave_append(wb, app, s, v, a, nnext);
+      mark_append(a, mark, s, v);
     }
     __syncthreads();
 #pragma unroll
@@ -831,14 +902,15 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
     bool any = false;
     for (uint32_t t0 = b; t0 < e; t0 += 64) {
       const uint32_t t = t0 + lane;
-      bool app = false;
+      bool app = false, mark = false;
       int32_t v = 0;
       if (t < e) {
         v = sl.out_col[row.x + t];
-        app = visit_edge(a, s, v, sv, sl, nfinal);
+        app = sl.mode ? visit_random(a, s, v, sl, nfinal, mark) : visit_edge(a, s, v, sv, sl, nfinal);
       }
       any |= app;
       wave_append(wb, app, s, v, a, nnext);
+      mark_append(a, mark, s, v);
     }
     if (__ballot(any) && lane == 0) a.has_next[s] = 1;
   }
@@ -880,6 +952,12 @@ struct DenseArgs {
   int32_t* has_next;
   unsigned long long* ctr;
   int cur;
+  // end-of-step clearing for randomized probes
+  const int2* list_cur;
+  long long* dense_cur;
+  long long* dense_next;
+  const int2* rclear;
+  uint64_t list_cap;
 };
 
 struct LaneInfo {
@@ -1057,6 +1135,23 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
 // Finishes the targets with long in-rows from their raw partial sums.
 __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   __shared__ unsigned long long s_nz;
+  if (a.ctr[C_RAND]) {
+    // Randomized probes ran this step: their members (still marked so that
+    // candidates could test them) and their last-level candidate marks are
+    // cleared now.  Every other listed entry is already zero.
+    const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+    const unsigned long long nl = min(a.ctr[C_LIST0 + a.cur], (unsigned long long)a.list_cap);
+    for (uint64_t i = gt; i < nl; i += gs) {
+      const int2 it = a.list_cur[i];
+      a.dense_cur[(size_t)it.x * a.n + it.y] = 0;
+    }
+    const unsigned long long nm = min(a.ctr[C_RCLEAR], (unsigned long long)a.list_cap);
+    for (uint64_t i = gt; i < nm; i += gs) {
+      const int2 it = a.rclear[i];
+      a.dense_next[(size_t)it.x * a.n + it.y] = 0;
+    }
+  }
   const unsigned long long ghi = a.ctr[C_GHI], gw = a.ctr[C_GW];
   if (ghi == 0) return;
   const int tid = threadIdx.x;
@@ -1208,7 +1303,7 @@ void session_free(Session* s) {
                     &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
                     &s->keys,
-                    &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring,
+                    &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring, &s->ring_k, &s->rclear,
                     &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp,
                     &s->sel_count};
   for (DevBuf* b : bufs) devbuf_free(*b);
@@ -1290,6 +1385,7 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->t_query, sizeof(int32_t) * (s->tree_pool + s->qmax)));
   PS_TRY(devbuf_reserve(s->t_weight, sizeof(int32_t) * (s->tree_pool + s->qmax)));
   PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
+  PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
   if (!s->h_ctr) PS_HIP(hipHostMalloc((void**)&s->h_ctr, sizeof(uint64_t) * C_COUNT, 0));
   if (fresh) {
     PS_HIP(hipMemsetAsync(s->dense[0].p, 0, sizeof(long long) * s->list_cap, st));
@@ -1324,6 +1420,18 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
   recs->clear();
   bounds->assign(qs.size(), 0);
   if (qs.empty()) return PS_OK;
+  bool randomized = false;
+  for (const QueryRun& q : qs) randomized |= q.randomized != 0;
+  if (randomized && s->rclear.bytes < sizeof(int2) * s->list_cap) {
+    // the marks list of randomized probes, on first use; the captured steps
+    // point at the old (absent) one
+    if (s->step_pair) {
+      PS_HIP(hipStreamSynchronize(st));
+      (void)hipGraphExecDestroy(s->step_pair);
+      s->step_pair = nullptr;
+    }
+    PS_TRY(devbuf_reserve(s->rclear, sizeof(int2) * s->list_cap));
+  }
   // one threshold row per query, alive until the synchronisation below
   std::vector<float> thr_all(qs.size() * PS_MAX_WALK_LEN, 0.0f);
   int64_t total = 0;
@@ -1357,7 +1465,10 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     d.flip = s->flip.as<double>() + r;
     // one flip moves an estimate by at most Score * sqrt(c)^e ~ eps_p per
     // walk sharing the probe (the near band is 1e-5 relative wide)
-    d.flip_unit = q.prm.eps_p * (1.0 + 1e-4) / (double)q.prm.n_r;
+    d.flip_unit = q.randomized ? 0.0 : q.prm.eps_p * (1.0 + 1e-4) / (double)q.prm.n_r;
+    d.randomized = q.randomized;
+    d.t_sc = (uint32_t)std::floor(sc * 4294967296.0);
+    d.key2 = make_uint2((uint32_t)q.seed, (uint32_t)(q.seed >> 32) ^ 0x9E3779B9u);
     total += d.walk_count;
     s->h_rec[(size_t)r] = d;
     {
@@ -1450,6 +1561,7 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
   a.t_query = s->t_query.as<int32_t>();
   a.t_weight = s->t_weight.as<int32_t>();
   a.ring = s->ring.as<int32_t>();
+  a.ring_k = s->ring_k.as<int32_t>();
   a.ring_mask = s->ring_cap - 1;
   a.remaining = s->remaining.as<unsigned long long>();
   a.ctr = s->counters.as<unsigned long long>();
@@ -1477,6 +1589,7 @@ StepKernels step_args(Session* s) {
   sa.slots = s->slots.as<Slot>();
   sa.has_next = s->has_next.as<int32_t>();
   sa.ring = s->ring.as<int32_t>();
+  sa.ring_k = s->ring_k.as<int32_t>();
   sa.ring_mask = s->ring_cap - 1;
   sa.t_parent = s->t_parent.as<int32_t>();
   sa.t_node = s->t_node.as<int32_t>();
@@ -1527,6 +1640,7 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k.ea.map_cur = s->rowmap[cur].as<uint8_t>();
   k.ea.dense_next = s->dense[nxt].as<long long>();
   k.ea.list_next = s->list[nxt].as<int2>();
+  k.ea.rclear = s->rclear.as<int2>();
   k.ea.nxt = nxt;
   if (ev0) (void)hipEventRecord(ev0, st);
   k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
@@ -1544,6 +1658,11 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   da.has_next = s->has_next.as<int32_t>();
   da.ctr = ctr;
   da.cur = cur;
+  da.list_cur = s->list[cur].as<int2>();
+  da.dense_cur = s->dense[cur].as<long long>();
+  da.dense_next = s->dense[nxt].as<long long>();
+  da.rclear = s->rclear.as<int2>();
+  da.list_cap = s->list_cap;
   k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
   k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
   if (ev2) (void)hipEventRecord(ev2, st);
@@ -1777,6 +1896,7 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
     for (DevBuf* b : {&s->t_parent, &s->t_node, &s->t_depth, &s->t_query, &s->t_weight})
       PS_TRY(devbuf_reserve(*b, sizeof(int32_t) * (s->tree_pool + s->qmax)));
     PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
+    PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
     s->tree_free.assign(1, {0, s->tree_pool});
   }
   PS_TRY(session_build(ctx, recs, bounds));

@@ -130,6 +130,9 @@ struct QueryDev {
   const unsigned long long* heavy_cnt;
   double* flip;        // Rule-2 near-threshold allowance of the query
   double flip_unit;    // eps_p / n_r (times a walk count when charged)
+  int32_t randomized;  // probes run Alg. 4, one per walk and prefix
+  uint32_t t_sc;       // floor(sqrt(c) * 2^32): the sqrt(c) coin of Alg. 4
+  uint2 key2;          // Philox key of Alg. 4's draws
 };
 
 // Host view of a query.
@@ -139,6 +142,7 @@ struct QueryRun {
   uint64_t seed = 0;
   int64_t walk_begin = 0, walk_end = 0;
   int bias_shift = 0;
+  int randomized = 0;  // Alg. 4 instead of Alg. 2
 };
 
 // State of one probe slot on the device.
@@ -153,6 +157,10 @@ struct Slot {
   float sc;        // sqrt(c)
   int32_t last;    // this level's expansion produces the returned score set
   int32_t lane;    // column of the dense frontier matrix, -1 for a sparse frontier
+  int32_t mode;    // 1: randomized PROBE (Alg. 4) of walk wk's prefix
+  uint32_t wk;     // walk index of a randomized probe
+  uint32_t t_sc;   // floor(sqrt(c) * 2^32)
+  uint2 key2;      // Philox key of Alg. 4's draws
   double w;        // number of walks sharing the probed prefix
   const uint2* out_rows;
   const int32_t* out_col;
@@ -191,6 +199,8 @@ enum CounterIdx {
   C_PULL_EDGES,  // in-edges read by dense passes
   C_PULL_T,      // dense threshold in out-edges (set by the host)
   C_NEAR,        // Rule 2 tests within 1e-5 relative of the threshold
+  C_RAND,        // slots running randomized probes this step
+  C_RCLEAR,      // last-level candidate marks of randomized probes to clear
   C_NZROWS0,     // rows of dense matrix 0 that may hold a nonzero score
   C_NZROWS1,     // the same for matrix 1
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
@@ -220,7 +230,8 @@ struct Session {
   DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_flag;
   DevBuf mat[2], rowmap[2], npart, lane_slot, dense_ver;  // dense frontier lanes
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
-  DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring;
+  DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring, ring_k;
+  DevBuf rclear;  // (slot, node) marks of randomized probes' last levels, allocated on first use
   DevBuf sort_keys[2], sort_vals[2], sort_tmp, sel_count;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)

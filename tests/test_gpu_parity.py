@@ -227,6 +227,48 @@ def test_topk_matches_oracle(ps, cl20k, orc):
 
 
 @pytest.mark.parametrize("eps", [0.1, 0.05])
+def test_randomized_probe_matches_oracle(ps, cl20k, er, orc, eps):
+    # Alg. 4 with the same Philox draws on both sides: the estimates are
+    # counts over n_r, equal up to FP64 summation order.
+    for n, s, d, G, O in (cl20k, er):
+        for i, u in enumerate(graphs.query_nodes(n, d, 2, seed=61)):
+            gpu = ps.ps_single_source(G, int(u), 0.6, eps, 0.01, 90 + i, probe_mode=1)
+            ref, st = orc.single_source(O, int(u), orc.params(n, 0.6, eps, 0.01), 90 + i, probe="randomized")
+            _parity(gpu, ref, st, f"randomized n={n} u={int(u)} eps={eps}")
+            assert G.ctx.stats()["flip_allowance"] == 0.0
+
+
+def test_randomized_probe_in_batch_shards_and_server(ps, ctx, cl20k, orc):
+    n, s, d, G, O = cl20k
+    qn = graphs.query_nodes(n, d, 4, seed=63)
+    qs = [dict(u=int(u), k=(0 if i % 2 == 0 else 20), c=0.6, eps=0.1, delta=0.01, seed=70 + i,
+               probe_mode=(i % 3 != 2)) for i, u in enumerate(qn)]
+    res = ps.ps_batch(G, qs)
+    for q, r in zip(qs, res):
+        if q["k"]:
+            a = ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"], probe_mode=q["probe_mode"])
+        else:
+            a = ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"], probe_mode=q["probe_mode"])
+        _same_query(r, 0.0, a, 0.0, f"batch vs alone u={q['u']} probe_mode={q['probe_mode']}")
+    u = qs[0]["u"]
+    p = orc.params(n, 0.6, 0.1, 0.01)
+    whole = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 70, probe_mode=1)
+    parts = [ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 70, probe_mode=1, walk_begin=a, walk_end=b)
+             for a, b in ((0, 777), (777, p.n_r))]
+    tot = parts[0] + parts[1]
+    tot[u] = 1.0
+    _same_query(tot, 0.0, whole, 0.0, "randomized shards vs whole")
+    srv = ps.Server(G, max_inflight=2)
+    try:
+        tickets = [srv.submit(q["u"], q["c"], q["eps"], q["delta"], q["seed"], k=q["k"], probe_mode=q["probe_mode"])
+                   for q in qs]
+        for q, t, r in zip(qs, tickets, res):
+            _same_query(srv.wait(t, timeout_us=60_000_000), 0.0, r, 0.0, f"served vs batch u={q['u']}")
+    finally:
+        srv.stop()
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.05])
 def test_error_against_fp64_definition_is_stated(ps, cl20k, orc, eps):
     # The stated per-result error: against the plain FP64 evaluation the GPU
     # is within 1e-5 plus its own and the oracle's near-threshold allowances.
@@ -576,3 +618,12 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
         rn, rv = orc.topk(whole, int(q), 50)
         assert np.abs(av - rv).max() <= TOL_MODEL
         _say(f"u={int(q)}: 2000 of {p.n_r} walks in {dt:.2f} s (whole query ~{dt * p.n_r / 2000:.0f} s)")
+    # randomized PROBE (Alg. 4) on the same graph: parity on a shard, cost
+    gpu = ps.ps_single_source(G, u, 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=20, probe_mode=1)
+    ref, st = orc.single_source(O, u, p, seed, 0, 20, probe="randomized")
+    _parity(gpu, ref, st, f"cl40m randomized u={u} walks [0,20)")
+    for q in qn[:2]:
+        t0 = time.perf_counter()
+        ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000, probe_mode=1)
+        dt = time.perf_counter() - t0
+        _say(f"u={int(q)} randomized: 2000 of {p.n_r} walks in {dt:.2f} s (whole query ~{dt * p.n_r / 2000:.0f} s)")
