@@ -627,3 +627,74 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
         ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000, probe_mode=1)
         dt = time.perf_counter() - t0
         _say(f"u={int(q)} randomized: 2000 of {p.n_r} walks in {dt:.2f} s (whole query ~{dt * p.n_r / 2000:.0f} s)")
+
+
+def test_hub_rows_compaction_and_long_rows(ps, ctx, orc):
+    # A hub with in- and out-degree n-1: its rows are longer than the push
+    # chunk and pull chunk sizes, so both long-row paths run; updates on the
+    # hub's edges rewrite its rows into the delta region until it overflows
+    # and the store is compacted.  The result equals the
+    # same edge set loaded from scratch and the oracle's FP32 model.  (Each
+    # batch rewrites both 3,000-entry hub rows once; the delta region holds
+    # 2^20 entries, so 400 batches overflow it.)
+    n = 3000
+    rng = np.random.default_rng(5)
+    hub = np.arange(1, n, dtype=np.int32)
+    s0, d0 = graphs.erdos_renyi(n, 15_000, seed=9)
+    keep = (s0 != 0) & (d0 != 0)
+    src = np.concatenate([s0[keep], hub, np.zeros(n - 1, np.int32)])
+    dst = np.concatenate([d0[keep], np.zeros(n - 1, np.int32), hub])
+    G = ps.Graph(ctx, n, src, dst)
+    live = set(zip(src.tolist(), dst.tolist()))
+    for b in range(400):
+        us, ud, op = [], [], []
+        for e in ((int(rng.integers(1, n)), 0), (0, int(rng.integers(1, n)))):
+            us.append(e[0]); ud.append(e[1])
+            if e in live:
+                op.append(1); live.discard(e)
+            else:
+                op.append(0); live.add(e)
+        pe, _ = G.update(np.array(us, np.int32), np.array(ud, np.int32), np.array(op, np.uint8))
+        assert (pe == 0).all()
+    es, ed = G.edges()
+    assert set(zip(es.tolist(), ed.tolist())) == live
+    R = ps.Graph(ctx, n, es, ed)
+    O = orc.Graph(n, es, ed)
+    for u in (0, 17):
+        for pull in (0, -1):
+            q = dict(u=u, k=0, c=0.6, eps=0.1, delta=0.01, seed=13)
+            a = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 13, pull_edges=pull)
+            b = ps.ps_single_source(R, u, 0.6, 0.1, 0.01, 13, pull_edges=pull)
+            _same_query(a, 0.0, b, 0.0, f"hub graph updated vs rebuilt u={u} pull={pull}")
+        ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 13, precision="f32")
+        _parity(a, ref, st, f"hub graph u={u}")
+
+
+def test_parameter_extremes(ps, ctx, er, orc):
+    n, s, d, G, O = er
+    # one node, no edges
+    G1 = ps.Graph(ctx, 1, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert ps.ps_single_source(G1, 0, 0.6, 0.1, 0.01, 1).tolist() == [1.0]
+    # walk length cap at the maximum, and beyond it
+    gpu = ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=64, eps_t=1e-30)
+    ref, st = orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f32")
+    _parity(gpu, ref, st, "walk cap 64")
+    with pytest.raises(ps.ProbeSimError):
+        ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=65)
+    # eps close to 1 (few walks), c close to 0 and 1
+    for c, eps in ((0.6, 0.95), (0.05, 0.2), (0.9, 0.5)):
+        gpu = ps.ps_single_source(G, 9, c, eps, 0.01, 4)
+        ref, st = orc.batch(O, 9, orc.params(n, c, eps, 0.01), 4, precision="f32")
+        _parity(gpu, ref, st, f"c={c} eps={eps}")
+    # top-k with k = n - 1 (every other node) and beyond
+    nodes, vals = ps.ps_topk(G, 9, n - 1, 0.6, 0.2, 0.01, 4)
+    assert sorted(nodes.tolist()) == [v for v in range(n) if v != 9]
+    with pytest.raises(ps.ProbeSimError):
+        ps.ps_topk(G, 9, n, 0.6, 0.2, 0.01, 4)
+    # randomized probes with the walk cap and a tiny graph
+    gpu = ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=64, eps_t=1e-30, probe_mode=1)
+    ref, st = orc.single_source(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, probe="randomized")
+    _parity(gpu, ref, st, "randomized, walk cap 64")
+    assert ps.ps_single_source(G1, 0, 0.6, 0.1, 0.01, 1, probe_mode=1).tolist() == [1.0]
+    with pytest.raises(ps.ProbeSimError):
+        ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, probe_mode=2)
