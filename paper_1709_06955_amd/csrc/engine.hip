@@ -604,10 +604,12 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned lo
     s_ver = 0ull;
   }
   __syncthreads();
-  if (tid < kLanes) {
+  if (tid < kLanes) {  // one wavefront: free columns listed lowest first
     const int32_t ls = lane_slot[tid];
-    if (ls < 0) s_free[atomicAdd(&s_nfree, 1u)] = tid;
+    const unsigned long long freem = __ballot(ls < 0);
+    if (ls < 0) s_free[__popcll(freem & ((1ull << tid) - 1ull))] = tid;
     else s_ver = (unsigned long long)slots[ls].in_rows;  // all active columns share it
+    if (tid == 0) s_nfree = (uint32_t)__popcll(freem);
   }
   __syncthreads();
   const unsigned long long T = ctr[C_PULL_T];
