@@ -385,7 +385,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
     s_avail = a.ctr[C_TAIL] - s_head;
   }
   __syncthreads();
-  Slot st[kSlotsPerSchedThread];
+  // Slots are updated field by field in place (a whole Slot per register set
+  // would spill).
   bool need[kSlotsPerSchedThread];
   uint32_t cnt = 0;
 #pragma unroll
@@ -393,21 +394,21 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
     const int s = tid * kSlotsPerSchedThread + r;
     need[r] = false;
     if (s >= a.P) continue;
-    st[r] = a.slots[s];
-    if (st[r].probe >= 0) {
-      if (st[r].last || !a.has_next[s]) {
-        const int q = st[r].query;
+    Slot& S = a.slots[s];
+    if (S.probe >= 0) {
+      if (S.last || !a.has_next[s]) {
+        const int q = S.query;
         if (atomicAdd(&a.remaining[q], ~0ull) == 1ull) {  // last probe of the query
           const unsigned long long pos = atomicAdd(&a.ctr[C_DONE], 1ull);
           a.done_ring[pos % (unsigned long long)a.qmax] = q;
         }
-        if (st[r].lane >= 0) a.lane_slot[st[r].lane] = -1;  // dense column free again
-        st[r].probe = -1;
-        st[r].lane = -1;
+        if (S.lane >= 0) a.lane_slot[S.lane] = -1;  // dense column free again
+        S.probe = -1;
+        S.lane = -1;
         need[r] = true;
       } else {
-        st[r].level++;
-        st[r].cursor = a.t_parent[st[r].cursor];
+        S.level = S.level + 1;
+        S.cursor = a.t_parent[S.cursor];
       }
     } else {
       need[r] = true;
@@ -427,38 +428,42 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
   }
   unsigned long long rank = before + incl - cnt;
   const unsigned long long head = s_head, avail = s_avail;
+  unsigned long long nrand = 0;
 #pragma unroll
   for (int r = 0; r < kSlotsPerSchedThread; ++r) {
     const int s = tid * kSlotsPerSchedThread + r;
     if (s >= a.P) continue;
+    Slot& S = a.slots[s];
     if (need[r]) {
       if (rank < avail) {
-        const int32_t t = a.ring[(head + rank) & a.ring_mask];
+        const uint64_t rp = (head + rank) & a.ring_mask;
+        const int32_t t = a.ring[rp];
         const int q = a.t_query[t];
         const QueryDev& Q = a.qr[q];
-        st[r].probe = t;
-        st[r].lane = -1;
-        st[r].level = 0;
-        st[r].depth = a.t_depth[t];
-        st[r].cursor = a.t_parent[t];
-        st[r].query = q;
-        st[r].mode = Q.randomized;
-        st[r].wk = (uint32_t)a.ring_k[(head + rank) & a.ring_mask];
-        st[r].t_sc = Q.t_sc;
-        st[r].key2 = Q.key2;
-        st[r].w = Q.randomized ? 1.0 : (double)a.t_weight[t];
-        st[r].sc = Q.sc;
-        st[r].out_rows = Q.out_rows;
-        st[r].out_col = Q.out_col;
-        st[r].inv_indeg = Q.inv_indeg;
-        st[r].acc = Q.acc;
-        st[r].in_rows = Q.in_rows;
-        st[r].in_col = Q.in_col;
-        st[r].heavy_nodes = Q.heavy_nodes;
-        st[r].heavy_chunks = Q.heavy_chunks;
-        st[r].heavy_cnt = Q.heavy_cnt;
-        st[r].flip = Q.flip;
-        st[r].flip_unit = Q.flip_unit * st[r].w;
+        const double w = Q.randomized ? 1.0 : (double)a.t_weight[t];
+        S.probe = t;
+        S.lane = -1;
+        S.level = 0;
+        S.depth = a.t_depth[t];
+        S.cursor = a.t_parent[t];
+        S.query = q;
+        S.mode = Q.randomized;
+        S.wk = (uint32_t)a.ring_k[rp];
+        S.t_sc = Q.t_sc;
+        S.key2 = Q.key2;
+        S.w = w;
+        S.sc = Q.sc;
+        S.out_rows = Q.out_rows;
+        S.out_col = Q.out_col;
+        S.inv_indeg = Q.inv_indeg;
+        S.acc = Q.acc;
+        S.in_rows = Q.in_rows;
+        S.in_col = Q.in_col;
+        S.heavy_nodes = Q.heavy_nodes;
+        S.heavy_chunks = Q.heavy_chunks;
+        S.heavy_cnt = Q.heavy_cnt;
+        S.flip = Q.flip;
+        S.flip_unit = Q.flip_unit * w;
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
@@ -472,15 +477,18 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
       }
       ++rank;
     }
-    if (st[r].probe >= 0 && st[r].mode) atomicAdd(&a.ctr[C_RAND], 1ull);
-    if (st[r].probe >= 0) {
-      const int e = st[r].depth - st[r].level - 1;  // iterations left, i-j-1 >= 1
-      st[r].thr = a.thr_tab[st[r].query * PS_MAX_WALK_LEN + e];
-      st[r].excl = a.t_node[st[r].cursor];
-      st[r].last = st[r].level == st[r].depth - 2;
+    const int32_t probe = S.probe;
+    if (probe >= 0) {
+      const int level = S.level, depth = S.depth, q = S.query;
+      const int e = depth - level - 1;  // iterations left, i-j-1 >= 1
+      S.thr = a.thr_tab[q * PS_MAX_WALK_LEN + e];
+      S.excl = a.t_node[S.cursor];
+      S.last = level == depth - 2;
+      if (S.mode) ++nrand;
     }
-    a.slots[s] = st[r];
   }
+  nrand = wave_sum(nrand);
+  if (lane == 0 && nrand) atomicAdd(&a.ctr[C_RAND], nrand);
   if (tid == 0) a.ctr[C_HEAD] = head + (total < avail ? total : avail);
 }
 
