@@ -45,7 +45,7 @@ class Stats(C.Structure):
         ("walk_nodes", C.c_int64), ("probes", C.c_int64), ("entries_expanded", C.c_int64),
         ("entries_pruned", C.c_int64), ("edges_scanned", C.c_int64), ("next_entries", C.c_int64),
         ("final_entries", C.c_int64), ("near_threshold", C.c_int64), ("flip_allowance", C.c_double),
-        ("tree_nodes", C.c_int64),
+        ("tree_nodes", C.c_int64), ("switched", C.c_int64),
     ]
 
     def as_dict(self):
@@ -78,6 +78,8 @@ def lib():
         for f in (L.orc_single_source, L.orc_batch):
             f.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int, C.c_int,
                           P(C.c_double), P(Stats)]
+        L.orc_batch_hybrid.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int,
+                                       C.c_int, C.c_double, P(C.c_double), P(Stats)]
         L.orc_topk.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_double)]
         _lib = L
     return _lib
@@ -152,7 +154,7 @@ def probe(g: Graph, path, c: float, eps_p: float = 0.0, precision: str = "f64") 
     return out
 
 
-PROBES = ("deterministic", "randomized")
+PROBES = ("deterministic", "randomized", "hybrid")
 
 
 def rprobe(g: Graph, path, c: float, seed: int, k: int) -> np.ndarray:
@@ -167,7 +169,7 @@ def rprobe(g: Graph, path, c: float, seed: int, k: int) -> np.ndarray:
     return out
 
 
-def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe="deterministic"):
+def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe="deterministic", c0=None):
     if probe not in PROBES:
         raise ValueError(f"probe must be one of {PROBES}")
     out = np.zeros(g.n, dtype=np.float64)
@@ -175,24 +177,32 @@ def _run(fn, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe="determ
     kb = 0 if k_begin is None else int(k_begin)
     ke = int(p.n_r) if k_end is None else int(k_end)
     mode = _f32(precision) | (2 if probe == "randomized" else 0)
-    rc = fn(g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift), mode,
-            out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
+    args = [g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift), mode]
+    if probe == "hybrid":
+        if c0 is None:
+            raise ValueError("the hybrid probe needs c0")
+        fn = lib().orc_batch_hybrid
+        args.append(float(c0))
+    rc = fn(*args, out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
     if rc != ORC_OK:
         raise ValueError(f"query failed with code {rc}")
     return out, st.as_dict()
 
 
 def single_source(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False,
-                  precision: str = "f64", probe: str = "deterministic"):
+                  precision: str = "f64", probe: str = "deterministic", c0=None):
     """Alg. 1 estimate s^(u, .) over walks [k_begin, k_end) (default all n_r),
-    with deterministic (Alg. 2) or randomized (Alg. 4) probes."""
-    return _run(lib().orc_single_source, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe)
+    with deterministic (Alg. 2) or randomized (Alg. 4) probes; "hybrid" is
+    the switch of Section 4.4 with constant c0, which works per tree node and
+    so runs Alg. 3."""
+    return _run(lib().orc_single_source, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe, c0)
 
 
 def batch(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False,
-          precision: str = "f64"):
-    """Alg. 3 (reverse reachability tree) estimate; equal to Alg. 1 up to rounding."""
-    return _run(lib().orc_batch, g, u, p, seed, k_begin, k_end, bias_shift, precision)
+          precision: str = "f64", probe: str = "deterministic", c0=None):
+    """Alg. 3 (reverse reachability tree) estimate; equal to Alg. 1 up to
+    rounding.  probe="hybrid" adds the switch of Section 4.4 at constant c0."""
+    return _run(lib().orc_batch, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe, c0)
 
 
 def topk(scores: np.ndarray, u: int, k: int):

@@ -21,6 +21,8 @@
 //   orc_single_source   Alg. 1 (basic ProbeSim) with Pruning Rules 1 and 2, or
 //                       with randomized PROBE (Section 4.3)
 //   orc_batch           Alg. 3 (reverse reachability tree), same estimate
+//   orc_batch_hybrid    Alg. 3 with the switch of Section 4.4 from
+//                       deterministic to randomized PROBE
 //   orc_topk            Definition 2 (top-k by sorting the estimates)
 //
 // Readings where the paper is silent or inconsistent (see the design notes):
@@ -47,6 +49,17 @@
 // word 2 < floor(sqrt(c) * 2^32) is the sqrt(c) coin.  Rule 2 does not apply
 // to it (Alg. 4 has none), and each walk's probes run on their own: sharing a
 // prefix saves nothing for randomized probes (Section 4.4).
+//
+// The switch of Section 4.4 (best of both): the probe of a tree node of
+// weight w runs deterministically; before each expansion of a level H_j
+// (j = 0..i-2, H_0 included), when the out-degrees of the entries Rule 2
+// keeps sum to more than c0 * w * n (c0 is the caller's: the paper leaves it
+// open), that probe is dropped without contributing and each of the w walks
+// through the node runs randomized PROBE on the prefix instead, with the
+// random numbers it draws in randomized mode.  So c0 = infinity gives the
+// deterministic estimate, and with Rule 2 off c0 = 0 gives the randomized
+// one (with Rule 2 on, a probe whose kept entries run out before any
+// out-edge is seen stays deterministic).
 
 #include <cmath>
 #include <cstdint>
@@ -86,6 +99,7 @@ typedef struct {
   int64_t near_threshold;    // Rule 2 tests within 1e-5 relative of eps_p
   double flip_allowance;     // sum of Score*sqrt(c)^e / n_r over those tests
   int64_t tree_nodes;        // Alg. 3 only: tree nodes below the root
+  int64_t switched;          // Section 4.4 only: tree nodes whose probe switched
 } orc_stats;
 
 enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ERANGE = 2, ORC_ESELF = 3, ORC_EDUP = 4 };
@@ -265,15 +279,19 @@ struct ScoreSet {
 // Score(x) * sqrt(c)^(i-j-1) <= eps_p, then for each kept x and each
 // out-neighbour v of x other than u_{i-j-1} add sqrt(c)/|I(v)| * Score(x) to
 // H_{j+1}[v].  The returned set is H_{i-1}; by Lemma 2 (Score) its value at v
-// is the first-meeting probability P(v, (u_1..u_i)).
-static void probe(const orc_graph* g, const int32_t* path, int32_t i, double sc, double eps_p,
-                  double n_r, ScoreSet& cur, ScoreSet& nxt, orc_stats* st) {
+// is the first-meeting probability P(v, (u_1..u_i)).  With switch_edges >= 0
+// (Section 4.4) it returns false, leaving no result, as soon as the entries
+// kept at some level have more than switch_edges out-edges.
+static bool probe(const orc_graph* g, const int32_t* path, int32_t i, double sc, double eps_p,
+                  double n_r, double switch_edges, ScoreSet& cur, ScoreSet& nxt, std::vector<int32_t>& kept,
+                  orc_stats* st) {
   cur.clear();
   cur.add(path[i - 1], 1.0);
   for (int32_t j = 0; j <= i - 2; ++j) {
     const int32_t excl = path[i - j - 2];  // u_{i-j-1}
     const double pw = std::pow(sc, (double)(i - j - 1));
-    nxt.clear();
+    kept.clear();
+    int64_t edges = 0;
     for (int32_t x : cur.keys) {
       const double s = cur.val[x];
       if (eps_p > 0.0) {
@@ -288,6 +306,13 @@ static void probe(const orc_graph* g, const int32_t* path, int32_t i, double sc,
         }
       }
       if (st) st->entries_expanded++;
+      kept.push_back(x);
+      edges += g->out_ptr[x + 1] - g->out_ptr[x];
+    }
+    if (switch_edges >= 0.0 && (double)edges > switch_edges) return false;  // Section 4.4
+    nxt.clear();
+    for (int32_t x : kept) {
+      const double s = cur.val[x];
       for (int64_t e = g->out_ptr[x]; e < g->out_ptr[x + 1]; ++e) {
         const int32_t v = g->out_col[e];
         if (st) st->edges_scanned++;
@@ -304,6 +329,7 @@ static void probe(const orc_graph* g, const int32_t* path, int32_t i, double sc,
     st->probes++;
     st->final_entries += (int64_t)cur.keys.size();
   }
+  return true;
 }
 
 // Exact sums on the grid 2^-62 for the FP32 score model: one 64-bit integer
@@ -357,16 +383,18 @@ static float recip_f32(int64_t d) {
 static inline float grid_to_f32(int64_t q) { return (float)q * (float)(1.0 / kGrid); }
 
 // Alg. 2 with Rule 2 in the FP32 score model (see the header).  The returned
-// set H_{i-1} keeps the exact grid sums.
-static void probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p, double n_r,
-                      const std::vector<float>& inv_indeg, FixSet& cur, FixSet& nxt, orc_stats* st) {
+// set H_{i-1} keeps the exact grid sums.  switch_edges as in probe().
+static bool probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double c, double eps_p, double n_r,
+                      double switch_edges, const std::vector<float>& inv_indeg, FixSet& cur, FixSet& nxt,
+                      std::vector<int32_t>& kept, orc_stats* st) {
   const float sig = (float)std::sqrt(c);
   cur.clear();
   cur.add(path[i - 1], (int64_t)kGrid);  // H_0 = {u_i: 1}
   for (int32_t j = 0; j <= i - 2; ++j) {
     const int32_t excl = path[i - j - 2];  // u_{i-j-1}
     const float thr = eps_p > 0.0 ? (float)(eps_p / std::pow(std::sqrt(c), (double)(i - j - 1))) : 0.0f;
-    nxt.clear();
+    kept.clear();
+    int64_t edges = 0;
     for (int32_t x : cur.keys) {
       const float h = grid_to_f32(cur.sum[x]);
       if (eps_p > 0.0) {
@@ -380,7 +408,13 @@ static void probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double
         }
       }
       if (st) st->entries_expanded++;
-      const float a = h * sig;
+      kept.push_back(x);
+      edges += g->out_ptr[x + 1] - g->out_ptr[x];
+    }
+    if (switch_edges >= 0.0 && (double)edges > switch_edges) return false;  // Section 4.4
+    nxt.clear();
+    for (int32_t x : kept) {
+      const float a = grid_to_f32(cur.sum[x]) * sig;
       for (int64_t e = g->out_ptr[x]; e < g->out_ptr[x + 1]; ++e) {
         const int32_t v = g->out_col[e];
         if (st) st->edges_scanned++;
@@ -398,14 +432,17 @@ static void probe_f32(const orc_graph* g, const int32_t* path, int32_t i, double
     st->probes++;
     st->final_entries += (int64_t)cur.keys.size();
   }
+  return true;
 }
 
-// One probe in either precision; adds weight * Score(v) to acc.
+// One probe in either precision; adds weight * Score(v) to acc.  Returns
+// false, adding nothing, when the probe switched (switch_edges as in probe()).
 struct Prober {
   const orc_graph* g;
   bool f32;
   ScoreSet cur, nxt;
   FixSet fcur, fnxt;
+  std::vector<int32_t> kept;
   std::vector<float> inv;  // fl32(1/|I(v)|), FP32 model only
   Prober(const orc_graph* g_, bool f) : g(g_), f32(f), cur(f ? 1 : g_->n), nxt(f ? 1 : g_->n),
                                         fcur(f ? g_->n : 1), fnxt(f ? g_->n : 1) {
@@ -415,15 +452,16 @@ struct Prober {
         if (indeg(g, v) > 0) inv[v] = recip_f32(indeg(g, v));
     }
   }
-  void run(const int32_t* path, int32_t i, double c, double eps_p, double n_r_over_w, double w,
-           std::vector<double>& acc, orc_stats* st) {
+  bool run(const int32_t* path, int32_t i, double c, double eps_p, double n_r_over_w, double w,
+           std::vector<double>& acc, orc_stats* st, double switch_edges = -1.0) {
     if (f32) {
-      probe_f32(g, path, i, c, eps_p, n_r_over_w, inv, fcur, fnxt, st);
+      if (!probe_f32(g, path, i, c, eps_p, n_r_over_w, switch_edges, inv, fcur, fnxt, kept, st)) return false;
       for (int32_t v : fcur.keys) acc[v] += w * ((double)fcur.sum[v] / kGrid);
     } else {
-      probe(g, path, i, std::sqrt(c), eps_p, n_r_over_w, cur, nxt, st);
+      if (!probe(g, path, i, std::sqrt(c), eps_p, n_r_over_w, switch_edges, cur, nxt, kept, st)) return false;
       for (int32_t v : cur.keys) acc[v] += w * cur.val[v];
     }
+    return true;
   }
 };
 
@@ -545,11 +583,12 @@ int orc_single_source(const orc_graph* g, int32_t u, const orc_params* p, uint64
 
 // Alg. 3: insert the walks into a reverse reachability tree (one tree node per
 // distinct prefix (u_1..u_q), q >= 2, weighted by the number of walks sharing
-// it), PROBE every tree node once and add weight/n_r * Score.
-int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
-              int64_t k_end, int bias_shift, int f32, double* out, orc_stats* st) {
-  if (f32 & 2)  // randomized probes are per walk: the tree changes nothing
-    return orc_single_source(g, u, p, seed, k_begin, k_end, bias_shift, f32, out, st);
+// it), PROBE every tree node once and add weight/n_r * Score.  With c0 >= 0
+// the probe of a node of weight w switches as Section 4.4 describes (see the
+// header): the node's walks then probe its prefix with Alg. 4, adding 1 per
+// returned node, each with its own random numbers.
+static int batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
+                 int64_t k_end, int bias_shift, int f32, double c0, double* out, orc_stats* st) {
   if (u < 0 || u >= g->n) return ORC_ERANGE;
   if (k_begin < 0 || k_end > p->n_r || k_begin > k_end) return ORC_EINVAL;
   if (st) memset(st, 0, sizeof(*st));
@@ -557,9 +596,11 @@ int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
     int64_t parent;
     int32_t node, depth;
     int64_t weight;
+    std::vector<int64_t> walks;  // the walks through the node (Section 4.4 only)
   };
+  const bool hybrid = c0 >= 0.0;
   std::vector<TNode> tree;
-  tree.push_back({-1, u, 1, 0});
+  tree.push_back({-1, u, 1, 0, {}});
   std::unordered_map<uint64_t, int64_t> child;  // (parent id, graph node) -> id
   std::vector<int32_t> walk((size_t)p->L);
   for (int64_t k = k_begin; k < k_end; ++k) {
@@ -570,26 +611,50 @@ int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed,
       const uint64_t key = ((uint64_t)cur << 32) | (uint32_t)walk[i - 1];
       auto it = child.find(key);
       if (it == child.end()) {
-        tree.push_back({cur, walk[i - 1], i, 0});
+        tree.push_back({cur, walk[i - 1], i, 0, {}});
         it = child.emplace(key, (int64_t)tree.size() - 1).first;
       }
       cur = it->second;
       tree[cur].weight++;
+      if (hybrid) tree[cur].walks.push_back(k);
     }
   }
   if (st) st->tree_nodes = (int64_t)tree.size() - 1;
   std::vector<double> acc((size_t)g->n, 0.0);
   std::vector<int32_t> path;
   Prober pr(g, (f32 & 1) != 0);
+  std::vector<int32_t> rcur, rcand;
+  std::vector<char> in(hybrid ? (size_t)g->n : 0, 0), seen(hybrid ? (size_t)g->n : 0, 0);
   for (size_t q = 1; q < tree.size(); ++q) {
     const int32_t i = tree[q].depth;
     path.assign((size_t)i, 0);
     for (int64_t a = (int64_t)q; a >= 0; a = tree[a].parent) path[tree[a].depth - 1] = tree[a].node;
     const double w = (double)tree[q].weight;
-    pr.run(path.data(), i, p->c, p->eps_p, (double)p->n_r / w, w, acc, st);
+    const double switch_edges = hybrid ? c0 * w * (double)g->n : -1.0;
+    if (pr.run(path.data(), i, p->c, p->eps_p, (double)p->n_r / w, w, acc, st, switch_edges)) continue;
+    if (st) st->switched++;
+    for (int64_t k : tree[q].walks) {
+      rprobe(g, path.data(), i, p->c, seed, k, rcur, rcand, in, seen, st);
+      for (int32_t v : rcur) acc[v] += 1.0;
+    }
   }
   finish(g, u, p, bias_shift, acc, out);
   return ORC_OK;
+}
+
+int orc_batch(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
+              int64_t k_end, int bias_shift, int f32, double* out, orc_stats* st) {
+  if (f32 & 2)  // randomized probes are per walk: the tree changes nothing
+    return orc_single_source(g, u, p, seed, k_begin, k_end, bias_shift, f32, out, st);
+  return batch(g, u, p, seed, k_begin, k_end, bias_shift, f32, -1.0, out, st);
+}
+
+// Alg. 3 with the switch of Section 4.4 at constant c0 >= 0 (f32: bit 0 as in
+// orc_single_source).
+int orc_batch_hybrid(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin,
+                     int64_t k_end, int bias_shift, int f32, double c0, double* out, orc_stats* st) {
+  if (!(c0 >= 0.0)) return ORC_EINVAL;
+  return batch(g, u, p, seed, k_begin, k_end, bias_shift, f32 & 1, c0, out, st);
 }
 
 // Definition 2: the k nodes v != u with the largest estimates; equal

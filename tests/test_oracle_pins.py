@@ -506,3 +506,98 @@ def test_randomized_probe_guarantee_against_power_method(orc):
         assert np.abs(est - S[0]).max() <= 0.1
         # each estimate is a count of returned nodes over n_r
         assert np.allclose(est[1:] * p.n_r, np.round(est[1:] * p.n_r), atol=1e-6)
+
+
+# ------------------------------------------------- best of both (Section 4.4)
+
+
+def _prefixes(orc, G, u, p, seed):
+    """Distinct walk prefixes (u_1..u_i), i >= 2, with the walks through them."""
+    walks = {}
+    for k in range(int(p.n_r)):
+        w = [int(x) for x in orc.walk(G, u, k, seed, p)]
+        for i in range(2, len(w) + 1):
+            walks.setdefault(tuple(w[:i]), []).append(k)
+    return walks
+
+
+def _level_edges(path, out_nb):
+    """Out-edge counts of the supports of H_0..H_{i-2} of PROBE(path) without
+    pruning: H_0 = {u_i}; H_{j+1} holds the out-neighbours of H_j other than
+    u_{i-j-1} (every contribution is positive, so supports are exact)."""
+    i = len(path)
+    cur = {path[-1]}
+    sums = []
+    for j in range(i - 1):
+        sums.append(sum(len(out_nb[x]) for x in cur))
+        excl = path[i - j - 2]
+        cur = {v for x in cur for v in out_nb[x] if v != excl}
+    return sums
+
+
+def test_hybrid_switches_exactly_the_nodes_over_the_bound(orc):
+    # Section 4.4: the probe of a tree node of weight w switches when some
+    # level about to be expanded has more than c0 * w * n out-edges.  The
+    # count of switched nodes is recomputed here from the walks and plain set
+    # propagation, for several c0; it falls as c0 grows.
+    n = 30
+    src, dst = refs.random_graph(n, 0.15, 41)
+    G = orc.Graph(n, src, dst)
+    out_nb = refs.out_lists(n, src, dst)
+    p = orc.params(n, 0.6, 0.2, 0.05, eps_p=0.0)
+    u, seed = 3, 9
+    pre = _prefixes(orc, G, u, p, seed)
+    last = None
+    for c0 in (0.0, 0.05, 0.3, 1.0, 3.0, 10.0):
+        want = sum(1 for path, ks in pre.items() if max(_level_edges(path, out_nb)) > c0 * len(ks) * n)
+        for precision in ("f64", "f32"):
+            _, st = orc.batch(G, u, p, seed, precision=precision, probe="hybrid", c0=c0)
+            assert st["tree_nodes"] == len(pre)
+            assert st["switched"] == want, (c0, precision)
+        if last is not None:
+            assert want <= last
+        last = want
+    assert last < len(pre)  # the sweep covers both outcomes
+
+
+def test_hybrid_limits_are_the_two_probes(orc):
+    # c0 = infinity never switches (Alg. 3 with deterministic PROBE); with
+    # Rule 2 off, c0 = 0 switches every probe with an out-edge, which gives
+    # exactly the randomized estimate of Alg. 1 (per-walk Alg. 4 runs; a
+    # probe without out-edges returns nothing either way).
+    from synth.graphs import erdos_renyi
+
+    n = 400
+    s_, d_ = erdos_renyi(n, 3000, seed=5)
+    G = orc.Graph(n, s_, d_)
+    p = orc.params(n, 0.6, 0.1, 0.01)
+    for precision in ("f64", "f32"):
+        det, _ = orc.batch(G, 7, p, 3, precision=precision)
+        hyb, st = orc.batch(G, 7, p, 3, precision=precision, probe="hybrid", c0=math.inf)
+        assert st["switched"] == 0
+        assert np.array_equal(det, hyb)
+    p0 = orc.params(n, 0.6, 0.1, 0.01, eps_p=0.0)
+    rnd, _ = orc.single_source(G, 7, p0, 3, probe="randomized")
+    hyb, st = orc.batch(G, 7, p0, 3, precision="f32", probe="hybrid", c0=0.0)
+    assert st["switched"] == st["tree_nodes"]  # every prefix node here has out-edges
+    assert np.array_equal(rnd, hyb)
+    with pytest.raises(ValueError):
+        orc.batch(G, 7, p0, 3, probe="hybrid", c0=-1.0)
+
+
+def test_hybrid_guarantee_against_power_method(orc):
+    # Theorems 2 and 3 together: switched probes are unbiased (Section 4.3),
+    # the others are Alg. 2 with Rule 2, so the estimate keeps
+    # max_v |s^ - s| <= eps_a at a c0 that switches part of the probes.
+    from synth.graphs import erdos_renyi
+
+    n = 1000
+    s_, d_ = erdos_renyi(n, 10000, seed=1)
+    S = refs.power_method(n, s_, d_, 0.6, iters=55)
+    G = orc.Graph(n, s_, d_)
+    p = orc.params(n, 0.6, 0.1, 0.01)
+    for seed in range(2):
+        est, st = orc.batch(G, 0, p, seed, precision="f32", probe="hybrid", c0=0.05)
+        assert 0 < st["switched"] < st["tree_nodes"]
+        assert est[0] == 1.0
+        assert np.abs(est - S[0]).max() <= 0.1
