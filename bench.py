@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "cl_1m_10m"
 C, EPS, DELTA = 0.6, 0.05, 0.01
 NQ = 32
+HYBRID_C0 = 0.03  # switch constant of Section 4.4 for the hybrid pass (the library's default)
 
 
 def expand_bytes(st: dict) -> float:
@@ -165,6 +166,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the passes with randomized PROBE and with the switch of Section 4.4")
+    ap.add_argument("--hybrid-c0", type=float, default=HYBRID_C0)
     ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
     ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
     ap.add_argument("--no-autotune", action="store_true")
@@ -241,6 +245,29 @@ def main():
     batched_qps = len(q) / (time.perf_counter() - tb)
     print(f"batched: {batched_qps:.2f} queries/s", file=sys.stderr, flush=True)
 
+    # The paper's other probes on the same queries, one pass each (reported
+    # beside the metric, which is the deterministic path).
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        for name, kw in (("randomized", dict(probe_mode=ps.PROBE_RANDOMIZED)),
+                         ("hybrid", dict(probe_mode=ps.PROBE_HYBRID, hybrid_c0=args.hybrid_c0))):
+            switched = probes = 0
+            torch.cuda.synchronize()
+            tv = time.perf_counter()
+            for i, u in enumerate(q):
+                ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots, pull_edges=args.pull,
+                                    **kw)
+                st = ctx.stats()
+                switched += st["switched_probes"]
+                probes += st["tree_nodes"]
+            torch.cuda.synchronize()
+            v = {"qps": len(q) / (time.perf_counter() - tv)}
+            if name == "hybrid":
+                v.update(c0=args.hybrid_c0, switched_tree_nodes=switched / max(probes, 1))
+            variants[name] = v
+            print(f"{name}: {v}", file=sys.stderr, flush=True)
+
     alg_bytes = expand_bytes(acc)
     launches = max(acc["expand_launches"], 1)
     avg_ms = acc["expand_ms"] / launches
@@ -265,6 +292,7 @@ def main():
         "autotune": tune,
         "batched_qps": batched_qps,
         "batched_speedup": batched_qps / qps,
+        "probe_variants": variants,
         "roofline": {"bound": "hbm", "kernel": "k_expand", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches,

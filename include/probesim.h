@@ -125,29 +125,43 @@ typedef struct ps_options {
   int64_t walk_begin; /* first walk index (default 0) */
   int64_t walk_end;   /* one past the last walk index; < 0: n_r.  A sub-range
                          returns that range's share of the sum over walks
-                         (still divided by the full n_r), so shards add up. */
+                         (still divided by the full n_r), so shards add up;
+                         under PS_PROBE_HYBRID a shard's tree weights, and so
+                         its switches, are the shard's own, so its shards
+                         give another valid estimate, not the whole's. */
   int32_t slots;      /* concurrent probes on the device; 0: the graph's autotuned
                          setting, else automatic (up to 1024).  Clamped so that
                          the per-slot buffers (52 B per slot and node) fit in
                          56 GiB. */
   int32_t probe_mode; /* PS_PROBE_DETERMINISTIC (Alg. 2 with Rule 2, the
-                         default) or PS_PROBE_RANDOMIZED (Alg. 4, Section 4.3:
+                         default), PS_PROBE_RANDOMIZED (Alg. 4, Section 4.3:
                          one randomized probe per walk and prefix, no Rule 2;
                          candidate v of iteration j of the probe of prefix
                          (u_1..u_i) of walk k draws Philox4x32-10 with key
                          (seed_lo, seed_hi ^ 0x9E3779B9) and counter
                          (k, i * 2^16 + j, v, 1): words 1:0 pick its
                          in-neighbour as walks do, word 2 < floor(sqrt(c) *
-                         2^32) is the sqrt(c) coin) */
+                         2^32) is the sqrt(c) coin) or PS_PROBE_HYBRID (the
+                         switch of Section 4.4: each tree node of weight w
+                         runs Alg. 2 with Rule 2; when a level about to be
+                         expanded, H_0 included, keeps entries with more than
+                         hybrid_c0 * w * n out-edges in total, that probe is
+                         dropped and each of the w walks through the node runs
+                         Alg. 4 on the prefix, drawing what it draws in
+                         randomized mode) */
   int64_t pull_edges; /* a probe level whose kept entries have at least this many
                          out-edges is computed by pulling along in-edges over
                          all nodes instead of pushing along its out-edges (same
                          sums, other order); 0: automatic, < 0: never */
+  double hybrid_c0;   /* the constant c0 of PS_PROBE_HYBRID (>= 0, infinity
+                         allowed; the paper gives no value): default 0.03,
+                         the fastest of 0.001..1 on power-law graphs */
 } ps_options;
 
 #define PS_MAX_WALK_LEN 64
 #define PS_PROBE_DETERMINISTIC 0
 #define PS_PROBE_RANDOMIZED 1
+#define PS_PROBE_HYBRID 2
 
 /* Fills the defaults above. */
 void ps_options_default(ps_options* opt);
@@ -216,6 +230,7 @@ typedef struct ps_query {
   uint64_t seed;
   int32_t probe_mode; /* as ps_options.probe_mode */
   int32_t pad;
+  double hybrid_c0;   /* c0 when this query's own probe_mode is PS_PROBE_HYBRID */
 } ps_query;
 
 typedef struct ps_result {
@@ -286,6 +301,7 @@ typedef struct ps_stats {
      levels with 2^b <= E < 2^(b+1) (count, and the sum of E) */
   int64_t level_hist_count[32];
   int64_t level_hist_edges[32];
+  int64_t switched_probes;  /* PS_PROBE_HYBRID: tree-node probes that switched */
 } ps_stats;
 
 ps_status ps_get_stats(ps_ctx* ctx, ps_stats* out);

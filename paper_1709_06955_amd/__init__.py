@@ -27,7 +27,7 @@ PS_LOAD_DROP_SELF_LOOPS = 2
 PS_MAX_WALK_LEN = 64
 
 # Every entry point declared in include/probesim.h.
-PROBE_DETERMINISTIC, PROBE_RANDOMIZED = 0, 1
+PROBE_DETERMINISTIC, PROBE_RANDOMIZED, PROBE_HYBRID = 0, 1, 2
 
 EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
@@ -50,7 +50,7 @@ class Options(C.Structure):
         ("max_len", C.c_int32), ("bias_shift", C.c_int32),
         ("walk_begin", C.c_int64), ("walk_end", C.c_int64),
         ("slots", C.c_int32), ("probe_mode", C.c_int32),
-        ("pull_edges", C.c_int64),
+        ("pull_edges", C.c_int64), ("hybrid_c0", C.c_double),
     ]
 
 
@@ -68,7 +68,8 @@ class Stats(C.Structure):
         "entries_pruned", "edges_scanned", "next_entries", "final_adds", "expand_launches", "pull_levels",
         "pull_edges", "near_threshold")] + [
         ("flip_allowance", C.c_double), ("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double),
-        ("level_hist_count", C.c_int64 * 32), ("level_hist_edges", C.c_int64 * 32)]
+        ("level_hist_count", C.c_int64 * 32), ("level_hist_edges", C.c_int64 * 32),
+        ("switched_probes", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -80,7 +81,8 @@ class Stats(C.Structure):
 
 class Query(C.Structure):
     _fields_ = [("u", C.c_int32), ("k", C.c_int32), ("c", C.c_double), ("eps", C.c_double),
-                ("delta", C.c_double), ("seed", C.c_uint64), ("probe_mode", C.c_int32), ("pad", C.c_int32)]
+                ("delta", C.c_double), ("seed", C.c_uint64), ("probe_mode", C.c_int32), ("pad", C.c_int32),
+                ("hybrid_c0", C.c_double)]
 
 
 class Result(C.Structure):
@@ -343,7 +345,8 @@ class BatchResults(list):
 
 
 def ps_batch(g: Graph, queries, outs=None, **opt):
-    """queries: list of dicts (u, k, c, eps, delta, seed).  Returns a list of
+    """queries: list of dicts (u, k, c, eps, delta, seed; optional probe_mode,
+    hybrid_c0).  Returns a list of
     score arrays (single-source) or (nodes, scores) pairs (top-k), with the
     per-query allowances in its `flip_allowance` attribute."""
     nq = len(queries)
@@ -352,7 +355,7 @@ def ps_batch(g: Graph, queries, outs=None, **opt):
     keep = []
     for i, q in enumerate(queries):
         qa[i] = Query(int(q["u"]), int(q.get("k", 0)), q["c"], q["eps"], q["delta"], int(q["seed"]),
-                      int(q.get("probe_mode", 0)), 0)
+                      int(q.get("probe_mode", 0)), 0, float(q.get("hybrid_c0", options().hybrid_c0)))
         if outs is not None:
             sc, nd = outs[i]
         elif q.get("k", 0) > 0:
@@ -384,8 +387,9 @@ class Server:
         self.g = g
         self._pending = {}
 
-    def submit(self, u, c, eps, delta, seed, k=0, probe_mode=0):
-        q = Query(int(u), int(k), c, eps, delta, int(seed), int(probe_mode), 0)
+    def submit(self, u, c, eps, delta, seed, k=0, probe_mode=0, hybrid_c0=None):
+        c0 = options().hybrid_c0 if hybrid_c0 is None else float(hybrid_c0)
+        q = Query(int(u), int(k), c, eps, delta, int(seed), int(probe_mode), 0, c0)
         if k > 0:
             sc, nd = np.zeros(k, np.float64), np.zeros(k, np.int32)
         else:

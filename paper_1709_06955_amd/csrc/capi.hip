@@ -93,6 +93,7 @@ extern "C" void ps_options_default(ps_options* o) {
   o->eps_p = -1.0;
   o->walk_begin = 0;
   o->walk_end = -1;
+  o->hybrid_c0 = 0.03;  // fastest measured on power-law graphs; the paper leaves c0 open
 }
 
 // Alg. 1 (number of walks), Rule 1 (truncation), Theorem 2 (error split).
@@ -135,8 +136,13 @@ ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, doub
   q->walk_begin = opt ? opt->walk_begin : 0;
   q->walk_end = (opt && opt->walk_end >= 0) ? opt->walk_end : q->prm.n_r;
   q->bias_shift = opt ? opt->bias_shift : 0;
-  q->randomized = opt ? opt->probe_mode : 0;
-  if (q->randomized != 0 && q->randomized != 1) return PS_ERR_INVALID_ARG;
+  const int mode = opt ? opt->probe_mode : PS_PROBE_DETERMINISTIC;
+  if (mode != PS_PROBE_DETERMINISTIC && mode != PS_PROBE_RANDOMIZED && mode != PS_PROBE_HYBRID)
+    return PS_ERR_INVALID_ARG;
+  q->randomized = mode == PS_PROBE_RANDOMIZED;
+  q->hybrid = mode == PS_PROBE_HYBRID;
+  q->c0 = q->hybrid ? opt->hybrid_c0 : 0.0;
+  if (q->hybrid && !(q->c0 >= 0.0)) return PS_ERR_INVALID_ARG;  // NaN too
   if (q->walk_begin < 0 || q->walk_end > q->prm.n_r || q->walk_begin > q->walk_end) return PS_ERR_INVALID_ARG;
   return PS_OK;
 }
@@ -223,7 +229,10 @@ extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const
     ps_options qo;
     if (opt) qo = *opt;
     else ps_options_default(&qo);
-    if (qv[i].probe_mode) qo.probe_mode = qv[i].probe_mode;
+    if (qv[i].probe_mode) {
+      qo.probe_mode = qv[i].probe_mode;
+      if (qv[i].probe_mode == PS_PROBE_HYBRID) qo.hybrid_c0 = qv[i].hybrid_c0;
+    }
     ps_status s = make_query_run(g, qv[i].u, qv[i].k, qv[i].c, qv[i].eps, qv[i].delta, qv[i].seed, &qo, &q);
     if (s == PS_OK && (!r[i].scores || (qv[i].k > 0 && !r[i].nodes))) s = PS_ERR_INVALID_ARG;
     r[i].status = s;

@@ -267,15 +267,55 @@ __global__ void k_walk_tree(TreeArgs a) {
       a.t_query[id] = r;
     }
     // a deterministic probe per tree node; a randomized one per walk and
-    // prefix (their draws differ per walk, so sharing saves nothing)
+    // prefix (their draws differ per walk, so sharing saves nothing).  The
+    // ring's walk index marks a randomized probe; -1 a deterministic one.
     if (inserted || q.randomized) {
       atomicAdd(&a.remaining[r], 1ull);
       atomicAdd(&a.ctr[C_LEVELS], (unsigned long long)(len - 1));
       const unsigned long long pos = atomicAdd(&a.ctr[C_TAIL], 1ull);
       a.ring[pos & a.ring_mask] = (int32_t)id;
-      a.ring_k[pos & a.ring_mask] = (int32_t)k;
+      a.ring_k[pos & a.ring_mask] = q.randomized ? (int32_t)k : -1;
     }
     atomicAdd(&a.t_weight[id], 1);
+    parent = id;
+  }
+}
+
+// Section 4.4, one hybrid query: gives every tree node of its region a range
+// of t_walks as long as its weight (ranges in hash order, which only decides
+// where a node's walks are kept); t_woff[t] is left at the range's start.
+// The weights sum to at most half the region, so the ranges stay inside it.
+__global__ void k_walk_offsets(const unsigned long long* __restrict__ keys, const int32_t* __restrict__ t_weight,
+                               uint32_t* __restrict__ t_woff, uint64_t base, uint64_t cap,
+                               unsigned long long* __restrict__ count) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cap || keys[base + i] == kEmpty) return;
+  t_woff[base + i] = (uint32_t)(base + atomicAdd(count, (unsigned long long)t_weight[base + i]));
+}
+
+// Section 4.4: samples the walks of the hybrid queries again (Philox is
+// counter-based) and files walk k under every tree node it passes.  Every
+// key is present, so the tree lookup inserts nothing.  Afterwards t_woff[t]
+// is one past t's range, which starts at t_woff[t] - weight.
+__global__ void k_walk_lists(TreeArgs a, uint32_t* __restrict__ t_woff, int32_t* __restrict__ t_walks) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.total) return;
+  const int r = find_record(a.qr, a.lq, a.nl, g);
+  const QueryDev q = a.qr[r];
+  if (!q.hybrid) return;
+  const uint32_t k = (uint32_t)(q.walk_begin + (g - q.walk_base));
+  uint32_t parent = (uint32_t)(a.root_base + r);
+  int32_t v = q.u;
+  int len = 1;
+  for (uint32_t t = 0; len < q.L; ++t) {
+    const int32_t nx = walk_move(v, k, t, q);
+    if (nx < 0) break;
+    v = nx;
+    ++len;
+    bool inserted;
+    const uint32_t id = tree_insert(a.keys, q.tree_base, q.tree_mask, ((unsigned long long)parent << 32) | (uint32_t)v,
+                                    inserted);
+    t_walks[atomicAdd(&t_woff[id], 1u)] = (int32_t)k;
     parent = id;
   }
 }
@@ -312,6 +352,7 @@ __global__ void k_reset_slots(Slot* slots, int32_t* has_next, int P) {
 
 // Graph version whose in-rows the dense pass reads (all dense lanes share it).
 struct DenseVer {
+  const uint2* out_rows;  // out-degrees of the targets (Section 4.4 counts)
   const uint2* in_rows;
   const int32_t* in_col;
   const float* inv_indeg;
@@ -440,15 +481,17 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         const int32_t t = a.ring[rp];
         const int q = a.t_query[t];
         const QueryDev& Q = a.qr[q];
-        const double w = Q.randomized ? 1.0 : (double)a.t_weight[t];
+        const int32_t wk = a.ring_k[rp];
+        const int mode = wk >= 0;  // a randomized probe of walk wk's prefix
+        const double w = mode ? 1.0 : (double)a.t_weight[t];
         S.probe = t;
         S.lane = -1;
         S.level = 0;
         S.depth = a.t_depth[t];
         S.cursor = a.t_parent[t];
         S.query = q;
-        S.mode = Q.randomized;
-        S.wk = (uint32_t)a.ring_k[rp];
+        S.mode = mode;
+        S.wk = mode ? (uint32_t)wk : 0u;
         S.t_sc = Q.t_sc;
         S.key2 = Q.key2;
         S.w = w;
@@ -463,12 +506,15 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         S.heavy_chunks = Q.heavy_chunks;
         S.heavy_cnt = Q.heavy_cnt;
         S.flip = Q.flip;
-        S.flip_unit = Q.flip_unit * w;
+        S.flip_unit = mode ? 0.0 : Q.flip_unit * w;
+        // Section 4.4: a hybrid query's deterministic probe of weight w
+        // switches past c0 * w * n out-edges
+        S.hyb_thr = !mode && Q.hybrid ? (Q.c0 * w) * (double)a.n : -1.0;
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
           // H_0 = {u_i: 1}; a randomized probe's members are marked 2
-          a.dense_cur[(size_t)s * a.n + x] = Q.randomized ? 2ll : kGridOne;
+          a.dense_cur[(size_t)s * a.n + x] = mode ? 2ll : kGridOne;
           a.list_cur[pos] = make_int2(s, x);
         } else {
           atomicOr(&a.ctr[C_OVERFLOW], 1ull);
@@ -482,6 +528,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
       const int level = S.level, depth = S.depth, q = S.query;
       const int e = depth - level - 1;  // iterations left, i-j-1 >= 1
       S.thr = a.thr_tab[q * PS_MAX_WALK_LEN + e];
+      S.thr_next = e > 1 ? a.thr_tab[q * PS_MAX_WALK_LEN + e - 1] : 0.0f;
       S.excl = a.t_node[S.cursor];
       S.last = level == depth - 2;
       if (S.mode) ++nrand;
@@ -590,18 +637,63 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
   }
 }
 
-// One workgroup: moves sparse slots whose kept entries have at least
-// ctr[C_PULL_T] out-edges into free dense columns, as long as they read the
-// graph version the dense pass uses (fixed by the columns already active, or
-// by the first slot moved).  Their entries are scattered into the dense
-// matrix by k_expand this step.  Also sets the column range of this step's
-// dense pass and records the version's arrays for it.
-__global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned long long* __restrict__ slot_edges,
-                                                         Slot* __restrict__ slots, int32_t* __restrict__ pull_flag,
-                                                         int32_t* __restrict__ lane_slot, DenseVer* __restrict__ dv,
-                                                         unsigned long long* __restrict__ ctr) {
+struct PickArgs {
+  int P;
+  unsigned long long* slot_edges;
+  unsigned long long* hyb_edges;
+  Slot* slots;
+  int32_t* pull_flag;
+  int32_t* lane_slot;
+  DenseVer* dv;
+  // Section 4.4 switches
+  const int32_t* t_weight;
+  const uint32_t* t_woff;
+  const int32_t* t_walks;
+  int32_t* ring;
+  int32_t* ring_k;
+  uint64_t ring_mask;
+  unsigned long long* remaining;
+  unsigned long long* ctr;
+};
+
+// Section 4.4: the deterministic probe in slot S stops (k_expand drops its
+// level, so it retires at the next step) and each walk through its tree node
+// is queued for a randomized probe of the same prefix.  A dense column it
+// held is free again; this step's pass writes that column as zeros.
+__device__ void switch_probe(const PickArgs& a, Slot& S) {
+  if (S.lane >= 0) {
+    a.lane_slot[S.lane] = -1;
+    S.lane = -1;
+  }
+  const int32_t t = S.probe;
+  const uint32_t w = (uint32_t)a.t_weight[t];
+  const uint32_t first = a.t_woff[t] - w;
+  atomicAdd(&a.remaining[S.query], (unsigned long long)w);  // before the switched probe retires
+  atomicAdd(&a.ctr[C_LEVELS], (unsigned long long)w * (unsigned long long)(S.depth - 1));
+  atomicAdd(&a.ctr[C_SWITCH], 1ull);
+  const unsigned long long pos = atomicAdd(&a.ctr[C_TAIL], (unsigned long long)w);
+  // admission reserves ring room for every walk of a hybrid query; a guard
+  if (pos + w - a.ctr[C_HEAD] > a.ring_mask + 1) atomicOr(&a.ctr[C_OVERFLOW], 16ull);
+  for (uint32_t m = 0; m < w; ++m) {
+    a.ring[(pos + m) & a.ring_mask] = t;
+    a.ring_k[(pos + m) & a.ring_mask] = a.t_walks[first + m];
+  }
+}
+
+// One workgroup.  First the switch of Section 4.4 for hybrid queries: a
+// deterministic probe switches when the level it is about to expand has more
+// kept out-edges than c0 * w * n (k_prep's sum for a sparse frontier, the
+// count of the last dense pass for a dense column).  Then it moves sparse
+// slots whose kept entries have at least ctr[C_PULL_T] out-edges into free
+// dense columns, as long as they read the graph version the dense pass uses
+// (fixed by the columns active at the start, or by the first slot moved).
+// Their entries are scattered into the dense matrix by k_expand this step.
+// A column freed by a switch is handed out at the next step only.  Also sets
+// the column range of this step's dense pass and records the version's
+// arrays for it.
+__global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
   __shared__ int32_t s_free[kLanes];
-  __shared__ uint32_t s_nfree, s_ncand, s_hi, s_active;
+  __shared__ uint32_t s_nfree, s_ncand, s_hi, s_active, s_fhi;
   __shared__ unsigned long long s_ver;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -609,43 +701,54 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned lo
     s_ncand = 0;
     s_hi = 0;
     s_active = 0;
+    s_fhi = 0;
     s_ver = 0ull;
   }
   __syncthreads();
   if (tid < kLanes) {  // one wavefront: free columns listed lowest first
-    const int32_t ls = lane_slot[tid];
+    const int32_t ls = a.lane_slot[tid];
     const unsigned long long freem = __ballot(ls < 0);
     if (ls < 0) s_free[__popcll(freem & ((1ull << tid) - 1ull))] = tid;
-    else s_ver = (unsigned long long)slots[ls].in_rows;  // all active columns share it
+    else s_ver = (unsigned long long)a.slots[ls].in_rows;  // all active columns share it
     if (tid == 0) s_nfree = (uint32_t)__popcll(freem);
   }
   __syncthreads();
+  unsigned long long* ctr = a.ctr;
   const unsigned long long T = ctr[C_PULL_T];
-  for (int s = tid; s < P; s += blockDim.x) {
-    const unsigned long long e = slot_edges[s];
+  for (int s = tid; s < a.P; s += blockDim.x) {
+    Slot& S = a.slots[s];
+    unsigned long long e = a.slot_edges[s];
+    const unsigned long long he = a.hyb_edges[s];
+    if (he) a.hyb_edges[s] = 0;
     int32_t flag = 0;
+    if (S.probe >= 0 && S.hyb_thr >= 0.0 && (double)(S.lane >= 0 ? he : e) > S.hyb_thr) {
+      if (S.lane >= 0) atomicMax(&s_fhi, (uint32_t)S.lane + 1u);
+      switch_probe(a, S);
+      flag = 2;
+      e = 0;
+    }
     if (e) {
       const int b = 63 - __clzll((long long)e);
       atomicAdd(&ctr[C_HIST_N + b], 1ull);
       atomicAdd(&ctr[C_HIST_E + b], e);
-      if (e >= T && slots[s].lane < 0 && !slots[s].mode) {
-        const unsigned long long ver = (unsigned long long)slots[s].in_rows;
+      if (e >= T && S.lane < 0 && !S.mode) {
+        const unsigned long long ver = (unsigned long long)S.in_rows;
         const unsigned long long old = atomicCAS(&s_ver, 0ull, ver);
         if ((old == 0ull ? ver : old) == ver) {
           const uint32_t k = atomicAdd(&s_ncand, 1u);
           if (k < s_nfree) {
             const int32_t lane = s_free[k];
-            slots[s].lane = lane;
-            lane_slot[lane] = s;
+            S.lane = lane;
+            a.lane_slot[lane] = s;
             flag = 1;
           }
         }
       }
     }
-    pull_flag[s] = flag;
+    a.pull_flag[s] = flag;
   }
   __syncthreads();
-  if (tid < kLanes && lane_slot[tid] >= 0) {
+  if (tid < kLanes && a.lane_slot[tid] >= 0) {
     atomicMax(&s_hi, (uint32_t)tid + 1u);
     atomicAdd(&s_active, 1u);
   }
@@ -655,18 +758,21 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(int P, const unsigned lo
     const unsigned long long prev = ctr[C_GPREV];
     ctr[C_GHI] = hi;
     ctr[C_GW] = hi > prev ? hi : prev;
-    ctr[C_GPREV] = hi;
+    // a column freed by a switch still holds its level in this step's input
+    // matrix, which the next step writes: it counts as in use until then
+    ctr[C_GPREV] = hi > s_fhi ? hi : s_fhi;
     if (s_active) atomicAdd(&ctr[C_PULLS], (unsigned long long)s_active);
     for (int g = 0; g < kLanes; ++g) {
-      const int32_t ls = lane_slot[g];
+      const int32_t ls = a.lane_slot[g];
       if (ls < 0) continue;
-      const Slot& sl = slots[ls];
-      dv->in_rows = sl.in_rows;
-      dv->in_col = sl.in_col;
-      dv->inv_indeg = sl.inv_indeg;
-      dv->heavy_nodes = sl.heavy_nodes;
-      dv->heavy_chunks = sl.heavy_chunks;
-      dv->heavy_cnt = sl.heavy_cnt;
+      const Slot& sl = a.slots[ls];
+      a.dv->out_rows = sl.out_rows;
+      a.dv->in_rows = sl.in_rows;
+      a.dv->in_col = sl.in_col;
+      a.dv->inv_indeg = sl.inv_indeg;
+      a.dv->heavy_nodes = sl.heavy_nodes;
+      a.dv->heavy_chunks = sl.heavy_chunks;
+      a.dv->heavy_cnt = sl.heavy_cnt;
       break;
     }
   }
@@ -831,10 +937,13 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
         if (row.y) {
           const int2 it = a.list_cur[i];
           long long* dc = a.dense_cur + (size_t)it.x * a.n + it.y;
-          if (a.pull_flag[it.x]) {  // slot moved to a dense column: scatter
+          const int32_t pf = a.pull_flag[it.x];
+          if (pf == 1) {  // slot moved to a dense column: scatter
             a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = grid_f32(*dc);
             a.map_cur[it.y] = 1;
             ++nconv;
+            *dc = 0;
+          } else if (pf == 2) {  // switched probe (Section 4.4): the level is dropped
             *dc = 0;
           } else {  // pushed: its score is consumed here (members of a
                     // randomized probe are read again, cleared at the step's end)
@@ -902,7 +1011,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
   for (uint64_t c = wave; c < nchunk; c += nwaves) {
     const int2 ch = a.chunk_list[c];
     const int32_t s = a.list_cur[ch.x].x;
-    if (a.pull_flag[s]) continue;
+    if (a.pull_flag[s]) continue;  // pulled or switched
     const Slot sl = a.slots[s];
     const float sv = a.item_val[ch.x];
     const uint2 row = a.item_row[ch.x];
@@ -959,6 +1068,7 @@ struct DenseArgs {
   const uint8_t* map_cur;  // per node: its row of mat_cur may hold a nonzero score
   uint8_t* map_next;       // the same for mat_next, written with it
   long long* npart;  // n x kLanes partial grid sums of long in-rows
+  unsigned long long* hyb_edges;  // Section 4.4: kept out-edges of each column's next level
   int32_t* has_next;
   unsigned long long* ctr;
   int cur;
@@ -973,6 +1083,9 @@ struct DenseArgs {
 struct LaneInfo {
   bool active;
   bool last;
+  bool hyb;        // count the next level's kept out-edges (Section 4.4)
+  float thr_next;  // Rule 2 threshold the next level applies
+  int32_t slot;
   float thr, sc;
   int32_t excl;
   double w;
@@ -997,17 +1110,21 @@ __device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigne
       li.acc = sl.acc;
       li.flip = sl.flip;
       li.flip_unit = sl.flip_unit;
+      li.hyb = sl.hyb_thr >= 0.0 && !sl.last;
+      li.thr_next = sl.thr_next;
+      li.slot = s;
     }
   }
   return li;
 }
 
 // Target v of column g with grid sum q of its contributions: the FP64
-// estimate on a probe's last level, else the next level's FP32 score.  Only
-// writer lanes (one per column) act; every lane of the wavefront calls it.
-__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, bool writer, int32_t v,
-                                             long long q, unsigned long long gw, unsigned long long& nfinal,
-                                             unsigned long long& nzrows) {
+// estimate on a probe's last level, else the next level's FP32 score, which
+// is returned (0 when none).  Only writer lanes (one per column) act; every
+// lane of the wavefront calls it.
+__device__ __forceinline__ float dense_finish(const DenseArgs& a, const LaneInfo& li, int g, bool writer, int32_t v,
+                                              long long q, unsigned long long gw, unsigned long long& nfinal,
+                                              unsigned long long& nzrows) {
   float out = 0.0f;
   bool nz = false;
   if (writer && li.active && v != li.excl && q > 0) {
@@ -1026,7 +1143,7 @@ __device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo&
   const bool any = __ballot(nz) != 0ull;  // the whole row is rewritten: its flag too
   if (lane_id() == 0) a.map_next[v] = any ? 1 : 0;
   nzrows += any ? 1ull : 0ull;
-  return nz;
+  return out;
 }
 
 // Grid value of the contribution of in-neighbour score h to target v (the
@@ -1055,7 +1172,8 @@ template <bool kMap>
 __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& li, const DenseVer& dv, int col,
                                            int grp, int L, uint64_t wave, uint64_t nwaves, unsigned long long gw,
                                            unsigned long long& nz_mask, unsigned long long& nfinal,
-                                           unsigned long long& inedges, unsigned long long& nzrows) {
+                                           unsigned long long& inedges, unsigned long long& nzrows,
+                                           unsigned long long& hedges) {
   const float* m = a.mat_cur + col;
   const uint32_t T = 64u / (uint32_t)L;
   const bool writer = grp == 0;
@@ -1076,7 +1194,10 @@ __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& l
     long long q = s0 + s1;
     for (int off = L; off < 64; off <<= 1) q += __shfl_xor(q, off, 64);
     inedges += row.y;
-    const bool nz = dense_finish(a, li, col, writer, (int32_t)v, q, gw, nfinal, nzrows);
+    const float out = dense_finish(a, li, col, writer, (int32_t)v, q, gw, nfinal, nzrows);
+    // Section 4.4: out-edges of the entries the next level's Rule 2 keeps
+    if (li.hyb && out > li.thr_next) hedges += dv.out_rows[v].y;
+    const bool nz = out > 0.0f;
     nz_mask |= __ballot(nz);
   }
   const unsigned long long nch = dv.heavy_cnt[1];
@@ -1125,12 +1246,13 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   const int col = g & (L - 1), grp = g / L;
   const LaneInfo li = lane_info(a, col, ghi);
   const DenseVer dv = *a.dv;
-  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0, nzrows = 0;
+  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0, nzrows = 0, hedges = 0;
   // the row map pays off when fewer than half of the rows may be nonzero
   if (2ull * a.ctr[C_NZROWS0 + a.cur] < (unsigned long long)a.n)
-    dense_rows<true>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows);
+    dense_rows<true>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows, hedges);
   else
-    dense_rows<false>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows);
+    dense_rows<false>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows, hedges);
+  if (hedges) atomicAdd(&a.hyb_edges[li.slot], hedges);
   if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
@@ -1172,7 +1294,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   const DenseVer dv = *a.dv;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  unsigned long long nz_mask = 0, nfinal = 0, nzrows = 0;
+  unsigned long long nz_mask = 0, nfinal = 0, nzrows = 0, hedges = 0;
   const unsigned long long nh = dv.heavy_cnt[0];
   for (uint64_t i = wave; i < nh; i += nwaves) {
     const int32_t v = dv.heavy_nodes[i];
@@ -1182,11 +1304,14 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
       sum = *p;
       *p = 0;
     }
-    const bool nz = dense_finish(a, li, g, true, v, sum, gw, nfinal, nzrows);
+    const float out = dense_finish(a, li, g, true, v, sum, gw, nfinal, nzrows);
+    if (li.hyb && out > li.thr_next) hedges += dv.out_rows[v].y;
+    const bool nz = out > 0.0f;
     nz_mask |= __ballot(nz);
   }
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
+  if (hedges) atomicAdd(&a.hyb_edges[li.slot], hedges);
   nfinal = wave_sum(nfinal);
   if (g == 0 && nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
   __syncthreads();
@@ -1274,7 +1399,7 @@ void tree_release(Session* s, uint64_t start, uint64_t len) {
 
 void report_overflow(const Session* s, const uint64_t* h) {
   std::fprintf(stderr,
-               "probesim: frontier capacity guard tripped (sites 0x%llx: 1 roots, 2 chunks, 4 next level); "
+               "probesim: capacity guard tripped (sites 0x%llx: 1 roots, 2 chunks, 4 next level, 8 marks, 16 ring); "
                "P %d n %d list cap %llu (lists %llu, %llu) chunk cap %llu (chunks %llu)\n",
                (unsigned long long)h[C_OVERFLOW], s->P, s->n, (unsigned long long)s->list_cap,
                (unsigned long long)h[C_LIST0], (unsigned long long)h[C_LIST1], (unsigned long long)s->chunk_cap,
@@ -1314,6 +1439,7 @@ void session_free(Session* s) {
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
                     &s->keys,
                     &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring, &s->ring_k, &s->rclear,
+                    &s->hyb_edges, &s->t_woff, &s->t_walks, &s->wcount,
                     &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp,
                     &s->sel_count};
   for (DevBuf* b : bufs) devbuf_free(*b);
@@ -1363,6 +1489,7 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->slots, sizeof(Slot) * (size_t)P));
   PS_TRY(devbuf_reserve(s->has_next, sizeof(int32_t) * (size_t)P));
   PS_TRY(devbuf_reserve(s->slot_edges, sizeof(unsigned long long) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->hyb_edges, sizeof(unsigned long long) * (size_t)P));
   PS_TRY(devbuf_reserve(s->pull_flag, sizeof(int32_t) * (size_t)P));
   PS_TRY(devbuf_reserve(s->mat[0], sizeof(float) * (size_t)n * kLanes));
   PS_TRY(devbuf_reserve(s->mat[1], sizeof(float) * (size_t)n * kLanes));
@@ -1394,6 +1521,9 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->t_depth, sizeof(int32_t) * (s->tree_pool + s->qmax)));
   PS_TRY(devbuf_reserve(s->t_query, sizeof(int32_t) * (s->tree_pool + s->qmax)));
   PS_TRY(devbuf_reserve(s->t_weight, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+  PS_TRY(devbuf_reserve(s->t_woff, sizeof(uint32_t) * s->tree_pool));
+  PS_TRY(devbuf_reserve(s->t_walks, sizeof(int32_t) * s->tree_pool));
+  PS_TRY(devbuf_reserve(s->wcount, sizeof(unsigned long long) * (size_t)s->qmax));
   PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
   PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
   if (!s->h_ctr) PS_HIP(hipHostMalloc((void**)&s->h_ctr, sizeof(uint64_t) * C_COUNT, 0));
@@ -1406,6 +1536,7 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   for (DevBuf* b : {&s->rowmap[0], &s->rowmap[1]}) PS_HIP(hipMemsetAsync(b->p, 0, (size_t)n, st));
   k_reset_lanes<<<1, kLanes, 0, st>>>(s->lane_slot.as<int32_t>());
   PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
+  PS_HIP(hipMemsetAsync(s->hyb_edges.p, 0, sizeof(unsigned long long) * (size_t)P, st));
   k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(s->slots.as<Slot>(), s->has_next.as<int32_t>(), P);
   PS_HIP(hipGetLastError());
   s->steps = 0;
@@ -1431,7 +1562,7 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
   bounds->assign(qs.size(), 0);
   if (qs.empty()) return PS_OK;
   bool randomized = false;
-  for (const QueryRun& q : qs) randomized |= q.randomized != 0;
+  for (const QueryRun& q : qs) randomized |= q.randomized != 0 || q.hybrid != 0;  // switched probes are randomized
   if (randomized && s->rclear.bytes < sizeof(int2) * s->list_cap) {
     // the marks list of randomized probes, on first use; the captured steps
     // point at the old (absent) one
@@ -1477,6 +1608,8 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     // walk sharing the probe (the near band is 1e-5 relative wide)
     d.flip_unit = q.randomized ? 0.0 : q.prm.eps_p * (1.0 + 1e-4) / (double)q.prm.n_r;
     d.randomized = q.randomized;
+    d.hybrid = q.hybrid;
+    d.c0 = q.c0;
     d.t_sc = (uint32_t)std::floor(sc * 4294967296.0);
     d.key2 = make_uint2((uint32_t)q.seed, (uint32_t)(q.seed >> 32) ^ 0x9E3779B9u);
     total += d.walk_count;
@@ -1513,6 +1646,12 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
   return PS_OK;
 }
 
+// Ring entries record r may need: one per tree node, plus one per walk and
+// prefix for the probes a hybrid query switches (Section 4.4).
+static uint64_t ring_share(const Session* s, int r, uint64_t bound) {
+  return s->h_rec[(size_t)r].hybrid ? 2 * bound : bound;
+}
+
 // Phase 2 of admission: tree regions, tree construction, probes queued.
 // Records with bound 0 have no probe and need no tree.
 ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds) {
@@ -1521,7 +1660,7 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
   std::vector<int32_t> launch;
   int64_t total = 0;
   uint64_t ring_need = 0;
-  for (size_t i = 0; i < recs.size(); ++i) ring_need += bounds[i];
+  for (size_t i = 0; i < recs.size(); ++i) ring_need += ring_share(s, recs[i], bounds[i]);
   if (s->ring_outstanding + ring_need > s->ring_cap) return PS_ERR_BUSY;
   std::vector<std::pair<int, uint64_t>> got;
   for (size_t i = 0; i < recs.size(); ++i) {
@@ -1544,8 +1683,8 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
     d.tree_mask = s->rec_tree[(size_t)r].second - 1;
     d.walk_base = total;
     total += d.walk_count;
-    s->rec_ring[(size_t)r] = bounds[i];
-    s->ring_outstanding += bounds[i];
+    s->rec_ring[(size_t)r] = ring_share(s, r, bounds[i]);
+    s->ring_outstanding += s->rec_ring[(size_t)r];
     launch.push_back(r);
     PS_HIP(hipMemcpyAsync(s->qrec.as<QueryDev>() + r, &d, sizeof(QueryDev), hipMemcpyHostToDevice, st));
     PS_HIP(hipMemsetAsync(s->keys.as<unsigned long long>() + d.tree_base, 0xFF,
@@ -1577,6 +1716,24 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
   a.ctr = s->counters.as<unsigned long long>();
   if (total > 0) {
     k_walk_tree<<<grid_for((uint64_t)total, kBlock), kBlock, 0, st>>>(a);
+    PS_HIP(hipGetLastError());
+  }
+  // Section 4.4: the walks through each tree node of the hybrid queries
+  bool hybrid = false;
+  for (int r : launch) {
+    const QueryDev& d = s->h_rec[(size_t)r];
+    if (!d.hybrid) continue;
+    hybrid = true;
+    unsigned long long* cnt = s->wcount.as<unsigned long long>() + r;
+    PS_HIP(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), st));
+    k_walk_offsets<<<grid_for(d.tree_mask + 1, kBlock), kBlock, 0, st>>>(
+        s->keys.as<unsigned long long>(), s->t_weight.as<int32_t>(), s->t_woff.as<uint32_t>(), d.tree_base,
+        d.tree_mask + 1, cnt);
+    PS_HIP(hipGetLastError());
+  }
+  if (hybrid && total > 0) {
+    k_walk_lists<<<grid_for((uint64_t)total, kBlock), kBlock, 0, st>>>(a, s->t_woff.as<uint32_t>(),
+                                                                      s->t_walks.as<int32_t>());
     PS_HIP(hipGetLastError());
   }
   return PS_OK;
@@ -1640,9 +1797,23 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<long long>(),
                                        s->item_val.as<float>(), s->item_row.as<uint2>(), s->chunk_list.as<int2>(),
                                        s->list_cap, s->chunk_cap, s->slot_edges.as<unsigned long long>(), ctr, cur);
-  k_pick<<<1, kSchedThreads, 0, st>>>(s->P, s->slot_edges.as<unsigned long long>(), s->slots.as<Slot>(),
-                                      s->pull_flag.as<int32_t>(), s->lane_slot.as<int32_t>(),
-                                      s->dense_ver.as<DenseVer>(), ctr);
+  PickArgs pa{};
+  pa.P = s->P;
+  pa.slot_edges = s->slot_edges.as<unsigned long long>();
+  pa.hyb_edges = s->hyb_edges.as<unsigned long long>();
+  pa.slots = s->slots.as<Slot>();
+  pa.pull_flag = s->pull_flag.as<int32_t>();
+  pa.lane_slot = s->lane_slot.as<int32_t>();
+  pa.dv = s->dense_ver.as<DenseVer>();
+  pa.t_weight = s->t_weight.as<int32_t>();
+  pa.t_woff = s->t_woff.as<uint32_t>();
+  pa.t_walks = s->t_walks.as<int32_t>();
+  pa.ring = s->ring.as<int32_t>();
+  pa.ring_k = s->ring_k.as<int32_t>();
+  pa.ring_mask = s->ring_cap - 1;
+  pa.remaining = s->remaining.as<unsigned long long>();
+  pa.ctr = ctr;
+  k_pick<<<1, kSchedThreads, 0, st>>>(pa);
   k.ea.list_cur = s->list[cur].as<int2>();
   k.ea.cur = cur;
   k.ea.dense_cur = s->dense[cur].as<long long>();
@@ -1665,6 +1836,7 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   da.map_cur = s->rowmap[cur].as<uint8_t>();
   da.map_next = s->rowmap[nxt].as<uint8_t>();
   da.npart = s->npart.as<long long>();
+  da.hyb_edges = s->hyb_edges.as<unsigned long long>();
   da.has_next = s->has_next.as<int32_t>();
   da.ctr = ctr;
   da.cur = cur;
@@ -1887,9 +2059,10 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   std::vector<uint64_t> bounds;
   PS_TRY(session_begin(ctx, g, gv, qs, &recs, &bounds));
   uint64_t pool_need = 0, ring_need = 0;
-  for (uint64_t b : bounds) {
+  for (size_t i = 0; i < bounds.size(); ++i) {
+    const uint64_t b = bounds[i];
     if (b) pool_need += next_pow2(std::max<uint64_t>(2 * b, 64));
-    ring_need += b;
+    ring_need += ring_share(s, recs[i], b);
   }
   if (pool_need > s->tree_pool || ring_need > s->ring_cap) {
     // Grow the tree pool / ring: only this call's records are admitted and
@@ -1905,6 +2078,8 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
     PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
     for (DevBuf* b : {&s->t_parent, &s->t_node, &s->t_depth, &s->t_query, &s->t_weight})
       PS_TRY(devbuf_reserve(*b, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+    PS_TRY(devbuf_reserve(s->t_woff, sizeof(uint32_t) * s->tree_pool));
+    PS_TRY(devbuf_reserve(s->t_walks, sizeof(int32_t) * s->tree_pool));
     PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
     PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
     s->tree_free.assign(1, {0, s->tree_pool});
@@ -1912,16 +2087,36 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   PS_TRY(session_build(ctx, recs, bounds));
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
-  const uint64_t levels = s->h_ctr[C_LEVELS] - before[C_LEVELS];
+  uint64_t levels = s->h_ctr[C_LEVELS] - before[C_LEVELS];
   const uint64_t probes = s->h_ctr[C_TAIL] - before[C_TAIL];
   int maxL = 2;
   for (auto& q : qs) maxL = std::max(maxL, q.prm.L);
   // Greedy list scheduling: every slot is busy while probes are pending, and a
   // probe holds its slot for depth-1 steps, so this many steps finish them all.
-  const uint64_t steps = probes ? (levels + P - 1) / P + (uint64_t)maxL + 2 : 0;
+  uint64_t steps = probes ? (levels + P - 1) / P + (uint64_t)maxL + 2 : 0;
   double expand_ms = 0.0, pull_ms = 0.0;
   PS_TRY(session_set_pull(ctx, pull_threshold(g->m, pull_opt)));
   PS_TRY(session_steps(ctx, steps, &expand_ms, &pull_ms));
+  bool hybrid = false;
+  uint64_t with_probes = 0;
+  for (size_t i = 0; i < qs.size(); ++i) {
+    hybrid |= qs[i].hybrid != 0;
+    with_probes += bounds[i] ? 1 : 0;
+  }
+  uint64_t total_steps = steps;
+  // Probes switched under Section 4.4 queue randomized probes while the
+  // steps run: they run in further rounds, sized the same way, until every
+  // query is complete (a few rounds at most; the cap is a guard).
+  for (int round = 0; hybrid && round < 16; ++round) {
+    PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
+    PS_HIP(hipStreamSynchronize(st));
+    if (s->h_ctr[C_OVERFLOW] || s->h_ctr[C_DONE] - before[C_DONE] >= with_probes) break;
+    const uint64_t lv = s->h_ctr[C_LEVELS] - before[C_LEVELS];
+    steps = (lv - levels + P - 1) / P + (uint64_t)maxL + 2;
+    levels = lv;
+    PS_TRY(session_steps(ctx, steps, &expand_ms, &pull_ms));
+    total_steps += steps;
+  }
   std::vector<double> flips((size_t)nq, 0.0);
   for (int i = 0; i < nq; ++i) {
     QueryOut o = outs[(size_t)i];
@@ -1945,14 +2140,15 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   for (auto& q : qs) stats.walks += q.walk_end - q.walk_begin;
   stats.walk_nodes = (int64_t)(h[C_WALK_NODES] - before[C_WALK_NODES]);
   stats.tree_nodes = (int64_t)probes;
-  stats.probe_levels = (int64_t)levels;
-  stats.steps = (int64_t)steps;
+  stats.probe_levels = (int64_t)(h[C_LEVELS] - before[C_LEVELS]);
+  stats.steps = (int64_t)total_steps;
+  stats.switched_probes = (int64_t)(h[C_SWITCH] - before[C_SWITCH]);
   stats.entries_expanded = (int64_t)(h[C_KEPT] - before[C_KEPT]);
   stats.entries_pruned = (int64_t)(h[C_PRUNED] - before[C_PRUNED]);
   stats.edges_scanned = (int64_t)(h[C_EDGES] - before[C_EDGES]);
   stats.next_entries = (int64_t)(h[C_NEXT] - before[C_NEXT]);
   stats.final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL]);
-  stats.expand_launches = (int64_t)steps;
+  stats.expand_launches = (int64_t)total_steps;
   stats.pull_levels = (int64_t)(h[C_PULLS] - before[C_PULLS]);
   stats.pull_edges = (int64_t)(h[C_PULL_EDGES] - before[C_PULL_EDGES]);
   stats.near_threshold = (int64_t)(h[C_NEAR] - before[C_NEAR]);

@@ -133,6 +133,9 @@ struct QueryDev {
   int32_t randomized;  // probes run Alg. 4, one per walk and prefix
   uint32_t t_sc;       // floor(sqrt(c) * 2^32): the sqrt(c) coin of Alg. 4
   uint2 key2;          // Philox key of Alg. 4's draws
+  double c0;           // Section 4.4: switch constant (hybrid queries)
+  int32_t hybrid;      // deterministic probes switch to Alg. 4 past c0 * w * n out-edges
+  int32_t pad2;
 };
 
 // Host view of a query.
@@ -143,6 +146,8 @@ struct QueryRun {
   int64_t walk_begin = 0, walk_end = 0;
   int bias_shift = 0;
   int randomized = 0;  // Alg. 4 instead of Alg. 2
+  int hybrid = 0;      // Alg. 2 per tree node, switching to Alg. 4 (Section 4.4)
+  double c0 = 0.0;     // the switch constant of a hybrid query
 };
 
 // State of one probe slot on the device.
@@ -173,6 +178,9 @@ struct Slot {
   const unsigned long long* heavy_cnt;
   double* flip;      // the query's near-threshold allowance
   double flip_unit;  // eps_p * w / n_r: what one Rule-2 flip can move an estimate by
+  double hyb_thr;    // Section 4.4: switch when a level to expand has more out-edges (< 0: never)
+  float thr_next;    // Rule 2 threshold of the next level (what the dense pass counts against)
+  int32_t pad;
 };
 
 enum CounterIdx {
@@ -203,6 +211,7 @@ enum CounterIdx {
   C_RCLEAR,      // last-level candidate marks of randomized probes to clear
   C_NZROWS0,     // rows of dense matrix 0 that may hold a nonzero score
   C_NZROWS1,     // the same for matrix 1
+  C_SWITCH,      // deterministic probes switched to randomized ones (Section 4.4)
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
   C_COUNT = C_HIST_E + 32
@@ -232,6 +241,9 @@ struct Session {
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring, ring_k;
   DevBuf rclear;  // (slot, node) marks of randomized probes' last levels, allocated on first use
+  // Section 4.4: out-edges of dense-lane frontiers (per slot), and per tree
+  // node the walks through it (t_walks[t_woff[t] - weight .. t_woff[t]))
+  DevBuf hyb_edges, t_woff, t_walks, wcount;
   DevBuf sort_keys[2], sort_vals[2], sort_tmp, sel_count;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)

@@ -276,6 +276,7 @@ ps_status serve_loop(ps_server* s) {
         ps_options opt;
         ps_options_default(&opt);
         opt.probe_mode = rq.q.probe_mode;
+        if (rq.q.probe_mode == PS_PROBE_HYBRID) opt.hybrid_c0 = rq.q.hybrid_c0;
         ps_status vs = make_query_run(g, rq.q.u, rq.q.k, rq.q.c, rq.q.eps, rq.q.delta, rq.q.seed, &opt, &qr);
         if (vs == PS_OK && (!rq.r->scores || (rq.q.k > 0 && !rq.r->nodes))) vs = PS_ERR_INVALID_ARG;
         if (vs != PS_OK) {

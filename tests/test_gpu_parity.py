@@ -268,6 +268,92 @@ def test_randomized_probe_in_batch_shards_and_server(ps, ctx, cl20k, orc):
         srv.stop()
 
 
+@pytest.mark.parametrize("pull", [0, 1, -1])
+def test_hybrid_probe_matches_oracle(ps, ctx, cl20k, er, orc, pull):
+    # Section 4.4: every tree node starts deterministic and switches to
+    # per-walk randomized probes past c0 * w * n kept out-edges.  Both sides
+    # take the switch on the same integer sums, so the switched-probe counts
+    # agree exactly and the estimates up to FP64 summation order, whether the
+    # big levels are pushed, pulled (counted by the dense pass) or mixed.
+    for n, s, d, G, O in (cl20k, er):
+        p = orc.params(n, 0.6, 0.1, 0.01)
+        for i, u in enumerate(graphs.query_nodes(n, d, 2, seed=91)):
+            for c0 in (0.01, 0.2, 1.0):
+                gpu = ps.ps_single_source(G, int(u), 0.6, 0.1, 0.01, 5 + i, probe_mode=2, hybrid_c0=c0,
+                                          pull_edges=pull)
+                st = ctx.stats()
+                ref, ost = orc.batch(O, int(u), p, 5 + i, precision="f32", probe="hybrid", c0=c0)
+                what = f"hybrid n={n} u={int(u)} c0={c0} pull={pull}"
+                print(f"{what}: switched {st['switched_probes']} of {ost['tree_nodes']} (oracle "
+                      f"{ost['switched']}), pulled levels {st['pull_levels']}", flush=True)
+                assert st["switched_probes"] == ost["switched"], what
+                assert st["tree_nodes"] == ost["tree_nodes"], what
+                if pull == 1 and n == 20_000:
+                    assert st["pull_levels"] > 0
+                _parity(gpu, ref, ost, what)
+
+
+def test_hybrid_limits_equal_the_two_probes(ps, ctx, cl20k):
+    # c0 = infinity never switches: the deterministic estimate.  With Rule 2
+    # off, c0 = 0 switches every probe with an out-edge, and the walks then
+    # draw what randomized mode draws: the randomized estimate.
+    n, s, d, G, O = cl20k
+    u = int(graphs.query_nodes(n, d, 1, seed=93)[0])
+    det = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3)
+    hyb = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=2, hybrid_c0=float("inf"))
+    assert ctx.stats()["switched_probes"] == 0
+    _same_query(hyb, 0.0, det, 0.0, "hybrid c0=inf vs deterministic")
+    rnd = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=1, eps_p=0.0)
+    hyb = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=2, hybrid_c0=0.0, eps_p=0.0)
+    st = ctx.stats()
+    assert st["switched_probes"] == st["tree_nodes"]
+    _same_query(hyb, 0.0, rnd, 0.0, "hybrid c0=0 vs randomized (no Rule 2)")
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(ps.ProbeSimError):
+            ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=2, hybrid_c0=bad)
+    with pytest.raises(ps.ProbeSimError):
+        ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=3)
+
+
+def test_hybrid_in_batch_shards_and_server(ps, ctx, cl20k, orc):
+    # Hybrid queries mixed with the other modes in one batch and served with
+    # continuous admission: each equals its run alone.  A walk-range shard
+    # builds its own tree, so its weights, and with them the switches, are
+    # the shard's: each shard equals the oracle on the same walk range.
+    n, s, d, G, O = cl20k
+    qn = graphs.query_nodes(n, d, 6, seed=95)
+    qs = [dict(u=int(u), k=(0 if i % 2 == 0 else 20), c=0.6, eps=[0.1, 0.05][i % 2], delta=0.01, seed=80 + i,
+               probe_mode=[2, 0, 2, 1, 2, 2][i], hybrid_c0=[0.05, 1.0, 0.5, 1.0, 0.01, 2.0][i])
+          for i, u in enumerate(qn)]
+    res = ps.ps_batch(G, qs)
+    alone = []
+    for q, r in zip(qs, res):
+        kw = dict(probe_mode=q["probe_mode"], hybrid_c0=q["hybrid_c0"])
+        if q["k"]:
+            a = ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"], **kw)
+        else:
+            a = ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"], **kw)
+        alone.append(a)
+        _same_query(r, 0.0, a, 0.0, f"batch vs alone u={q['u']} mode={q['probe_mode']} c0={q['hybrid_c0']}")
+    q = qs[0]
+    p = orc.params(n, 0.6, q["eps"], 0.01)
+    for a, b in ((0, 1000), (1000, p.n_r)):
+        part = ps.ps_single_source(G, q["u"], 0.6, q["eps"], 0.01, q["seed"], walk_begin=a, walk_end=b,
+                                   probe_mode=2, hybrid_c0=q["hybrid_c0"])
+        sw = ctx.stats()["switched_probes"]
+        ref, ost = orc.batch(O, q["u"], p, q["seed"], a, b, precision="f32", probe="hybrid", c0=q["hybrid_c0"])
+        assert sw == ost["switched"]
+        _parity(part, ref, ost, f"hybrid shard [{a}, {b})")
+    srv = ps.Server(G, max_inflight=3)
+    try:
+        tickets = [srv.submit(q["u"], q["c"], q["eps"], q["delta"], q["seed"], k=q["k"],
+                              probe_mode=q["probe_mode"], hybrid_c0=q["hybrid_c0"]) for q in qs]
+        for q, t, a in zip(qs, tickets, alone):
+            _same_query(srv.wait(t, timeout_us=60_000_000), 0.0, a, 0.0, f"served vs alone u={q['u']}")
+    finally:
+        srv.stop()
+
+
 @pytest.mark.parametrize("eps", [0.1, 0.05])
 def test_error_against_fp64_definition_is_stated(ps, cl20k, orc, eps):
     # The stated per-result error: against the plain FP64 evaluation the GPU
@@ -696,5 +782,12 @@ def test_parameter_extremes(ps, ctx, er, orc):
     ref, st = orc.single_source(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, probe="randomized")
     _parity(gpu, ref, st, "randomized, walk cap 64")
     assert ps.ps_single_source(G1, 0, 0.6, 0.1, 0.01, 1, probe_mode=1).tolist() == [1.0]
+    # the switch of Section 4.4 with the walk cap and a tiny graph
+    gpu = ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=64, eps_t=1e-30, probe_mode=2, hybrid_c0=0.05)
+    ref, st = orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f32",
+                        probe="hybrid", c0=0.05)
+    assert ctx.stats()["switched_probes"] == st["switched"] > 0
+    _parity(gpu, ref, st, "hybrid, walk cap 64")
+    assert ps.ps_single_source(G1, 0, 0.6, 0.1, 0.01, 1, probe_mode=2).tolist() == [1.0]
     with pytest.raises(ps.ProbeSimError):
-        ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, probe_mode=2)
+        ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, probe_mode=3)
