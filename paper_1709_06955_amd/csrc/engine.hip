@@ -762,6 +762,14 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
     // matrix, which the next step writes: it counts as in use until then
     ctr[C_GPREV] = hi > s_fhi ? hi : s_fhi;
     if (s_active) atomicAdd(&ctr[C_PULLS], (unsigned long long)s_active);
+    // columns of hybrid queries' deterministic probes with a level after
+    // this one: k_hyb_count measures their next level
+    unsigned long long hyb = 0;
+    for (int g = 0; g < kLanes; ++g) {
+      const int32_t ls = a.lane_slot[g];
+      if (ls >= 0 && a.slots[ls].hyb_thr >= 0.0 && !a.slots[ls].last) hyb |= 1ull << g;
+    }
+    ctr[C_HYBMASK] = hyb;
     for (int g = 0; g < kLanes; ++g) {
       const int32_t ls = a.lane_slot[g];
       if (ls < 0) continue;
@@ -1083,9 +1091,6 @@ struct DenseArgs {
 struct LaneInfo {
   bool active;
   bool last;
-  bool hyb;        // count the next level's kept out-edges (Section 4.4)
-  float thr_next;  // Rule 2 threshold the next level applies
-  int32_t slot;
   float thr, sc;
   int32_t excl;
   double w;
@@ -1110,21 +1115,17 @@ __device__ __forceinline__ LaneInfo lane_info(const DenseArgs& a, int g, unsigne
       li.acc = sl.acc;
       li.flip = sl.flip;
       li.flip_unit = sl.flip_unit;
-      li.hyb = sl.hyb_thr >= 0.0 && !sl.last;
-      li.thr_next = sl.thr_next;
-      li.slot = s;
     }
   }
   return li;
 }
 
 // Target v of column g with grid sum q of its contributions: the FP64
-// estimate on a probe's last level, else the next level's FP32 score, which
-// is returned (0 when none).  Only writer lanes (one per column) act; every
-// lane of the wavefront calls it.
-__device__ __forceinline__ float dense_finish(const DenseArgs& a, const LaneInfo& li, int g, bool writer, int32_t v,
-                                              long long q, unsigned long long gw, unsigned long long& nfinal,
-                                              unsigned long long& nzrows) {
+// estimate on a probe's last level, else the next level's FP32 score.  Only
+// writer lanes (one per column) act; every lane of the wavefront calls it.
+__device__ __forceinline__ bool dense_finish(const DenseArgs& a, const LaneInfo& li, int g, bool writer, int32_t v,
+                                             long long q, unsigned long long gw, unsigned long long& nfinal,
+                                             unsigned long long& nzrows) {
   float out = 0.0f;
   bool nz = false;
   if (writer && li.active && v != li.excl && q > 0) {
@@ -1143,7 +1144,7 @@ __device__ __forceinline__ float dense_finish(const DenseArgs& a, const LaneInfo
   const bool any = __ballot(nz) != 0ull;  // the whole row is rewritten: its flag too
   if (lane_id() == 0) a.map_next[v] = any ? 1 : 0;
   nzrows += any ? 1ull : 0ull;
-  return out;
+  return nz;
 }
 
 // Grid value of the contribution of in-neighbour score h to target v (the
@@ -1172,8 +1173,7 @@ template <bool kMap>
 __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& li, const DenseVer& dv, int col,
                                            int grp, int L, uint64_t wave, uint64_t nwaves, unsigned long long gw,
                                            unsigned long long& nz_mask, unsigned long long& nfinal,
-                                           unsigned long long& inedges, unsigned long long& nzrows,
-                                           unsigned long long& hedges) {
+                                           unsigned long long& inedges, unsigned long long& nzrows) {
   const float* m = a.mat_cur + col;
   const uint32_t T = 64u / (uint32_t)L;
   const bool writer = grp == 0;
@@ -1194,10 +1194,7 @@ __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& l
     long long q = s0 + s1;
     for (int off = L; off < 64; off <<= 1) q += __shfl_xor(q, off, 64);
     inedges += row.y;
-    const float out = dense_finish(a, li, col, writer, (int32_t)v, q, gw, nfinal, nzrows);
-    // Section 4.4: out-edges of the entries the next level's Rule 2 keeps
-    if (li.hyb && out > li.thr_next) hedges += dv.out_rows[v].y;
-    const bool nz = out > 0.0f;
+    const bool nz = dense_finish(a, li, col, writer, (int32_t)v, q, gw, nfinal, nzrows);
     nz_mask |= __ballot(nz);
   }
   const unsigned long long nch = dv.heavy_cnt[1];
@@ -1246,13 +1243,12 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   const int col = g & (L - 1), grp = g / L;
   const LaneInfo li = lane_info(a, col, ghi);
   const DenseVer dv = *a.dv;
-  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0, nzrows = 0, hedges = 0;
+  unsigned long long nz_mask = 0, nfinal = 0, inedges = 0, nzrows = 0;
   // the row map pays off when fewer than half of the rows may be nonzero
   if (2ull * a.ctr[C_NZROWS0 + a.cur] < (unsigned long long)a.n)
-    dense_rows<true>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows, hedges);
+    dense_rows<true>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows);
   else
-    dense_rows<false>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows, hedges);
-  if (hedges) atomicAdd(&a.hyb_edges[li.slot], hedges);
+    dense_rows<false>(a, li, dv, col, grp, L, wave, nwaves, gw, nz_mask, nfinal, inedges, nzrows);
   if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
@@ -1294,7 +1290,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   const DenseVer dv = *a.dv;
   const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  unsigned long long nz_mask = 0, nfinal = 0, nzrows = 0, hedges = 0;
+  unsigned long long nz_mask = 0, nfinal = 0, nzrows = 0;
   const unsigned long long nh = dv.heavy_cnt[0];
   for (uint64_t i = wave; i < nh; i += nwaves) {
     const int32_t v = dv.heavy_nodes[i];
@@ -1304,18 +1300,49 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
       sum = *p;
       *p = 0;
     }
-    const float out = dense_finish(a, li, g, true, v, sum, gw, nfinal, nzrows);
-    if (li.hyb && out > li.thr_next) hedges += dv.out_rows[v].y;
-    const bool nz = out > 0.0f;
+    const bool nz = dense_finish(a, li, g, true, v, sum, gw, nfinal, nzrows);
     nz_mask |= __ballot(nz);
   }
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
-  if (hedges) atomicAdd(&a.hyb_edges[li.slot], hedges);
   nfinal = wave_sum(nfinal);
   if (g == 0 && nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
   __syncthreads();
   if (tid < kLanes && ((s_nz >> tid) & 1ull)) a.has_next[a.lane_slot[tid]] = 1;
+}
+
+// Section 4.4 for probes in dense columns: the out-edges of the entries of
+// the level just written to the next matrix that Rule 2 will keep there
+// (score above the next level's threshold), per hybrid column, into
+// hyb_edges for k_pick's test at the next step.  One wavefront per row, one
+// lane per column; rows the row map marks zero are skipped.  A pass of its
+// own: counting inside k_dense slows every dense pass, hybrid or not.
+__global__ void __launch_bounds__(kBlock) k_hyb_count(DenseArgs a) {
+  __shared__ unsigned long long s_cnt[kLanes];
+  const unsigned long long mask = a.ctr[C_HYBMASK];
+  if (mask == 0ull) return;
+  const int tid = threadIdx.x;
+  const int g = lane_id();
+  if (tid < kLanes) s_cnt[tid] = 0ull;
+  __syncthreads();
+  const bool mine = (mask >> g) & 1ull;
+  float thr = 0.0f;
+  int32_t slot = -1;
+  if (mine) {
+    slot = a.lane_slot[g];
+    thr = a.slots[slot].thr_next;
+  }
+  const uint2* out_rows = a.dv->out_rows;
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  unsigned long long cnt = 0;
+  for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
+    if (!a.map_next[v]) continue;
+    if (mine && a.mat_next[v * kLanes + g] > thr) cnt += out_rows[v].y;
+  }
+  if (cnt) atomicAdd(&s_cnt[g], cnt);
+  __syncthreads();
+  if (tid < kLanes && s_cnt[tid]) atomicAdd(&a.hyb_edges[a.lane_slot[tid]], s_cnt[tid]);
 }
 
 // s^(u, v) = acc / n_r (+ shift for v != u), s^(u, u) = 1.
@@ -1847,6 +1874,7 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   da.list_cap = s->list_cap;
   k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
   k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
+  k_hyb_count<<<kStepGrid / 4, kBlock, 0, st>>>(da);
   if (ev2) (void)hipEventRecord(ev2, st);
 }
 
