@@ -693,14 +693,12 @@ __device__ void switch_probe(const PickArgs& a, Slot& S) {
 // arrays for it.
 __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
   __shared__ int32_t s_free[kLanes];
-  __shared__ uint32_t s_nfree, s_ncand, s_hi, s_active, s_fhi;
+  __shared__ uint32_t s_nfree, s_ncand, s_fhi;
   __shared__ unsigned long long s_ver;
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_nfree = 0;
     s_ncand = 0;
-    s_hi = 0;
-    s_active = 0;
     s_fhi = 0;
     s_ver = 0ull;
   }
@@ -748,31 +746,25 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
     a.pull_flag[s] = flag;
   }
   __syncthreads();
-  if (tid < kLanes && a.lane_slot[tid] >= 0) {
-    atomicMax(&s_hi, (uint32_t)tid + 1u);
-    atomicAdd(&s_active, 1u);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned long long hi = s_hi;
-    const unsigned long long prev = ctr[C_GPREV];
-    ctr[C_GHI] = hi;
-    ctr[C_GW] = hi > prev ? hi : prev;
-    // a column freed by a switch still holds its level in this step's input
-    // matrix, which the next step writes: it counts as in use until then
-    ctr[C_GPREV] = hi > s_fhi ? hi : s_fhi;
-    if (s_active) atomicAdd(&ctr[C_PULLS], (unsigned long long)s_active);
+  if (tid < kLanes) {  // the first wavefront: one lane per column
+    const int32_t ls = a.lane_slot[tid];
     // columns of hybrid queries' deterministic probes with a level after
     // this one: k_hyb_count measures their next level
-    unsigned long long hyb = 0;
-    for (int g = 0; g < kLanes; ++g) {
-      const int32_t ls = a.lane_slot[g];
-      if (ls >= 0 && a.slots[ls].hyb_thr >= 0.0 && !a.slots[ls].last) hyb |= 1ull << g;
+    const bool hyb = ls >= 0 && a.slots[ls].hyb_thr >= 0.0 && !a.slots[ls].last;
+    const unsigned long long act = __ballot(ls >= 0);
+    const unsigned long long hmask = __ballot(hyb);
+    if (tid == 0) {
+      const unsigned long long hi = act ? (unsigned long long)(64 - __clzll((long long)act)) : 0ull;
+      const unsigned long long prev = ctr[C_GPREV];
+      ctr[C_GHI] = hi;
+      ctr[C_GW] = hi > prev ? hi : prev;
+      // a column freed by a switch still holds its level in this step's
+      // input matrix, which the next step writes: it counts as in use until then
+      ctr[C_GPREV] = hi > s_fhi ? hi : s_fhi;
+      if (act) atomicAdd(&ctr[C_PULLS], (unsigned long long)__popcll(act));
+      ctr[C_HYBMASK] = hmask;
     }
-    ctr[C_HYBMASK] = hyb;
-    for (int g = 0; g < kLanes; ++g) {
-      const int32_t ls = a.lane_slot[g];
-      if (ls < 0) continue;
+    if (act && tid == __ffsll((long long)act) - 1) {  // the version's arrays, from the lowest active column
       const Slot& sl = a.slots[ls];
       a.dv->out_rows = sl.out_rows;
       a.dv->in_rows = sl.in_rows;
@@ -781,7 +773,6 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
       a.dv->heavy_nodes = sl.heavy_nodes;
       a.dv->heavy_chunks = sl.heavy_chunks;
       a.dv->heavy_cnt = sl.heavy_cnt;
-      break;
     }
   }
 }
