@@ -61,7 +61,7 @@ def chung_lu_weights(n: int, m: int, gamma: float) -> np.ndarray:
     return w
 
 
-def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
+def chung_lu(n: int, m: int, gamma: float, seed: int = 1, progress=None):
     """Directed Chung-Lu graph: src ~ w_out, dst ~ w_in with independent
     seeded permutations of the same power-law weights; self-loops and
     duplicates rejected.  Draws about 10% more pairs than needed, keeps the
@@ -71,7 +71,9 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
 
     Pairs are drawn in chunks of 2^22, each from its own Philox stream, so the
     chunks run on worker threads and the result does not depend on how many
-    there are."""
+    there are.  `progress` (optional) is called with a short message every
+    64 chunks and after each merge, so that long generations report as they
+    go."""
     rng = _rng(seed, 2)
     w = chung_lu_weights(n, m, gamma)
     w_out = np.empty(n)
@@ -95,6 +97,8 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
         np.minimum(src, n - 1, out=src)
         np.minimum(dst, n - 1, out=dst)
         k = src.astype(np.int64) * n + dst
+        if progress is not None and index % 64 == 63:
+            progress(f"chung_lu: chunk {index + 1} drawn")
         return k[src != dst]
 
     next_chunk = 0
@@ -109,6 +113,8 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1):
             return np.concatenate(list(ex.map(chunk, ids, sizes)))
 
     keys = np.unique(draw(int(m * 1.1) + 1024))
+    if progress is not None:
+        progress(f"chung_lu: {keys.size} distinct pairs")
     while keys.size < m:
         keys = np.unique(np.concatenate([keys, draw(int((m - keys.size) * 2) + 1024)]))
     if keys.size > m:
@@ -215,10 +221,10 @@ WORKLOADS = {
 }
 
 
-def make_workload(name: str, seed: int = 1):
+def make_workload(name: str, seed: int = 1, progress=None):
     spec = WORKLOADS[name]
     if spec["kind"] == "er":
         s, d = erdos_renyi(spec["n"], spec["m"], seed)
     else:
-        s, d = chung_lu(spec["n"], spec["m"], spec["gamma"], seed)
+        s, d = chung_lu(spec["n"], spec["m"], spec["gamma"], seed, progress=progress)
     return spec["n"], s, d

@@ -676,7 +676,7 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
     # (an estimate is a sum over walks): walks bit-exact, a shard against the
     # oracle's FP32 model, the top-50 of a shard in a batch-sized split equal
     # to the same shard alone, and the projected cost of a whole query.
-    n, s, d = graphs.make_workload("cl_40m_1400m")
+    n, s, d = graphs.make_workload("cl_40m_1400m", progress=_say)
     _say("cl40m generated")
     G = ps.Graph(ctx, n, s, d)
     _say("cl40m loaded")
