@@ -354,6 +354,36 @@ def test_hybrid_in_batch_shards_and_server(ps, ctx, cl20k, orc):
         srv.stop()
 
 
+def test_accuracy_against_power_method(ps, ctx, er):
+    # Definitions 1 and 2 against SimRank itself (the Power Method, n = 1000)
+    # for all three probes: every estimate within eps of s(u, v) (at
+    # delta = 1e-4 per query, so the 18 queries here fail together with
+    # probability below 0.2 %), and the top-k list within 2 eps of the true
+    # i-th value at every rank (what sorting eps-accurate estimates gives).
+    # Section 5's Precision@k, NDCG@k and tau_k are printed for context.
+    from oracle import refs
+
+    from tests import topk_metrics as tm
+
+    cl = graphs.chung_lu(1000, 8000, 2.1, seed=5)
+    for name, (n, s, d, G) in (("er1k", er[:4]), ("cl1k", (1000, cl[0], cl[1], ps.Graph(ctx, 1000, *cl)))):
+        S = refs.power_method(n, s, d, 0.6, iters=55)
+        for i, u in enumerate(graphs.query_nodes(n, d, 3, seed=97)):
+            u = int(u)
+            truth = tm.true_topk(S[u], u, 50)
+            for mode in (0, 1, 2):
+                est = ps.ps_single_source(G, u, 0.6, 0.1, 1e-4, 200 + i, probe_mode=mode)
+                err = float(np.abs(est - S[u]).max())
+                nodes, vals = ps.ps_topk(G, u, 50, 0.6, 0.1, 1e-4, 200 + i, probe_mode=mode)
+                gap = float((S[u][truth] - S[u][nodes]).max())
+                print(f"{name} u={u} mode={mode}: max|s^-s| = {err:.4f}, worst rank gap {gap:.4f}, "
+                      f"Precision@50 {tm.precision_at_k(nodes, truth):.3f}, "
+                      f"NDCG@50 {tm.ndcg_at_k(nodes, truth, S[u]):.4f}, tau_50 {tm.kendall_tau_k(nodes, S[u]):.3f}",
+                      flush=True)
+                assert err <= 0.1
+                assert gap <= 0.2
+
+
 @pytest.mark.parametrize("eps", [0.1, 0.05])
 def test_error_against_fp64_definition_is_stated(ps, cl20k, orc, eps):
     # The stated per-result error: against the plain FP64 evaluation the GPU
@@ -462,6 +492,32 @@ def test_full_size_power_law_walk_shards(ps, ctx, orc):
     assert full[int(q[0])] == 1.0 and full.min() >= 0.0
     off = np.delete(full, int(q[0]))
     assert off.max() <= 1.0
+
+
+def test_full_size_hybrid_walk_shards(ps, ctx, orc):
+    # The switch of Section 4.4 on the 1M-node / 10M-edge workload at
+    # eps = 0.05 in the launch configuration the benchmark times (the
+    # library's default c0): walk-range shards, each its own tree, against
+    # the oracle on the same ranges, switch counts exact.
+    n, s, d = graphs.make_workload("cl_1m_10m")
+    G = ps.Graph(ctx, n, s, d)
+    O = orc.Graph(n, s, d)
+    q = graphs.query_nodes(n, d, 32)
+    p = orc.params(n, 0.6, 0.05, 0.01)
+    c0 = ps.options().hybrid_c0
+    for i in (0, 17):
+        u = int(q[i])
+        for a, b in ((0, 300), (20000, 20400)):
+            gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3 + i, walk_begin=a, walk_end=b, probe_mode=2)
+            sw = ctx.stats()["switched_probes"]
+            ref, st = orc.batch(O, u, p, 3 + i, a, b, precision="f32", probe="hybrid", c0=c0)
+            print(f"cl1m hybrid u={u} walks [{a},{b}): switched {sw} of {st['tree_nodes']} (oracle {st['switched']})",
+                  flush=True)
+            assert sw == st["switched"]
+            _parity(gpu, ref, st, f"cl1m hybrid u={u} walks [{a},{b})")
+    full = ps.ps_single_source(G, int(q[0]), 0.6, 0.05, 0.01, 3, probe_mode=2)
+    assert full[int(q[0])] == 1.0 and full.min() >= 0.0
+    assert np.delete(full, int(q[0])).max() <= 1.0
 
 
 def test_server_equals_alone_with_continuous_admission(ps, ctx):

@@ -601,3 +601,34 @@ def test_hybrid_guarantee_against_power_method(orc):
         assert 0 < st["switched"] < st["tree_nodes"]
         assert est[0] == 1.0
         assert np.abs(est - S[0]).max() <= 0.1
+
+
+# ------------------------------------------------------ top-k accuracy measures
+
+
+def test_topk_measures_on_known_lists():
+    # Section 5's measures on hand-made cases: the ground truth scores 1 on
+    # all three; a reversed list keeps precision and loses the ranking
+    # (tau = -1); a disjoint list scores 0 precision; NDCG falls below 1 when
+    # lower-valued nodes replace higher ones.
+    from tests import topk_metrics as tm
+
+    s = np.array([1.0, 0.9, 0.7, 0.5, 0.3, 0.1, 0.0])
+    truth = tm.true_topk(s, 0, 3)
+    assert truth.tolist() == [1, 2, 3]
+    assert tm.precision_at_k(truth, truth) == 1.0
+    assert tm.ndcg_at_k(truth, truth, s) == pytest.approx(1.0)
+    assert tm.kendall_tau_k(truth.tolist(), s) == 1.0
+    rev = truth[::-1].tolist()
+    assert tm.precision_at_k(rev, truth) == 1.0
+    assert tm.kendall_tau_k(rev, s) == -1.0
+    assert tm.ndcg_at_k(rev, truth, s) < 1.0
+    assert tm.precision_at_k([4, 5, 6], truth) == 0.0
+    worse = [1, 2, 4]
+    want = ((2 ** 0.9 - 1) / math.log(2) + (2 ** 0.7 - 1) / math.log(3) + (2 ** 0.3 - 1) / math.log(4)) / (
+        (2 ** 0.9 - 1) / math.log(2) + (2 ** 0.7 - 1) / math.log(3) + (2 ** 0.5 - 1) / math.log(4))
+    assert tm.ndcg_at_k(worse, truth, s) == pytest.approx(want)
+    # one swapped adjacent pair out of three pairs: (2 - 1) / 3
+    assert tm.kendall_tau_k([2, 1, 3], s) == pytest.approx(1 / 3)
+    # ties count as neither
+    assert tm.kendall_tau_k([5, 6], np.array([0, 0, 0, 0, 0, 0.2, 0.2])) == 0.0
