@@ -61,10 +61,11 @@ def _parity64(gpu, ref, stats, what, gpu_flip):
 
 def _alone(ps, G, q):
     """The query run alone, and its Rule-2 near-threshold allowance."""
+    kw = {k: q[k] for k in ("probe_mode", "hybrid_c0") if k in q}
     if q.get("k", 0):
-        r = ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"])
+        r = ps.ps_topk(G, q["u"], q["k"], q["c"], q["eps"], q["delta"], q["seed"], **kw)
     else:
-        r = ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"])
+        r = ps.ps_single_source(G, q["u"], q["c"], q["eps"], q["delta"], q["seed"], **kw)
     return r, G.ctx.stats()["flip_allowance"]
 
 
@@ -540,19 +541,22 @@ def test_server_equals_alone_with_continuous_admission(ps, ctx):
         srv.stop()
 
 
-def test_server_interleaves_updates(ps, ctx):
+@pytest.mark.parametrize("mode", [0, 2])
+def test_server_interleaves_updates(ps, ctx, orc, mode):
+    # mode 2: the switch of Section 4.4, whose walk lists and switches must
+    # follow the graph version each query reads
     n = 5000
     s, d = graphs.chung_lu(n, 40_000, 2.1, seed=31)
     G = ps.Graph(ctx, n, s, d)
     us, ud, op = graphs.update_stream(n, s, d, 300, seed=37)
     u = int(graphs.query_nodes(n, d, 1, seed=41)[0])
-    q = dict(u=u, k=0, c=0.6, eps=0.1, delta=0.01, seed=9)
+    q = dict(u=u, k=0, c=0.6, eps=0.1, delta=0.01, seed=9, probe_mode=mode, hybrid_c0=0.05)
     before, fb = _alone(ps, G, q)
     srv = ps.Server(G, max_inflight=4)
     try:
-        t1 = srv.submit(u, 0.6, 0.1, 0.01, 9)
+        t1 = srv.submit(u, 0.6, 0.1, 0.01, 9, probe_mode=mode, hybrid_c0=0.05)
         srv.update(us, ud, op)
-        t2 = srv.submit(u, 0.6, 0.1, 0.01, 9)
+        t2 = srv.submit(u, 0.6, 0.1, 0.01, 9, probe_mode=mode, hybrid_c0=0.05)
         r1, f1 = srv.wait(t1, timeout_us=60_000_000, allowance=True)
         r2, f2 = srv.wait(t2, timeout_us=60_000_000, allowance=True)
     finally:
@@ -566,6 +570,11 @@ def test_server_interleaves_updates(ps, ctx):
     # each query reads exactly the updates submitted before it
     _same_query(r1, f1, before, fb, "submitted before the update")
     _same_query(r2, f2, after, fa, "submitted after the update")
+    if mode == 2:  # and the oracle on the updated edge set agrees
+        O2 = orc.Graph(n, es, ed)
+        ref, st = orc.batch(O2, u, orc.params(n, 0.6, 0.1, 0.01), 9, precision="f32", probe="hybrid", c0=0.05)
+        assert 0 < st["switched"] < st["tree_nodes"]
+        _parity(r2, ref, st, "served hybrid after the update")
 
 
 def test_server_busy_and_stop(ps, ctx):
