@@ -276,6 +276,30 @@ typedef struct ps_tune {
 ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double c, double eps, double delta,
                       const char* cache_path, ps_tune* out);
 
+/* Split of the error eps_a among sampling, truncation and pruning chosen by
+ * measurement (Theorem 2).  Candidates: eps_s = a_s * eps and eps_t = a_t *
+ * eps for a_s in {0.5, 0.6, 0.7, 0.8} and a_t in {1/4, 1/16}, with eps_p
+ * taking the rest of the inequality of Theorem 2:
+ *   eps_s + (1 + eps_s) / (1 - sqrt c) * eps_p + eps_t' = eps
+ * (eps_t' = eps_t / 2 when opt->bias_shift is set, Section 4.1; else eps_t).
+ * Every candidate keeps the guarantee of Definition 1.  The nsample query
+ * nodes `nodes` (host array) are timed under each (one untimed run first)
+ * with the rest of *opt as given (probe mode, slots, ...), and the fastest
+ * split is written into opt->eps_s, eps_t and eps_p.  The estimates change
+ * with the split (another estimate with the same guarantee), so unlike
+ * ps_autotune the choice is applied only through the options it returns.
+ * PS_ERR_INVALID_ARG when opt's walk range or split fields are not the
+ * defaults. */
+typedef struct ps_split {
+  double eps_s, eps_t, eps_p;  /* the split chosen (also written into opt) */
+  double ms_per_query;         /* measured time of the chosen split */
+  double default_ms_per_query; /* measured time of the first candidate (a_s 0.5, a_t 1/4:
+                                  the default split when the shift is off) */
+} ps_split;
+
+ps_status ps_tune_split(ps_graph* g, int32_t nsample, const int32_t* nodes, double c, double eps, double delta,
+                        ps_options* opt, ps_split* out);
+
 /* Work counters and timings of the last query call on this context. */
 typedef struct ps_stats {
   int64_t queries;

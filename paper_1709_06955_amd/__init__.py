@@ -35,6 +35,7 @@ EXPORTS = [
     "ps_derive_params", "ps_walks", "ps_single_source", "ps_single_source_sparse", "ps_topk", "ps_batch",
     "ps_get_stats",
     "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
+    "ps_tune_split",
 ]
 
 
@@ -93,6 +94,11 @@ class Result(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("slots", C.c_int32), ("from_cache", C.c_int32), ("dense_edges", C.c_int64),
                 ("ms_per_query", C.c_double)]
+
+
+class Split(C.Structure):
+    _fields_ = [("eps_s", C.c_double), ("eps_t", C.c_double), ("eps_p", C.c_double),
+                ("ms_per_query", C.c_double), ("default_ms_per_query", C.c_double)]
 
 
 class ServerCfg(C.Structure):
@@ -158,6 +164,7 @@ def load_library(path: str = LIB_PATH):
         "ps_server_update": ([vp, C.c_int64, vp, vp, vp], C.c_int),
         "ps_server_stop": ([vp], C.c_int),
         "ps_autotune": ([vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, C.c_char_p, P(Tune)], C.c_int),
+        "ps_tune_split": ([vp, C.c_int32, vp, C.c_double, C.c_double, C.c_double, P(Options), P(Split)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -334,6 +341,18 @@ def ps_autotune(g: Graph, nodes, c, eps, delta, cache_path=None) -> dict:
     t = Tune()
     _check(load_library().ps_autotune(g._h, int(nd.size), nd.ctypes.data, c, eps, delta,
                                       cache_path.encode() if cache_path else None, C.byref(t)), "ps_autotune")
+    return {k: getattr(t, k) for k, _ in t._fields_}
+
+
+def ps_tune_split(g: Graph, nodes, c, eps, delta, **opt) -> dict:
+    """Times the split candidates of Theorem 2 on the sample query nodes and
+    returns the fastest split (eps_s, eps_t, eps_p) with the measured times;
+    pass its eps_s/eps_t/eps_p to later queries to use it."""
+    nd = np.ascontiguousarray(nodes, dtype=np.int32)
+    o = options(**opt)
+    t = Split()
+    _check(load_library().ps_tune_split(g._h, int(nd.size), nd.ctypes.data, c, eps, delta, C.byref(o), C.byref(t)),
+           "ps_tune_split")
     return {k: getattr(t, k) for k, _ in t._fields_}
 
 

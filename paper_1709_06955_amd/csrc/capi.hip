@@ -287,6 +287,83 @@ bool cache_lookup(const char* path, int32_t n, int64_t m, double eps, ps_tune* o
 
 }  // namespace
 
+// Theorem 2: the split candidates of ps_tune_split, each meeting the
+// inequality with equality (the pruning share takes what sampling and
+// truncation leave).
+extern "C" ps_status ps_tune_split(ps_graph* g, int32_t nsample, const int32_t* nodes, double c, double eps,
+                                   double delta, ps_options* opt, ps_split* out) {
+  if (!g || nsample <= 0 || !nodes || !opt || !out) return PS_ERR_INVALID_ARG;
+  if (opt->walk_begin != 0 || opt->walk_end >= 0 || opt->eps_s >= 0.0 || opt->eps_t >= 0.0 || opt->eps_p >= 0.0)
+    return PS_ERR_INVALID_ARG;
+  if (!(c > 0.0 && c < 1.0) || !(eps > 0.0 && eps < 1.0)) return PS_ERR_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  ps_ctx* ctx = g->ctx;
+  const double sc = std::sqrt(c);
+  const double shift = opt->bias_shift ? 0.5 : 1.0;
+  struct Cand {
+    double s, t, p;
+  };
+  std::vector<Cand> cands;
+  for (double at : {0.25, 0.0625}) {
+    for (double as : {0.5, 0.6, 0.7, 0.8}) {
+      const double es = as * eps, et = at * eps;
+      const double rest = eps - es - shift * et;
+      if (!(rest > 0.0)) continue;
+      cands.push_back({es, et, rest * (1.0 - sc) / (1.0 + es)});
+    }
+  }
+  double* dout = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    PS_HIP(hipSetDevice(ctx->device));
+    PS_HIP(hipMalloc(&dout, sizeof(double) * (size_t)g->n));
+  }
+  double best = 1e300;
+  ps_status st = PS_OK;
+  for (size_t ci = 0; ci < cands.size() && st == PS_OK; ++ci) {
+    ps_options o = *opt;
+    o.eps_s = cands[ci].s;
+    o.eps_t = cands[ci].t;
+    o.eps_p = cands[ci].p;
+    std::vector<QueryRun> qs;
+    for (int32_t i = 0; i < nsample && st == PS_OK; ++i) {
+      QueryRun q;
+      st = make_query_run(g, nodes[i], 0, c, eps, delta, (uint64_t)(7 + i), &o, &q);
+      qs.push_back(q);
+    }
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && st == PS_OK; ++rep) {
+      const auto t0 = std::chrono::steady_clock::now();
+      for (auto& q : qs) {
+        QueryOut qo;
+        qo.scores = dout;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        GraphVersion* gv = graph_acquire(g);
+        st = engine_run(ctx, g, gv, {q}, {qo}, o.slots, o.pull_edges);
+        graph_release(g, gv);
+        if (st != PS_OK) break;
+      }
+      if (rep == 1)
+        ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / nsample;
+    }
+    if (st != PS_OK) break;
+    if (ci == 0) out->default_ms_per_query = ms;
+    if (ms < best) {
+      best = ms;
+      out->eps_s = cands[ci].s;
+      out->eps_t = cands[ci].t;
+      out->eps_p = cands[ci].p;
+      out->ms_per_query = ms;
+    }
+  }
+  (void)hipFree(dout);
+  if (st != PS_OK) return st;
+  opt->eps_s = out->eps_s;
+  opt->eps_t = out->eps_t;
+  opt->eps_p = out->eps_p;
+  return PS_OK;
+}
+
 extern "C" ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double c, double eps,
                                  double delta, const char* cache_path, ps_tune* out) {
   if (!g || nsample <= 0 || !nodes || !out) return PS_ERR_INVALID_ARG;

@@ -62,7 +62,8 @@ def test_params_agree_with_oracle(orc):
 
 
 STRUCTS = {"ps_options": "Options", "ps_params": "Params", "ps_stats": "Stats", "ps_query": "Query",
-           "ps_result": "Result", "ps_tune": "Tune", "ps_server_cfg": "ServerCfg"}
+           "ps_result": "Result", "ps_tune": "Tune", "ps_server_cfg": "ServerCfg",
+           "ps_split": "Split"}
 
 
 def test_binding_structs_match_header_layout(tmp_path):

@@ -615,6 +615,34 @@ def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
     _parity(gpu, ref, ost, f"pull_edges={pull}")
 
 
+@pytest.mark.parametrize("mode", [0, 2])
+def test_tune_split_meets_theorem2_and_matches_oracle(ps, ctx, cl20k, orc, mode):
+    # The split tuner returns one of its Theorem 2 candidates (checked here
+    # from the inequality), no slower than the default split on its sample,
+    # and queries run with that split equal the oracle given the same split.
+    import math
+
+    n, s, d, G, O = cl20k
+    c, eps, delta = 0.6, 0.05, 0.01
+    sample = graphs.query_nodes(n, d, 2, seed=101)
+    kw = dict(probe_mode=mode)
+    t = ps.ps_tune_split(G, sample, c, eps, delta, **kw)
+    print(f"mode {mode}: chose {t}", flush=True)
+    es, et, ep = t["eps_s"], t["eps_t"], t["eps_p"]
+    assert any(abs(es - a * eps) < 1e-15 for a in (0.5, 0.6, 0.7, 0.8))
+    assert any(abs(et - a * eps) < 1e-15 for a in (0.25, 0.0625))
+    assert es + (1 + es) / (1 - math.sqrt(c)) * ep + et <= eps * (1 + 1e-12)
+    assert t["ms_per_query"] <= t["default_ms_per_query"]
+    p = orc.params(n, c, eps, delta, eps_s=es, eps_t=et, eps_p=ep)
+    u = int(graphs.query_nodes(n, d, 1, seed=103)[0])
+    gpu = ps.ps_single_source(G, u, c, eps, delta, 17, eps_s=es, eps_t=et, eps_p=ep, **kw)
+    probe = "hybrid" if mode == 2 else "deterministic"
+    ref, st = orc.batch(O, u, p, 17, precision="f32", probe=probe, c0=ps.options().hybrid_c0 if mode == 2 else None)
+    _parity(gpu, ref, st, f"tuned split mode {mode}")
+    with pytest.raises(ps.ProbeSimError):
+        ps.ps_tune_split(G, sample, c, eps, delta, eps_s=0.02)
+
+
 def test_autotune_keeps_results(ps, ctx, cl20k, orc, tmp_path):
     # The autotuner only picks launch settings; estimates must not change.
     n, s, d, G, O = cl20k

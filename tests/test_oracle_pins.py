@@ -632,3 +632,28 @@ def test_topk_measures_on_known_lists():
     assert tm.kendall_tau_k([2, 1, 3], s) == pytest.approx(1 / 3)
     # ties count as neither
     assert tm.kendall_tau_k([5, 6], np.array([0, 0, 0, 0, 0, 0.2, 0.2])) == 0.0
+
+
+def test_guarantee_holds_for_other_splits_of_theorem2(orc):
+    # Theorem 2 allows any split meeting
+    #   eps_s + (1 + eps_s) / (1 - sqrt c) * eps_p + eps_t <= eps_a;
+    # the extreme candidates the split tuner tries (most of the error to
+    # sampling, a sixteenth to truncation) keep max_v |s^ - s| <= eps_a
+    # against the Power Method, and fewer walks are drawn.
+    from synth.graphs import erdos_renyi
+
+    n, c, eps = 1000, 0.6, 0.1
+    s_, d_ = erdos_renyi(n, 10000, seed=1)
+    S = refs.power_method(n, s_, d_, c, iters=55)
+    G = orc.Graph(n, s_, d_)
+    base = orc.params(n, c, eps, 0.01)
+    for a_s, a_t in ((0.8, 1 / 16), (0.7, 1 / 4)):
+        es, et = a_s * eps, a_t * eps
+        ep = (eps - es - et) * (1 - math.sqrt(c)) / (1 + es)
+        p = orc.params(n, c, eps, 0.01, eps_s=es, eps_t=et, eps_p=ep)
+        assert p.n_r < base.n_r
+        assert es + (1 + es) / (1 - math.sqrt(c)) * ep + et <= eps * (1 + 1e-12)
+        for seed in range(2):
+            for precision in ("f64", "f32"):
+                est, _ = orc.batch(G, 0, p, seed, precision=precision)
+                assert np.abs(est - S[0]).max() <= eps
