@@ -383,6 +383,16 @@ def test_accuracy_against_power_method(ps, ctx, er):
                       flush=True)
                 assert err <= 0.1
                 assert gap <= 0.2
+        # the split chosen by measurement (Theorem 2) keeps the guarantee
+        t = ps.ps_tune_split(G, graphs.query_nodes(n, d, 2, seed=99), 0.6, 0.1, 1e-4)
+        for i, u in enumerate(graphs.query_nodes(n, d, 3, seed=97)):
+            u = int(u)
+            est = ps.ps_single_source(G, u, 0.6, 0.1, 1e-4, 300 + i, eps_s=t["eps_s"], eps_t=t["eps_t"],
+                                      eps_p=t["eps_p"])
+            err = float(np.abs(est - S[u]).max())
+            print(f"{name} u={u} tuned split {t['eps_s']:.3f}/{t['eps_t']:.4f}/{t['eps_p']:.5f}: "
+                  f"max|s^-s| = {err:.4f}", flush=True)
+            assert err <= 0.1
 
 
 @pytest.mark.parametrize("eps", [0.1, 0.05])
