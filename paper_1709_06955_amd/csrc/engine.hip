@@ -27,6 +27,13 @@
 //                sparse lists while the sums stay exact and independent of
 //                the order of the adds.  A probe's last level adds weight *
 //                score straight into the query's FP64 estimate.
+//   switch       for a hybrid query (Section 4.4) k_pick stops a
+//                deterministic probe whose level about to be expanded keeps
+//                more than c0 * w * n out-edges and queues one randomized
+//                probe (Alg. 4) per walk through its tree node; the walks of
+//                each tree node are listed at admission (k_walk_offsets,
+//                k_walk_lists), and k_hyb_count measures the levels of
+//                probes held in dense columns.
 //   finish       k_finalize divides by n_r and sets s(u,u) = 1; top-k sorts.
 
 #include <hipcub/hipcub.hpp>
@@ -2124,8 +2131,8 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   }
   uint64_t total_steps = steps;
   // Probes switched under Section 4.4 queue randomized probes while the
-  // steps run: they run in further rounds, sized the same way, until every
-  // query is complete (a few rounds at most; the cap is a guard).
+  // steps run: those run in further batches of steps, sized the same way,
+  // until every query is complete (a few batches at most; the cap is a guard).
   for (int round = 0; hybrid && round < 16; ++round) {
     PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
     PS_HIP(hipStreamSynchronize(st));
