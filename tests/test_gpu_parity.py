@@ -816,6 +816,19 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
         ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000, probe_mode=1)
         dt = time.perf_counter() - t0
         _say(f"u={int(q)} randomized: 2000 of {p.n_r} walks in {dt:.2f} s (whole query ~{dt * p.n_r / 2000:.0f} s)")
+    # the switch of Section 4.4 (default c0): parity and switch count on a
+    # shard, cost
+    c0 = ps.options().hybrid_c0
+    gpu = ps.ps_single_source(G, u, 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=20, probe_mode=2)
+    sw = ctx.stats()["switched_probes"]
+    ref, st = orc.batch(O, u, p, seed, 0, 20, precision="f32", probe="hybrid", c0=c0)
+    assert sw == st["switched"]
+    _parity(gpu, ref, st, f"cl40m hybrid u={u} walks [0,20), switched {sw} of {st['tree_nodes']}")
+    for q in qn[:2]:
+        t0 = time.perf_counter()
+        ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000, probe_mode=2)
+        dt = time.perf_counter() - t0
+        _say(f"u={int(q)} hybrid: 2000 of {p.n_r} walks in {dt:.2f} s (whole query ~{dt * p.n_r / 2000:.0f} s)")
 
 
 def test_hub_rows_compaction_and_long_rows(ps, ctx, orc):
