@@ -84,7 +84,8 @@ ps_status ps_ctx_set_timing(ps_ctx* ctx, int enable);
 #define PS_LOAD_DROP_SELF_LOOPS 2u /* drop self-loops instead of failing */
 
 /* Loads the directed simple graph G = (V, E), |V| = n, with m edges
- * src[i] -> dst[i] (host arrays of m int32).  Builds, on the device, the
+ * src[i] -> dst[i] (arrays of m int32, host memory or device memory of the
+ * context's GPU, borrowed for the call only).  Builds, on the device, the
  * in-adjacency (each row in ascending source id: the canonical order walks
  * index into) and the out-adjacency, plus 1/|I(v)|.  Errors:
  * PS_ERR_NODE_RANGE for an id outside [0, n); PS_ERR_SELF_LOOP /

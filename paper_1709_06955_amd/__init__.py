@@ -235,15 +235,29 @@ class Context:
             pass
 
 
+def _edge_array(a):
+    """(object kept alive, pointer, length) of an edge array."""
+    if hasattr(a, "data_ptr") and getattr(a, "is_cuda", False):
+        if str(a.dtype) != "torch.int32" or not a.is_contiguous():
+            raise ValueError("device edge arrays must be contiguous int32 tensors")
+        return a, a.data_ptr(), a.numel()
+    h = np.ascontiguousarray(a, dtype=np.int32)
+    return h, h.ctypes.data, h.size
+
+
 class Graph:
     """A device-resident graph (edges src[i] -> dst[i])."""
 
     def __init__(self, ctx: Context, n: int, src, dst, flags: int = 0):
-        s = np.ascontiguousarray(src, dtype=np.int32)
-        d = np.ascontiguousarray(dst, dtype=np.int32)
+        """src, dst: int32 edge arrays (numpy/host, or contiguous int32 torch
+        tensors on the context's GPU)."""
+        s, sp, sm = _edge_array(src)
+        d, dp, dm = _edge_array(dst)
+        if sm != dm:
+            raise ValueError("src and dst differ in length")
         h = C.c_void_p()
-        _check(load_library().ps_graph_load(ctx._h, int(n), int(s.size), s.ctypes.data, d.ctypes.data,
-                                            int(flags), C.byref(h)), "ps_graph_load")
+        _check(load_library().ps_graph_load(ctx._h, int(n), int(sm), sp, dp, int(flags), C.byref(h)),
+               "ps_graph_load")
         self._h = h
         self.ctx = ctx
         self.n = int(n)

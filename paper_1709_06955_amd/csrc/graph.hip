@@ -233,6 +233,18 @@ extern "C" ps_status ps_graph_load(ps_ctx* ctx, int32_t n, int64_t m, const int3
   if (!out) return PS_ERR_INVALID_ARG;
   *out = nullptr;
   if (!ctx || n <= 0 || m < 0 || m >= (1ll << 31) || (m > 0 && (!src || !dst))) return PS_ERR_INVALID_ARG;
+  // Edge lists in device memory (a torch tensor's pointer) are copied to the
+  // host first: the host mirror is built from them.
+  std::vector<int32_t> hsrc, hdst;
+  if (m > 0 && (ps_is_device_ptr(src) || ps_is_device_ptr(dst))) {
+    PS_HIP(hipSetDevice(ctx->device));
+    hsrc.resize((size_t)m);
+    hdst.resize((size_t)m);
+    PS_HIP(hipMemcpy(hsrc.data(), src, sizeof(int32_t) * (size_t)m, hipMemcpyDefault));
+    PS_HIP(hipMemcpy(hdst.data(), dst, sizeof(int32_t) * (size_t)m, hipMemcpyDefault));
+    src = hsrc.data();
+    dst = hdst.data();
+  }
   for (int64_t i = 0; i < m; ++i)
     if (src[i] < 0 || src[i] >= n || dst[i] < 0 || dst[i] >= n) return PS_ERR_NODE_RANGE;
   // Counting sort by source, then sort each out-row by target.

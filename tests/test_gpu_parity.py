@@ -418,6 +418,21 @@ def test_batch_equals_alone(ps, cl20k):
         _same_query(r, f, a, fa, f"batch vs alone u={q['u']} k={q['k']}")
 
 
+def test_graph_load_from_device_arrays(ps, ctx, cl20k):
+    # Edge arrays in device memory load the same graph as host arrays.
+    import torch
+
+    n, s, d, G, O = cl20k
+    G2 = ps.Graph(ctx, n, torch.from_numpy(s).cuda(), torch.from_numpy(d).cuda())
+    e1, e2 = G.edges(), G2.edges()
+    assert np.array_equal(e1[0], e2[0]) and np.array_equal(e1[1], e2[1])
+    u = int(graphs.query_nodes(n, d, 1, seed=107)[0])
+    a = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 5)
+    b = ps.ps_single_source(G2, u, 0.6, 0.1, 0.01, 5)
+    _same_query(a, 0.0, b, 0.0, "device-loaded graph")
+    G2.close()
+
+
 def test_sparse_output_equals_dense(ps, cl20k):
     import torch
 
