@@ -290,7 +290,7 @@ ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double
  * with the split (another estimate with the same guarantee), so unlike
  * ps_autotune the choice is applied only through the options it returns.
  * PS_ERR_INVALID_ARG when opt's walk range or split fields are not the
- * defaults. */
+ * defaults.  The context must not have a running server. */
 typedef struct ps_split {
   double eps_s, eps_t, eps_p;  /* the split chosen (also written into opt) */
   double ms_per_query;         /* measured time of the chosen split */
@@ -307,7 +307,7 @@ typedef struct ps_stats {
   int64_t walks;            /* walks sampled */
   int64_t walk_nodes;       /* sum of walk lengths */
   int64_t tree_nodes;       /* probes: reverse reachability tree nodes below the roots */
-  int64_t probe_levels;     /* sum over probes of (depth - 1) */
+  int64_t probe_levels;     /* sum over probes of (depth - 1), switched probes' walks included */
   int64_t steps;            /* level steps launched */
   int64_t entries_expanded; /* frontier entries kept by Rule 2 and expanded */
   int64_t entries_pruned;   /* frontier entries removed by Rule 2 */
