@@ -279,8 +279,9 @@ ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double
 
 /* Split of the error eps_a among sampling, truncation and pruning chosen by
  * measurement (Theorem 2).  Candidates: eps_s = a_s * eps and eps_t = a_t *
- * eps for a_s in {0.5, 0.6, 0.7, 0.8} and a_t in {1/4, 1/16}, with eps_p
- * taking the rest of the inequality of Theorem 2:
+ * eps for a_s in {0.5, 0.6, 0.7, 0.75, 0.8, 0.85} and a_t in {1/4, 1/16,
+ * 1/256} (those whose parameters are valid: L within PS_MAX_WALK_LEN), with
+ * eps_p taking the rest of the inequality of Theorem 2:
  *   eps_s + (1 + eps_s) / (1 - sqrt c) * eps_p + eps_t' = eps
  * (eps_t' = eps_t / 2 when opt->bias_shift is set, Section 4.1; else eps_t).
  * Every candidate keeps the guarantee of Definition 1.  The nsample query

@@ -304,14 +304,21 @@ extern "C" ps_status ps_tune_split(ps_graph* g, int32_t nsample, const int32_t* 
     double s, t, p;
   };
   std::vector<Cand> cands;
-  for (double at : {0.25, 0.0625}) {
-    for (double as : {0.5, 0.6, 0.7, 0.8}) {
+  for (double at : {0.25, 0.0625, 1.0 / 256.0}) {
+    for (double as : {0.5, 0.6, 0.7, 0.75, 0.8, 0.85}) {
       const double es = as * eps, et = at * eps;
       const double rest = eps - es - shift * et;
       if (!(rest > 0.0)) continue;
-      cands.push_back({es, et, rest * (1.0 - sc) / (1.0 + es)});
+      ps_options o = *opt;
+      o.eps_s = es;
+      o.eps_t = et;
+      o.eps_p = rest * (1.0 - sc) / (1.0 + es);
+      ps_params prm;
+      if (derive_params(g->n, c, eps, delta, &o, &prm) != PS_OK) continue;  // e.g. L beyond the cap
+      cands.push_back({es, et, o.eps_p});
     }
   }
+  if (cands.empty()) return PS_ERR_INVALID_ARG;
   double* dout = nullptr;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);

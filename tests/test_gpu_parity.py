@@ -654,8 +654,8 @@ def test_tune_split_meets_theorem2_and_matches_oracle(ps, ctx, cl20k, orc, mode)
     t = ps.ps_tune_split(G, sample, c, eps, delta, **kw)
     print(f"mode {mode}: chose {t}", flush=True)
     es, et, ep = t["eps_s"], t["eps_t"], t["eps_p"]
-    assert any(abs(es - a * eps) < 1e-15 for a in (0.5, 0.6, 0.7, 0.8))
-    assert any(abs(et - a * eps) < 1e-15 for a in (0.25, 0.0625))
+    assert any(abs(es - a * eps) < 1e-15 for a in (0.5, 0.6, 0.7, 0.75, 0.8, 0.85))
+    assert any(abs(et - a * eps) < 1e-15 for a in (0.25, 0.0625, 1 / 256))
     assert es + (1 + es) / (1 - math.sqrt(c)) * ep + et <= eps * (1 + 1e-12)
     assert t["ms_per_query"] <= t["default_ms_per_query"]
     p = orc.params(n, c, eps, delta, eps_s=es, eps_t=et, eps_p=ep)

@@ -638,7 +638,7 @@ def test_guarantee_holds_for_other_splits_of_theorem2(orc):
     # Theorem 2 allows any split meeting
     #   eps_s + (1 + eps_s) / (1 - sqrt c) * eps_p + eps_t <= eps_a;
     # the extreme candidates the split tuner tries (most of the error to
-    # sampling, a sixteenth to truncation) keep max_v |s^ - s| <= eps_a
+    # sampling, 1/256 to truncation) keep max_v |s^ - s| <= eps_a
     # against the Power Method, and fewer walks are drawn.
     from synth.graphs import erdos_renyi
 
@@ -647,7 +647,7 @@ def test_guarantee_holds_for_other_splits_of_theorem2(orc):
     S = refs.power_method(n, s_, d_, c, iters=55)
     G = orc.Graph(n, s_, d_)
     base = orc.params(n, c, eps, 0.01)
-    for a_s, a_t in ((0.8, 1 / 16), (0.7, 1 / 4)):
+    for a_s, a_t in ((0.85, 1 / 256), (0.7, 1 / 4)):
         es, et = a_s * eps, a_t * eps
         ep = (eps - es - et) * (1 - math.sqrt(c)) / (1 + es)
         p = orc.params(n, c, eps, 0.01, eps_s=es, eps_t=et, eps_p=ep)
