@@ -106,16 +106,16 @@ def cpu_baseline(n, s, d, q, seconds_target=15.0, threads=None):
                       f"on {threads} threads, {wall:.1f} s, scaled by n_r / {walks}"}
 
 
-def served(ps, G, q, n, seconds=8.0, rate_frac=0.5, seed=7):
+def served(ps, G, q, n, seconds=8.0, rate_frac=0.5, seed=7, **defaults):
     """Continuous-batching server on the same graph and queries: closed-loop
     saturation throughput X_sat (all queries submitted at once), then
     open-loop Poisson arrivals at rate_frac * X_sat; latency is submit to
-    result on the host."""
+    result on the host.  defaults: options every served query runs with."""
     import threading
 
     import numpy as np
 
-    srv = ps.Server(G, max_inflight=32)
+    srv = ps.Server(G, max_inflight=32, **defaults)
     try:
         t0 = time.perf_counter()
         ts = [srv.submit(int(u), C, EPS, DELTA, 1000 + i) for i, u in enumerate(q)]
@@ -352,6 +352,10 @@ def main():
         print(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written", file=sys.stderr)
     if not args.no_served:
         result["served"] = served(ps, G, q, n)
+        if split is not None:  # the same, every query with the tuned split and the switch of Section 4.4
+            result["served_tuned"] = served(ps, G, q, n, eps_s=split["eps_s"], eps_t=split["eps_t"],
+                                            eps_p=split["eps_p"], probe_mode=ps.PROBE_HYBRID,
+                                            hybrid_c0=args.hybrid_c0)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, s, d, q)
     print(json.dumps(result), flush=True)

@@ -340,6 +340,11 @@ typedef struct ps_server_cfg {
   int32_t slots;          /* probe slots (0: the graph's autotuned setting, else automatic) */
   int32_t reserved;
   int64_t frontier_bytes; /* device memory budget for admitted queries (0: automatic) */
+  const ps_options* defaults; /* nullable: options every served query runs with (the
+                                 error split, probe mode and its c0, bias shift), copied
+                                 at start; a query's own nonzero probe_mode (and then its
+                                 hybrid_c0) overrides them.  Walk ranges must be the
+                                 defaults (PS_ERR_INVALID_ARG) */
 } ps_server_cfg;
 
 /* Starts a serving loop on the graph's context: a host thread that drains

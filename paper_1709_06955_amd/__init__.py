@@ -103,7 +103,7 @@ class Split(C.Structure):
 
 class ServerCfg(C.Structure):
     _fields_ = [("ring", C.c_int32), ("max_inflight", C.c_int32), ("slots", C.c_int32),
-                ("reserved", C.c_int32), ("frontier_bytes", C.c_int64)]
+                ("reserved", C.c_int32), ("frontier_bytes", C.c_int64), ("defaults", C.POINTER(Options))]
 
 
 _lib = None
@@ -412,8 +412,13 @@ def ps_batch(g: Graph, queries, outs=None, **opt):
 class Server:
     """Continuous-batching query server on one graph."""
 
-    def __init__(self, g: Graph, ring=1024, max_inflight=64, slots=0, frontier_bytes=0):
-        cfg = ServerCfg(ring, max_inflight, slots, 0, frontier_bytes)
+    def __init__(self, g: Graph, ring=1024, max_inflight=64, slots=0, frontier_bytes=0, **defaults):
+        """defaults: ps_options fields every served query runs with (split,
+        probe_mode, hybrid_c0, ...); a query's own probe_mode overrides."""
+        cfg = ServerCfg(ring, max_inflight, slots, 0, frontier_bytes, None)
+        if defaults:
+            o = options(**defaults)
+            cfg.defaults = C.pointer(o)
         h = C.c_void_p()
         _check(load_library().ps_server_start(g._h, C.byref(cfg), C.byref(h)), "ps_server_start")
         self._h = h

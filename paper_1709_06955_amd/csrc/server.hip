@@ -56,6 +56,7 @@ struct Completion {
 struct ps_server {
   ps_graph* g = nullptr;
   ps_server_cfg cfg{};
+  ps_options defaults{};  // options of every served query (cfg.defaults copied)
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_comp;
   std::deque<Request> ring;
@@ -273,10 +274,11 @@ ps_status serve_loop(ps_server* s) {
       std::vector<Request> ok;
       for (auto& rq : fresh) {
         QueryRun qr;
-        ps_options opt;
-        ps_options_default(&opt);
-        opt.probe_mode = rq.q.probe_mode;
-        if (rq.q.probe_mode == PS_PROBE_HYBRID) opt.hybrid_c0 = rq.q.hybrid_c0;
+        ps_options opt = s->defaults;
+        if (rq.q.probe_mode) {
+          opt.probe_mode = rq.q.probe_mode;
+          if (rq.q.probe_mode == PS_PROBE_HYBRID) opt.hybrid_c0 = rq.q.hybrid_c0;
+        }
         ps_status vs = make_query_run(g, rq.q.u, rq.q.k, rq.q.c, rq.q.eps, rq.q.delta, rq.q.seed, &opt, &qr);
         if (vs == PS_OK && (!rq.r->scores || (rq.q.k > 0 && !rq.r->nodes))) vs = PS_ERR_INVALID_ARG;
         if (vs != PS_OK) {
@@ -428,6 +430,15 @@ extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_s
   auto* s = new ps_server();
   s->g = g;
   if (cfg) s->cfg = *cfg;
+  ps_options_default(&s->defaults);
+  if (s->cfg.defaults) {
+    if (s->cfg.defaults->walk_begin != 0 || s->cfg.defaults->walk_end >= 0) {
+      delete s;
+      return PS_ERR_INVALID_ARG;
+    }
+    s->defaults = *s->cfg.defaults;
+  }
+  s->cfg.defaults = nullptr;  // the caller's struct is not kept
   if (s->cfg.ring <= 0) s->cfg.ring = 1024;
   if (s->cfg.max_inflight <= 0) s->cfg.max_inflight = 64;
   {

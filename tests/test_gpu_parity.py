@@ -602,6 +602,30 @@ def test_server_interleaves_updates(ps, ctx, orc, mode):
         _parity(r2, ref, st, "served hybrid after the update")
 
 
+def test_server_defaults_apply_to_every_query(ps, ctx, cl20k):
+    # A server started with default options (a Theorem 2 split and the
+    # switch of Section 4.4) runs every query with them; a query's own
+    # probe_mode overrides the mode; walk ranges are refused.
+    n, s, d, G, O = cl20k
+    eps = 0.05
+    split = dict(eps_s=0.8 * eps, eps_t=eps / 256, eps_p=(eps - 0.8 * eps - eps / 256) * (1 - 0.6 ** 0.5) / (1 + 0.8 * eps))
+    qn = [int(u) for u in graphs.query_nodes(n, d, 3, seed=109)]
+    srv = ps.Server(G, max_inflight=3, probe_mode=2, hybrid_c0=0.05, **split)
+    try:
+        t = [srv.submit(u, 0.6, eps, 0.01, 11 + i) for i, u in enumerate(qn)]
+        t.append(srv.submit(qn[0], 0.6, eps, 0.01, 11, probe_mode=1))
+        got = [srv.wait(x, timeout_us=60_000_000) for x in t]
+    finally:
+        srv.stop()
+    for i, u in enumerate(qn):
+        a = ps.ps_single_source(G, u, 0.6, eps, 0.01, 11 + i, probe_mode=2, hybrid_c0=0.05, **split)
+        _same_query(got[i], 0.0, a, 0.0, f"served with defaults u={u}")
+    a = ps.ps_single_source(G, qn[0], 0.6, eps, 0.01, 11, probe_mode=1, **split)
+    _same_query(got[3], 0.0, a, 0.0, "served, own probe_mode over the defaults")
+    with pytest.raises(ps.ProbeSimError):
+        ps.Server(G, walk_end=100)
+
+
 def test_server_busy_and_stop(ps, ctx):
     src = np.array([0, 1, 2, 3], np.int32)
     dst = np.array([1, 2, 3, 0], np.int32)
