@@ -169,6 +169,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the passes with randomized PROBE and with the switch of Section 4.4")
     ap.add_argument("--hybrid-c0", type=float, default=HYBRID_C0)
+    ap.add_argument("--probe-mode", choices=["deterministic", "randomized", "hybrid"], default="deterministic",
+                    help="probe of the one-at-a-time and batched passes (the metric is quoted with deterministic PROBE)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the passes with the error split tuned by measurement (Theorem 2)")
     ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
@@ -204,9 +206,13 @@ def main():
         print(f"autotune: {tune}", file=sys.stderr, flush=True)
     ctx.set_timing(True)
 
+    mode_kw = {"deterministic": {}, "randomized": dict(probe_mode=ps.PROBE_RANDOMIZED),
+               "hybrid": dict(probe_mode=ps.PROBE_HYBRID, hybrid_c0=args.hybrid_c0)}[args.probe_mode]
+
     def plain_step(acc, tag):
         for i, u in enumerate(q):
-            ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots, pull_edges=args.pull)
+            ps.ps_single_source(G, int(u), C, EPS, DELTA, 3 + i, out=out, slots=args.slots, pull_edges=args.pull,
+                                **mode_kw)
             st = ctx.stats()
             print(f"[{tag}] query {i} u={int(u)}: {st['total_ms']:.1f} ms, push {st['expand_ms']:.1f} ms + pull "
                   f"{st['pull_ms']:.1f} ms in {st['expand_launches']} steps, tree nodes {st['tree_nodes']}, "
@@ -238,7 +244,7 @@ def main():
 
     # Batched: the same 32 queries in one launch.
     outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in range(len(q))]
-    qlist = [dict(u=int(u), k=0, c=C, eps=EPS, delta=DELTA, seed=3 + i) for i, u in enumerate(q)]
+    qlist = [dict(u=int(u), k=0, c=C, eps=EPS, delta=DELTA, seed=3 + i, **mode_kw) for i, u in enumerate(q)]
     ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
     torch.cuda.synchronize()
     tb = time.perf_counter()
@@ -250,12 +256,13 @@ def main():
     # Smaller queries (eps = 0.1, about a quarter of the walks): one query no
     # longer keeps every probe slot busy to its end, which batching recovers.
     small = {"eps": 0.1}
-    qsmall = [dict(u=int(u), k=0, c=C, eps=0.1, delta=DELTA, seed=3 + i) for i, u in enumerate(q)]
+    qsmall = [dict(u=int(u), k=0, c=C, eps=0.1, delta=DELTA, seed=3 + i, **mode_kw) for i, u in enumerate(q)]
     for rep_ in range(2):  # the first pass is a warm-up
         torch.cuda.synchronize()
         ts = time.perf_counter()
         for i, u in enumerate(q):
-            ps.ps_single_source(G, int(u), C, 0.1, DELTA, 3 + i, out=outs[i][0], slots=args.slots, pull_edges=args.pull)
+            ps.ps_single_source(G, int(u), C, 0.1, DELTA, 3 + i, out=outs[i][0], slots=args.slots, pull_edges=args.pull,
+                                **mode_kw)
         torch.cuda.synchronize()
         small["plain_qps"] = len(q) / (time.perf_counter() - ts)
         ts = time.perf_counter()
@@ -317,7 +324,8 @@ def main():
     achieved = (alg_bytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic, traffic_bytes = measured_traffic(avg_ms)
     result = {
-        "metric": "single-source queries/s at eps=0.05 (plain, one query at a time)",
+        "metric": "single-source queries/s at eps=0.05 (plain, one query at a time)" + (
+            "" if args.probe_mode == "deterministic" else f", {args.probe_mode} PROBE"),
         "value": qps,
         "unit": "queries/s",
         "n_gpus": 1,
