@@ -427,8 +427,6 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
     a.ctr[C_CHUNK] = 0;
     a.ctr[C_LIST0 + (a.cur ^ 1)] = 0;
     a.ctr[C_NZROWS0 + (a.cur ^ 1)] = 0;  // k_dense rewrites that matrix this step
-    a.ctr[C_RAND] = 0;
-    a.ctr[C_RCLEAR] = 0;
     s_head = a.ctr[C_HEAD];
     s_avail = a.ctr[C_TAIL] - s_head;
   }
@@ -476,7 +474,6 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
   }
   unsigned long long rank = before + incl - cnt;
   const unsigned long long head = s_head, avail = s_avail;
-  unsigned long long nrand = 0;
 #pragma unroll
   for (int r = 0; r < kSlotsPerSchedThread; ++r) {
     const int s = tid * kSlotsPerSchedThread + r;
@@ -520,8 +517,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
         const int32_t x = a.t_node[t];
         const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
         if (pos < a.list_cap) {
-          // H_0 = {u_i: 1}; a randomized probe's members are marked 2
-          a.dense_cur[(size_t)s * a.n + x] = mode ? 2ll : kGridOne;
+          // H_0 = {u_i: 1} (a randomized probe's sets are its lists alone)
+          if (!mode) a.dense_cur[(size_t)s * a.n + x] = kGridOne;
           a.list_cur[pos] = make_int2(s, x);
         } else {
           atomicOr(&a.ctr[C_OVERFLOW], 1ull);
@@ -538,11 +535,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
       S.thr_next = e > 1 ? a.thr_tab[q * PS_MAX_WALK_LEN + e - 1] : 0.0f;
       S.excl = a.t_node[S.cursor];
       S.last = level == depth - 2;
-      if (S.mode) ++nrand;
     }
   }
-  nrand = wave_sum(nrand);
-  if (lane == 0 && nrand) atomicAdd(&a.ctr[C_RAND], nrand);
   if (tid == 0) a.ctr[C_HEAD] = head + (total < avail ? total : avail);
 }
 
@@ -554,7 +548,8 @@ __global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
 // also cut into kChunk-edge chunks for the wavefront-per-chunk part of
 // k_expand (marked with the top bit of the length so that the tile part skips
 // them).  Per slot, the out-degrees of its kept entries are summed: that
-// decides between pushing and pulling the slot's level.
+// decides between pushing and pulling the slot's level.  A randomized probe
+// (Alg. 4) lists exactly the members of its set: they are kept as listed.
 __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restrict__ slots,
                                                  const int2* __restrict__ list_cur, long long* __restrict__ dense_cur,
                                                  float* __restrict__ item_val, uint2* __restrict__ item_row,
@@ -575,14 +570,12 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
     if (i < cnt) {
       const int2 it = list_cur[i];
       long long* d = dense_cur + (size_t)it.x * n + it.y;
-      const long long raw = *d;
-      const float val = grid_f32(raw);
       const Slot& sl = slots[it.x];
       uint2 row = make_uint2(0u, 0u);
-      bool keep;
-      if (sl.mode) {  // Alg. 4: listed candidates are kept iff they were selected
-        keep = raw == 2;
-      } else {
+      bool keep = true;  // Alg. 4: a randomized probe lists exactly its members
+      float val = 0.0f;
+      if (!sl.mode) {
+        val = grid_f32(*d);
         if (fabsf(val - sl.thr) <= 1e-5f * sl.thr) {  // FP32 rounding may decide this test
           ++near;
           unsafeAtomicAdd(sl.flip, sl.flip_unit);
@@ -603,8 +596,7 @@ __global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restri
       } else {
         ++pruned;
       }
-      // members of a randomized probe stay marked until the step's end
-      if (sl.mode ? !keep : !row.y) *d = 0;
+      if (!sl.mode && !row.y) *d = 0;
       item_row[i] = row;
     }
     // segmented sum of out-degrees per slot over the wavefront
@@ -797,7 +789,6 @@ struct ExpandArgs {
   const Slot* slots;
   long long* dense_next;
   int2* list_next;
-  int2* rclear;  // last-level candidate marks of randomized probes
   uint64_t list_cap;
   uint64_t chunk_cap;
   int32_t* has_next;
@@ -864,49 +855,31 @@ __device__ __forceinline__ bool visit_edge(const ExpandArgs& a, int32_t s, int32
   return old == 0ull;
 }
 
-// One out-edge x -> v of a member x of randomized probe slot s (Alg. 4):
-// v is a candidate of the next set unless it is the excluded walk node.  The
-// first visitor of v (a compare-and-swap marks it) draws v's in-neighbour and
-// coin from Philox with counter (walk, i * 2^16 + j, v, 1); v joins the next
-// set (mark 2) when the drawn in-neighbour is a member and the coin falls
-// below sqrt(c).  On the probe's last level a member adds 1 to the estimate
-// and the mark is recorded for clearing at the step's end.  Returns whether v
-// is listed for the next level.
-__device__ __forceinline__ bool visit_random(const ExpandArgs& a, int32_t s, int32_t v, const Slot& sl,
-                                             unsigned long long& nfinal, bool& mark) {
+// One out-edge x -> v of a member x of randomized probe slot s (Alg. 4).
+// Candidate v (any out-neighbour of a member but the excluded walk node)
+// draws its in-neighbour and sqrt(c) coin from Philox with counter (walk,
+// i * 2^16 + j, v, 1), the same numbers whichever member reaches it; v joins
+// the next set when the drawn in-neighbour is a member and the coin falls
+// below sqrt(c).  The draw depends on v alone, so it is tested on the visit
+// from the drawn in-neighbour itself: that visit happens exactly when the
+// drawn node is a member.  Each selected v is so found once, with no marks
+// and no lookups of membership.  On the probe's last level a selected v adds
+// 1 to the estimate.  Returns whether v is listed for the next level.
+__device__ __forceinline__ bool visit_random(const ExpandArgs& a, int32_t v, int32_t x, const Slot& sl,
+                                             unsigned long long& nfinal) {
   if (v == sl.excl) return false;
-  unsigned long long* p = reinterpret_cast<unsigned long long*>(&a.dense_next[(size_t)s * a.n + v]);
-  if (atomicCAS(p, 0ull, 1ull) != 0ull) return false;
   const uint4 w = philox4x32_10(make_uint4(sl.wk, ((uint32_t)sl.depth << 16) | (uint32_t)sl.level, (uint32_t)v, 1u),
                                 sl.key2);
-  const uint2 row = sl.in_rows[v];  // |I(v)| >= 1: a member is an in-neighbour
+  if (w.z >= sl.t_sc) return false;  // the coin
+  const uint2 row = sl.in_rows[v];   // |I(v)| >= 1: x is an in-neighbour
   const uint64_t r = ((uint64_t)w.y << 32) | w.x;
-  const int32_t x = sl.in_col[row.x + (uint32_t)__umul64hi(r, (uint64_t)row.y)];
-  const bool sel = a.dense_cur[(size_t)s * a.n + x] == 2ll && w.z < sl.t_sc;
+  if (sl.in_col[row.x + (uint32_t)__umul64hi(r, (uint64_t)row.y)] != x) return false;
   if (sl.last) {
-    mark = true;
-    if (sel) {
-      unsafeAtomicAdd(&sl.acc[v], sl.w);
-      ++nfinal;
-    }
+    unsafeAtomicAdd(&sl.acc[v], sl.w);
+    ++nfinal;
     return false;
   }
-  if (sel) *p = 2ull;
   return true;
-}
-
-// Appends the marked (slot, node) pairs of a wavefront to the clearing list.
-__device__ __forceinline__ void mark_append(const ExpandArgs& a, bool flag, int32_t s, int32_t v) {
-  const unsigned long long mask = __ballot(flag);
-  if (!mask) return;
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(&a.ctr[C_RCLEAR], (unsigned long long)__popcll(mask));
-  base = __shfl(base, 0, 64);
-  if (flag) {
-    const unsigned long long pos = base + (unsigned long long)__popcll(mask & ((1ull << lane_id()) - 1ull));
-    if (pos < a.list_cap) a.rclear[pos] = make_int2(s, v);
-    else atomicOr(&a.ctr[C_OVERFLOW], 8ull);
-  }
 }
 
 // PROBE expansion.  Part 1: workgroups take tiles of kTile listed entries,
@@ -951,8 +924,8 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
             *dc = 0;
           } else if (pf == 2) {  // switched probe (Section 4.4): the level is dropped
             *dc = 0;
-          } else {  // pushed: its score is consumed here (members of a
-                    // randomized probe are read again, cleared at the step's end)
+          } else {  // pushed: its score is consumed here (a randomized
+                    // probe's entries never hold one)
             if (!a.slots[it.x].mode) *dc = 0;
             if (!(row.y & kBigFlag)) {
               deg[r] = row.y;
@@ -985,7 +958,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
     __syncthreads();
     for (uint32_t e0 = 0; e0 < total; e0 += kBlock) {
       const uint32_t e = e0 + (uint32_t)tid;
-      bool app = false, mark = false;
+      bool app = false;
       int32_t s = 0, v = 0;
       if (e < total) {
         int lo = 0, hi = kTile - 1;  // last entry j with s_pref[j] <= e
@@ -996,11 +969,11 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
         s = s_slot[lo];
         const Slot& sl = a.slots[s];
         v = sl.out_col[s_start[lo] + (e - s_pref[lo])];
-        app = sl.mode ? visit_random(a, s, v, sl, nfinal, mark) : visit_edge(a, s, v, s_val[lo], sl, nfinal);
+        app = sl.mode ? visit_random(a, v, a.list_cur[tile0 + lo].y, sl, nfinal)
+                      : visit_edge(a, s, v, s_val[lo], sl, nfinal);
         if (app) s_flag[lo] = 1;
       }
       wave_append(wb, app, s, v, a, nnext);
-      mark_append(a, mark, s, v);
     }
     __syncthreads();
 #pragma unroll
@@ -1016,7 +989,8 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
   const unsigned long long nchunk = min(a.ctr[C_CHUNK], (unsigned long long)a.chunk_cap);
   for (uint64_t c = wave; c < nchunk; c += nwaves) {
     const int2 ch = a.chunk_list[c];
-    const int32_t s = a.list_cur[ch.x].x;
+    const int2 it = a.list_cur[ch.x];
+    const int32_t s = it.x;
     if (a.pull_flag[s]) continue;  // pulled or switched
     const Slot sl = a.slots[s];
     const float sv = a.item_val[ch.x];
@@ -1027,15 +1001,14 @@ __global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
     bool any = false;
     for (uint32_t t0 = b; t0 < e; t0 += 64) {
       const uint32_t t = t0 + lane;
-      bool app = false, mark = false;
+      bool app = false;
       int32_t v = 0;
       if (t < e) {
         v = sl.out_col[row.x + t];
-        app = sl.mode ? visit_random(a, s, v, sl, nfinal, mark) : visit_edge(a, s, v, sv, sl, nfinal);
+        app = sl.mode ? visit_random(a, v, it.y, sl, nfinal) : visit_edge(a, s, v, sv, sl, nfinal);
       }
       any |= app;
       wave_append(wb, app, s, v, a, nnext);
-      mark_append(a, mark, s, v);
     }
     if (__ballot(any) && lane == 0) a.has_next[s] = 1;
   }
@@ -1078,12 +1051,6 @@ struct DenseArgs {
   int32_t* has_next;
   unsigned long long* ctr;
   int cur;
-  // end-of-step clearing for randomized probes
-  const int2* list_cur;
-  long long* dense_cur;
-  long long* dense_next;
-  const int2* rclear;
-  uint64_t list_cap;
 };
 
 struct LaneInfo {
@@ -1261,23 +1228,6 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
 // Finishes the targets with long in-rows from their raw partial sums.
 __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   __shared__ unsigned long long s_nz;
-  if (a.ctr[C_RAND]) {
-    // Randomized probes ran this step: their members (still marked so that
-    // candidates could test them) and their last-level candidate marks are
-    // cleared now.  Every other listed entry is already zero.
-    const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-    const unsigned long long nl = min(a.ctr[C_LIST0 + a.cur], (unsigned long long)a.list_cap);
-    for (uint64_t i = gt; i < nl; i += gs) {
-      const int2 it = a.list_cur[i];
-      a.dense_cur[(size_t)it.x * a.n + it.y] = 0;
-    }
-    const unsigned long long nm = min(a.ctr[C_RCLEAR], (unsigned long long)a.list_cap);
-    for (uint64_t i = gt; i < nm; i += gs) {
-      const int2 it = a.rclear[i];
-      a.dense_next[(size_t)it.x * a.n + it.y] = 0;
-    }
-  }
   const unsigned long long ghi = a.ctr[C_GHI], gw = a.ctr[C_GW];
   if (ghi == 0) return;
   const int tid = threadIdx.x;
@@ -1424,7 +1374,7 @@ void tree_release(Session* s, uint64_t start, uint64_t len) {
 
 void report_overflow(const Session* s, const uint64_t* h) {
   std::fprintf(stderr,
-               "probesim: capacity guard tripped (sites 0x%llx: 1 roots, 2 chunks, 4 next level, 8 marks, 16 ring); "
+               "probesim: capacity guard tripped (sites 0x%llx: 1 roots, 2 chunks, 4 next level, 16 ring); "
                "P %d n %d list cap %llu (lists %llu, %llu) chunk cap %llu (chunks %llu)\n",
                (unsigned long long)h[C_OVERFLOW], s->P, s->n, (unsigned long long)s->list_cap,
                (unsigned long long)h[C_LIST0], (unsigned long long)h[C_LIST1], (unsigned long long)s->chunk_cap,
@@ -1463,7 +1413,7 @@ void session_free(Session* s) {
                     &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
                     &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
                     &s->keys,
-                    &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring, &s->ring_k, &s->rclear,
+                    &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring, &s->ring_k,
                     &s->hyb_edges, &s->t_woff, &s->t_walks, &s->wcount,
                     &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp,
                     &s->sel_count};
@@ -1586,18 +1536,6 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
   recs->clear();
   bounds->assign(qs.size(), 0);
   if (qs.empty()) return PS_OK;
-  bool randomized = false;
-  for (const QueryRun& q : qs) randomized |= q.randomized != 0 || q.hybrid != 0;  // switched probes are randomized
-  if (randomized && s->rclear.bytes < sizeof(int2) * s->list_cap) {
-    // the marks list of randomized probes, on first use; the captured steps
-    // point at the old (absent) one
-    if (s->step_pair) {
-      PS_HIP(hipStreamSynchronize(st));
-      (void)hipGraphExecDestroy(s->step_pair);
-      s->step_pair = nullptr;
-    }
-    PS_TRY(devbuf_reserve(s->rclear, sizeof(int2) * s->list_cap));
-  }
   // one threshold row per query, alive until the synchronisation below
   std::vector<float> thr_all(qs.size() * PS_MAX_WALK_LEN, 0.0f);
   int64_t total = 0;
@@ -1846,7 +1784,6 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   k.ea.map_cur = s->rowmap[cur].as<uint8_t>();
   k.ea.dense_next = s->dense[nxt].as<long long>();
   k.ea.list_next = s->list[nxt].as<int2>();
-  k.ea.rclear = s->rclear.as<int2>();
   k.ea.nxt = nxt;
   if (ev0) (void)hipEventRecord(ev0, st);
   k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
@@ -1865,11 +1802,6 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
   da.has_next = s->has_next.as<int32_t>();
   da.ctr = ctr;
   da.cur = cur;
-  da.list_cur = s->list[cur].as<int2>();
-  da.dense_cur = s->dense[cur].as<long long>();
-  da.dense_next = s->dense[nxt].as<long long>();
-  da.rclear = s->rclear.as<int2>();
-  da.list_cap = s->list_cap;
   k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
   k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
   k_hyb_count<<<kStepGrid / 4, kBlock, 0, st>>>(da);

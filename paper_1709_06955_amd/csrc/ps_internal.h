@@ -207,8 +207,6 @@ enum CounterIdx {
   C_PULL_EDGES,  // in-edges read by dense passes
   C_PULL_T,      // dense threshold in out-edges (set by the host)
   C_NEAR,        // Rule 2 tests within 1e-5 relative of the threshold
-  C_RAND,        // slots running randomized probes this step
-  C_RCLEAR,      // last-level candidate marks of randomized probes to clear
   C_NZROWS0,     // rows of dense matrix 0 that may hold a nonzero score
   C_NZROWS1,     // the same for matrix 1
   C_SWITCH,      // deterministic probes switched to randomized ones (Section 4.4)
@@ -241,7 +239,6 @@ struct Session {
   DevBuf mat[2], rowmap[2], npart, lane_slot, dense_ver;  // dense frontier lanes
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring, ring_k;
-  DevBuf rclear;  // (slot, node) marks of randomized probes' last levels, allocated on first use
   // Section 4.4: out-edges of dense-lane frontiers (per slot), and per tree
   // node the walks through it (t_walks[t_woff[t] - weight .. t_woff[t]))
   DevBuf hyb_edges, t_woff, t_walks, wcount;
