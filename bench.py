@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "cl_1m_10m"
 C, EPS, DELTA = 0.6, 0.05, 0.01
 NQ = 32
-HYBRID_C0 = 0.03  # switch constant of Section 4.4 for the hybrid pass (the library's default)
+HYBRID_C0 = 0.003  # switch constant of Section 4.4 for the hybrid pass (the library's default)
 
 
 def expand_bytes(st: dict) -> float:

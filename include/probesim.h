@@ -155,7 +155,7 @@ typedef struct ps_options {
                          all nodes instead of pushing along its out-edges (same
                          sums, other order); 0: automatic, < 0: never */
   double hybrid_c0;   /* the constant c0 of PS_PROBE_HYBRID (>= 0, infinity
-                         allowed; the paper gives no value): default 0.03,
+                         allowed; the paper gives no value): default 0.003,
                          the fastest of 0.001..1 on power-law graphs */
 } ps_options;
 

@@ -93,7 +93,7 @@ extern "C" void ps_options_default(ps_options* o) {
   o->eps_p = -1.0;
   o->walk_begin = 0;
   o->walk_end = -1;
-  o->hybrid_c0 = 0.03;  // fastest measured on power-law graphs; the paper leaves c0 open
+  o->hybrid_c0 = 0.003;  // fastest measured on power-law graphs; the paper leaves c0 open
 }
 
 // Alg. 1 (number of walks), Rule 1 (truncation), Theorem 2 (error split).
