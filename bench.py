@@ -166,6 +166,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the plain-versus-batched passes at eps = 0.1")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the passes with randomized PROBE and with the switch of Section 4.4")
     ap.add_argument("--hybrid-c0", type=float, default=HYBRID_C0)
@@ -255,9 +256,9 @@ def main():
 
     # Smaller queries (eps = 0.1, about a quarter of the walks): one query no
     # longer keeps every probe slot busy to its end, which batching recovers.
-    small = {"eps": 0.1}
+    small = None if args.no_small else {"eps": 0.1}
     qsmall = [dict(u=int(u), k=0, c=C, eps=0.1, delta=DELTA, seed=3 + i, **mode_kw) for i, u in enumerate(q)]
-    for rep_ in range(2):  # the first pass is a warm-up
+    for rep_ in range(0 if args.no_small else 2):  # the first pass is a warm-up
         torch.cuda.synchronize()
         ts = time.perf_counter()
         for i, u in enumerate(q):
@@ -269,8 +270,9 @@ def main():
         ps.ps_batch(G, qsmall, outs=outs, slots=args.slots, pull_edges=args.pull)
         torch.cuda.synchronize()
         small["batched_qps"] = len(q) / (time.perf_counter() - ts)
-    small["batched_speedup"] = small["batched_qps"] / small["plain_qps"]
-    print(f"eps 0.1: {small}", file=sys.stderr, flush=True)
+    if small is not None:
+        small["batched_speedup"] = small["batched_qps"] / small["plain_qps"]
+        print(f"eps 0.1: {small}", file=sys.stderr, flush=True)
 
     # The paper's other probes on the same queries, one pass each (reported
     # beside the metric, which is the deterministic path).
