@@ -339,7 +339,11 @@ typedef struct ps_server_cfg {
   int32_t max_inflight;   /* queries admitted on the device at once (0: 64) */
   int32_t slots;          /* probe slots (0: the graph's autotuned setting, else automatic) */
   int32_t reserved;
-  int64_t frontier_bytes; /* device memory budget for admitted queries (0: automatic) */
+  int64_t frontier_bytes; /* device memory budget for the queries admitted at once
+                             (0: none beyond max_inflight): each takes 8 * n bytes of
+                             FP64 accumulators and about 92 MB of tree and ring space;
+                             the budget lowers max_inflight to what fits (at least one),
+                             and further queries wait in the request ring */
   const ps_options* defaults; /* nullable: options every served query runs with (the
                                  error split, probe mode and its c0, bias shift), copied
                                  at start; a query's own nonzero probe_mode (and then its

@@ -441,13 +441,22 @@ extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_s
   s->cfg.defaults = nullptr;  // the caller's struct is not kept
   if (s->cfg.ring <= 0) s->cfg.ring = 1024;
   if (s->cfg.max_inflight <= 0) s->cfg.max_inflight = 64;
+  // tree pool / ring sized for max_inflight queries of up to ~1M tree nodes
+  const uint64_t per_q = 1ull << 21;
+  if (s->cfg.frontier_bytes > 0) {
+    // device memory of one admitted query: its FP64 accumulators and its
+    // share of the tree pool (key, five int32 node fields, walk offset and
+    // walk list per entry) and of the ring; the budget caps how many are
+    // admitted at once (at least one), the others wait in the request ring
+    const uint64_t each = 8ull * (uint64_t)g->n + 40ull * per_q + 4ull * per_q;
+    const uint64_t fit = std::max<uint64_t>((uint64_t)s->cfg.frontier_bytes / each, 1);
+    s->cfg.max_inflight = (int32_t)std::min<uint64_t>((uint64_t)s->cfg.max_inflight, fit);
+  }
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
     ps_status st = PS_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) st = PS_ERR_DEVICE;
     const int P = session_slots_for(g->n, s->cfg.slots ? s->cfg.slots : g->tuned_slots);
-    // tree pool / ring sized for max_inflight queries of up to ~1M tree nodes
-    const uint64_t per_q = 1ull << 21;
     const uint64_t pool = std::max<uint64_t>((uint64_t)s->cfg.max_inflight * per_q, 1ull << 22);
     if (st == PS_OK)
       st = session_ensure(ctx, g->n, std::max<uint64_t>(g->cur->out_store->cap, 1), P, s->cfg.max_inflight, pool,

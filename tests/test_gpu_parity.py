@@ -626,6 +626,23 @@ def test_server_defaults_apply_to_every_query(ps, ctx, cl20k):
         ps.Server(G, walk_end=100)
 
 
+def test_server_tiny_memory_budget_queues(ps, ctx, cl20k):
+    # A device memory budget smaller than one query still admits one query at
+    # a time: the others wait in the ring and every result equals the query
+    # run alone.
+    n, s, d, G, O = cl20k
+    qn = [int(u) for u in graphs.query_nodes(n, d, 4, seed=111)]
+    srv = ps.Server(G, frontier_bytes=1)
+    try:
+        t = [srv.submit(u, 0.6, 0.1, 0.01, 21 + i) for i, u in enumerate(qn)]
+        got = [srv.wait(x, timeout_us=60_000_000) for x in t]
+    finally:
+        srv.stop()
+    for i, u in enumerate(qn):
+        a = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 21 + i)
+        _same_query(got[i], 0.0, a, 0.0, f"served under a tiny budget u={u}")
+
+
 def test_server_busy_and_stop(ps, ctx):
     src = np.array([0, 1, 2, 3], np.int32)
     dst = np.array([1, 2, 3, 0], np.int32)
