@@ -657,3 +657,41 @@ def test_guarantee_holds_for_other_splits_of_theorem2(orc):
             for precision in ("f64", "f32"):
                 est, _ = orc.batch(G, 0, p, seed, precision=precision)
                 assert np.abs(est - S[0]).max() <= eps
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_randomized_probe_selection_on_the_drawn_visit(orc, seed):
+    # Alg. 4 selects a candidate v when its one drawn in-neighbour x* is in
+    # H_j and its sqrt(c) coin succeeds.  The draw depends on v alone, so the
+    # same sets come out when v is tested only on the visit along x* -> v from
+    # a member x (select iff x* == x and the coin succeeds): that visit
+    # happens exactly when x* is a member.  Recomputed here in plain Python
+    # from the paper's draw and compared with the oracle's literal Alg. 4.
+    n, c, key_seed = 20, 0.6, 1234 + seed
+    src, dst = refs.random_graph(n, 0.3, 50 + seed)
+    G = orc.Graph(n, src, dst)
+    ins, outs = refs.in_lists(n, src, dst), refs.out_lists(n, src, dst)
+    key = (key_seed & 0xFFFFFFFF, ((key_seed >> 32) ^ 0x9E3779B9) & 0xFFFFFFFF)
+    t_sc = math.floor(math.sqrt(c) * 2 ** 32)
+    rng = np.random.default_rng(seed)
+    for k in range(40):
+        i = int(rng.integers(2, 6))
+        path = [int(x) for x in rng.integers(0, n, size=i)]
+        H = {path[-1]}
+        for j in range(i - 1):
+            excl = path[i - j - 2]
+            nxt = set()
+            for x in sorted(H):
+                for v in outs[x]:
+                    if v == excl:
+                        continue
+                    w = orc.philox((k, (i << 16) | j, v, 1), key)
+                    r = (int(w[1]) << 32) | int(w[0])
+                    drawn = ins[v][(r * len(ins[v])) >> 64]
+                    if drawn == x and int(w[2]) < t_sc:
+                        nxt.add(v)
+            H = nxt
+        want = orc.rprobe(G, path, c, key_seed, k)
+        got = np.zeros(n)
+        got[list(H)] = 1.0
+        assert np.array_equal(got, want), (path, k)
