@@ -35,12 +35,13 @@ def expand_bytes(st: dict) -> float:
     """Algorithmic bytes moved by k_expand for the given work counters:
     28 B per expanded entry (list entry 8, scaled score 4, row start/len 8,
     clearing its 8-byte grid sum),
-    8 B per scanned out-edge (neighbour id 4, 1/|I(v)| 4),
+    8 B per pushed out-edge (neighbour id 4, 1/|I(v)| 4; levels moved to the
+    dense pass or switched are not pushed),
     16 B per inner-level contribution (64-bit grid sum read-modify-write),
     8 B per new next-level entry (list write),
     16 B per final contribution (FP64 estimate read-modify-write)."""
-    F, E = st["entries_expanded"], st["edges_scanned"]
-    N, Fin = st["next_entries"], st["final_adds"]
+    F, E = st["entries_expanded"], st["pushed_edges"]
+    N, Fin = st["next_entries"], st["pushed_final_adds"]
     inner = max(E - Fin, 0)
     return 28.0 * F + 8.0 * E + 16.0 * inner + 8.0 * N + 16.0 * Fin
 
@@ -231,7 +232,8 @@ def main():
 
     for _ in range(args.warmup):
         plain_step(None, "warmup")
-    keys = ["expand_ms", "pull_ms", "pull_levels", "pull_edges", "expand_launches", "entries_expanded", "edges_scanned", "next_entries", "final_adds",
+    keys = ["expand_ms", "pull_ms", "pull_levels", "pull_edges", "expand_launches", "entries_expanded", "edges_scanned",
+            "pushed_edges", "next_entries", "final_adds", "pushed_final_adds",
             "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned"]
     acc = {k: 0 for k in keys}
     torch.cuda.synchronize()

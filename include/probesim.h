@@ -328,6 +328,9 @@ typedef struct ps_stats {
   int64_t level_hist_count[32];
   int64_t level_hist_edges[32];
   int64_t switched_probes;  /* PS_PROBE_HYBRID: tree-node probes that switched */
+  int64_t pushed_edges;     /* edges_scanned less those of levels pulled or switched instead
+                               of pushed: the out-edges the push kernel visits */
+  int64_t pushed_final_adds; /* final_adds made by the push kernel (the rest by pulls) */
 } ps_stats;
 
 ps_status ps_get_stats(ps_ctx* ctx, ps_stats* out);

@@ -722,6 +722,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
       if (S.lane >= 0) atomicMax(&s_fhi, (uint32_t)S.lane + 1u);
       switch_probe(a, S);
       flag = 2;
+      if (e) atomicAdd(&ctr[C_EDGES_UNPUSHED], e);  // k_prep counted them
       e = 0;
     }
     if (e) {
@@ -738,6 +739,7 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
             S.lane = lane;
             a.lane_slot[lane] = s;
             flag = 1;
+            atomicAdd(&ctr[C_EDGES_UNPUSHED], e);  // pulled, not pushed
           }
         }
       }
@@ -1218,7 +1220,7 @@ __global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   nfinal = wave_sum(nfinal);
   if (g == 0) {
-    if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
+    if (nfinal) atomicAdd(&a.ctr[C_FINAL_PULL], nfinal);
     if (inedges) atomicAdd(&a.ctr[C_PULL_EDGES], inedges);
   }
   __syncthreads();
@@ -1254,7 +1256,7 @@ __global__ void __launch_bounds__(kBlock) k_dense_fin(DenseArgs a) {
   if (g == 0 && nz_mask) atomicOr(&s_nz, nz_mask);
   if (g == 0 && nzrows) atomicAdd(&a.ctr[C_NZROWS0 + (a.cur ^ 1)], nzrows);
   nfinal = wave_sum(nfinal);
-  if (g == 0 && nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
+  if (g == 0 && nfinal) atomicAdd(&a.ctr[C_FINAL_PULL], nfinal);
   __syncthreads();
   if (tid < kLanes && ((s_nz >> tid) & 1ull)) a.has_next[a.lane_slot[tid]] = 1;
 }
@@ -2105,7 +2107,9 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   stats.entries_pruned = (int64_t)(h[C_PRUNED] - before[C_PRUNED]);
   stats.edges_scanned = (int64_t)(h[C_EDGES] - before[C_EDGES]);
   stats.next_entries = (int64_t)(h[C_NEXT] - before[C_NEXT]);
-  stats.final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL]);
+  stats.final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL] + h[C_FINAL_PULL] - before[C_FINAL_PULL]);
+  stats.pushed_final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL]);
+  stats.pushed_edges = stats.edges_scanned - (int64_t)(h[C_EDGES_UNPUSHED] - before[C_EDGES_UNPUSHED]);
   stats.expand_launches = (int64_t)total_steps;
   stats.pull_levels = (int64_t)(h[C_PULLS] - before[C_PULLS]);
   stats.pull_edges = (int64_t)(h[C_PULL_EDGES] - before[C_PULL_EDGES]);

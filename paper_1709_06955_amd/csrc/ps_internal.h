@@ -211,6 +211,8 @@ enum CounterIdx {
   C_NZROWS1,     // the same for matrix 1
   C_SWITCH,      // deterministic probes switched to randomized ones (Section 4.4)
   C_HYBMASK,     // dense columns whose next level k_hyb_count measures (bit per column)
+  C_EDGES_UNPUSHED,  // out-edges counted by k_prep of levels k_expand does not push (pulled or switched)
+  C_FINAL_PULL,  // final contributions added by the dense pass
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
   C_COUNT = C_HIST_E + 32

@@ -675,8 +675,10 @@ def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
     st = ctx.stats()
     if pull == 1:
         assert st["pull_levels"] > 0 and st["pull_edges"] > 0
+        assert st["pushed_edges"] < st["edges_scanned"] and st["pushed_final_adds"] < st["final_adds"]
     if pull == -1:
         assert st["pull_levels"] == 0
+        assert st["pushed_edges"] == st["edges_scanned"] and st["pushed_final_adds"] == st["final_adds"]
     ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f32")
     _parity(gpu, ref, ost, f"pull_edges={pull}")
 
