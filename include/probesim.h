@@ -157,7 +157,26 @@ typedef struct ps_options {
   double hybrid_c0;   /* the constant c0 of PS_PROBE_HYBRID (>= 0, infinity
                          allowed; the paper gives no value): default 0.003,
                          the fastest of 0.001..1 on power-law graphs */
+  int32_t rule2_bound; /* which per-probe error of Pruning Rule 2 the default
+                         eps_p (and ps_tune_split's candidates) are derived
+                         from in Theorem 2's inequality.  PS_RULE2_AS_STATED
+                         (default): the paper's lemma, eps_p per probe, so the
+                         pruning term is (1 + eps_s) / (1 - sqrt c) * eps_p
+                         (E[l] = 1/(1 - sqrt c) probes per walk).
+                         PS_RULE2_PROVEN: the bound the lemma's induction
+                         gives when the pruned node's own score is kept,
+                         (i - 1) * eps_p for a probe of depth i, so a walk of
+                         l nodes loses at most l(l-1)/2 * eps_p and the term
+                         is (1 + eps_s) * sqrt(c) / (1 - sqrt c)^2 * eps_p
+                         (E[l(l-1)/2] = sqrt(c) / (1 - sqrt c)^2 for
+                         geometric lengths; truncation and dead ends only
+                         shorten walks): about 3.4x smaller eps_p at c = 0.6,
+                         more work, a proven guarantee. */
+  int32_t pad;
 } ps_options;
+
+#define PS_RULE2_AS_STATED 0
+#define PS_RULE2_PROVEN 1
 
 #define PS_MAX_WALK_LEN 64
 #define PS_PROBE_DETERMINISTIC 0
@@ -178,7 +197,9 @@ typedef struct ps_params {
 /* Derives the query parameters for a graph of n nodes.  Default split of the
  * absolute error eps (Definition 1) into sampling, truncation and pruning
  * error satisfies Theorem 2 with the optional shift off:
- *   eps_s = eps/2, eps_t = eps/4, eps_p = (eps/4)(1 - sqrt c)/(1 + eps_s).
+ *   eps_s = eps/2, eps_t = eps/4, eps_p = (eps/4)(1 - sqrt c)/(1 + eps_s)
+ * (with opt->rule2_bound = PS_RULE2_PROVEN instead
+ *   eps_p = (eps/4)(1 - sqrt c)^2 / ((1 + eps_s) sqrt c)).
  * PS_ERR_INVALID_ARG for c, eps, delta outside (0,1), for L < 2 or
  * L > PS_MAX_WALK_LEN. */
 ps_status ps_derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt,
@@ -283,8 +304,10 @@ ps_status ps_autotune(ps_graph* g, int32_t nsample, const int32_t* nodes, double
  * 1/256} (those whose parameters are valid: L within PS_MAX_WALK_LEN), with
  * eps_p taking the rest of the inequality of Theorem 2:
  *   eps_s + (1 + eps_s) / (1 - sqrt c) * eps_p + eps_t' = eps
- * (eps_t' = eps_t / 2 when opt->bias_shift is set, Section 4.1; else eps_t).
- * Every candidate keeps the guarantee of Definition 1.  The nsample query
+ * (eps_t' = eps_t / 2 when opt->bias_shift is set, Section 4.1; else eps_t;
+ * with opt->rule2_bound = PS_RULE2_PROVEN the pruning term is
+ * (1 + eps_s) sqrt(c) / (1 - sqrt c)^2 * eps_p).  Every candidate meets
+ * Theorem 2 under the chosen bound.  The nsample query
  * nodes `nodes` (host array) are timed under each (one untimed run first)
  * with the rest of *opt as given (probe mode, slots, ...), and the fastest
  * split is written into opt->eps_s, eps_t and eps_p.  The estimates change

@@ -12,8 +12,8 @@
 //   orc_params_derive   Alg. 1 (number of trials), Pruning Rule 1 (walk
 //                       truncation), Theorem 2 (error split)
 //   orc_philox4x32_10   Philox4x32-10 of Salmon et al., SC'11 (the paper leaves
-//                       the random source open; parity unpinned against an
-//                       external known-answer table, which is not available)
+//                       the random source open); pinned bit for bit against
+//                       rocRAND's independent header-only engine
 //   orc_walk            Definition of the sqrt(c)-walk (Section 2.2)
 //   orc_probe           Alg. 2 (deterministic PROBE) with Pruning Rule 2, in
 //                       FP64 or in the FP32 score model below

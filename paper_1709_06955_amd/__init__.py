@@ -28,6 +28,7 @@ PS_MAX_WALK_LEN = 64
 
 # Every entry point declared in include/probesim.h.
 PROBE_DETERMINISTIC, PROBE_RANDOMIZED, PROBE_HYBRID = 0, 1, 2
+RULE2_AS_STATED, RULE2_PROVEN = 0, 1
 
 EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
@@ -52,6 +53,7 @@ class Options(C.Structure):
         ("walk_begin", C.c_int64), ("walk_end", C.c_int64),
         ("slots", C.c_int32), ("probe_mode", C.c_int32),
         ("pull_edges", C.c_int64), ("hybrid_c0", C.c_double),
+        ("rule2_bound", C.c_int32), ("pad", C.c_int32),
     ]
 
 

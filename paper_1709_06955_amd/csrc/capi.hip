@@ -96,6 +96,15 @@ extern "C" void ps_options_default(ps_options* o) {
   o->hybrid_c0 = 0.003;  // fastest measured on power-law graphs; the paper leaves c0 open
 }
 
+// Theorem 2's pruning term is (1 + eps_s) * eps_p / factor: the expected
+// number of probes per walk, 1 / (1 - sqrt c), times eps_p per probe as the
+// paper's Rule 2 lemma states; or E[l(l-1)/2] = sqrt(c) / (1 - sqrt c)^2
+// times eps_p under the per-probe bound (i - 1) * eps_p that the lemma's
+// induction gives with the pruned node's own score kept.
+static double rule2_factor(double sc, int32_t bound) {
+  return bound == PS_RULE2_PROVEN ? (1.0 - sc) * (1.0 - sc) / sc : 1.0 - sc;
+}
+
 // Alg. 1 (number of walks), Rule 1 (truncation), Theorem 2 (error split).
 ps_status derive_params(int32_t n, double c, double eps, double delta, const ps_options* opt, ps_params* p) {
   if (!p || n <= 0) return PS_ERR_INVALID_ARG;
@@ -109,7 +118,8 @@ ps_status derive_params(int32_t n, double c, double eps, double delta, const ps_
   p->delta = delta;
   p->eps_s = opt->eps_s >= 0.0 ? opt->eps_s : eps / 2.0;
   p->eps_t = opt->eps_t >= 0.0 ? opt->eps_t : eps / 4.0;
-  p->eps_p = opt->eps_p >= 0.0 ? opt->eps_p : (eps / 4.0) * (1.0 - sc) / (1.0 + p->eps_s);
+  if (opt->rule2_bound != PS_RULE2_AS_STATED && opt->rule2_bound != PS_RULE2_PROVEN) return PS_ERR_INVALID_ARG;
+  p->eps_p = opt->eps_p >= 0.0 ? opt->eps_p : (eps / 4.0) * rule2_factor(sc, opt->rule2_bound) / (1.0 + p->eps_s);
   if (!(p->eps_s > 0.0) || !(p->eps_t > 0.0 && p->eps_t < 1.0)) return PS_ERR_INVALID_ARG;
   const double nr = std::ceil(3.0 * c * std::log((double)n / delta) / (p->eps_s * p->eps_s));
   if (!(nr >= 1.0) || nr > 2147483647.0) return PS_ERR_INVALID_ARG;
@@ -312,7 +322,7 @@ extern "C" ps_status ps_tune_split(ps_graph* g, int32_t nsample, const int32_t* 
       ps_options o = *opt;
       o.eps_s = es;
       o.eps_t = et;
-      o.eps_p = rest * (1.0 - sc) / (1.0 + es);
+      o.eps_p = rest * rule2_factor(sc, opt->rule2_bound) / (1.0 + es);
       ps_params prm;
       if (derive_params(g->n, c, eps, delta, &o, &prm) != PS_OK) continue;  // e.g. L beyond the cap
       cands.push_back({es, et, o.eps_p});

@@ -4,12 +4,12 @@ This module holds input generation only: graphs, query nodes and update
 streams.  It contains none of ProbeSim's arithmetic (no walks, no probes, no
 scores), so both sides can draw the same inputs without sharing method code.
 
-The paper evaluates on public SNAP/LAW graphs (Section 5, Table 3: Wiki-Vote,
+The paper evaluates on public SNAP/LAW graphs (Section 6, Table 3: Wiki-Vote,
 HepTh, AS, HepPh, LiveJournal, IT-2004, Twitter, Friendster).  None of them is
 available here, so seeded synthetic graphs with the same character stand in:
 a directed Erdos-Renyi graph for the small exact-ground-truth case and directed
 Chung-Lu graphs with power-law in/out degrees for the large cases, with query
-nodes drawn uniformly from the nodes of nonzero in-degree as in Section 5.1.
+nodes drawn uniformly from the nodes of nonzero in-degree as in Section 6.1.
 """
 
 from __future__ import annotations
@@ -130,7 +130,7 @@ def in_degrees(n: int, dst: np.ndarray) -> np.ndarray:
 
 def query_nodes(n: int, dst: np.ndarray, count: int, seed: int = 2) -> np.ndarray:
     """Query nodes drawn uniformly (without replacement) from the nodes of
-    nonzero in-degree, as the paper's experiments do (Section 5.1)."""
+    nonzero in-degree, as the paper's experiments do (Sections 6.1 and 6.2)."""
     rng = _rng(seed, 3)
     cand = np.nonzero(in_degrees(n, dst) > 0)[0]
     count = min(count, cand.size)

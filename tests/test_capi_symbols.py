@@ -61,6 +61,31 @@ def test_params_agree_with_oracle(orc):
         assert a.eps_p == b.eps_p and a.eps_s == b.eps_s and a.eps_t == b.eps_t
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_proven_rule2_split(orc):
+    # PS_RULE2_PROVEN derives the default eps_p from the corrected per-probe
+    # bound of Rule 2, (i - 1) * eps_p: Theorem 2's pruning term becomes
+    # (1 + eps_s) * E[l(l-1)/2] * eps_p with E[l(l-1)/2] = sqrt(c)/(1-sqrt c)^2
+    # for geometric walk lengths, which the inequality meets with equality.
+    import math
+
+    import paper_1709_06955_amd as ps
+
+    c, eps = 0.6, 0.05
+    sc = math.sqrt(c)
+    a = ps.derive_params(10**6, c, eps, 0.01, rule2_bound=ps.RULE2_PROVEN)
+    b = ps.derive_params(10**6, c, eps, 0.01)
+    assert (a.n_r, a.L) == (b.n_r, b.L)
+    lhs = a.eps_s + (1 + a.eps_s) * sc / (1 - sc) ** 2 * a.eps_p + a.eps_t
+    assert abs(lhs - eps) <= 1e-15
+    assert 3.3 < b.eps_p / a.eps_p < 3.5
+    # E[l(l-1)/2] of the geometric law P(l) = sc^(l-1) (1 - sc), l >= 1
+    mean = sum(l * (l - 1) / 2 * sc ** (l - 1) * (1 - sc) for l in range(1, 4000))
+    assert abs(mean - sc / (1 - sc) ** 2) <= 1e-9
+    with pytest.raises(ps.ProbeSimError):
+        ps.derive_params(1000, c, eps, 0.01, rule2_bound=2)
+
+
 STRUCTS = {"ps_options": "Options", "ps_params": "Params", "ps_stats": "Stats", "ps_query": "Query",
            "ps_result": "Result", "ps_tune": "Tune", "ps_server_cfg": "ServerCfg",
            "ps_split": "Split"}

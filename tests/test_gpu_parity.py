@@ -361,7 +361,7 @@ def test_accuracy_against_power_method(ps, ctx, er):
     # delta = 1e-4 per query, so the 18 queries here fail together with
     # probability below 0.2 %), and the top-k list within 2 eps of the true
     # i-th value at every rank (what sorting eps-accurate estimates gives).
-    # Section 5's Precision@k, NDCG@k and tau_k are printed for context.
+    # Section 6's Precision@k, NDCG@k and tau_k are printed for context.
     from oracle import refs
 
     from tests import topk_metrics as tm

@@ -607,7 +607,7 @@ def test_hybrid_guarantee_against_power_method(orc):
 
 
 def test_topk_measures_on_known_lists():
-    # Section 5's measures on hand-made cases: the ground truth scores 1 on
+    # Section 6's measures on hand-made cases: the ground truth scores 1 on
     # all three; a reversed list keeps precision and loses the ranking
     # (tau = -1); a disjoint list scores 0 precision; NDCG falls below 1 when
     # lower-valued nodes replace higher ones.

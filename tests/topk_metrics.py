@@ -1,4 +1,4 @@
-"""Top-k accuracy measures of the paper's experiments (Section 5, top-k
+"""Top-k accuracy measures of the paper's experiments (Section 6, top-k
 queries), for evaluating results against ground-truth SimRank values.
 TEST INFRASTRUCTURE.
 
