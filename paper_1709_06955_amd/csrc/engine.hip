@@ -42,6 +42,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "ps_internal.h"
@@ -49,16 +50,30 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kSchedThreads = 1024;
-constexpr int kSlotsPerSchedThread = 4;  // P <= 4096
-constexpr uint32_t kBigDeg = 1024;       // longer rows: one wavefront per kChunk edges
+constexpr int kSchedBlock = 256;         // k_sched: one thread per slot
+constexpr int kPickThreads = 1024;       // k_pick: one workgroup
+constexpr int kThreads = 1024;           // k_expand and k_reduce workgroups
+constexpr int kExpGrid = 256;            // k_expand workgroups (one per CU); segments per bin
+constexpr int kRedGrid = 256;            // k_reduce workgroups
+constexpr int kTile = kThreads;          // listed entries per tile in k_expand (one per thread)
+constexpr uint32_t kBigDeg = 256;        // longer out-rows: one wavefront per kChunk edges
 constexpr uint32_t kChunk = 512;
 constexpr uint32_t kBigFlag = 0x80000000u;
-constexpr int kTile = 1024;              // listed entries per workgroup tile in k_expand
-constexpr int kWaveBuf = 512;            // staged new frontier entries per wavefront
+constexpr int kMaxBins = 16384;          // record bins of a step: node ranges of 2^sh nodes
+constexpr uint32_t kBinRecords = 8192;   // records per bin a step's bin width aims at
+constexpr int kPartRows = 16;            // rows of per-slot partial sums (workgroups add into row wg % 16)
+constexpr uint64_t kStepRecords = (uint64_t)kMaxBins * kBinRecords;  // records a step may write
+constexpr int kMaxSh = 20;               // bin width limit: slot ids keep 12 bits of a key
+constexpr int kTblBits = 13;             // LDS hash table of k_reduce: 2^13 (key, sum) pairs
+constexpr uint32_t kTbl = 1u << kTblBits;
+constexpr int kMaxProbe = 64;            // linear-probe steps before a slice splits
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+constexpr int kMaxSlots = 2048;          // LDS arrays are sized for this many slots
+constexpr int kSlotCap = 2000;           // slot ids stay below it, so no key equals kNoKey
+constexpr int kWaveStage = 128;          // listed entries a wavefront of k_reduce stages in LDS
 constexpr int kLanes = 64;               // dense frontier columns (one wavefront lane each)
 constexpr unsigned long long kEmpty = ~0ull;
-constexpr int kStepGrid = 2048;          // 8 workgroups per CU for the step kernels
+constexpr int kStepGrid = 2048;          // 8 workgroups per CU for the dense kernels
 
 // ------------------------------------------------------------- Philox ----
 
@@ -347,6 +362,9 @@ __global__ void k_fill(T* p, T v, uint64_t cnt) {
 
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 
+// Publishes the probes queued so far to the next k_sched.
+__global__ void k_snap_tail(unsigned long long* ctr) { ctr[C_TAIL_SNAP] = ctr[C_TAIL]; }
+
 __global__ void k_reset_slots(Slot* slots, int32_t* has_next, int P) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= P) return;
@@ -357,33 +375,176 @@ __global__ void k_reset_slots(Slot* slots, int32_t* has_next, int P) {
   has_next[s] = 0;
 }
 
-// Graph version whose in-rows the dense pass reads (all dense lanes share it).
-struct DenseVer {
-  const uint2* out_rows;  // out-degrees of the targets (Section 4.4 counts)
-  const uint2* in_rows;
-  const int32_t* in_col;
-  const float* inv_indeg;
-  const int32_t* heavy_nodes;
-  const int2* heavy_chunks;
-  const unsigned long long* heavy_cnt;
-};
-
 __global__ void k_reset_lanes(int32_t* lane_slot) {
   if (threadIdx.x < kLanes) lane_slot[threadIdx.x] = -1;
 }
 
 // ------------------------------------------------------- level steps ----
-
+//
 // Probe scores.  The scores of inner levels are FP32 numbers.  The
 // contributions that make up a level are summed exactly, as 64-bit integers
-// on the grid 2^-62 (a level's scores never exceed 1), so no order of atomic
-// adds changes a bit; a level's FP32 score is its sum rounded to nearest.
-// Rule 2 then compares FP32 numbers only, and the same query gives the same
-// result alone, in a batch, pushed or pulled.
+// on the grid 2^-62 (a level's scores never exceed 1), so no order of adds
+// changes a bit; a level's FP32 score is its sum rounded to nearest.  Rule 2
+// then compares FP32 numbers only, and the same query gives the same result
+// alone, in a batch, pushed or pulled.
+//
+// Frontier lists.  The entries of every probe level about to be expanded
+// (Rule 2 already applied) form one list of (slot, node) pairs with the
+// node's FP32 score and out-row; lists alternate between two buffers by step
+// parity.  An out-row longer than kBigDeg edges also gets chunks of kChunk
+// edges in a chunk list, so that one wavefront takes each chunk (best effort:
+// when the chunk list is full the row is expanded whole).
+//
+// A step.  k_sched advances, retires and assigns slots, lists the H_0 of new
+// probes and takes the switch of Section 4.4; k_pick (only when levels may be
+// pulled) moves large levels to dense columns.  k_expand pushes every listed
+// entry along its out-edges: the contribution to (slot s, node v) becomes an
+// 8-byte record in the bin of v's node range; each workgroup first counts
+// its records per bin, so it writes them to exact, contiguous places.
+// k_reduce sums each bin's records per (s, v) exactly in an LDS hash table,
+// then applies Rule 2 to the next level and lists its survivors, or, on a
+// probe's last level, adds weight * sum to the FP64 estimate.  No per-slot
+// vector of n scores exists and no device-scope atomic is made per edge.
 __device__ __forceinline__ long long to_grid(float c) { return __float2ll_rn(c * 0x1p62f); }
 __device__ __forceinline__ float grid_f32(long long q) { return __ll2float_rn(q) * 0x1p-62f; }
 __device__ __forceinline__ double grid_f64(long long q) { return (double)q * 0x1p-62; }
-constexpr long long kGridOne = 1ll << 62;
+
+// Bijective mix of a 32-bit key (the MurmurHash3 finaliser): its low bits
+// split a bin into slices, its high bits place a key in the LDS table.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+struct FList {
+  int2* sn;     // (slot, node)
+  float* val;   // the node's FP32 score (unused by randomized probes)
+  uint2* row;   // its out-row: start, length | kBigFlag when chunked
+  int2* chunk;  // (entry position, chunk index) of chunked rows; entry -1: empty
+  unsigned long long* n_ent;    // kSubLists counters
+  unsigned long long* n_chunk;  // kSubLists counters
+  uint64_t sub_cap, sub_chunk_cap;  // places of one sub-list; sub-list k starts at k * sub_cap
+};
+
+__device__ __forceinline__ int wave_sublist() {
+  return (int)(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) & (kSubLists - 1));
+}
+
+// Writes n entries (at most 128, two per lane) to the wavefront's sub-list:
+// entry i is (sn[i], h[i]) with out-row rowp[i]; rows longer than kBigDeg get
+// chunks when the chunk sub-list has room.  One atomic for the entries and
+// one for the chunks.  Every lane of the wavefront takes part.
+__device__ void wave_write(int n, const int2* sn, const float* h, const uint2* rowp, const FList& L,
+                           unsigned long long* ctr) {
+  const int lane = lane_id();
+  const int k = wave_sublist();
+  uint2 row[2];
+  uint32_t nch[2], mine = 0;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int i = lane + 64 * j;
+    row[j] = make_uint2(0u, 0u);
+    nch[j] = 0;
+    if (i < n) {
+      row[j] = rowp[i];
+      nch[j] = row[j].y > kBigDeg ? (row[j].y + kChunk - 1) / kChunk : 0u;
+      mine += nch[j];
+    }
+  }
+  const uint32_t incl = wave_incl_scan(mine);
+  const uint32_t tot = __shfl(incl, 63, 64);
+  unsigned long long eb = 0, cb = 0;
+  if (lane == 0) {
+    eb = atomicAdd(&L.n_ent[k], (unsigned long long)n);
+    if (tot) cb = atomicAdd(&L.n_chunk[k], (unsigned long long)tot);
+  }
+  eb = __shfl(eb, 0, 64);
+  cb = __shfl(cb, 0, 64);
+  const bool room = cb + tot <= L.sub_chunk_cap;
+  uint32_t c = incl - mine;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int i = lane + 64 * j;
+    if (i >= n) break;
+    const unsigned long long off = eb + (unsigned long long)i;
+    const bool fits = off < L.sub_cap;
+    const unsigned long long pos = (unsigned long long)k * L.sub_cap + off;
+    for (uint32_t q = 0; q < nch[j]; ++q, ++c) {
+      const unsigned long long cq = cb + c;
+      if (room && fits) L.chunk[(unsigned long long)k * L.sub_chunk_cap + cq] = make_int2((int32_t)pos, (int32_t)q);
+      else if (cq < L.sub_chunk_cap) L.chunk[(unsigned long long)k * L.sub_chunk_cap + cq] = make_int2(-1, 0);
+    }
+    if (fits) {
+      L.sn[pos] = sn[i];
+      L.val[pos] = h[i];
+      L.row[pos] = make_uint2(row[j].x, room && nch[j] ? (row[j].y | kBigFlag) : row[j].y);
+    } else {
+      atomicOr(&ctr[C_OVERFLOW], 4ull);
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wavefront staging of listed entries in LDS: lanes put entries with no
+// global atomic; a flush writes up to kWaveStage of them with one (and one
+// for their chunks) to the wavefront's sub-list.  The wavefront's lanes all
+// take part in every call (loops around the calls are wavefront-uniform).
+struct WaveStage {
+  int2* sn;
+  float* h;
+  uint2* row;
+  int cap;  // at most kWaveStage
+  int n;    // the same value in every lane
+};
+
+__device__ __forceinline__ void stage_flush(WaveStage& ws, const FList& L, unsigned long long* ctr) {
+  if (ws.n == 0) return;
+  wave_sync_lds();
+  wave_write(ws.n, ws.sn, ws.h, ws.row, L, ctr);
+  wave_sync_lds();
+  ws.n = 0;
+}
+
+__device__ __forceinline__ void stage_put(bool want, int32_t s, int32_t v, float h, uint2 row, WaveStage& ws,
+                                          const FList& L, unsigned long long* ctr) {
+  const unsigned long long mask = __ballot(want);
+  if (!mask) return;
+  const int cnt = __popcll(mask);
+  if (ws.n + cnt > ws.cap) stage_flush(ws, L, ctr);
+  if (want) {
+    const int pos = ws.n + __popcll(mask & ((1ull << lane_id()) - 1ull));
+    ws.sn[pos] = make_int2(s, v);
+    ws.h[pos] = h;
+    ws.row[pos] = row;
+  }
+  ws.n += cnt;
+}
+
+// Exclusive scan of one value per thread over the workgroup; returns the
+// prefix and writes the total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* s_wtot, uint32_t* total) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+  const uint32_t incl = wave_incl_scan(x);
+  if (lane == 63) s_wtot[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wv) before += s_wtot[w];
+    tot += s_wtot[w];
+  }
+  *total = tot;
+  __syncthreads();
+  return before + incl - x;
+}
 
 struct SchedArgs {
   int P;
@@ -391,277 +552,43 @@ struct SchedArgs {
   int qmax;
   Slot* slots;
   int32_t* has_next;
-  const int32_t* ring;
-  const int32_t* ring_k;
+  int32_t* pull_flag;  // in: last step's decision (3: paused); out: 0 push, 2 switched
+  uint8_t* was_paused;
+  int32_t* ring;
+  int32_t* ring_k;
   uint64_t ring_mask;
   const int32_t* t_parent;
   const int32_t* t_node;
   const int32_t* t_depth;
   const int32_t* t_query;
   const int32_t* t_weight;
+  const uint32_t* t_woff;
+  const int32_t* t_walks;
   const QueryDev* qr;
   const float* thr_tab;
   unsigned long long* remaining;
   int32_t* done_ring;
-  long long* dense_cur;
-  int2* list_cur;
-  uint64_t list_cap;
-  unsigned long long* slot_edges;
+  unsigned long long* hyb_edges;
   int32_t* lane_slot;
+  uint32_t* part;  // kPartRows rows of partial (edges, entries) per slot of this step's list
+  uint32_t* slot_edges;  // out: out-edges of each slot's listed entries
+  uint32_t* slot_cnt;    // out: its listed entries
+  uint4* cost;           // out: (records, next-list bound, entries, flags) of a pushed level
+  FList list;            // this step's list (new probes' H_0 appended)
+  FList next;            // next step's list (its counters cleared here)
   unsigned long long* ctr;
   int cur;
 };
 
-// One workgroup: advances every slot by one PROBE iteration, retires probes
-// whose last level (i-2) ran or whose frontier Rule 2 emptied, and hands free
-// slots the next pending probes in ring order.  A new probe on (u_1..u_i)
-// starts with H_0 = {u_i: 1}.
-__global__ void __launch_bounds__(kSchedThreads) k_sched(SchedArgs a) {
-  __shared__ uint32_t wave_tot[kSchedThreads / 64];
-  __shared__ unsigned long long s_head, s_avail;
-  const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wv = tid >> 6;
-  if (tid == 0) {
-    a.ctr[C_SMALL] = 0;
-    a.ctr[C_CHUNK] = 0;
-    a.ctr[C_LIST0 + (a.cur ^ 1)] = 0;
-    a.ctr[C_NZROWS0 + (a.cur ^ 1)] = 0;  // k_dense rewrites that matrix this step
-    s_head = a.ctr[C_HEAD];
-    s_avail = a.ctr[C_TAIL] - s_head;
-  }
-  __syncthreads();
-  // Slots are updated field by field in place (a whole Slot per register set
-  // would spill).
-  bool need[kSlotsPerSchedThread];
-  uint32_t cnt = 0;
-#pragma unroll
-  for (int r = 0; r < kSlotsPerSchedThread; ++r) {
-    const int s = tid * kSlotsPerSchedThread + r;
-    need[r] = false;
-    if (s >= a.P) continue;
-    Slot& S = a.slots[s];
-    if (S.probe >= 0) {
-      if (S.last || !a.has_next[s]) {
-        const int q = S.query;
-        if (atomicAdd(&a.remaining[q], ~0ull) == 1ull) {  // last probe of the query
-          const unsigned long long pos = atomicAdd(&a.ctr[C_DONE], 1ull);
-          a.done_ring[pos % (unsigned long long)a.qmax] = q;
-        }
-        if (S.lane >= 0) a.lane_slot[S.lane] = -1;  // dense column free again
-        S.probe = -1;
-        S.lane = -1;
-        need[r] = true;
-      } else {
-        S.level = S.level + 1;
-        S.cursor = a.t_parent[S.cursor];
-      }
-    } else {
-      need[r] = true;
-    }
-    a.has_next[s] = 0;
-    a.slot_edges[s] = 0;
-    cnt += need[r] ? 1u : 0u;
-  }
-  // Exclusive scan of the per-thread counts of free slots.
-  const uint32_t incl = wave_incl_scan(cnt);
-  if (lane == 63) wave_tot[wv] = incl;
-  __syncthreads();
-  uint32_t before = 0, total = 0;
-  for (int w = 0; w < kSchedThreads / 64; ++w) {
-    if (w < wv) before += wave_tot[w];
-    total += wave_tot[w];
-  }
-  unsigned long long rank = before + incl - cnt;
-  const unsigned long long head = s_head, avail = s_avail;
-#pragma unroll
-  for (int r = 0; r < kSlotsPerSchedThread; ++r) {
-    const int s = tid * kSlotsPerSchedThread + r;
-    if (s >= a.P) continue;
-    Slot& S = a.slots[s];
-    if (need[r]) {
-      if (rank < avail) {
-        const uint64_t rp = (head + rank) & a.ring_mask;
-        const int32_t t = a.ring[rp];
-        const int q = a.t_query[t];
-        const QueryDev& Q = a.qr[q];
-        const int32_t wk = a.ring_k[rp];
-        const int mode = wk >= 0;  // a randomized probe of walk wk's prefix
-        const double w = mode ? 1.0 : (double)a.t_weight[t];
-        S.probe = t;
-        S.lane = -1;
-        S.level = 0;
-        S.depth = a.t_depth[t];
-        S.cursor = a.t_parent[t];
-        S.query = q;
-        S.mode = mode;
-        S.wk = mode ? (uint32_t)wk : 0u;
-        S.t_sc = Q.t_sc;
-        S.key2 = Q.key2;
-        S.w = w;
-        S.sc = Q.sc;
-        S.out_rows = Q.out_rows;
-        S.out_col = Q.out_col;
-        S.inv_indeg = Q.inv_indeg;
-        S.acc = Q.acc;
-        S.in_rows = Q.in_rows;
-        S.in_col = Q.in_col;
-        S.heavy_nodes = Q.heavy_nodes;
-        S.heavy_chunks = Q.heavy_chunks;
-        S.heavy_cnt = Q.heavy_cnt;
-        S.flip = Q.flip;
-        S.flip_unit = mode ? 0.0 : Q.flip_unit * w;
-        // Section 4.4: a hybrid query's deterministic probe of weight w
-        // switches past c0 * w * n out-edges
-        S.hyb_thr = !mode && Q.hybrid ? (Q.c0 * w) * (double)a.n : -1.0;
-        const int32_t x = a.t_node[t];
-        const unsigned long long pos = atomicAdd(&a.ctr[C_LIST0 + a.cur], 1ull);
-        if (pos < a.list_cap) {
-          // H_0 = {u_i: 1} (a randomized probe's sets are its lists alone)
-          if (!mode) a.dense_cur[(size_t)s * a.n + x] = kGridOne;
-          a.list_cur[pos] = make_int2(s, x);
-        } else {
-          atomicOr(&a.ctr[C_OVERFLOW], 1ull);
-        }
-        atomicAdd(&a.ctr[C_LEVEL0], 1ull);
-      }
-      ++rank;
-    }
-    const int32_t probe = S.probe;
-    if (probe >= 0) {
-      const int level = S.level, depth = S.depth, q = S.query;
-      const int e = depth - level - 1;  // iterations left, i-j-1 >= 1
-      S.thr = a.thr_tab[q * PS_MAX_WALK_LEN + e];
-      S.thr_next = e > 1 ? a.thr_tab[q * PS_MAX_WALK_LEN + e - 1] : 0.0f;
-      S.excl = a.t_node[S.cursor];
-      S.last = level == depth - 2;
-    }
-  }
-  if (tid == 0) a.ctr[C_HEAD] = head + (total < avail ? total : avail);
-}
-
-// Reads the scores of the listed entries and applies Rule 2 (remove x when
-// Score(x) * sqrt(c)^(i-j-1) <= eps_p, i.e. Score(x) <= thr).  Removed
-// entries and entries without out-edges are cleared at once; the others keep
-// their score in the dense vector (a pulled slot reads it there) and get
-// their out-row and sqrt(c) * Score(x) recorded.  Rows longer than kBigDeg are
-// also cut into kChunk-edge chunks for the wavefront-per-chunk part of
-// k_expand (marked with the top bit of the length so that the tile part skips
-// them).  Per slot, the out-degrees of its kept entries are summed: that
-// decides between pushing and pulling the slot's level.  A randomized probe
-// (Alg. 4) lists exactly the members of its set: they are kept as listed.
-__global__ void __launch_bounds__(kBlock) k_prep(int32_t n, const Slot* __restrict__ slots,
-                                                 const int2* __restrict__ list_cur, long long* __restrict__ dense_cur,
-                                                 float* __restrict__ item_val, uint2* __restrict__ item_row,
-                                                 int2* __restrict__ chunk_list, uint64_t list_cap, uint64_t chunk_cap,
-                                                 unsigned long long* __restrict__ slot_edges,
-                                                 unsigned long long* __restrict__ ctr, int cur) {
-  // after an overflow the counter runs past the list; never read beyond it
-  const unsigned long long cnt = min(ctr[C_LIST0 + cur], (unsigned long long)list_cap);
-  const int lane = lane_id();
-  const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  unsigned long long kept = 0, pruned = 0, edges = 0, near = 0;
-  for (uint64_t i0 = gtid - lane; i0 < cnt; i0 += stride) {
-    const uint64_t i = i0 + lane;
-    uint32_t nch = 0;
-    int32_t myslot = -1;
-    unsigned long long mydeg = 0;
-    if (i < cnt) {
-      const int2 it = list_cur[i];
-      long long* d = dense_cur + (size_t)it.x * n + it.y;
-      const Slot& sl = slots[it.x];
-      uint2 row = make_uint2(0u, 0u);
-      bool keep = true;  // Alg. 4: a randomized probe lists exactly its members
-      float val = 0.0f;
-      if (!sl.mode) {
-        val = grid_f32(*d);
-        if (fabsf(val - sl.thr) <= 1e-5f * sl.thr) {  // FP32 rounding may decide this test
-          ++near;
-          unsafeAtomicAdd(sl.flip, sl.flip_unit);
-        }
-        keep = val > sl.thr;
-      }
-      if (keep) {
-        ++kept;
-        row = sl.out_rows[it.y];
-        edges += row.y;
-        item_val[i] = val * sl.sc;
-        myslot = it.x;
-        mydeg = row.y;
-        if (row.y > kBigDeg) {
-          nch = (row.y + kChunk - 1) / kChunk;
-          row.y |= kBigFlag;
-        }
-      } else {
-        ++pruned;
-      }
-      if (!sl.mode && !row.y) *d = 0;
-      item_row[i] = row;
-    }
-    // segmented sum of out-degrees per slot over the wavefront
-    for (;;) {
-      const unsigned long long live = __ballot(myslot >= 0 && mydeg > 0);
-      if (!live) break;
-      const int leader = __ffsll((long long)live) - 1;
-      const int32_t s0 = __shfl(myslot, leader, 64);
-      const bool mine = myslot == s0;
-      const unsigned long long sum = wave_sum(mine ? mydeg : 0ull);
-      if (lane == leader) atomicAdd(&slot_edges[s0], sum);
-      if (mine) myslot = -1;
-    }
-    const uint32_t incl = wave_incl_scan(nch);
-    const uint32_t total = __shfl(incl, 63, 64);
-    if (total) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&ctr[C_CHUNK], (unsigned long long)total);
-      base = __shfl(base, 0, 64);
-      const uint64_t first = base + incl - nch;
-      if (first + nch <= chunk_cap) {
-        for (uint32_t c = 0; c < nch; ++c) chunk_list[first + c] = make_int2((int32_t)i, (int32_t)c);
-      } else if (nch) {
-        atomicOr(&ctr[C_OVERFLOW], 2ull);
-      }
-    }
-  }
-  kept = wave_sum(kept);
-  pruned = wave_sum(pruned);
-  edges = wave_sum(edges);
-  near = wave_sum(near);
-  if (lane == 0) {
-    if (near) atomicAdd(&ctr[C_NEAR], near);
-    if (kept) atomicAdd(&ctr[C_KEPT], kept);
-    if (pruned) atomicAdd(&ctr[C_PRUNED], pruned);
-    if (edges) atomicAdd(&ctr[C_EDGES], edges);
-  }
-}
-
-struct PickArgs {
-  int P;
-  unsigned long long* slot_edges;
-  unsigned long long* hyb_edges;
-  Slot* slots;
-  int32_t* pull_flag;
-  int32_t* lane_slot;
-  DenseVer* dv;
-  // Section 4.4 switches
-  const int32_t* t_weight;
-  const uint32_t* t_woff;
-  const int32_t* t_walks;
-  int32_t* ring;
-  int32_t* ring_k;
-  uint64_t ring_mask;
-  unsigned long long* remaining;
-  unsigned long long* ctr;
-};
-
-// Section 4.4: the deterministic probe in slot S stops (k_expand drops its
-// level, so it retires at the next step) and each walk through its tree node
-// is queued for a randomized probe of the same prefix.  A dense column it
-// held is free again; this step's pass writes that column as zeros.
-__device__ void switch_probe(const PickArgs& a, Slot& S) {
+// Section 4.4: the deterministic probe in slot S stops (its listed level is
+// dropped, so it retires at the next step) and each walk through its tree
+// node is queued for a randomized probe of the same prefix.  A dense column it
+// held still holds its level, which this step's pass overwrites with zeros,
+// so it is free again only at the next step.
+__device__ void switch_probe(const SchedArgs& a, Slot& S) {
   if (S.lane >= 0) {
-    a.lane_slot[S.lane] = -1;
+    a.lane_slot[S.lane] = -2;
+    atomicOr(&a.ctr[C_SWLANES], 1ull << S.lane);
     S.lane = -1;
   }
   const int32_t t = S.probe;
@@ -679,73 +606,313 @@ __device__ void switch_probe(const PickArgs& a, Slot& S) {
   }
 }
 
-// One workgroup.  First the switch of Section 4.4 for hybrid queries: a
-// deterministic probe switches when the level it is about to expand has more
-// kept out-edges than c0 * w * n (k_prep's sum for a sparse frontier, the
-// count of the last dense pass for a dense column).  Then it moves sparse
-// slots whose kept entries have at least ctr[C_PULL_T] out-edges into free
+// One thread per slot.  Advances every slot by one PROBE iteration (a slot
+// paused last step stays at its level), retires probes whose last level
+// (i-2) ran or whose frontier Rule 2 emptied, and hands free slots the next
+// pending probes in ring order (each workgroup claims a range of the ring).
+// A new probe on (u_1..u_i) starts with H_0 = {u_i: 1}, listed here after
+// Rule 2.  Sums each slot's listed out-edges and entries from the partial
+// sums of the last step's kernels, then takes the switch of Section 4.4 for
+// hybrid queries: a deterministic probe switches when the level it is about
+// to expand keeps more than c0 * w * n out-edges.
+__global__ void __launch_bounds__(kSchedBlock) k_sched(SchedArgs a) {
+  __shared__ uint32_t s_wtot[kSchedBlock / 64];
+  __shared__ unsigned long long s_base, s_take;
+
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid >> 6;
+  const int s = blockIdx.x * kSchedBlock + tid;
+  unsigned long long* ctr = a.ctr;
+  __shared__ int2 w_sn[kSchedBlock];
+  __shared__ float w_h[kSchedBlock];
+  __shared__ uint2 w_row[kSchedBlock];
+  if (blockIdx.x == 0 && tid < kSubLists) {
+    a.next.n_ent[tid] = 0;
+    a.next.n_chunk[tid] = 0;
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    ctr[C_REC] = 0;
+    ctr[C_BIN] = 0;
+    ctr[C_NZROWS0 + (a.cur ^ 1)] = 0;  // the dense pass rewrites that matrix this step
+  }
+  const bool valid = s < a.P;
+  bool need = false, paused = false;
+  uint32_t E = 0, F = 0;
+  if (valid) {
+    Slot& S = a.slots[s];
+    paused = a.pull_flag[s] == 3;
+    a.was_paused[s] = paused ? 1 : 0;
+    if (S.probe >= 0) {
+      if (paused) {
+        // its entries were carried into this step's list unchanged
+      } else if (S.last || !a.has_next[s]) {
+        const int q = S.query;
+        if (atomicAdd(&a.remaining[q], ~0ull) == 1ull) {  // last probe of the query
+          const unsigned long long pos = atomicAdd(&ctr[C_DONE], 1ull);
+          a.done_ring[pos % (unsigned long long)a.qmax] = q;
+        }
+        // a column after a last or empty level holds zeros: free at once
+        if (S.lane >= 0) a.lane_slot[S.lane] = -1;
+        S.probe = -1;
+        S.lane = -1;
+        need = true;
+      } else {
+        S.level = S.level + 1;
+        S.cursor = a.t_parent[S.cursor];
+      }
+    } else {
+      need = true;
+    }
+    a.has_next[s] = 0;
+    // the sums the last step's kernels added for this slot; the rows are
+    // cleared for this step's kernels
+    uint32_t pe[kPartRows], pf[kPartRows];
+#pragma unroll
+    for (int r = 0; r < kPartRows; ++r) {
+      pe[r] = a.part[(size_t)r * 2 * a.P + s];
+      pf[r] = a.part[(size_t)r * 2 * a.P + a.P + s];
+    }
+#pragma unroll
+    for (int r = 0; r < kPartRows; ++r) {
+      a.part[(size_t)r * 2 * a.P + s] = 0u;
+      a.part[(size_t)r * 2 * a.P + a.P + s] = 0u;
+      if (!need && S.lane < 0) {
+        E += pe[r];
+        F += pf[r];
+      }
+    }
+  }
+  // free slots of this workgroup claim a range of pending probes
+  const uint32_t incl = wave_incl_scan(need ? 1u : 0u);
+  if (lane == 63) s_wtot[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kSchedBlock / 64; ++w) {
+    if (w < wv) before += s_wtot[w];
+    total += s_wtot[w];
+  }
+  if (tid == 0) {
+    unsigned long long h = 0, take = 0;
+    if (total) {
+      const unsigned long long lim = __hip_atomic_load(&ctr[C_TAIL_SNAP], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      h = __hip_atomic_load(&ctr[C_HEAD], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (;;) {
+        take = h < lim ? min((unsigned long long)total, lim - h) : 0ull;
+        if (!take) break;
+        const unsigned long long prev = atomicCAS(&ctr[C_HEAD], h, h + take);
+        if (prev == h) break;
+        h = prev;
+      }
+    }
+    s_base = h;
+    s_take = take;
+  }
+  __syncthreads();
+  const unsigned long long rank = before + incl - (need ? 1u : 0u);
+  bool want = false;
+  int32_t x = 0;
+  uint2 row = make_uint2(0u, 0u);
+  unsigned long long n0 = 0, kept = 0, pruned = 0, near = 0;
+  if (valid && need && rank < s_take) {
+    Slot& S = a.slots[s];
+    const uint64_t rp = (s_base + rank) & a.ring_mask;
+    const int32_t t = a.ring[rp];
+    const int q = a.t_query[t];
+    const QueryDev& Q = a.qr[q];
+    const int32_t wk = a.ring_k[rp];
+    const int mode = wk >= 0;  // a randomized probe of walk wk's prefix
+    const double w = mode ? 1.0 : (double)a.t_weight[t];
+    S.probe = t;
+    S.lane = -1;
+    S.level = 0;
+    S.depth = a.t_depth[t];
+    S.cursor = a.t_parent[t];
+    S.query = q;
+    S.mode = mode;
+    S.wk = mode ? (uint32_t)wk : 0u;
+    S.t_sc = Q.t_sc;
+    S.key2 = Q.key2;
+    S.w = w;
+    S.sc = Q.sc;
+    S.out_rows = Q.out_rows;
+    S.out_col = Q.out_col;
+    S.inv_indeg = Q.inv_indeg;
+    S.acc = Q.acc;
+    S.in_rows = Q.in_rows;
+    S.in_col = Q.in_col;
+    S.heavy_nodes = Q.heavy_nodes;
+    S.heavy_chunks = Q.heavy_chunks;
+    S.heavy_cnt = Q.heavy_cnt;
+    S.flip = Q.flip;
+    S.flip_unit = mode ? 0.0 : Q.flip_unit * w;
+    // Section 4.4: a hybrid query's deterministic probe of weight w
+    // switches past c0 * w * n out-edges
+    S.hyb_thr = !mode && Q.hybrid ? (Q.c0 * w) * (double)a.n : -1.0;
+    x = a.t_node[t];
+    row = Q.out_rows[x];
+    n0 = 1;
+    bool keep = true;  // Alg. 4 has no Rule 2
+    if (!mode) {       // Rule 2 on H_0 = {u_i: 1}
+      const float thr = a.thr_tab[q * PS_MAX_WALK_LEN + S.depth - 1];
+      if (fabsf(1.0f - thr) <= 1e-5f * thr) {
+        ++near;
+        unsafeAtomicAdd(S.flip, S.flip_unit);
+      }
+      keep = 1.0f > thr;
+      kept = keep ? 1 : 0;
+      pruned = keep ? 0 : 1;
+    }
+    want = keep && row.y > 0;
+  }
+  {
+    WaveStage ws{w_sn + (tid & ~63), w_h + (tid & ~63), w_row + (tid & ~63), 64, 0};
+    stage_put(want, s, x, 1.0f, row, ws, a.list, ctr);
+    stage_flush(ws, a.list, ctr);
+  }
+  if (want) {
+    E = row.y;
+    F = 1;
+  }
+  int32_t pf = 0;
+  unsigned long long te = 0, tn = 0, tf = 0;
+  if (valid) {
+    Slot& S = a.slots[s];
+    if (S.probe >= 0) {
+      const int level = S.level, depth = S.depth, q = S.query;
+      const int e = depth - level - 1;  // iterations left, i-j-1 >= 1
+      S.thr = a.thr_tab[q * PS_MAX_WALK_LEN + e];
+      S.thr_next = e > 1 ? a.thr_tab[q * PS_MAX_WALK_LEN + e - 1] : 0.0f;
+      S.excl = a.t_node[S.cursor];
+      S.last = level == depth - 2;
+      if (S.hyb_thr >= 0.0) {
+        unsigned long long he = E;
+        if (S.lane >= 0) {  // dense column: the count of the last pass
+          he = a.hyb_edges[s];
+          a.hyb_edges[s] = 0;
+        }
+        if ((double)he > S.hyb_thr) {
+          switch_probe(a, S);
+          pf = 2;
+        }
+      }
+      if (E && !paused) {  // probe levels by the out-edge count of their kept entries
+        const int b = 31 - __clz((int)E);
+        atomicAdd(&ctr[C_HIST_N + b], 1ull);
+        atomicAdd(&ctr[C_HIST_E + b], (unsigned long long)E);
+      }
+      if (pf == 0 && S.lane < 0) {
+        te = S.mode ? 0 : E;
+        tn = S.last ? 0 : min(E, (uint32_t)a.n);
+        tf = F;
+      }
+    }
+    a.pull_flag[s] = pf;
+    a.slot_edges[s] = E;
+    a.slot_cnt[s] = F;
+    // what pushing this level costs the step budget (k_expand); flag bit 0:
+    // a candidate, bit 1: not paused last step (lower priority)
+    const bool cand = S.probe >= 0 && S.lane < 0 && pf == 0 && F > 0;
+    a.cost[s] = make_uint4((uint32_t)te, (uint32_t)tn, F, (cand ? 1u : 0u) | (paused ? 0u : 2u));
+  }
+  n0 = wave_sum(n0);
+  kept = wave_sum(kept);
+  pruned = wave_sum(pruned);
+  near = wave_sum(near);
+  te = wave_sum(te);
+  tn = wave_sum(tn);
+  tf = wave_sum(tf);
+  if (lane == 0) {
+    if (n0) atomicAdd(&ctr[C_LEVEL0], n0);
+    if (kept) atomicAdd(&ctr[C_KEPT], kept);
+    if (pruned) atomicAdd(&ctr[C_PRUNED], pruned);
+    if (near) atomicAdd(&ctr[C_NEAR], near);
+    if (te) atomicAdd(&ctr[C_TOT_E], te);
+    if (tn) atomicAdd(&ctr[C_TOT_N], tn);
+    if (tf) atomicAdd(&ctr[C_TOT_F], tf);
+  }
+}
+
+// Graph version whose in-rows the dense pass reads (all dense lanes share it).
+struct DenseVer {
+  const uint2* out_rows;  // out-degrees of the targets (Section 4.4 counts)
+  const uint2* in_rows;
+  const int32_t* in_col;
+  const float* inv_indeg;
+  const int32_t* heavy_nodes;
+  const int2* heavy_chunks;
+  const unsigned long long* heavy_cnt;
+};
+
+struct PickArgs {
+  int P;
+  int32_t n;
+  uint4* cost;
+  Slot* slots;
+  int32_t* pull_flag;
+  int32_t* lane_slot;
+  DenseVer* dv;
+  const uint32_t* slot_edges;
+  const uint32_t* slot_cnt;
+  unsigned long long* ctr;
+};
+
+// One workgroup, run only when levels may be pulled.  Moves pushed sparse
+// slots whose listed entries have at least ctr[C_PULL_T] out-edges into free
 // dense columns, as long as they read the graph version the dense pass uses
 // (fixed by the columns active at the start, or by the first slot moved).
 // Their entries are scattered into the dense matrix by k_expand this step.
-// A column freed by a switch is handed out at the next step only.  Also sets
-// the column range of this step's dense pass and records the version's
-// arrays for it.
-__global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
+// A column freed by a switch becomes free one step later.  Also sets the
+// column range of this step's dense pass and records the version's arrays.
+__global__ void __launch_bounds__(kPickThreads) k_pick(PickArgs a) {
   __shared__ int32_t s_free[kLanes];
-  __shared__ uint32_t s_nfree, s_ncand, s_fhi;
+  __shared__ uint32_t s_nfree, s_ncand;
   __shared__ unsigned long long s_ver;
   const int tid = threadIdx.x;
+  unsigned long long* ctr = a.ctr;
+  const unsigned long long sw = ctr[C_SWLANES];
   if (tid == 0) {
     s_nfree = 0;
     s_ncand = 0;
-    s_fhi = 0;
     s_ver = 0ull;
   }
   __syncthreads();
   if (tid < kLanes) {  // one wavefront: free columns listed lowest first
-    const int32_t ls = a.lane_slot[tid];
-    const unsigned long long freem = __ballot(ls < 0);
-    if (ls < 0) s_free[__popcll(freem & ((1ull << tid) - 1ull))] = tid;
-    else s_ver = (unsigned long long)a.slots[ls].in_rows;  // all active columns share it
+    int32_t ls = a.lane_slot[tid];
+    if (ls == -2 && !((sw >> tid) & 1ull)) {  // switched at an earlier step: zero by now
+      a.lane_slot[tid] = -1;
+      ls = -1;
+    }
+    const unsigned long long freem = __ballot(ls == -1);
+    if (ls == -1) s_free[__popcll(freem & ((1ull << tid) - 1ull))] = tid;
+    else if (ls >= 0) s_ver = (unsigned long long)a.slots[ls].in_rows;  // all active columns share it
     if (tid == 0) s_nfree = (uint32_t)__popcll(freem);
   }
   __syncthreads();
-  unsigned long long* ctr = a.ctr;
   const unsigned long long T = ctr[C_PULL_T];
+  unsigned long long de = 0, dn = 0, df = 0;
   for (int s = tid; s < a.P; s += blockDim.x) {
     Slot& S = a.slots[s];
-    unsigned long long e = a.slot_edges[s];
-    const unsigned long long he = a.hyb_edges[s];
-    if (he) a.hyb_edges[s] = 0;
-    int32_t flag = 0;
-    if (S.probe >= 0 && S.hyb_thr >= 0.0 && (double)(S.lane >= 0 ? he : e) > S.hyb_thr) {
-      if (S.lane >= 0) atomicMax(&s_fhi, (uint32_t)S.lane + 1u);
-      switch_probe(a, S);
-      flag = 2;
-      if (e) atomicAdd(&ctr[C_EDGES_UNPUSHED], e);  // k_prep counted them
-      e = 0;
-    }
-    if (e) {
-      const int b = 63 - __clzll((long long)e);
-      atomicAdd(&ctr[C_HIST_N + b], 1ull);
-      atomicAdd(&ctr[C_HIST_E + b], e);
-      if (e >= T && S.lane < 0 && !S.mode) {
-        const unsigned long long ver = (unsigned long long)S.in_rows;
-        const unsigned long long old = atomicCAS(&s_ver, 0ull, ver);
-        if ((old == 0ull ? ver : old) == ver) {
-          const uint32_t k = atomicAdd(&s_ncand, 1u);
-          if (k < s_nfree) {
-            const int32_t lane = s_free[k];
-            S.lane = lane;
-            a.lane_slot[lane] = s;
-            flag = 1;
-            atomicAdd(&ctr[C_EDGES_UNPUSHED], e);  // pulled, not pushed
-          }
-        }
-      }
-    }
-    a.pull_flag[s] = flag;
+    const uint32_t e = a.slot_edges[s];
+    if (S.probe < 0 || S.lane >= 0 || S.mode || a.pull_flag[s] != 0 || e == 0 || e < T) continue;
+    const unsigned long long ver = (unsigned long long)S.in_rows;
+    const unsigned long long old = atomicCAS(&s_ver, 0ull, ver);
+    if ((old == 0ull ? ver : old) != ver) continue;
+    const uint32_t k = atomicAdd(&s_ncand, 1u);
+    if (k >= s_nfree) continue;
+    const int32_t lane = s_free[k];
+    S.lane = lane;
+    a.lane_slot[lane] = s;
+    a.pull_flag[s] = 1;
+    a.cost[s].w &= ~1u;  // pulled: not pushed
+    de += e;
+    dn += S.last ? 0 : min(e, (uint32_t)a.n);
+    df += a.slot_cnt[s];
   }
+  if (de) atomicAdd(&ctr[C_TOT_E], 0ull - de);
+  if (dn) atomicAdd(&ctr[C_TOT_N], 0ull - dn);
+  if (df) atomicAdd(&ctr[C_TOT_F], 0ull - df);
   __syncthreads();
   if (tid < kLanes) {  // the first wavefront: one lane per column
     const int32_t ls = a.lane_slot[tid];
@@ -756,14 +923,16 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
     const unsigned long long hmask = __ballot(hyb);
     if (tid == 0) {
       const unsigned long long hi = act ? (unsigned long long)(64 - __clzll((long long)act)) : 0ull;
+      const unsigned long long fhi = sw ? (unsigned long long)(64 - __clzll((long long)sw)) : 0ull;
       const unsigned long long prev = ctr[C_GPREV];
       ctr[C_GHI] = hi;
-      ctr[C_GW] = hi > prev ? hi : prev;
+      ctr[C_GW] = max(max(hi, prev), fhi);
       // a column freed by a switch still holds its level in this step's
       // input matrix, which the next step writes: it counts as in use until then
-      ctr[C_GPREV] = hi > s_fhi ? hi : s_fhi;
+      ctr[C_GPREV] = max(hi, fhi);
       if (act) atomicAdd(&ctr[C_PULLS], (unsigned long long)__popcll(act));
       ctr[C_HYBMASK] = hmask;
+      ctr[C_SWLANES] = 0ull;
     }
     if (act && tid == __ffsll((long long)act) - 1) {  // the version's arrays, from the lowest active column
       const Slot& sl = a.slots[ls];
@@ -780,81 +949,132 @@ __global__ void __launch_bounds__(kSchedThreads) k_pick(PickArgs a) {
 
 struct ExpandArgs {
   int32_t n;
-  long long* dense_cur;
-  float* mat_cur;  // dense frontier matrix (n x kLanes) of this step
-  uint8_t* map_cur;  // its row map (rows given a score here are flagged)
-  const int32_t* pull_flag;
-  const int2* list_cur;
-  const float* item_val;
-  const uint2* item_row;
-  const int2* chunk_list;
+  int P;
+  int sh_min;  // smallest bin shift that keeps the bins within kMaxBins
   const Slot* slots;
-  long long* dense_next;
-  int2* list_next;
-  uint64_t list_cap;
-  uint64_t chunk_cap;
+  int32_t* pull_flag;
+  const uint4* cost;
+  FList cur, nxt;
+  uint2* rec;  // records: (slot << sh | v & mask, FP32 contribution bits)
+  uint64_t rec_cap;
+  uint2* seg;  // seg[bin * kExpGrid + workgroup] = (first record, count)
+  float* mat_cur;
+  uint8_t* map_cur;
   int32_t* has_next;
+  uint32_t* part;
+  uint64_t list_soft;  // entries the next list may take before slots pause
   unsigned long long* ctr;
-  int cur;
-  int nxt;
+  int cur_par;
 };
 
-// Per-wavefront staging of new frontier entries in LDS: one global atomic per
-// flush instead of one per append.  Every lane of the wavefront must call
-// these together (the callers' loops are wavefront-uniform).
-struct WaveBuf {
-  int2* buf;   // kWaveBuf entries of this wavefront
-  uint32_t n;  // entries staged (same value in every lane)
-};
-
-__device__ __forceinline__ void wave_flush(WaveBuf& wb, const ExpandArgs& a, unsigned long long& nnext) {
-  if (wb.n == 0) return;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+__device__ __forceinline__ long long wave_incl_scan64(long long x) {
   const int lane = lane_id();
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(&a.ctr[C_LIST0 + a.nxt], (unsigned long long)wb.n);
-  base = __shfl(base, 0, 64);
-  for (uint32_t k = (uint32_t)lane; k < wb.n; k += 64) {
-    const unsigned long long pos = base + k;
-    if (pos < a.list_cap) a.list_next[pos] = wb.buf[k];
-    else atomicOr(&a.ctr[C_OVERFLOW], 4ull);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  if (lane == 0) nnext += wb.n;
-  wb.n = 0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  return x;
 }
 
-__device__ __forceinline__ void wave_append(WaveBuf& wb, bool flag, int32_t s, int32_t v, const ExpandArgs& a,
-                                            unsigned long long& nnext) {
-  const unsigned long long mask = __ballot(flag);
-  if (!mask) return;
-  const uint32_t cnt = (uint32_t)__popcll(mask);
-  if (wb.n + cnt > (uint32_t)kWaveBuf) wave_flush(wb, a, nnext);
-  const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
-  if (flag) wb.buf[wb.n + rank] = make_int2(s, v);
-  wb.n += cnt;
-}
-
-// One out-edge x -> v of a listed entry of slot s: add sqrt(c)/|I(v)| *
-// Score(x) to H_{j+1}[v] unless v is the excluded walk node u_{i-j-1}
-// (Alg. 2); sv = fl32(Score(x) * sqrt(c)).  Returns whether (s, v) became a
-// new frontier entry.
-__device__ __forceinline__ bool visit_edge(const ExpandArgs& a, int32_t s, int32_t v, float sv, const Slot& sl,
-                                           unsigned long long& nfinal) {
-  if (v == sl.excl) return false;
-  const float c = sv * sl.inv_indeg[v];
-  const long long q = to_grid(c);
-  if (q == 0) return false;  // below the grid
-  if (sl.last) {
-    unsafeAtomicAdd(&sl.acc[v], (double)c * sl.w);
-    ++nfinal;
-    return false;
+// Pauses (slow path of the per-step budget).  The records of the pushed
+// levels must fit rec_cap, and the next list list_soft: a pushed inner
+// level lists at most min(out-edges, n) entries, a paused level keeps its
+// entries, a pushed last level lists none.  Every workgroup decides the same
+// way: slots in priority order (those paused last step first, then by
+// index) are pushed as long as the running sums fit; the others keep their
+// listed level for a later step.  The first slot in that order is always
+// pushed (the capacity guards report it if even that does not fit).
+// Returns the records of the pushed levels.
+__device__ unsigned long long decide_pauses(const ExpandArgs& a, uint32_t* s_pause, long long* s_w0,
+                                            long long* s_w1) {
+  __shared__ unsigned long long s_base, s_adm;
+  __shared__ int s_first;
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+  const int per = (a.P + (int)blockDim.x - 1) / (int)blockDim.x;
+  for (int i = tid; i < (a.P + 31) / 32; i += blockDim.x) s_pause[i] = 0u;
+  if (tid == 0) {
+    s_base = 0;
+    s_adm = 0;
+    s_first = 0x7fffffff;
   }
-  const unsigned long long old =
-      atomicAdd(reinterpret_cast<unsigned long long*>(&a.dense_next[(size_t)s * a.n + v]), (unsigned long long)q);
-  return old == 0ull;
+  __syncthreads();
+  unsigned long long base = 0;  // entries of every candidate, as if all were carried
+  long long rec[2] = {0, 0}, grow[2] = {0, 0};
+  for (int k = 0; k < per; ++k) {
+    const int s = tid * per + k;
+    if (s >= a.P) break;
+    const uint4 c = a.cost[s];
+    if (!(c.w & 1u)) continue;
+    const int g = (c.w >> 1) & 1u;
+    base += c.z;
+    rec[g] += (long long)c.x;
+    grow[g] += (long long)c.y - (long long)c.z;
+    atomicMin(&s_first, g * a.P + s);
+  }
+  base = wave_sum(base);
+  if (lane == 0 && base) atomicAdd(&s_base, base);
+  // prefix sums in priority order: group 0 (paused last step), then group 1
+  long long pre_rec[2], pre_grow[2];
+  for (int g = 0; g < 2; ++g) {
+    const long long ir = wave_incl_scan64(rec[g]);
+    const long long ig = wave_incl_scan64(grow[g]);
+    if (lane == 63) {
+      s_w0[g * 32 + wv] = ir;
+      s_w1[g * 32 + wv] = ig;
+    }
+    pre_rec[g] = ir - rec[g];
+    pre_grow[g] = ig - grow[g];
+  }
+  __syncthreads();
+  long long tot_rec0 = 0, tot_grow0 = 0;
+  for (int g = 0; g < 2; ++g) {
+    long long br = 0, bg = 0, tr = 0, tg = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      if (w < wv) {
+        br += s_w0[g * 32 + w];
+        bg += s_w1[g * 32 + w];
+      }
+      tr += s_w0[g * 32 + w];
+      tg += s_w1[g * 32 + w];
+    }
+    pre_rec[g] += br;
+    pre_grow[g] += bg;
+    if (g == 0) {
+      tot_rec0 = tr;
+      tot_grow0 = tg;
+    }
+  }
+  const long long lim_rec = (long long)min(a.rec_cap, (unsigned long long)kStepRecords);
+  const long long lim_list = (long long)a.list_soft - (long long)s_base;
+  unsigned long long paused = 0, adm = 0;
+  for (int g = 0; g < 2; ++g) {
+    long long cr = pre_rec[g] + (g ? tot_rec0 : 0), cg = pre_grow[g] + (g ? tot_grow0 : 0);
+    for (int k = 0; k < per; ++k) {
+      const int s = tid * per + k;
+      if (s >= a.P) break;
+      const uint4 c = a.cost[s];
+      if (!(c.w & 1u) || (int)((c.w >> 1) & 1u) != g) continue;
+      cr += (long long)c.x;
+      cg += (long long)c.y - (long long)c.z;
+      if ((cr <= lim_rec && cg <= lim_list) || g * a.P + s == s_first) {
+        adm += c.x;
+      } else {
+        atomicOr(&s_pause[s >> 5], 1u << (s & 31));
+        ++paused;
+      }
+    }
+  }
+  adm = wave_sum(adm);
+  if (lane == 0 && adm) atomicAdd(&s_adm, adm);
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int s = tid; s < a.P; s += blockDim.x)
+      if ((s_pause[s >> 5] >> (s & 31)) & 1u) a.pull_flag[s] = 3;
+    paused = wave_sum(paused);
+    if (lane == 0 && paused) atomicAdd(&a.ctr[C_PAUSED], paused);
+  }
+  return s_adm;
 }
 
 // One out-edge x -> v of a member x of randomized probe slot s (Alg. 4).
@@ -867,8 +1087,7 @@ __device__ __forceinline__ bool visit_edge(const ExpandArgs& a, int32_t s, int32
 // drawn node is a member.  Each selected v is so found once, with no marks
 // and no lookups of membership.  On the probe's last level a selected v adds
 // 1 to the estimate.  Returns whether v is listed for the next level.
-__device__ __forceinline__ bool visit_random(const ExpandArgs& a, int32_t v, int32_t x, const Slot& sl,
-                                             unsigned long long& nfinal) {
+__device__ __forceinline__ bool visit_random(int32_t v, int32_t x, const Slot& sl, unsigned long long& nfinal) {
   if (v == sl.excl) return false;
   const uint4 w = philox4x32_10(make_uint4(sl.wk, ((uint32_t)sl.depth << 16) | (uint32_t)sl.level, (uint32_t)v, 1u),
                                 sl.key2);
@@ -884,145 +1103,606 @@ __device__ __forceinline__ bool visit_random(const ExpandArgs& a, int32_t v, int
   return true;
 }
 
-// PROBE expansion.  Part 1: workgroups take tiles of kTile listed entries,
-// scan their out-degrees in LDS and walk the tile's edges 256 at a time, each
-// lane finding its entry by binary search, so the work per lane is one edge
-// whatever the degree mix.  Part 2: one wavefront per kChunk-edge chunk of the
-// long rows.
-__global__ void __launch_bounds__(kBlock) k_expand(ExpandArgs a) {
+// What happens to a listed entry of slot s this step.
+enum EntryFate { kPush = 0, kPull = 1, kDrop = 2, kCarry = 3 };
+
+__device__ __forceinline__ int entry_fate(const ExpandArgs& a, int32_t s, bool slow, const uint32_t* s_pause) {
+  const int32_t pf = a.pull_flag[s];
+  if (pf == 1) return kPull;
+  if (pf == 2) return kDrop;
+  // 0 or 3 (the pause flag other workgroups may be writing)
+  if (slow && ((s_pause[s >> 5] >> (s & 31)) & 1u)) return kCarry;
+  return kPush;
+}
+
+// PROBE expansion (Alg. 2 per listed entry, Alg. 4 for randomized probes).
+// Workgroups take tiles of kTile listed entries, scan their out-degrees in
+// LDS and walk the tile's edges kThreads at a time, each thread finding its
+// entry by binary search, so the work per thread is one edge whatever the
+// degree mix; chunked long rows go one wavefront per chunk.  Pass 1 counts
+// the records of each bin, pass 2 writes them (and lists randomized probes'
+// next sets, carries paused slots' entries and scatters pulled slots'
+// entries into the dense matrix).
+constexpr int kEdgeBatch = 4;  // edges a thread has in flight
+
+// Entry j of a tile whose edge e (tile-relative) a thread takes: the last j
+// with s_pref[j] <= e.
+__device__ __forceinline__ int tile_entry(const uint32_t* s_pref, uint32_t e) {
+  int lo = 0, hi = kTile - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_pref[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kThreads) k_expand(ExpandArgs a) {
+  __shared__ uint32_t s_hist[kMaxBins];
   __shared__ uint32_t s_pref[kTile + 1];
-  __shared__ int32_t s_slot[kTile];
-  __shared__ uint32_t s_start[kTile];
-  __shared__ float s_val[kTile];
-  __shared__ int32_t s_flag[kTile];
-  __shared__ uint32_t s_wtot[kBlock / 64];
-  __shared__ int2 s_buf[kBlock / 64][kWaveBuf];
+  __shared__ int32_t s_slot[kTile];  // slot, with kBigFlag set for a randomized probe
+  __shared__ const int32_t* s_col[kTile];  // the entry's out-row
+  __shared__ const float* s_inv[kTile];    // 1/|I(.)| of its graph version
+  __shared__ int32_t s_excl[kTile];
+  __shared__ float s_sv[kTile];
+  __shared__ int32_t s_x[kTile];
+  __shared__ uint32_t s_part[2 * kMaxSlots];
+  __shared__ uint32_t s_pause[kMaxSlots / 32];
+  __shared__ uint32_t s_wtot[kThreads / 64];
+  __shared__ long long s_w0[64], s_w1[64];
+  __shared__ unsigned long long s_rbase;
+  __shared__ int s_dirty, s_skip;
+  __shared__ uint32_t s_cnt[kSubLists], s_tpre[kSubLists + 1], s_cpre[kSubLists + 1];
+  __shared__ int2 w_sn[kThreads];  // one 64-entry stage per wavefront
+  __shared__ float w_h[kThreads];
+  __shared__ uint2 w_row[kThreads];
   const int tid = threadIdx.x;
   const int lane = lane_id();
-  const int wv = tid >> 6;
-  WaveBuf wb{s_buf[wv], 0u};
-  unsigned long long nfinal = 0, nnext = 0, nconv = 0;
+  unsigned long long* ctr = a.ctr;
+  const unsigned long long tot_e = ctr[C_TOT_E], tot_n = ctr[C_TOT_N];
+  const bool slow = tot_e > min(a.rec_cap, (unsigned long long)kStepRecords) || tot_n > a.list_soft;
+  const unsigned long long recs = slow ? decide_pauses(a, s_pause, s_w0, s_w1) : tot_e;
+  // bin width of this step: about kBinRecords records per bin (v >> sh)
+  uint32_t sh = (uint32_t)a.sh_min;
+  while (sh < (uint32_t)kMaxSh && ((unsigned long long)a.n >> (sh + 1)) * kBinRecords >= recs) ++sh;
+  const int nbins = (int)(((uint32_t)a.n - 1u) >> sh) + 1;
+  if (blockIdx.x == 0 && tid == 0) {
+    ctr[C_SH] = sh;
+    ctr[C_NB] = (unsigned long long)nbins;
+  }
+  for (int b = tid; b < nbins; b += kThreads) s_hist[b] = 0u;
+  if (tid == 0) {
+    s_dirty = 0;
+    s_skip = 0;
+    // tiles of kTile entries and chunks in each sub-list of this step's list
+    uint32_t tp = 0, cp = 0;
+    for (int k = 0; k < kSubLists; ++k) {
+      const uint32_t c = (uint32_t)min(a.cur.n_ent[k], (unsigned long long)a.cur.sub_cap);
+      s_cnt[k] = c;
+      s_tpre[k] = tp;
+      s_cpre[k] = cp;
+      tp += (c + kTile - 1) / kTile;
+      cp += (uint32_t)min(a.cur.n_chunk[k], (unsigned long long)a.cur.sub_chunk_cap);
+    }
+    s_tpre[kSubLists] = tp;
+    s_cpre[kSubLists] = cp;
+  }
+  __syncthreads();
+  const uint32_t ntiles = s_tpre[kSubLists];
+  const uint32_t nchunk = s_cpre[kSubLists];
+  const uint32_t vmask = (1u << sh) - 1u;
+  const uint64_t wave = ((uint64_t)blockIdx.x * kThreads + tid) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * kThreads) >> 6;
 
-  const unsigned long long cnt = min(a.ctr[C_LIST0 + a.cur], (unsigned long long)a.list_cap);
-  for (uint64_t tile0 = (uint64_t)blockIdx.x * kTile; tile0 < cnt; tile0 += (uint64_t)gridDim.x * kTile) {
-    constexpr int kPer = kTile / kBlock;
-    uint32_t deg[kPer];
-    uint32_t sum = 0;
+  // ---- pass 1: records per bin
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int k = 0;
+    while (k + 1 < kSubLists && s_tpre[k + 1] <= t) ++k;
+    const uint32_t lt = t - s_tpre[k];
+    const bool in = lt * kTile + (uint32_t)tid < s_cnt[k];  // this thread's entry exists
+    const uint64_t i = (uint64_t)k * a.cur.sub_cap + (uint64_t)lt * kTile + tid;
+    uint32_t deg = 0;
+    if (in) {
+      const uint2 row = a.cur.row[i];
+      if (!(row.y & kBigFlag)) {
+        const int32_t s = a.cur.sn[i].x;
+        const Slot& sl = a.slots[s];
+        if (entry_fate(a, s, slow, s_pause) == kPush && !sl.mode) {
+          deg = row.y;
+          s_col[tid] = sl.out_col + row.x;
+          s_excl[tid] = sl.excl;
+        }
+      }
+    }
+    uint32_t total;
+    s_pref[tid] = block_excl_scan(deg, s_wtot, &total);
+    if (tid == 0) s_pref[kTile] = total;
+    __syncthreads();
+    for (uint32_t e0 = 0; e0 < total; e0 += kThreads * kEdgeBatch) {
+      int32_t v[kEdgeBatch], ex[kEdgeBatch];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int j = tid * kPer + r;
-      const uint64_t i = tile0 + j;
-      deg[r] = 0;
-      if (i < cnt) {
-        const uint2 row = a.item_row[i];
-        if (row.y) {
-          const int2 it = a.list_cur[i];
-          long long* dc = a.dense_cur + (size_t)it.x * a.n + it.y;
-          const int32_t pf = a.pull_flag[it.x];
-          if (pf == 1) {  // slot moved to a dense column: scatter
-            a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = grid_f32(*dc);
-            a.map_cur[it.y] = 1;
-            ++nconv;
-            *dc = 0;
-          } else if (pf == 2) {  // switched probe (Section 4.4): the level is dropped
-            *dc = 0;
-          } else {  // pushed: its score is consumed here (a randomized
-                    // probe's entries never hold one)
-            if (!a.slots[it.x].mode) *dc = 0;
-            if (!(row.y & kBigFlag)) {
-              deg[r] = row.y;
-              s_start[j] = row.x;
-              s_val[j] = a.item_val[i];
-              s_slot[j] = it.x;
-            }
+      for (int k = 0; k < kEdgeBatch; ++k) {
+        const uint32_t e = e0 + (uint32_t)(k * kThreads + tid);
+        v[k] = -1;
+        ex[k] = -1;
+        if (e < total) {
+          const int lo = tile_entry(s_pref, e);
+          v[k] = s_col[lo][e - s_pref[lo]];
+          ex[k] = s_excl[lo];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k)
+        if (v[k] >= 0 && v[k] != ex[k]) atomicAdd(&s_hist[(uint32_t)v[k] >> sh], 1u);
+    }
+    __syncthreads();
+  }
+  for (uint64_t c = wave; c < nchunk; c += nwaves) {
+    int k = 0;
+    while (k + 1 < kSubLists && s_cpre[k + 1] <= c) ++k;
+    const int2 ch = a.cur.chunk[(uint64_t)k * a.cur.sub_chunk_cap + (c - s_cpre[k])];
+    if (ch.x < 0) continue;
+    const uint64_t ek = (uint64_t)ch.x / a.cur.sub_cap;  // the entry's sub-list
+    if (ek >= kSubLists || (uint64_t)ch.x - ek * a.cur.sub_cap >= s_cnt[ek]) continue;
+    const int32_t s = a.cur.sn[ch.x].x;
+    if (entry_fate(a, s, slow, s_pause) != kPush) continue;
+    const Slot& sl = a.slots[s];
+    if (sl.mode) continue;
+    const uint2 row = a.cur.row[ch.x];
+    const uint32_t len = row.y & ~kBigFlag;
+    const uint32_t b = (uint32_t)ch.y * kChunk, e = min(len, b + kChunk);
+    const int32_t* col = sl.out_col + row.x;
+    const int32_t ex = sl.excl;
+    for (uint32_t t0 = b; t0 < e; t0 += 64 * kEdgeBatch) {
+      int32_t v[kEdgeBatch];
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k) {
+        const uint32_t t = t0 + (uint32_t)(k * 64 + lane);
+        v[k] = t < e ? col[t] : -1;
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k)
+        if (v[k] >= 0 && v[k] != ex) atomicAdd(&s_hist[(uint32_t)v[k] >> sh], 1u);
+    }
+  }
+  __syncthreads();
+  // this workgroup's records: one contiguous range, cut by bin
+  {
+    uint32_t mine = 0;
+    const int per = (nbins + kThreads - 1) / kThreads;
+    for (int k = 0; k < per; ++k) {
+      const int b = tid * per + k;
+      if (b < nbins) mine += s_hist[b];
+    }
+    uint32_t total;
+    const uint32_t pre = block_excl_scan(mine, s_wtot, &total);
+    if (tid == 0) {
+      const unsigned long long base = total ? atomicAdd(&ctr[C_REC], (unsigned long long)total) : 0ull;
+      s_rbase = base;
+      if (base + total > a.rec_cap) {
+        s_skip = 1;  // a guard: the budget keeps records within capacity
+        atomicOr(&ctr[C_OVERFLOW], 8ull);
+      }
+    }
+    __syncthreads();
+    uint32_t run = (uint32_t)s_rbase + pre;
+    for (int k = 0; k < per; ++k) {
+      const int b = tid * per + k;
+      if (b >= nbins) break;
+      const uint32_t c = s_hist[b];
+      a.seg[(size_t)b * kExpGrid + blockIdx.x] = make_uint2(run, s_skip ? 0u : c);
+      s_hist[b] = run;  // write cursor of pass 2
+      run += c;
+    }
+  }
+  for (int i = tid; i < 2 * a.P; i += kThreads) s_part[i] = 0u;
+  __syncthreads();
+
+  // ---- pass 2
+  const bool skip = s_skip != 0;
+  WaveStage ws{w_sn + (tid & ~63), w_h + (tid & ~63), w_row + (tid & ~63), 64, 0};
+  unsigned long long nfinal = 0, nnext = 0, nconv = 0, edges = 0, unpushed = 0;
+  bool dirty = false;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int k = 0;
+    while (k + 1 < kSubLists && s_tpre[k + 1] <= t) ++k;
+    const uint32_t lt = t - s_tpre[k];
+    const bool in = lt * kTile + (uint32_t)tid < s_cnt[k];  // this thread's entry exists
+    const uint64_t i = (uint64_t)k * a.cur.sub_cap + (uint64_t)lt * kTile + tid;
+    uint32_t deg = 0;
+    bool carry = false;
+    int32_t cs = 0, cx = 0;
+    float cval = 0.0f;
+    uint2 crow = make_uint2(0u, 0u);
+    if (in) {
+      const int2 it = a.cur.sn[i];
+      const uint2 row = a.cur.row[i];
+      const uint32_t len = row.y & ~kBigFlag;
+      const int fate = entry_fate(a, it.x, slow, s_pause);
+      if (fate == kPull) {  // scattered into the slot's dense column
+        a.mat_cur[(size_t)it.y * kLanes + a.slots[it.x].lane] = a.cur.val[i];
+        a.map_cur[it.y] = 1;
+        ++nconv;
+        edges += len;
+        unpushed += len;
+      } else if (fate == kDrop) {  // switched probe (Section 4.4): the level is dropped
+        edges += len;
+        unpushed += len;
+      } else if (fate == kCarry) {
+        carry = true;
+        cs = it.x;
+        cx = it.y;
+        cval = a.cur.val[i];
+        crow = make_uint2(row.x, len);
+      } else {
+        edges += len;
+        if (!(row.y & kBigFlag)) {
+          const Slot& sl = a.slots[it.x];
+          deg = row.y;
+          s_slot[tid] = sl.mode ? (int32_t)((uint32_t)it.x | kBigFlag) : it.x;
+          s_col[tid] = sl.out_col + row.x;
+          s_inv[tid] = sl.inv_indeg;
+          s_excl[tid] = sl.excl;
+          s_x[tid] = it.y;
+          s_sv[tid] = a.cur.val[i] * sl.sc;  // fl32(Score(x) * sqrt c)
+        }
+      }
+    }
+    stage_put(carry, cs, cx, cval, crow, ws, a.nxt, ctr);
+    if (carry) {
+      a.has_next[cs] = 1;
+      atomicAdd(&s_part[cs], crow.y);
+      atomicAdd(&s_part[a.P + cs], 1u);
+      dirty = true;
+    }
+    uint32_t total;
+    s_pref[tid] = block_excl_scan(deg, s_wtot, &total);
+    if (tid == 0) s_pref[kTile] = total;
+    __syncthreads();
+    for (uint32_t e0 = 0; e0 < total; e0 += kThreads * kEdgeBatch) {
+      int32_t v[kEdgeBatch], lo[kEdgeBatch];
+      float inv[kEdgeBatch];
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k) {
+        const uint32_t e = e0 + (uint32_t)(k * kThreads + tid);
+        v[k] = -1;
+        lo[k] = 0;
+        if (e < total) {
+          lo[k] = tile_entry(s_pref, e);
+          v[k] = s_col[lo[k]][e - s_pref[lo[k]]];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k) {  // Alg. 2: contributions of the deterministic entries
+        inv[k] = 0.0f;
+        if (v[k] >= 0 && s_slot[lo[k]] >= 0 && v[k] != s_excl[lo[k]]) inv[k] = s_inv[lo[k]][v[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k) {
+        const int32_t s = s_slot[lo[k]];
+        if (v[k] >= 0 && s >= 0 && v[k] != s_excl[lo[k]] && !skip) {
+          const float c = s_sv[lo[k]] * inv[k];
+          const uint32_t pos = atomicAdd(&s_hist[(uint32_t)v[k] >> sh], 1u);
+          a.rec[pos] = make_uint2(((uint32_t)s << sh) | ((uint32_t)v[k] & vmask), __float_as_uint(c));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgeBatch; ++k) {  // Alg. 4: the randomized entries
+        bool app = false;
+        int32_t s = 0;
+        uint2 vrow = make_uint2(0u, 0u);
+        if (v[k] >= 0 && s_slot[lo[k]] < 0) {
+          s = (int32_t)((uint32_t)s_slot[lo[k]] & ~kBigFlag);
+          const Slot& sl = a.slots[s];
+          if (visit_random(v[k], s_x[lo[k]], sl, nfinal)) {
+            ++nnext;
+            vrow = sl.out_rows[v[k]];
+            app = vrow.y > 0;
+          }
+        }
+        stage_put(app, s, v[k], 0.0f, vrow, ws, a.nxt, ctr);
+        if (app) {
+          a.has_next[s] = 1;
+          atomicAdd(&s_part[s], vrow.y);
+          atomicAdd(&s_part[a.P + s], 1u);
+          dirty = true;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (uint64_t c = wave; c < nchunk; c += nwaves) {
+    int k = 0;
+    while (k + 1 < kSubLists && s_cpre[k + 1] <= c) ++k;
+    const int2 ch = a.cur.chunk[(uint64_t)k * a.cur.sub_chunk_cap + (c - s_cpre[k])];
+    if (ch.x < 0) continue;
+    const uint64_t ek = (uint64_t)ch.x / a.cur.sub_cap;  // the entry's sub-list
+    if (ek >= kSubLists || (uint64_t)ch.x - ek * a.cur.sub_cap >= s_cnt[ek]) continue;
+    const int2 it = a.cur.sn[ch.x];
+    const int32_t s = it.x;
+    if (entry_fate(a, s, slow, s_pause) != kPush) continue;
+    const Slot& sl = a.slots[s];
+    const uint2 row = a.cur.row[ch.x];
+    const float sv = a.cur.val[ch.x] * sl.sc;
+    const uint32_t len = row.y & ~kBigFlag;
+    const uint32_t b = (uint32_t)ch.y * kChunk, e = min(len, b + kChunk);
+    const int32_t* col = sl.out_col + row.x;
+    if (!sl.mode) {  // Alg. 2
+      for (uint32_t t0 = b; t0 < e; t0 += 64 * kEdgeBatch) {
+        int32_t v[kEdgeBatch];
+        float inv[kEdgeBatch];
+#pragma unroll
+        for (int k = 0; k < kEdgeBatch; ++k) {
+          const uint32_t t = t0 + (uint32_t)(k * 64 + lane);
+          v[k] = t < e ? col[t] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kEdgeBatch; ++k) inv[k] = v[k] >= 0 && v[k] != sl.excl ? sl.inv_indeg[v[k]] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kEdgeBatch; ++k) {
+          if (v[k] >= 0 && v[k] != sl.excl && !skip) {
+            const float c = sv * inv[k];
+            const uint32_t pos = atomicAdd(&s_hist[(uint32_t)v[k] >> sh], 1u);
+            a.rec[pos] = make_uint2(((uint32_t)s << sh) | ((uint32_t)v[k] & vmask), __float_as_uint(c));
           }
         }
       }
-      s_flag[j] = 0;
-      sum += deg[r];
+      continue;
     }
-    const uint32_t incl = wave_incl_scan(sum);
-    if (lane == 63) s_wtot[wv] = incl;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      if (w < wv) before += s_wtot[w];
-      total += s_wtot[w];
-    }
-    uint32_t run = before + incl - sum;
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      s_pref[tid * kPer + r] = run;
-      run += deg[r];
-    }
-    if (tid == 0) s_pref[kTile] = total;
-    __syncthreads();
-    for (uint32_t e0 = 0; e0 < total; e0 += kBlock) {
-      const uint32_t e = e0 + (uint32_t)tid;
-      bool app = false;
-      int32_t s = 0, v = 0;
-      if (e < total) {
-        int lo = 0, hi = kTile - 1;  // last entry j with s_pref[j] <= e
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pref[mid] <= e) lo = mid; else hi = mid - 1;
-        }
-        s = s_slot[lo];
-        const Slot& sl = a.slots[s];
-        v = sl.out_col[s_start[lo] + (e - s_pref[lo])];
-        app = sl.mode ? visit_random(a, v, a.list_cur[tile0 + lo].y, sl, nfinal)
-                      : visit_edge(a, s, v, s_val[lo], sl, nfinal);
-        if (app) s_flag[lo] = 1;
-      }
-      wave_append(wb, app, s, v, a, nnext);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const int j = tid * kPer + r;
-      if (s_flag[j]) a.has_next[s_slot[j]] = 1;
-    }
-    __syncthreads();
-  }
-
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + tid) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  const unsigned long long nchunk = min(a.ctr[C_CHUNK], (unsigned long long)a.chunk_cap);
-  for (uint64_t c = wave; c < nchunk; c += nwaves) {
-    const int2 ch = a.chunk_list[c];
-    const int2 it = a.list_cur[ch.x];
-    const int32_t s = it.x;
-    if (a.pull_flag[s]) continue;  // pulled or switched
-    const Slot sl = a.slots[s];
-    const float sv = a.item_val[ch.x];
-    const uint2 row = a.item_row[ch.x];
-    const uint32_t len = row.y & ~kBigFlag;
-    const uint32_t b = (uint32_t)ch.y * kChunk;
-    const uint32_t e = min(len, b + kChunk);
-    bool any = false;
-    for (uint32_t t0 = b; t0 < e; t0 += 64) {
+    for (uint32_t t0 = b; t0 < e; t0 += 64) {  // Alg. 4
       const uint32_t t = t0 + lane;
       bool app = false;
       int32_t v = 0;
+      uint2 vrow = make_uint2(0u, 0u);
       if (t < e) {
-        v = sl.out_col[row.x + t];
-        app = sl.mode ? visit_random(a, v, it.y, sl, nfinal) : visit_edge(a, s, v, sv, sl, nfinal);
+        v = col[t];
+        if (visit_random(v, it.y, sl, nfinal)) {
+          ++nnext;
+          vrow = sl.out_rows[v];
+          app = vrow.y > 0;
+        }
       }
-      any |= app;
-      wave_append(wb, app, s, v, a, nnext);
+      stage_put(app, s, v, 0.0f, vrow, ws, a.nxt, ctr);
+      if (app) {
+        a.has_next[s] = 1;
+        atomicAdd(&s_part[s], vrow.y);
+        atomicAdd(&s_part[a.P + s], 1u);
+        dirty = true;
+      }
     }
-    if (__ballot(any) && lane == 0) a.has_next[s] = 1;
   }
-  wave_flush(wb, a, nnext);
-
+  stage_flush(ws, a.nxt, ctr);
+  if (dirty) s_dirty = 1;
+  __syncthreads();
+  // partial per-slot sums of what this workgroup listed (k_sched adds them up)
+  if (s_dirty) {
+    uint32_t* prow = a.part + (size_t)(blockIdx.x % kPartRows) * 2 * a.P;
+    for (int i = tid; i < 2 * a.P; i += kThreads)
+      if (s_part[i]) atomicAdd(&prow[i], s_part[i]);
+  }
   nfinal = wave_sum(nfinal);
   nnext = wave_sum(nnext);
   nconv = wave_sum(nconv);
+  edges = wave_sum(edges);
+  unpushed = wave_sum(unpushed);
   if (lane == 0) {
-    if (nfinal) atomicAdd(&a.ctr[C_FINAL], nfinal);
-    if (nnext) atomicAdd(&a.ctr[C_NEXT], nnext);
-    if (nconv) atomicAdd(&a.ctr[C_NZROWS0 + a.cur], nconv);  // rows given scores in the dense matrix
+    if (nfinal) atomicAdd(&ctr[C_FINAL], nfinal);
+    if (nnext) atomicAdd(&ctr[C_NEXT], nnext);
+    if (nconv) atomicAdd(&ctr[C_NZROWS0 + a.cur_par], nconv);  // rows given scores in the dense matrix
+    if (edges) atomicAdd(&ctr[C_EDGES], edges);
+    if (unpushed) atomicAdd(&ctr[C_EDGES_UNPUSHED], unpushed);
+  }
+}
+
+struct ReduceArgs {
+  int32_t n;
+  int P;
+  const Slot* slots;
+  const uint2* rec;
+  const uint2* seg;
+  FList nxt;
+  int32_t* has_next;
+  uint32_t* part;
+  unsigned long long* ctr;
+};
+
+constexpr int kRecBatch = 4;  // records a thread loads before it inserts them
+
+// Sums the records of each bin per (slot, node) exactly: 64-bit integer
+// adds on the grid 2^-62 in an LDS hash table (linear probing) of at least
+// twice as many places as the bin has records.  A bin whose keys still
+// overflow the table is split by the low bits of the key's mix into slices,
+// each summed on its own (the mix is a bijection, so slices end up small
+// enough).  Then each sum is the next level's score: on a probe's last
+// level weight * sum goes into the FP64 estimate; otherwise Rule 2 keeps the
+// node when its FP32 score exceeds the next level's threshold, and a kept
+// node with out-edges is listed.  Workgroup w takes bins w, w + kRedGrid, ...
+__global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
+  __shared__ uint32_t s_key[kTbl];
+  __shared__ unsigned long long s_val[kTbl];
+  __shared__ uint32_t s_part[2 * kMaxSlots];
+  __shared__ uint32_t s_pre[kExpGrid + 1];
+  __shared__ uint32_t s_st[kExpGrid];
+  __shared__ uint32_t s_wtot[kThreads / 64];
+  __shared__ int s_ovf, s_dirty;
+  __shared__ int2 w_sn[kThreads / 64 * kWaveStage];  // one stage per wavefront
+  __shared__ float w_h[kThreads / 64 * kWaveStage];
+  __shared__ uint2 w_row[kThreads / 64 * kWaveStage];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  unsigned long long* ctr = a.ctr;
+  const uint32_t sh = (uint32_t)ctr[C_SH], nbins = (uint32_t)ctr[C_NB];
+  const int wv = tid >> 6;
+  WaveStage ws{w_sn + wv * kWaveStage, w_h + wv * kWaveStage, w_row + wv * kWaveStage, kWaveStage, 0};
+  __syncthreads();  // every thread has read the bin layout before block 0 moves on
+  if (blockIdx.x == 0 && tid == 0) {
+    // pending probes the next k_sched may claim (switches made this step included)
+    ctr[C_TAIL_SNAP] = ctr[C_TAIL];
+    ctr[C_TOT_E] = 0;
+    ctr[C_TOT_N] = 0;
+    ctr[C_TOT_F] = 0;
+  }
+  for (uint32_t t = tid; t < kTbl; t += kThreads) {
+    s_key[t] = kNoKey;
+    s_val[t] = 0ull;
+  }
+  for (int i = tid; i < 2 * a.P; i += kThreads) s_part[i] = 0u;
+  if (tid == 0) s_dirty = 0;
+  const uint32_t vmask = (1u << sh) - 1u;
+  unsigned long long nfin = 0, nnext = 0, kept = 0, pruned = 0, near = 0;
+  bool dirty = false;
+  uint2 nseg = make_uint2(0u, 0u);  // segment of the next bin, loaded ahead
+  if (blockIdx.x < nbins && tid < kExpGrid) nseg = a.seg[(size_t)blockIdx.x * kExpGrid + tid];
+  for (uint32_t b = blockIdx.x; b < nbins; b += gridDim.x) {
+    const uint2 sg = nseg;
+    const uint32_t bn = b + gridDim.x;
+    if (bn < nbins && tid < kExpGrid) nseg = a.seg[(size_t)bn * kExpGrid + tid];
+    __syncthreads();  // the last bin's table and segments are no longer read
+    if (tid < kExpGrid) s_st[tid] = sg.x;
+    uint32_t R;
+    const uint32_t pre = block_excl_scan(tid < kExpGrid ? sg.y : 0u, s_wtot, &R);
+    if (tid < kExpGrid) s_pre[tid] = pre;
+    if (tid == 0) {
+      s_pre[kExpGrid] = R;
+      s_ovf = 0;
+    }
+    __syncthreads();
+    if (R == 0) continue;
+    uint32_t tb = 9;  // table of 2^tb places, at least 2R
+    while (tb < (uint32_t)kTblBits && (1u << tb) < 2u * R) ++tb;
+    const uint32_t T = 1u << tb;
+    // Slices, depth first: slice (M, r) holds the keys whose mix is r mod M;
+    // one that overflows is replaced by its halves (2M, r) and (2M, r + M).
+    // Every thread keeps the same (M, r).
+    uint32_t M = 1u, r = 0u;
+    for (;;) {
+      for (uint32_t i0 = 0; i0 < R; i0 += kThreads * kRecBatch) {
+        uint2 rc[kRecBatch];
+#pragma unroll
+        for (int k = 0; k < kRecBatch; ++k) {
+          const uint32_t i = i0 + (uint32_t)k * kThreads + tid;
+          rc[k] = make_uint2(kNoKey, 0u);
+          if (i < R) {
+            int lo = 0, hi = kExpGrid - 1;  // last segment g with s_pre[g] <= i
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_pre[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            rc[k] = a.rec[s_st[lo] + (i - s_pre[lo])];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kRecBatch; ++k) {
+          if (rc[k].x == kNoKey) continue;
+          const uint32_t h = fmix32(rc[k].x);
+          if ((h & (M - 1u)) != r) continue;
+          const long long q = to_grid(__uint_as_float(rc[k].y));
+          if (q == 0) continue;  // below the grid
+          uint32_t p = h >> (32 - tb);
+          for (int probe = 0;; ++probe) {
+            if (probe == kMaxProbe || s_ovf) {
+              s_ovf = 1;
+              break;
+            }
+            const uint32_t k0 = __hip_atomic_load(&s_key[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k0 == rc[k].x) {
+              atomicAdd(&s_val[p], (unsigned long long)q);
+              break;
+            }
+            if (k0 == kNoKey) {
+              const uint32_t prev = atomicCAS(&s_key[p], kNoKey, rc[k].x);
+              if (prev == kNoKey || prev == rc[k].x) {
+                atomicAdd(&s_val[p], (unsigned long long)q);
+                break;
+              }
+            }
+            p = (p + 1u) & (T - 1u);
+          }
+        }
+      }
+      __syncthreads();
+      if (s_ovf) {  // split this slice in two and clear the table
+        for (uint32_t t = tid; t < T; t += kThreads) {
+          s_key[t] = kNoKey;
+          s_val[t] = 0ull;
+        }
+        __syncthreads();
+        if (tid == 0) s_ovf = 0;
+        __syncthreads();
+        M *= 2u;
+        continue;
+      }
+      for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {
+        const uint32_t t = t0 + tid;
+        const uint32_t key = t < T ? s_key[t] : kNoKey;
+        bool want = false;
+        int32_t s = 0, v = 0;
+        float h = 0.0f;
+        uint2 row = make_uint2(0u, 0u);
+        if (key != kNoKey) {
+          const long long q = (long long)s_val[t];
+          s_key[t] = kNoKey;
+          s_val[t] = 0ull;
+          s = (int32_t)(key >> sh);
+          v = (int32_t)((b << sh) | (key & vmask));
+          const Slot& S = a.slots[s];
+          if (S.last) {  // the returned level: weight * exact sum into the estimate
+            unsafeAtomicAdd(&S.acc[v], grid_f64(q) * S.w);
+            ++nfin;
+          } else {
+            ++nnext;
+            h = grid_f32(q);
+            // Rule 2 on the next level: keep v when Score(v) > eps_p / sqrt(c)^(i-j-2)
+            const float thr = S.thr_next;
+            if (fabsf(h - thr) <= 1e-5f * thr) {  // FP32 rounding may decide this test
+              ++near;
+              unsafeAtomicAdd(S.flip, S.flip_unit);
+            }
+            if (h > thr) {
+              ++kept;
+              row = S.out_rows[v];
+              want = row.y > 0;
+            } else {
+              ++pruned;
+            }
+          }
+        }
+        if (want) {
+          a.has_next[s] = 1;
+          atomicAdd(&s_part[s], row.y);
+          atomicAdd(&s_part[a.P + s], 1u);
+          dirty = true;
+        }
+        stage_put(want, s, v, h, row, ws, a.nxt, ctr);
+      }
+      // next slice: the sibling of the nearest first-half ancestor
+      while (M > 1u && r >= (M >> 1)) {
+        r -= M >> 1;
+        M >>= 1;
+      }
+      if (M == 1u) break;
+      r += M >> 1;
+      __syncthreads();  // this slice's table is emptied before the next fills it
+    }
+  }
+  stage_flush(ws, a.nxt, ctr);
+  if (dirty) s_dirty = 1;
+  __syncthreads();
+  if (s_dirty) {  // partial per-slot sums of what this workgroup listed (k_sched adds them up)
+    uint32_t* prow = a.part + (size_t)(blockIdx.x % kPartRows) * 2 * a.P;
+    for (int i = tid; i < 2 * a.P; i += kThreads)
+      if (s_part[i]) atomicAdd(&prow[i], s_part[i]);
+  }
+  nfin = wave_sum(nfin);
+  nnext = wave_sum(nnext);
+  kept = wave_sum(kept);
+  pruned = wave_sum(pruned);
+  near = wave_sum(near);
+  if (lane == 0) {
+    if (nfin) atomicAdd(&ctr[C_FINAL], nfin);
+    if (nnext) atomicAdd(&ctr[C_NEXT], nnext);
+    if (kept) atomicAdd(&ctr[C_KEPT], kept);
+    if (pruned) atomicAdd(&ctr[C_PRUNED], pruned);
+    if (near) atomicAdd(&ctr[C_NEAR], near);
   }
 }
 
@@ -1374,13 +2054,18 @@ void tree_release(Session* s, uint64_t start, uint64_t len) {
 
 }  // namespace
 
+static uint64_t list_total(const uint64_t* h, int par) {
+  uint64_t t = 0;
+  for (int k = 0; k < kSubLists; ++k) t += h[C_LIST + par * kSubLists + k];
+  return t;
+}
+
 void report_overflow(const Session* s, const uint64_t* h) {
   std::fprintf(stderr,
-               "probesim: capacity guard tripped (sites 0x%llx: 1 roots, 2 chunks, 4 next level, 16 ring); "
-               "P %d n %d list cap %llu (lists %llu, %llu) chunk cap %llu (chunks %llu)\n",
+               "probesim: capacity guard tripped (sites 0x%llx: 4 frontier list, 8 records, 16 ring); "
+               "P %d n %d list cap %llu (lists %llu, %llu) record cap %llu\n",
                (unsigned long long)h[C_OVERFLOW], s->P, s->n, (unsigned long long)s->list_cap,
-               (unsigned long long)h[C_LIST0], (unsigned long long)h[C_LIST1], (unsigned long long)s->chunk_cap,
-               (unsigned long long)h[C_CHUNK]);
+               (unsigned long long)list_total(h, 0), (unsigned long long)list_total(h, 1), (unsigned long long)s->rec_cap);
 }
 
 void session_clear_guard(Session* s, hipStream_t st) {
@@ -1411,14 +2096,15 @@ void devbuf_free(DevBuf& b) {
 
 void session_free(Session* s) {
   if (!s) return;
-  DevBuf* bufs[] = {&s->mat[0], &s->mat[1], &s->rowmap[0], &s->rowmap[1], &s->npart, &s->lane_slot, &s->dense_ver, &s->slot_edges, &s->pull_flag, &s->slots,    &s->has_next,  &s->dense[0],   &s->dense[1],    &s->list[0],      &s->list[1],
-                    &s->item_val, &s->item_row, &s->chunk_list, &s->counters,   &s->qrec,         &s->thr,
-                    &s->remaining, &s->done_ring, &s->qbound,     &s->acc,         &s->lq,           &s->flip,
-                    &s->keys,
-                    &s->t_parent, &s->t_node,    &s->t_depth,     &s->t_query,     &s->t_weight,     &s->ring, &s->ring_k,
-                    &s->hyb_edges, &s->t_woff, &s->t_walks, &s->wcount,
-                    &s->sort_keys[0], &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp,
-                    &s->sel_count};
+  DevBuf* bufs[] = {&s->mat[0],    &s->mat[1],       &s->rowmap[0],  &s->rowmap[1],  &s->npart,     &s->lane_slot,
+                    &s->dense_ver, &s->slots,        &s->has_next,   &s->pull_flag,  &s->was_paused, &s->slot_edges,
+                    &s->slot_cnt,  &s->cost, &s->counters,     &s->l_sn[0],    &s->l_sn[1],    &s->l_val[0],  &s->l_val[1],
+                    &s->l_row[0],  &s->l_row[1],     &s->l_chunk[0], &s->l_chunk[1], &s->rec,       &s->seg,
+                    &s->part,      &s->qrec,       &s->thr,        &s->remaining, &s->done_ring,
+                    &s->qbound,    &s->acc,          &s->lq,         &s->flip,       &s->keys,      &s->t_parent,
+                    &s->t_node,    &s->t_depth,      &s->t_query,    &s->t_weight,   &s->ring,      &s->ring_k,
+                    &s->hyb_edges, &s->t_woff,       &s->t_walks,    &s->wcount,     &s->sort_keys[0],
+                    &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp, &s->sel_count};
   for (DevBuf* b : bufs) devbuf_free(*b);
   if (s->h_ctr) (void)hipHostFree(s->h_ctr);
   if (s->step_pair) (void)hipGraphExecDestroy(s->step_pair);
@@ -1426,16 +2112,30 @@ void session_free(Session* s) {
 }
 
 // Probe slots: enough concurrent probes to fill the GPU (more slots also
-// mean fewer level steps), at most 1024 by default, and never more than the
-// per-slot buffers (grid sums 16 B, frontier lists 16 B, scaled scores 4 B,
-// rows 8 B, chunks 8 B per node) fit in a fixed share of HBM, with slot * n
-// within 31 bits.  An explicit request is clamped the same way.
+// mean fewer level steps).  A slot costs a few hundred bytes; its frontier
+// lives in the shared lists, so the count is bounded by the scheduler's LDS
+// arrays only.  1024 by default.
 int session_slots_for(int32_t n, int opt) {
-  const uint64_t budget = 56ull << 30;
-  uint64_t p = budget / (52ull * (uint64_t)n);
-  p = std::min<uint64_t>(p, ((1ull << 31) - 1) / (uint64_t)n);
-  p = std::min<uint64_t>(p, opt > 0 ? (uint64_t)std::min(opt, kSchedThreads * kSlotsPerSchedThread) : 1024ull);
-  return (int)std::max<uint64_t>(p, 1);
+  (void)n;
+  const int p = opt > 0 ? std::min(opt, kSlotCap) : 1024;
+  return std::max(p, 1);
+}
+
+// Dense lanes (levels computed by pulling): two node-major n x kLanes FP32
+// matrices, their row maps and the partial sums of long in-rows; allocated
+// the first time levels may be pulled.
+static ps_status session_dense(Session* s, hipStream_t st) {
+  const size_t n = (size_t)s->n;
+  PS_TRY(devbuf_reserve(s->mat[0], sizeof(float) * n * kLanes));
+  PS_TRY(devbuf_reserve(s->mat[1], sizeof(float) * n * kLanes));
+  PS_TRY(devbuf_reserve(s->npart, sizeof(long long) * n * kLanes));
+  PS_TRY(devbuf_reserve(s->rowmap[0], n));
+  PS_TRY(devbuf_reserve(s->rowmap[1], n));
+  for (DevBuf* b : {&s->mat[0], &s->mat[1]}) PS_HIP(hipMemsetAsync(b->p, 0, sizeof(float) * n * kLanes, st));
+  PS_HIP(hipMemsetAsync(s->npart.p, 0, sizeof(long long) * n * kLanes, st));
+  for (DevBuf* b : {&s->rowmap[0], &s->rowmap[1]}) PS_HIP(hipMemsetAsync(b->p, 0, n, st));
+  s->dense_on = true;
+  return PS_OK;
 }
 
 ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax, uint64_t tree_pool,
@@ -1444,8 +2144,17 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   hipStream_t st = ctx->stream;
   ring_cap = next_pow2(std::max<uint64_t>(ring_cap, 1024));
   tree_pool = std::max<uint64_t>(tree_pool, 1024);
+  // Capacities of one step, sized by the graph: 8 m records (2^24..2^30)
+  // and as many list entries (up to 2^29).  A level step whose levels would
+  // write more than kStepRecords records, or list more than the list holds
+  // (at most one entry per record for the next levels), pauses slots
+  // (k_expand); a single level may still use the whole record store.
+  const uint64_t cap8 = 8ull * m_cap;
+  const uint64_t rec_cap = std::min<uint64_t>(std::max<uint64_t>(cap8, 1ull << 24), 1ull << 30);
+  const uint64_t list_cap = std::min<uint64_t>(std::max<uint64_t>(cap8, 1ull << 24), 1ull << 29);
+  const uint64_t chunk_cap = std::max<uint64_t>(list_cap / 8, 1ull << 22);
   if (s && s->n == n && s->P == P && s->qmax >= qmax && s->tree_pool >= tree_pool && s->ring_cap >= ring_cap &&
-      s->chunk_cap >= s->list_cap + ((uint64_t)P * m_cap) / kChunk + 1)
+      s->rec_cap >= rec_cap)
     return PS_OK;
   if (s && (int)s->free_recs.size() != s->qmax) return PS_ERR_STATE;  // queries admitted
   if (!s) s = new Session();
@@ -1453,36 +2162,37 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
     (void)hipGraphExecDestroy(s->step_pair);
     s->step_pair = nullptr;
   }
-  const bool shape = s->n != n || s->P != P;
   s->n = n;
   s->P = P;
   s->qmax = std::max(qmax, s->qmax);
   s->tree_pool = std::max(tree_pool, s->tree_pool);
   s->ring_cap = std::max(ring_cap, s->ring_cap);
-  // Every (slot, node) pair enters a frontier list at most once per step, so
-  // P * n entries never overflow; chunks add at most m / 512 per slot.
-  s->list_cap = (uint64_t)P * (uint64_t)n;
-  s->chunk_cap = s->list_cap + ((uint64_t)P * m_cap) / kChunk + 1;
+  s->sh = 0;
+  while ((((uint64_t)n - 1) >> s->sh) >= (uint64_t)kMaxBins) ++s->sh;
+  s->rec_cap = std::max(rec_cap, s->rec_cap);
+  s->list_cap = std::max(list_cap, s->list_cap);
+  s->chunk_cap = std::max(chunk_cap, s->chunk_cap);
+  s->list_soft = s->list_cap - (uint64_t)P;  // room for every slot's H_0 at the next step
   PS_TRY(devbuf_reserve(s->slots, sizeof(Slot) * (size_t)P));
   PS_TRY(devbuf_reserve(s->has_next, sizeof(int32_t) * (size_t)P));
-  PS_TRY(devbuf_reserve(s->slot_edges, sizeof(unsigned long long) * (size_t)P));
-  PS_TRY(devbuf_reserve(s->hyb_edges, sizeof(unsigned long long) * (size_t)P));
   PS_TRY(devbuf_reserve(s->pull_flag, sizeof(int32_t) * (size_t)P));
-  PS_TRY(devbuf_reserve(s->mat[0], sizeof(float) * (size_t)n * kLanes));
-  PS_TRY(devbuf_reserve(s->mat[1], sizeof(float) * (size_t)n * kLanes));
-  PS_TRY(devbuf_reserve(s->npart, sizeof(long long) * (size_t)n * kLanes));
-  PS_TRY(devbuf_reserve(s->rowmap[0], (size_t)n));
-  PS_TRY(devbuf_reserve(s->rowmap[1], (size_t)n));
+  PS_TRY(devbuf_reserve(s->was_paused, (size_t)P));
+  PS_TRY(devbuf_reserve(s->slot_edges, sizeof(uint32_t) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->slot_cnt, sizeof(uint32_t) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->cost, sizeof(uint4) * (size_t)P));
+  PS_TRY(devbuf_reserve(s->hyb_edges, sizeof(unsigned long long) * (size_t)P));
   PS_TRY(devbuf_reserve(s->lane_slot, sizeof(int32_t) * kLanes));
   PS_TRY(devbuf_reserve(s->dense_ver, sizeof(DenseVer)));
-  const bool fresh = !s->dense[0].p || shape;
-  PS_TRY(devbuf_reserve(s->dense[0], sizeof(long long) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->dense[1], sizeof(long long) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->list[0], sizeof(int2) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->list[1], sizeof(int2) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->item_val, sizeof(float) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->item_row, sizeof(uint2) * s->list_cap));
-  PS_TRY(devbuf_reserve(s->chunk_list, sizeof(int2) * s->chunk_cap));
+  for (int p = 0; p < 2; ++p) {
+    PS_TRY(devbuf_reserve(s->l_sn[p], sizeof(int2) * s->list_cap));
+    PS_TRY(devbuf_reserve(s->l_val[p], sizeof(float) * s->list_cap));
+    PS_TRY(devbuf_reserve(s->l_row[p], sizeof(uint2) * s->list_cap));
+    PS_TRY(devbuf_reserve(s->l_chunk[p], sizeof(int2) * s->chunk_cap));
+  }
+  PS_TRY(devbuf_reserve(s->rec, sizeof(uint2) * s->rec_cap));
+  PS_TRY(devbuf_reserve(s->seg, sizeof(uint2) * (size_t)kMaxBins * kExpGrid));
+  PS_TRY(devbuf_reserve(s->part, sizeof(uint32_t) * 2 * (size_t)P * kPartRows));
+
   PS_TRY(devbuf_reserve(s->counters, sizeof(unsigned long long) * C_COUNT));
   PS_TRY(devbuf_reserve(s->qrec, sizeof(QueryDev) * (size_t)s->qmax));
   PS_TRY(devbuf_reserve(s->thr, sizeof(float) * (size_t)s->qmax * PS_MAX_WALK_LEN));
@@ -1504,16 +2214,12 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
   PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
   if (!s->h_ctr) PS_HIP(hipHostMalloc((void**)&s->h_ctr, sizeof(uint64_t) * C_COUNT, 0));
-  if (fresh) {
-    PS_HIP(hipMemsetAsync(s->dense[0].p, 0, sizeof(long long) * s->list_cap, st));
-    PS_HIP(hipMemsetAsync(s->dense[1].p, 0, sizeof(long long) * s->list_cap, st));
-  }
-  for (DevBuf* b : {&s->mat[0], &s->mat[1]}) PS_HIP(hipMemsetAsync(b->p, 0, sizeof(float) * (size_t)n * kLanes, st));
-  PS_HIP(hipMemsetAsync(s->npart.p, 0, sizeof(long long) * (size_t)n * kLanes, st));
-  for (DevBuf* b : {&s->rowmap[0], &s->rowmap[1]}) PS_HIP(hipMemsetAsync(b->p, 0, (size_t)n, st));
+  if (s->dense_on) PS_TRY(session_dense(s, st));
   k_reset_lanes<<<1, kLanes, 0, st>>>(s->lane_slot.as<int32_t>());
   PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
   PS_HIP(hipMemsetAsync(s->hyb_edges.p, 0, sizeof(unsigned long long) * (size_t)P, st));
+  PS_HIP(hipMemsetAsync(s->pull_flag.p, 0, sizeof(int32_t) * (size_t)P, st));
+  PS_HIP(hipMemsetAsync(s->part.p, 0, sizeof(uint32_t) * 2 * (size_t)P * kPartRows, st));
   k_reset_slots<<<grid_for((uint64_t)P, kBlock), kBlock, 0, st>>>(s->slots.as<Slot>(), s->has_next.as<int32_t>(), P);
   PS_HIP(hipGetLastError());
   s->steps = 0;
@@ -1701,25 +2407,39 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
                                                                       s->t_walks.as<int32_t>());
     PS_HIP(hipGetLastError());
   }
+  k_snap_tail<<<1, 1, 0, st>>>(s->counters.as<unsigned long long>());
+  PS_HIP(hipGetLastError());
   return PS_OK;
 }
 
 namespace {
 
-struct StepKernels {
-  SchedArgs sa;
-  ExpandArgs ea;
-};
+FList flist(Session* s, int par) {
+  FList L;
+  L.sn = s->l_sn[par].as<int2>();
+  L.val = s->l_val[par].as<float>();
+  L.row = s->l_row[par].as<uint2>();
+  L.chunk = s->l_chunk[par].as<int2>();
+  L.n_ent = s->counters.as<unsigned long long>() + C_LIST + par * kSubLists;
+  L.n_chunk = s->counters.as<unsigned long long>() + C_CHUNK + par * kSubLists;
+  L.sub_cap = s->list_cap / kSubLists;
+  L.sub_chunk_cap = s->chunk_cap / kSubLists;
+  return L;
+}
 
-StepKernels step_args(Session* s) {
-  StepKernels k{};
+// One level step with the frontier lists of parity `cur`: k_sched, k_pick and
+// the dense pass only when levels may be pulled, k_expand, k_reduce.
+void launch_step(Session* s, int cur, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
+  const int nxt = cur ^ 1;
   unsigned long long* ctr = s->counters.as<unsigned long long>();
-  SchedArgs& sa = k.sa;
+  SchedArgs sa{};
   sa.P = s->P;
   sa.n = s->n;
   sa.qmax = s->qmax;
   sa.slots = s->slots.as<Slot>();
   sa.has_next = s->has_next.as<int32_t>();
+  sa.pull_flag = s->pull_flag.as<int32_t>();
+  sa.was_paused = s->was_paused.as<uint8_t>();
   sa.ring = s->ring.as<int32_t>();
   sa.ring_k = s->ring_k.as<int32_t>();
   sa.ring_mask = s->ring_cap - 1;
@@ -1728,85 +2448,89 @@ StepKernels step_args(Session* s) {
   sa.t_depth = s->t_depth.as<int32_t>();
   sa.t_query = s->t_query.as<int32_t>();
   sa.t_weight = s->t_weight.as<int32_t>();
+  sa.t_woff = s->t_woff.as<uint32_t>();
+  sa.t_walks = s->t_walks.as<int32_t>();
   sa.qr = s->qrec.as<QueryDev>();
   sa.thr_tab = s->thr.as<float>();
   sa.remaining = s->remaining.as<unsigned long long>();
   sa.done_ring = s->done_ring.as<int32_t>();
-  sa.list_cap = s->list_cap;
-  sa.slot_edges = s->slot_edges.as<unsigned long long>();
+  sa.hyb_edges = s->hyb_edges.as<unsigned long long>();
   sa.lane_slot = s->lane_slot.as<int32_t>();
+  sa.part = s->part.as<uint32_t>();
+  sa.slot_edges = s->slot_edges.as<uint32_t>();
+  sa.slot_cnt = s->slot_cnt.as<uint32_t>();
+  sa.cost = s->cost.as<uint4>();
+  sa.list = flist(s, cur);
+  sa.next = flist(s, nxt);
   sa.ctr = ctr;
-  ExpandArgs& ea = k.ea;
-  ea.pull_flag = s->pull_flag.as<int32_t>();
+  sa.cur = cur;
+  k_sched<<<(s->P + kSchedBlock - 1) / kSchedBlock, kSchedBlock, 0, st>>>(sa);
+  if (s->pull) {
+    PickArgs pa{};
+    pa.P = s->P;
+    pa.n = s->n;
+    pa.slots = s->slots.as<Slot>();
+    pa.pull_flag = s->pull_flag.as<int32_t>();
+    pa.lane_slot = s->lane_slot.as<int32_t>();
+    pa.dv = s->dense_ver.as<DenseVer>();
+    pa.slot_edges = s->slot_edges.as<uint32_t>();
+    pa.slot_cnt = s->slot_cnt.as<uint32_t>();
+    pa.cost = s->cost.as<uint4>();
+    pa.ctr = ctr;
+    k_pick<<<1, kPickThreads, 0, st>>>(pa);
+  }
+  ExpandArgs ea{};
   ea.n = s->n;
-  ea.item_val = s->item_val.as<float>();
-  ea.item_row = s->item_row.as<uint2>();
-  ea.chunk_list = s->chunk_list.as<int2>();
+  ea.P = s->P;
+  ea.sh_min = s->sh;
+  ea.cost = s->cost.as<uint4>();
   ea.slots = s->slots.as<Slot>();
-  ea.list_cap = s->list_cap;
-  ea.chunk_cap = s->chunk_cap;
+  ea.pull_flag = s->pull_flag.as<int32_t>();
+  ea.cur = flist(s, cur);
+  ea.nxt = flist(s, nxt);
+  ea.rec = s->rec.as<uint2>();
+  ea.rec_cap = s->rec_cap;
+  ea.seg = s->seg.as<uint2>();
+  ea.mat_cur = s->dense_on ? s->mat[cur].as<float>() : nullptr;
+  ea.map_cur = s->dense_on ? s->rowmap[cur].as<uint8_t>() : nullptr;
   ea.has_next = s->has_next.as<int32_t>();
+  ea.part = s->part.as<uint32_t>();
+  ea.list_soft = s->list_soft;
   ea.ctr = ctr;
-  return k;
-}
-
-// One level step with the frontier lists of parity `cur`.
-void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
-                 hipEvent_t ev2) {
-  const int nxt = cur ^ 1;
-  unsigned long long* ctr = s->counters.as<unsigned long long>();
-  k.sa.dense_cur = s->dense[cur].as<long long>();
-  k.sa.list_cur = s->list[cur].as<int2>();
-  k.sa.cur = cur;
-  k_sched<<<1, kSchedThreads, 0, st>>>(k.sa);
-  k_prep<<<kStepGrid, kBlock, 0, st>>>(s->n, s->slots.as<Slot>(), s->list[cur].as<int2>(), s->dense[cur].as<long long>(),
-                                       s->item_val.as<float>(), s->item_row.as<uint2>(), s->chunk_list.as<int2>(),
-                                       s->list_cap, s->chunk_cap, s->slot_edges.as<unsigned long long>(), ctr, cur);
-  PickArgs pa{};
-  pa.P = s->P;
-  pa.slot_edges = s->slot_edges.as<unsigned long long>();
-  pa.hyb_edges = s->hyb_edges.as<unsigned long long>();
-  pa.slots = s->slots.as<Slot>();
-  pa.pull_flag = s->pull_flag.as<int32_t>();
-  pa.lane_slot = s->lane_slot.as<int32_t>();
-  pa.dv = s->dense_ver.as<DenseVer>();
-  pa.t_weight = s->t_weight.as<int32_t>();
-  pa.t_woff = s->t_woff.as<uint32_t>();
-  pa.t_walks = s->t_walks.as<int32_t>();
-  pa.ring = s->ring.as<int32_t>();
-  pa.ring_k = s->ring_k.as<int32_t>();
-  pa.ring_mask = s->ring_cap - 1;
-  pa.remaining = s->remaining.as<unsigned long long>();
-  pa.ctr = ctr;
-  k_pick<<<1, kSchedThreads, 0, st>>>(pa);
-  k.ea.list_cur = s->list[cur].as<int2>();
-  k.ea.cur = cur;
-  k.ea.dense_cur = s->dense[cur].as<long long>();
-  k.ea.mat_cur = s->mat[cur].as<float>();
-  k.ea.map_cur = s->rowmap[cur].as<uint8_t>();
-  k.ea.dense_next = s->dense[nxt].as<long long>();
-  k.ea.list_next = s->list[nxt].as<int2>();
-  k.ea.nxt = nxt;
+  ea.cur_par = cur;
   if (ev0) (void)hipEventRecord(ev0, st);
-  k_expand<<<kStepGrid, kBlock, 0, st>>>(k.ea);
+  k_expand<<<kExpGrid, kThreads, 0, st>>>(ea);
+  ReduceArgs ra{};
+  ra.n = s->n;
+  ra.P = s->P;
+  ra.slots = s->slots.as<Slot>();
+  ra.rec = s->rec.as<uint2>();
+  ra.seg = s->seg.as<uint2>();
+  ra.nxt = flist(s, nxt);
+  ra.has_next = s->has_next.as<int32_t>();
+  ra.part = s->part.as<uint32_t>();
+  ra.ctr = ctr;
+  k_reduce<<<kRedGrid, kThreads, 0, st>>>(ra);
   if (ev1) (void)hipEventRecord(ev1, st);
-  DenseArgs da{};
-  da.n = s->n;
-  da.slots = s->slots.as<Slot>();
-  da.lane_slot = s->lane_slot.as<int32_t>();
-  da.dv = s->dense_ver.as<DenseVer>();
-  da.mat_cur = s->mat[cur].as<float>();
-  da.mat_next = s->mat[nxt].as<float>();
-  da.map_cur = s->rowmap[cur].as<uint8_t>();
-  da.map_next = s->rowmap[nxt].as<uint8_t>();
-  da.npart = s->npart.as<long long>();
-  da.hyb_edges = s->hyb_edges.as<unsigned long long>();
-  da.has_next = s->has_next.as<int32_t>();
-  da.ctr = ctr;
-  da.cur = cur;
-  k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
-  k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
-  k_hyb_count<<<kStepGrid / 4, kBlock, 0, st>>>(da);
+  if (s->pull) {
+    DenseArgs da{};
+    da.n = s->n;
+    da.slots = s->slots.as<Slot>();
+    da.lane_slot = s->lane_slot.as<int32_t>();
+    da.dv = s->dense_ver.as<DenseVer>();
+    da.mat_cur = s->mat[cur].as<float>();
+    da.mat_next = s->mat[nxt].as<float>();
+    da.map_cur = s->rowmap[cur].as<uint8_t>();
+    da.map_next = s->rowmap[nxt].as<uint8_t>();
+    da.npart = s->npart.as<long long>();
+    da.hyb_edges = s->hyb_edges.as<unsigned long long>();
+    da.has_next = s->has_next.as<int32_t>();
+    da.ctr = ctr;
+    da.cur = cur;
+    k_dense<<<kStepGrid, kBlock, 0, st>>>(da);
+    k_dense_fin<<<kStepGrid / 4, kBlock, 0, st>>>(da);
+    k_hyb_count<<<kStepGrid / 4, kBlock, 0, st>>>(da);
+  }
   if (ev2) (void)hipEventRecord(ev2, st);
 }
 
@@ -1818,7 +2542,6 @@ void launch_step(Session* s, StepKernels& k, int cur, hipStream_t st, hipEvent_t
 ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* pull_ms) {
   Session* s = ctx->sess;
   hipStream_t st = ctx->stream;
-  StepKernels k = step_args(s);
   const bool timing = ctx->timing && expand_ms;
   if (timing) {
     while (ctx->ev_pool.size() < 3 * count) {
@@ -1827,7 +2550,7 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* 
       ctx->ev_pool.push_back(ev);
     }
     for (uint64_t t = 0; t < count; ++t) {
-      launch_step(s, k, (int)(s->steps & 1), st, ctx->ev_pool[3 * t], ctx->ev_pool[3 * t + 1],
+      launch_step(s, (int)(s->steps & 1), st, ctx->ev_pool[3 * t], ctx->ev_pool[3 * t + 1],
                   ctx->ev_pool[3 * t + 2]);
       s->steps++;
     }
@@ -1847,17 +2570,18 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* 
   }
   if (count >= 4) {
     if (s->steps & 1) {
-      launch_step(s, k, 1, st, nullptr, nullptr, nullptr);
+      launch_step(s, 1, st, nullptr, nullptr, nullptr);
       s->steps++;
       count--;
     }
     if (!s->step_pair) {
       hipGraph_t graph = nullptr;
       PS_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      launch_step(s, k, 0, st, nullptr, nullptr, nullptr);
-      launch_step(s, k, 1, st, nullptr, nullptr, nullptr);
+      launch_step(s, 0, st, nullptr, nullptr, nullptr);
+      launch_step(s, 1, st, nullptr, nullptr, nullptr);
       PS_HIP(hipStreamEndCapture(st, &graph));
       const hipError_t e = hipGraphInstantiate(&s->step_pair, graph, nullptr, nullptr, 0);
+      s->pair_dense = s->pull;
       (void)hipGraphDestroy(graph);
       PS_HIP(e);
     }
@@ -1867,7 +2591,7 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* 
     }
   }
   for (; count > 0; --count) {
-    launch_step(s, k, (int)(s->steps & 1), st, nullptr, nullptr, nullptr);
+    launch_step(s, (int)(s->steps & 1), st, nullptr, nullptr, nullptr);
     s->steps++;
   }
   PS_HIP(hipGetLastError());
@@ -1978,6 +2702,11 @@ ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun&
 // Pull threshold in out-edges of a slot's kept entries: a pull reads every
 // in-edge of the graph once, so it pays off when the level would push along
 // a sizable share of them.
+// Pull threshold in out-edges of a slot's listed entries.  Pushing costs
+// records per out-edge, pulling reads every in-edge of the graph once for up
+// to kLanes levels, so pulling pays off for levels with a sizable share of m
+// out-edges: m/20 by default (the fastest of m/80..m/10 and never on the
+// 1M-node workload), opt > 0 sets it, opt < 0 never pulls.
 uint64_t pull_threshold(int64_t m, int64_t opt) {
   if (opt < 0) return ~0ull;
   if (opt > 0) return (uint64_t)opt;
@@ -1986,6 +2715,14 @@ uint64_t pull_threshold(int64_t m, int64_t opt) {
 
 ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold) {
   Session* s = ctx->sess;
+  const bool dense = threshold != ~0ull;
+  if (dense && !s->dense_on) PS_TRY(session_dense(s, ctx->stream));
+  if (s->step_pair && s->pair_dense != dense) {  // captured with the other kernel sequence
+    PS_HIP(hipStreamSynchronize(ctx->stream));
+    (void)hipGraphExecDestroy(s->step_pair);
+    s->step_pair = nullptr;
+  }
+  s->pull = dense;
   k_set_u64<<<1, 1, 0, ctx->stream>>>(s->counters.as<unsigned long long>() + C_PULL_T,
                                       (unsigned long long)threshold);
   PS_HIP(hipGetLastError());
@@ -2051,31 +2788,73 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   const uint64_t probes = s->h_ctr[C_TAIL] - before[C_TAIL];
   int maxL = 2;
   for (auto& q : qs) maxL = std::max(maxL, q.prm.L);
-  // Greedy list scheduling: every slot is busy while probes are pending, and a
-  // probe holds its slot for depth-1 steps, so this many steps finish them all.
+  uint64_t with_probes = 0;
+  for (size_t i = 0; i < qs.size(); ++i) with_probes += bounds[i] ? 1 : 0;
+  // List scheduling: every slot is busy while probes are pending, and a
+  // probe holds its slot for depth-1 steps, so this many steps finish them
+  // all unless the per-step budget pauses slots or Section 4.4 switches
+  // queue more probes; then further batches of steps, sized the same way,
+  // run until every query is complete.
   uint64_t steps = probes ? (levels + P - 1) / P + (uint64_t)maxL + 2 : 0;
   double expand_ms = 0.0, pull_ms = 0.0;
   PS_TRY(session_set_pull(ctx, pull_threshold(g->m, pull_opt)));
-  PS_TRY(session_steps(ctx, steps, &expand_ms, &pull_ms));
-  bool hybrid = false;
-  uint64_t with_probes = 0;
-  for (size_t i = 0; i < qs.size(); ++i) {
-    hybrid |= qs[i].hybrid != 0;
-    with_probes += bounds[i] ? 1 : 0;
-  }
-  uint64_t total_steps = steps;
-  // Probes switched under Section 4.4 queue randomized probes while the
-  // steps run: those run in further batches of steps, sized the same way,
-  // until every query is complete (a few batches at most; the cap is a guard).
-  for (int round = 0; hybrid && round < 16; ++round) {
+  const bool progress = std::getenv("PS_PROGRESS") != nullptr;
+  uint64_t total_steps = 0;
+  // runs `cnt` level steps (in batches of 256 when progress is printed)
+  auto run_steps = [&](uint64_t cnt) -> ps_status {
+    while (cnt) {
+      const uint64_t b = progress ? std::min<uint64_t>(cnt, 256) : cnt;
+      PS_TRY(session_steps(ctx, b, &expand_ms, &pull_ms));
+      total_steps += b;
+      cnt -= b;
+      if (progress && cnt) {
+        PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
+        PS_HIP(hipStreamSynchronize(st));
+        std::fprintf(stderr, "probesim: %llu steps, %llu probes handed out, %llu paused\n",
+                     (unsigned long long)total_steps, (unsigned long long)(s->h_ctr[C_HEAD] - before[C_HEAD]),
+                     (unsigned long long)(s->h_ctr[C_PAUSED] - before[C_PAUSED]));
+      }
+    }
+    return PS_OK;
+  };
+  PS_TRY(run_steps(steps));
+  uint64_t stuck = 0, last_work = ~0ull;
+  for (;;) {
     PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
     PS_HIP(hipStreamSynchronize(st));
-    if (s->h_ctr[C_OVERFLOW] || s->h_ctr[C_DONE] - before[C_DONE] >= with_probes) break;
+    const uint64_t* h = s->h_ctr;
+    if (h[C_OVERFLOW] || h[C_DONE] - before[C_DONE] >= with_probes) break;
+    // a guard: no probe handed out, expanded, pulled or finished over whole batches
+    const uint64_t work = h[C_HEAD] + h[C_DONE] + h[C_EDGES] + h[C_PULLS] + h[C_FINAL] + h[C_LEVEL0];
+    stuck = work == last_work ? stuck + 1 : 0;
+    if (stuck > 2) break;
+    last_work = work;
+    if (progress)
+      std::fprintf(stderr, "probesim: %llu steps, %llu of %llu queries done, %llu of %llu probes handed out, %llu paused\n",
+                   (unsigned long long)total_steps, (unsigned long long)(h[C_DONE] - before[C_DONE]),
+                   (unsigned long long)with_probes, (unsigned long long)(h[C_HEAD] - before[C_HEAD]),
+                   (unsigned long long)(h[C_TAIL] - before[C_TAIL]), (unsigned long long)(h[C_PAUSED] - before[C_PAUSED]));
     const uint64_t lv = s->h_ctr[C_LEVELS] - before[C_LEVELS];
-    steps = (lv - levels + P - 1) / P + (uint64_t)maxL + 2;
-    levels = lv;
-    PS_TRY(session_steps(ctx, steps, &expand_ms, &pull_ms));
-    total_steps += steps;
+    steps = (lv > levels ? (lv - levels + P - 1) / P : 0) + (uint64_t)maxL + 2;
+    levels = std::max(levels, lv);
+    PS_TRY(run_steps(steps));
+  }
+  {
+    const uint64_t* h = s->h_ctr;
+    const bool over = h[C_OVERFLOW] != 0;
+    if (over || h[C_DONE] - before[C_DONE] != with_probes) {
+      if (over) report_overflow(s, h);
+      else
+        std::fprintf(stderr, "probesim: level steps ended with %llu of %llu queries complete\n",
+                     (unsigned long long)(h[C_DONE] - before[C_DONE]), (unsigned long long)with_probes);
+      // the session's device state is not usable any more: drop it
+      for (int r : recs)
+        if (s->rec_version[(size_t)r]) graph_release(g, s->rec_version[(size_t)r]);
+      (void)hipStreamSynchronize(st);
+      session_free(s);
+      ctx->sess = nullptr;
+      return over ? PS_ERR_OOM : PS_ERR_STATE;
+    }
   }
   std::vector<double> flips((size_t)nq, 0.0);
   for (int i = 0; i < nq; ++i) {
@@ -2091,11 +2870,6 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
     stats.flip_allowance = std::max(stats.flip_allowance, f);
   }
   const uint64_t* h = s->h_ctr;
-  if (h[C_OVERFLOW]) {  // impossible with worst-case capacities; a guard
-    report_overflow(s, h);
-    return PS_ERR_OOM;
-  }
-  if (h[C_HEAD] != h[C_TAIL]) return PS_ERR_STATE;
   stats.walks = 0;
   for (auto& q : qs) stats.walks += q.walk_end - q.walk_begin;
   stats.walk_nodes = (int64_t)(h[C_WALK_NODES] - before[C_WALK_NODES]);

@@ -150,28 +150,34 @@ struct QueryRun {
   double c0 = 0.0;     // the switch constant of a hybrid query
 };
 
-// State of one probe slot on the device.
+// A frontier list is kSubLists sub-lists, each with its own counter, so that
+// appends from many wavefronts spread their atomics over several addresses.
+constexpr int kSubLists = 16;
+
+// State of one probe slot on the device.  The fields the expansion and the
+// reduction read per edge or per entry come first (one cache line).
 struct Slot {
-  int32_t probe;   // tree node of the probe being run, -1 when idle
-  int32_t level;   // PROBE iteration j of the entries currently listed
-  int32_t depth;   // i: the probe runs on (u_1..u_i)
-  int32_t cursor;  // tree node whose graph node is excluded at this level
-  int32_t query;   // query record
-  int32_t excl;    // graph node u_{i-j-1}, skipped by this level's expansion
-  float thr;       // Rule 2: entries with score <= thr are removed
-  float sc;        // sqrt(c)
-  int32_t last;    // this level's expansion produces the returned score set
-  int32_t lane;    // column of the dense frontier matrix, -1 for a sparse frontier
-  int32_t mode;    // 1: randomized PROBE (Alg. 4) of walk wk's prefix
-  uint32_t wk;     // walk index of a randomized probe
-  uint32_t t_sc;   // floor(sqrt(c) * 2^32)
-  uint2 key2;      // Philox key of Alg. 4's draws
-  double w;        // number of walks sharing the probed prefix
-  const uint2* out_rows;
   const int32_t* out_col;
   const float* inv_indeg;
+  const uint2* out_rows;
   double* acc;
-  const uint2* in_rows;  // for levels computed by pulling
+  double w;          // number of walks sharing the probed prefix (1 for a randomized probe)
+  int32_t excl;      // graph node u_{i-j-1}, skipped by this level's expansion
+  float sc;          // sqrt(c)
+  float thr_next;    // Rule 2 threshold of the next level (score <= thr_next is removed)
+  int32_t last;      // this level's expansion produces the returned score set
+  int32_t mode;      // 1: randomized PROBE (Alg. 4) of walk wk's prefix
+  uint32_t wk;       // walk index of a randomized probe
+  int32_t probe;     // tree node of the probe being run, -1 when idle
+  int32_t level;     // PROBE iteration j of the entries currently listed
+  int32_t depth;     // i: the probe runs on (u_1..u_i)
+  int32_t cursor;    // tree node whose graph node is excluded at this level
+  int32_t query;     // query record
+  int32_t lane;      // column of the dense frontier matrix, -1 for a sparse frontier
+  float thr;         // Rule 2 threshold of the level being expanded
+  uint32_t t_sc;     // floor(sqrt(c) * 2^32)
+  uint2 key2;        // Philox key of Alg. 4's draws
+  const uint2* in_rows;  // for levels computed by pulling and Alg. 4's draws
   const int32_t* in_col;
   const int32_t* heavy_nodes;
   const int2* heavy_chunks;
@@ -179,17 +185,11 @@ struct Slot {
   double* flip;      // the query's near-threshold allowance
   double flip_unit;  // eps_p * w / n_r: what one Rule-2 flip can move an estimate by
   double hyb_thr;    // Section 4.4: switch when a level to expand has more out-edges (< 0: never)
-  float thr_next;    // Rule 2 threshold of the next level (what the dense pass counts against)
-  int32_t pad;
 };
 
 enum CounterIdx {
   C_TAIL = 0,    // probes appended to the ring
   C_HEAD,        // probes handed to slots
-  C_LIST0,       // entries in frontier list 0
-  C_LIST1,       // entries in frontier list 1
-  C_SMALL,       // short-row work items this step
-  C_CHUNK,       // chunk work items this step
   C_DONE,        // queries completed (entries in the done ring)
   C_LEVELS,      // sum over inserted probes of (depth - 1)
   C_WALK_NODES,
@@ -211,11 +211,24 @@ enum CounterIdx {
   C_NZROWS1,     // the same for matrix 1
   C_SWITCH,      // deterministic probes switched to randomized ones (Section 4.4)
   C_HYBMASK,     // dense columns whose next level k_hyb_count measures (bit per column)
-  C_EDGES_UNPUSHED,  // out-edges counted by k_prep of levels k_expand does not push (pulled or switched)
+  C_EDGES_UNPUSHED,  // listed out-edges of levels k_expand does not push (pulled or switched)
   C_FINAL_PULL,  // final contributions added by the dense pass
+  C_REC,         // records reserved by this step's expansion
+  C_BIN,         // bins taken by this step's reduction
+  C_TAIL_SNAP,   // C_TAIL when the last step's reduction started: what k_sched may claim
+  C_TOT_E,       // out-edges of the levels to push this step (deterministic)
+  C_TOT_N,       // bound on the next list's entries from this step's levels
+  C_TOT_F,       // listed entries of this step's levels
+  C_SWLANES,     // dense columns freed by switches this step (bit per column)
+  C_PAUSED,      // slot levels held back a step by the per-step budget
+  C_SH,          // bin shift of this step's records
+  C_NB,          // bins of this step's records
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
-  C_COUNT = C_HIST_E + 32
+  // entries and chunks of the frontier lists: kSubLists counters per parity
+  C_LIST = C_HIST_E + 32,
+  C_CHUNK = C_LIST + 2 * kSubLists,
+  C_COUNT = C_CHUNK + 2 * kSubLists
 };
 
 struct QueryOut {
@@ -234,10 +247,15 @@ struct Session {
   int32_t n = 0;
   int P = 0;
   int qmax = 0;
-  uint64_t list_cap = 0, chunk_cap = 0;
+  int sh = 0;               // smallest bin shift of the records (at most kMaxBins bins)
+  uint64_t list_cap = 0, chunk_cap = 0, rec_cap = 0, list_soft = 0;  // lists: all sub-lists together
   uint64_t tree_pool = 0;   // entries
   uint64_t ring_cap = 0;    // power of two
-  DevBuf slots, has_next, dense[2], list[2], item_val, item_row, chunk_list, counters, slot_edges, pull_flag;
+  DevBuf slots, has_next, pull_flag, was_paused, slot_edges, slot_cnt, cost, counters;
+  DevBuf l_sn[2], l_val[2], l_row[2], l_chunk[2];  // frontier lists by step parity
+  DevBuf rec, seg, part;                           // records, bin segments, per-slot partial sums
+  bool dense_on = false;                           // dense lanes allocated
+  bool pull = false;                               // levels may be pulled: steps run the dense pass
   DevBuf mat[2], rowmap[2], npart, lane_slot, dense_ver;  // dense frontier lanes
   DevBuf qrec, thr, remaining, done_ring, qbound, acc, lq, flip;
   DevBuf keys, t_parent, t_node, t_depth, t_query, t_weight, ring, ring_k;
@@ -248,6 +266,7 @@ struct Session {
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)
   hipGraphExec_t step_pair = nullptr;  // captured even + odd level step
+  bool pair_dense = false;             // whether the captured steps include the dense pass
   // host bookkeeping
   std::vector<int> free_recs;
   std::vector<QueryDev> h_rec;
