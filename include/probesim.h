@@ -245,6 +245,17 @@ ps_status ps_single_source_sparse(ps_graph* g, int32_t u, double c, double eps, 
 ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta, uint64_t seed,
                   const ps_options* opt, int32_t* nodes, double* scores);
 
+/* The selection step of Definition 2 on its own: given estimates s[n] of
+ * s(u, .) (host or device; for instance the sum of walk-range shards
+ * computed on several devices), writes the k nodes v != u with the largest
+ * s[v], ties broken by ascending node id, to nodes[k] and their values to
+ * out_scores[k] (host or device), in that order.  ps_topk ends with the same
+ * selection.  PS_ERR_NODE_RANGE for u outside [0, n); PS_ERR_INVALID_ARG for
+ * n < 2 or k outside [1, n-1].  Runs on the context's stream and returns
+ * when the outputs are written. */
+ps_status ps_select_topk(ps_ctx* c, const double* s, int32_t n, int32_t u, int32_t k, int32_t* nodes,
+                         double* out_scores);
+
 typedef struct ps_query {
   int32_t u;
   int32_t k; /* 0: single-source (n scores); > 0: top-k */

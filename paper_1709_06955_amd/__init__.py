@@ -33,7 +33,8 @@ RULE2_AS_STATED, RULE2_PROVEN = 0, 1
 EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
     "ps_graph_free", "ps_graph_info", "ps_graph_update", "ps_graph_edges", "ps_options_default",
-    "ps_derive_params", "ps_walks", "ps_single_source", "ps_single_source_sparse", "ps_topk", "ps_batch",
+    "ps_derive_params", "ps_walks", "ps_single_source", "ps_single_source_sparse", "ps_topk",
+    "ps_select_topk", "ps_batch",
     "ps_get_stats",
     "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
     "ps_tune_split",
@@ -158,6 +159,7 @@ def load_library(path: str = LIB_PATH):
                                      C.c_int64, vp, vp, P(C.c_int64)], C.c_int),
         "ps_topk": ([vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), vp,
                      vp], C.c_int),
+        "ps_select_topk": ([vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp], C.c_int),
         "ps_batch": ([vp, C.c_int32, P(Query), P(Options), P(Result)], C.c_int),
         "ps_get_stats": ([vp, P(Stats)], C.c_int),
         "ps_server_start": ([vp, P(ServerCfg), P(vp)], C.c_int),
@@ -348,6 +350,19 @@ def ps_topk(g: Graph, u, k, c, eps, delta, seed, out_nodes=None, out_scores=None
     _check(load_library().ps_topk(g._h, int(u), int(k), c, eps, delta, C.c_uint64(seed), C.byref(o),
                                   _ptr(nodes), _ptr(scores)), "ps_topk")
     return nodes, scores
+
+
+def ps_select_topk(ctx: Context, scores, u, k, out_nodes=None, out_scores=None):
+    """Definition 2's selection over a given estimate vector (numpy array or
+    device tensor of n doubles)."""
+    if isinstance(scores, np.ndarray):
+        scores = np.ascontiguousarray(scores, dtype=np.float64)
+    n = int(scores.shape[0])
+    nodes = out_nodes if out_nodes is not None else np.zeros(k, np.int32)
+    vals = out_scores if out_scores is not None else np.zeros(k, np.float64)
+    _check(load_library().ps_select_topk(ctx._h, _ptr(scores), n, int(u), int(k), _ptr(nodes), _ptr(vals)),
+           "ps_select_topk")
+    return nodes, vals
 
 
 def ps_autotune(g: Graph, nodes, c, eps, delta, cache_path=None) -> dict:

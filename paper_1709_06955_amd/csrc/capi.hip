@@ -74,6 +74,7 @@ void ctx_release(ps_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   session_free(c->sess);
   c->sess = nullptr;
+  for (DevBuf* b : {&c->sel.state, &c->sel.keys, &c->sel.ids, &c->sel_in, &c->sel_ids, &c->sel_scores}) devbuf_free(*b);
   for (hipEvent_t ev : c->ev_pool) (void)hipEventDestroy(ev);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -226,6 +227,29 @@ extern "C" ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double
   o.scores = scores;
   o.nodes = nodes;
   return run_locked(g, {q}, {o}, opt);
+}
+
+extern "C" ps_status ps_select_topk(ps_ctx* c, const double* scores, int32_t n, int32_t u, int32_t k,
+                                    int32_t* nodes, double* out_scores) {
+  if (!c || !scores || !nodes || !out_scores || n < 2) return PS_ERR_INVALID_ARG;
+  if (u < 0 || u >= n) return PS_ERR_NODE_RANGE;
+  if (k < 1 || k > n - 1) return PS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  PS_HIP(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const double* s = scores;
+  if (!ps_is_device_ptr(scores)) {
+    PS_TRY(devbuf_reserve(c->sel_in, sizeof(double) * (size_t)n));
+    PS_HIP(hipMemcpyAsync(c->sel_in.p, scores, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, st));
+    s = c->sel_in.as<double>();
+  }
+  PS_TRY(devbuf_reserve(c->sel_ids, sizeof(int32_t) * (size_t)k));
+  PS_TRY(devbuf_reserve(c->sel_scores, sizeof(double) * (size_t)k));
+  PS_TRY(select_topk(c->sel, s, n, u, k, c->sel_ids.as<int32_t>(), c->sel_scores.as<double>(), st));
+  PS_TRY(copy_out(nodes, c->sel_ids.p, sizeof(int32_t) * (size_t)k, st));
+  PS_TRY(copy_out(out_scores, c->sel_scores.p, sizeof(double) * (size_t)k, st));
+  PS_HIP(hipStreamSynchronize(st));
+  return PS_OK;
 }
 
 extern "C" ps_status ps_batch(ps_graph* g, int32_t nq, const ps_query* qv, const ps_options* opt, ps_result* r) {

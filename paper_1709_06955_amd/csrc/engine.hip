@@ -36,7 +36,6 @@
 //                probes held in dense columns.
 //   finish       k_finalize divides by n_r and sets s(u,u) = 1; top-k sorts.
 
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -633,7 +632,7 @@ __global__ void __launch_bounds__(kSchedBlock) k_sched(SchedArgs a) {
   }
   if (blockIdx.x == 0 && tid == 0) {
     ctr[C_REC] = 0;
-    ctr[C_BIN] = 0;
+    ctr[C_BIN] = kRedGrid;  // k_reduce's workgroups start on bins 0..kRedGrid-1
     ctr[C_NZROWS0 + (a.cur ^ 1)] = 0;  // the dense pass rewrites that matrix this step
   }
   const bool valid = s < a.P;
@@ -1524,6 +1523,7 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
   __shared__ uint32_t s_st[kExpGrid];
   __shared__ uint32_t s_wtot[kThreads / 64];
   __shared__ int s_ovf, s_dirty;
+  __shared__ uint32_t s_next;
   __shared__ int2 w_sn[kThreads / 64 * kWaveStage];  // one stage per wavefront
   __shared__ float w_h[kThreads / 64 * kWaveStage];
   __shared__ uint2 w_row[kThreads / 64 * kWaveStage];
@@ -1550,13 +1550,16 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
   const uint32_t vmask = (1u << sh) - 1u;
   unsigned long long nfin = 0, nnext = 0, kept = 0, pruned = 0, near = 0;
   bool dirty = false;
-  uint2 nseg = make_uint2(0u, 0u);  // segment of the next bin, loaded ahead
+  // Bins are taken from a counter (workgroup w starts on bin w): the next
+  // bin is claimed while this one is summed, and its segments are loaded
+  // ahead.
+  uint2 nseg = make_uint2(0u, 0u);
   if (blockIdx.x < nbins && tid < kExpGrid) nseg = a.seg[(size_t)blockIdx.x * kExpGrid + tid];
-  for (uint32_t b = blockIdx.x; b < nbins; b += gridDim.x) {
+  uint32_t b = blockIdx.x;
+  while (b < nbins) {
     const uint2 sg = nseg;
-    const uint32_t bn = b + gridDim.x;
-    if (bn < nbins && tid < kExpGrid) nseg = a.seg[(size_t)bn * kExpGrid + tid];
     __syncthreads();  // the last bin's table and segments are no longer read
+    if (tid == 0) s_next = (uint32_t)atomicAdd(&ctr[C_BIN], 1ull);
     if (tid < kExpGrid) s_st[tid] = sg.x;
     uint32_t R;
     const uint32_t pre = block_excl_scan(tid < kExpGrid ? sg.y : 0u, s_wtot, &R);
@@ -1566,7 +1569,12 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
       s_ovf = 0;
     }
     __syncthreads();
-    if (R == 0) continue;
+    if (R == 0) {
+      const uint32_t bn = s_next;
+      if (bn < nbins && tid < kExpGrid) nseg = a.seg[(size_t)bn * kExpGrid + tid];
+      b = bn;
+      continue;
+    }
     uint32_t tb = 9;  // table of 2^tb places, at least 2R
     while (tb < (uint32_t)kTblBits && (1u << tb) < 2u * R) ++tb;
     const uint32_t T = 1u << tb;
@@ -1683,6 +1691,9 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
       r += M >> 1;
       __syncthreads();  // this slice's table is emptied before the next fills it
     }
+    const uint32_t bn = s_next;
+    if (bn < nbins && tid < kExpGrid) nseg = a.seg[(size_t)bn * kExpGrid + tid];
+    b = bn;
   }
   stage_flush(ws, a.nxt, ctr);
   if (dirty) s_dirty = 1;
@@ -1982,26 +1993,6 @@ __global__ void k_finalize(int32_t n, const QueryDev* __restrict__ qr, int r) {
     Q.acc[v] = v == Q.u ? 1.0 : Q.acc[v] * Q.inv_nr + Q.shift;
 }
 
-// Sort keys for top-k: the estimate, with u itself pushed below every node.
-__global__ void k_topk_keys(int32_t n, int32_t u, const double* __restrict__ s, double* __restrict__ keys,
-                            int32_t* __restrict__ ids) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    keys[v] = v == u ? -1.0 : s[v];
-    ids[v] = (int32_t)v;
-  }
-}
-
-struct NonZero {
-  const double* acc;
-  __device__ bool operator()(int32_t v) const { return acc[v] != 0.0; }
-};
-
-__global__ void k_gather_scores(const double* __restrict__ acc, const int32_t* __restrict__ ids, int64_t cnt,
-                                double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) out[i] = acc[ids[i]];
-}
-
 // ------------------------------------------------------------- host side ----
 
 uint64_t next_pow2(uint64_t x) {
@@ -2015,12 +2006,6 @@ int grid_for(uint64_t work, int block) {
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 1u << 30));
 }
 
-ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st) {
-  if (!bytes) return PS_OK;
-  const hipMemcpyKind kind = ps_is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  PS_HIP(hipMemcpyAsync(dst, src, bytes, kind, st));
-  return PS_OK;
-}
 
 bool tree_alloc(Session* s, uint64_t len, uint64_t* start) {
   for (size_t i = 0; i < s->tree_free.size(); ++i) {
@@ -2103,8 +2088,8 @@ void session_free(Session* s) {
                     &s->part,      &s->qrec,       &s->thr,        &s->remaining, &s->done_ring,
                     &s->qbound,    &s->acc,          &s->lq,         &s->flip,       &s->keys,      &s->t_parent,
                     &s->t_node,    &s->t_depth,      &s->t_query,    &s->t_weight,   &s->ring,      &s->ring_k,
-                    &s->hyb_edges, &s->t_woff,       &s->t_walks,    &s->wcount,     &s->sort_keys[0],
-                    &s->sort_keys[1], &s->sort_vals[0], &s->sort_vals[1], &s->sort_tmp, &s->sel_count};
+                    &s->hyb_edges, &s->t_woff,       &s->t_walks,    &s->wcount,     &s->out_ids,
+                    &s->out_scores, &s->sel.state, &s->sel.keys, &s->sel.ids};
   for (DevBuf* b : bufs) devbuf_free(*b);
   if (s->h_ctr) (void)hipHostFree(s->h_ctr);
   if (s->step_pair) (void)hipGraphExecDestroy(s->step_pair);
@@ -2607,50 +2592,25 @@ ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, con
   k_finalize<<<grid_for((uint64_t)n, kBlock) > 4096 ? 4096 : grid_for((uint64_t)n, kBlock), kBlock, 0, st>>>(
       n, s->qrec.as<QueryDev>(), r);
   PS_HIP(hipGetLastError());
+  if (out.cap >= 0 || q.k > 0) {
+    PS_TRY(devbuf_reserve(s->out_ids, sizeof(int32_t) * (size_t)n));
+    PS_TRY(devbuf_reserve(s->out_scores, sizeof(double) * (size_t)n));
+  }
   if (out.cap >= 0) {
-    // nonzero estimates in ascending node order (stable selection)
-    PS_TRY(devbuf_reserve(s->sort_vals[0], sizeof(int32_t) * (size_t)n));
-    PS_TRY(devbuf_reserve(s->sort_keys[0], sizeof(double) * (size_t)n));
-    PS_TRY(devbuf_reserve(s->sel_count, sizeof(int64_t)));
-    const NonZero pred{acc};
-    const hipcub::CountingInputIterator<int32_t> ids(0);
-    size_t tmp = 0;
-    PS_HIP(hipcub::DeviceSelect::If(nullptr, tmp, ids, s->sort_vals[0].as<int32_t>(), s->sel_count.as<int64_t>(), n,
-                                    pred, st));
-    PS_TRY(devbuf_reserve(s->sort_tmp, tmp));
-    PS_HIP(hipcub::DeviceSelect::If(s->sort_tmp.p, tmp, ids, s->sort_vals[0].as<int32_t>(), s->sel_count.as<int64_t>(),
-                                    n, pred, st));
     int64_t total = 0;
-    PS_HIP(hipMemcpyAsync(&total, s->sel_count.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PS_HIP(hipStreamSynchronize(st));
+    PS_TRY(select_nonzero(s->sel, acc, n, out.cap, s->out_ids.as<int32_t>(), s->out_scores.as<double>(), &total, st));
     const int64_t w = std::min(total, out.cap);
     if (w > 0) {
-      k_gather_scores<<<grid_for((uint64_t)w, kBlock), kBlock, 0, st>>>(acc, s->sort_vals[0].as<int32_t>(), w,
-                                                                         s->sort_keys[0].as<double>());
-      PS_HIP(hipGetLastError());
-      PS_TRY(copy_out(out.nodes, s->sort_vals[0].p, sizeof(int32_t) * (size_t)w, st));
-      PS_TRY(copy_out(out.scores, s->sort_keys[0].p, sizeof(double) * (size_t)w, st));
+      PS_TRY(copy_out(out.nodes, s->out_ids.p, sizeof(int32_t) * (size_t)w, st));
+      PS_TRY(copy_out(out.scores, s->out_scores.p, sizeof(double) * (size_t)w, st));
     }
     *out.count = total;
   } else if (q.k <= 0) {
     PS_TRY(copy_out(out.scores, acc, sizeof(double) * (size_t)n, st));
   } else {
-    PS_TRY(devbuf_reserve(s->sort_keys[0], sizeof(double) * (size_t)n));
-    PS_TRY(devbuf_reserve(s->sort_keys[1], sizeof(double) * (size_t)n));
-    PS_TRY(devbuf_reserve(s->sort_vals[0], sizeof(int32_t) * (size_t)n));
-    PS_TRY(devbuf_reserve(s->sort_vals[1], sizeof(int32_t) * (size_t)n));
-    k_topk_keys<<<kStepGrid, kBlock, 0, st>>>(n, q.u, acc, s->sort_keys[0].as<double>(), s->sort_vals[0].as<int32_t>());
-    PS_HIP(hipGetLastError());
-    size_t tmp = 0;
-    PS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tmp, s->sort_keys[0].as<double>(),
-                                                         s->sort_keys[1].as<double>(), s->sort_vals[0].as<int32_t>(),
-                                                         s->sort_vals[1].as<int32_t>(), n, 0, 64, st));
-    PS_TRY(devbuf_reserve(s->sort_tmp, tmp));
-    PS_HIP(hipcub::DeviceRadixSort::SortPairsDescending(s->sort_tmp.p, tmp, s->sort_keys[0].as<double>(),
-                                                         s->sort_keys[1].as<double>(), s->sort_vals[0].as<int32_t>(),
-                                                         s->sort_vals[1].as<int32_t>(), n, 0, 64, st));
-    PS_TRY(copy_out(out.scores, s->sort_keys[1].p, sizeof(double) * (size_t)q.k, st));
-    PS_TRY(copy_out(out.nodes, s->sort_vals[1].p, sizeof(int32_t) * (size_t)q.k, st));
+    PS_TRY(select_topk(s->sel, acc, n, q.u, q.k, s->out_ids.as<int32_t>(), s->out_scores.as<double>(), st));
+    PS_TRY(copy_out(out.scores, s->out_scores.p, sizeof(double) * (size_t)q.k, st));
+    PS_TRY(copy_out(out.nodes, s->out_ids.p, sizeof(int32_t) * (size_t)q.k, st));
   }
   if (out.flip) PS_TRY(copy_out(out.flip, s->flip.as<double>() + r, sizeof(double), st));
   // release the record (later users are ordered after these copies on the stream)
@@ -2896,5 +2856,13 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
   }
   stats.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   ctx->last = stats;
+  return PS_OK;
+}
+
+// Copies device bytes to a host or device destination (stream-ordered).
+ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!bytes) return PS_OK;
+  const hipMemcpyKind kind = ps_is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  PS_HIP(hipMemcpyAsync(dst, src, bytes, kind, st));
   return PS_OK;
 }

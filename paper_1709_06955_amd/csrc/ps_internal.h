@@ -240,6 +240,12 @@ struct QueryOut {
   int64_t* count = nullptr;  // host
 };
 
+// Output selection (select.hip).  Buffers grow on demand and are reused.
+struct SelectBufs {
+  DevBuf state, keys, ids;
+  unsigned long long h_total = 0;
+};
+
 // A persistent set of device buffers that runs the level steps of every
 // admitted query: P probe slots, a ring of pending probes, a pool of tree
 // regions and per-query records with FP64 accumulators.
@@ -262,7 +268,8 @@ struct Session {
   // Section 4.4: out-edges of dense-lane frontiers (per slot), and per tree
   // node the walks through it (t_walks[t_woff[t] - weight .. t_woff[t]))
   DevBuf hyb_edges, t_woff, t_walks, wcount;
-  DevBuf sort_keys[2], sort_vals[2], sort_tmp, sel_count;
+  DevBuf out_ids, out_scores;
+  SelectBufs sel;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)
   hipGraphExec_t step_pair = nullptr;  // captured even + odd level step
@@ -284,6 +291,8 @@ struct ps_ctx {
   bool own_stream = false;
   bool timing = false;
   Session* sess = nullptr;
+  SelectBufs sel;                          // ps_select_topk
+  DevBuf sel_in, sel_ids, sel_scores;
   ps_stats last{};
   std::vector<hipEvent_t> ev_pool;
   std::mutex mu;
@@ -317,6 +326,19 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* 
 // Finalises record r (divide by n_r, s(u,u) = 1, top-k), copies its result
 // to `out` on the context stream and frees the record.
 ps_status session_finish(ps_ctx* ctx, ps_graph* g, int r, const QueryRun& q, const QueryOut& out);
+
+// Copies device bytes to a host or device destination (stream-ordered).
+ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+// Output selection (select.hip).
+// The k nodes v != u of largest s[v] (ties to the smaller id), in that order,
+// with their values; 1 <= k <= n - 1.  Asynchronous on `st`.
+ps_status select_topk(SelectBufs& b, const double* s, int32_t n, int32_t u, int32_t k, int32_t* out_ids,
+                      double* out_s, hipStream_t st);
+// The first `cap` nodes with s[v] != 0 in ascending id order, with their
+// values; `*total` receives the count of all of them (synchronises `st`).
+ps_status select_nonzero(SelectBufs& b, const double* s, int32_t n, int64_t cap, int32_t* out_ids, double* out_s,
+                         int64_t* total, hipStream_t st);
 ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, double eps, double delta,
                          uint64_t seed, const ps_options* opt, QueryRun* q);
 
