@@ -256,6 +256,22 @@ ps_status ps_topk(ps_graph* g, int32_t u, int32_t k, double c, double eps, doubl
 ps_status ps_select_topk(ps_ctx* c, const double* s, int32_t n, int32_t u, int32_t k, int32_t* nodes,
                          double* out_scores);
 
+/* ps_select_topk for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same selection and results, with no hipMalloc, hipFree or
+ * other allocating call.  Its scratch is a fixed array in the library's
+ * device memory (about 0.8 MB per device, kept until the process ends).
+ * s[n], nodes[k] and out_scores[k] must be device memory of the context's
+ * device; k must lie in [1, min(n-1, PS_NOALLOC_MAX_K)] (PS_ERR_INVALID_ARG
+ * otherwise, also for host pointers).  Asynchronous: the work is queued on
+ * the context's stream and the outputs are ready when the stream reaches it.
+ * Every call on one device shares that device's scratch, so calls that
+ * overlap on one device (other streams, other contexts) race; calls queued
+ * on one stream do not. */
+#define PS_NOALLOC_MAX_K 65536
+ps_status ps_select_topk_noalloc(ps_ctx* c, const double* s, int32_t n, int32_t u, int32_t k, int32_t* nodes,
+                                 double* out_scores);
+
 typedef struct ps_query {
   int32_t u;
   int32_t k; /* 0: single-source (n scores); > 0: top-k */

@@ -34,7 +34,7 @@ EXPORTS = [
     "ps_status_string", "ps_ctx_create", "ps_ctx_destroy", "ps_ctx_set_timing", "ps_graph_load",
     "ps_graph_free", "ps_graph_info", "ps_graph_update", "ps_graph_edges", "ps_options_default",
     "ps_derive_params", "ps_walks", "ps_single_source", "ps_single_source_sparse", "ps_topk",
-    "ps_select_topk", "ps_batch",
+    "ps_select_topk", "ps_select_topk_noalloc", "ps_batch",
     "ps_get_stats",
     "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
     "ps_tune_split",
@@ -160,6 +160,7 @@ def load_library(path: str = LIB_PATH):
         "ps_topk": ([vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_uint64, P(Options), vp,
                      vp], C.c_int),
         "ps_select_topk": ([vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp], C.c_int),
+        "ps_select_topk_noalloc": ([vp, vp, C.c_int32, C.c_int32, C.c_int32, vp, vp], C.c_int),
         "ps_batch": ([vp, C.c_int32, P(Query), P(Options), P(Result)], C.c_int),
         "ps_get_stats": ([vp, P(Stats)], C.c_int),
         "ps_server_start": ([vp, P(ServerCfg), P(vp)], C.c_int),
@@ -363,6 +364,16 @@ def ps_select_topk(ctx: Context, scores, u, k, out_nodes=None, out_scores=None):
     _check(load_library().ps_select_topk(ctx._h, _ptr(scores), n, int(u), int(k), _ptr(nodes), _ptr(vals)),
            "ps_select_topk")
     return nodes, vals
+
+
+NOALLOC_MAX_K = 65536
+
+
+def ps_select_topk_noalloc(ctx: Context, scores, u, k, out_nodes, out_scores):
+    """ps_select_topk without any device allocation: scores, out_nodes and
+    out_scores are device tensors; queued on the context's stream."""
+    _check(load_library().ps_select_topk_noalloc(ctx._h, _ptr(scores), int(scores.shape[0]), int(u), int(k),
+                                                 _ptr(out_nodes), _ptr(out_scores)), "ps_select_topk_noalloc")
 
 
 def ps_autotune(g: Graph, nodes, c, eps, delta, cache_path=None) -> dict:

@@ -45,6 +45,7 @@ extern "C" ps_status ps_ctx_create(int device, void* hip_stream, ps_ctx** out) {
   PS_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return PS_ERR_INVALID_ARG;
   PS_HIP(hipSetDevice(device));
+  PS_TRY(select_scratch_init(device));
   auto* c = new ps_ctx();
   c->device = device;
   if (hip_stream) {

@@ -335,6 +335,9 @@ ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st);
 // with their values; 1 <= k <= n - 1.  Asynchronous on `st`.
 ps_status select_topk(SelectBufs& b, const double* s, int32_t n, int32_t u, int32_t k, int32_t* out_ids,
                       double* out_s, hipStream_t st);
+// Looks up, once per device and with that device current, the device
+// address of the scratch array of ps_select_topk_noalloc.
+ps_status select_scratch_init(int device);
 // The first `cap` nodes with s[v] != 0 in ascending id order, with their
 // values; `*total` receives the count of all of them (synchronises `st`).
 ps_status select_nonzero(SelectBufs& b, const double* s, int32_t n, int64_t cap, int32_t* out_ids, double* out_s,

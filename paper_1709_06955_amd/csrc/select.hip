@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "ps_internal.h"
 
@@ -361,18 +362,13 @@ int sel_grid(int32_t n) {
 
 }  // namespace
 
-ps_status select_topk(SelectBufs& b, const double* s, int32_t n, int32_t u, int32_t k, int32_t* out_ids,
-                      double* out_s, hipStream_t st) {
-  if (k < 1 || k > n - 1) return PS_ERR_INVALID_ARG;
-  int64_t padded = 64;
-  while (padded < k) padded <<= 1;
+namespace {
+
+// The selection on caller-provided scratch: S (one SelState), K and I (room
+// for `padded` pairs each, padded = the power of two >= max(k, 64)).
+ps_status select_topk_on(SelState* S, unsigned long long* K, int32_t* I, int64_t padded, const double* s, int32_t n,
+                         int32_t u, int32_t k, int32_t* out_ids, double* out_s, hipStream_t st) {
   const int tile = (int)std::min<int64_t>(padded, kSortTile);
-  PS_TRY(devbuf_reserve(b.state, sizeof(SelState)));
-  PS_TRY(devbuf_reserve(b.keys, sizeof(unsigned long long) * (size_t)padded));
-  PS_TRY(devbuf_reserve(b.ids, sizeof(int32_t) * (size_t)padded));
-  SelState* S = b.state.as<SelState>();
-  auto* K = b.keys.as<unsigned long long>();
-  auto* I = b.ids.as<int32_t>();
   const int grid = sel_grid(n);
   k_sel_init<<<1, kSelBlock, 0, st>>>(S, k);
   for (int p = 0; p < kPasses; ++p) k_sel_pass<<<grid, kSelBlock, 0, st>>>(n, u, s, S, kDigitBits[p]);
@@ -397,6 +393,25 @@ ps_status select_topk(SelectBufs& b, const double* s, int32_t n, int32_t u, int3
   return PS_OK;
 }
 
+int64_t padded_for(int32_t k) {
+  int64_t padded = 64;
+  while (padded < k) padded <<= 1;
+  return padded;
+}
+
+}  // namespace
+
+ps_status select_topk(SelectBufs& b, const double* s, int32_t n, int32_t u, int32_t k, int32_t* out_ids,
+                      double* out_s, hipStream_t st) {
+  if (k < 1 || k > n - 1) return PS_ERR_INVALID_ARG;
+  const int64_t padded = padded_for(k);
+  PS_TRY(devbuf_reserve(b.state, sizeof(SelState)));
+  PS_TRY(devbuf_reserve(b.keys, sizeof(unsigned long long) * (size_t)padded));
+  PS_TRY(devbuf_reserve(b.ids, sizeof(int32_t) * (size_t)padded));
+  return select_topk_on(b.state.as<SelState>(), b.keys.as<unsigned long long>(), b.ids.as<int32_t>(), padded, s, n,
+                        u, k, out_ids, out_s, st);
+}
+
 ps_status select_nonzero(SelectBufs& b, const double* s, int32_t n, int64_t cap, int32_t* out_ids, double* out_s,
                          int64_t* total, hipStream_t st) {
   PS_TRY(devbuf_reserve(b.state, sizeof(SelState)));
@@ -409,4 +424,58 @@ ps_status select_nonzero(SelectBufs& b, const double* s, int32_t n, int64_t cap,
   PS_HIP(hipStreamSynchronize(st));
   *total = (int64_t)b.h_total;
   return PS_OK;
+}
+
+// ------------------------------------------------- allocation-free variant --
+//
+// ps_select_topk_noalloc keeps its scratch (one SelState and room for
+// kNoAllocMaxK (key, id) pairs) in the file-scope array below: one copy per
+// device, held until the process ends.  In host code `scratch` names a host
+// stand-in, never the device memory: its device address is looked up once
+// per device (select_scratch_init, from ps_ctx_create with the device
+// current) and only that address reaches kernels.
+
+namespace {
+
+constexpr size_t kStateBytes = (sizeof(SelState) + 255) & ~(size_t)255;
+constexpr size_t kNoAllocBytes = kStateBytes + (size_t)PS_NOALLOC_MAX_K * (sizeof(unsigned long long) + sizeof(int32_t));
+static_assert((PS_NOALLOC_MAX_K & (PS_NOALLOC_MAX_K - 1)) == 0, "the pair room must be a power of two");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+ps_status select_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return PS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return PS_OK;
+  void* p = nullptr;
+  PS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return PS_ERR_DEVICE;
+  g_scratch[device] = p;
+  return PS_OK;
+}
+
+extern "C" ps_status ps_select_topk_noalloc(ps_ctx* c, const double* s, int32_t n, int32_t u, int32_t k,
+                                            int32_t* nodes, double* out_scores) {
+  if (!c || !s || !nodes || !out_scores || n < 2) return PS_ERR_INVALID_ARG;
+  if (u < 0 || u >= n) return PS_ERR_NODE_RANGE;
+  if (k < 1 || k > n - 1 || k > PS_NOALLOC_MAX_K) return PS_ERR_INVALID_ARG;
+  if (!ps_is_device_ptr(s) || !ps_is_device_ptr(nodes) || !ps_is_device_ptr(out_scores)) return PS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  PS_HIP(hipSetDevice(c->device));
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk2(g_scratch_mu);
+    if (c->device < kMaxDevices) base = g_scratch[c->device];
+  }
+  if (!base) return PS_ERR_STATE;  // the context's set-up did not find the array
+  auto* S = reinterpret_cast<SelState*>(base);
+  auto* K = reinterpret_cast<unsigned long long*>(static_cast<unsigned char*>(base) + kStateBytes);
+  auto* I = reinterpret_cast<int32_t*>(K + PS_NOALLOC_MAX_K);
+  return select_topk_on(S, K, I, padded_for(k), s, n, u, k, nodes, out_scores, c->stream);
 }
