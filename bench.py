@@ -8,9 +8,15 @@ a time through ps_single_source (plain mode), every stage on the GPU, inputs
 resident in HBM, estimates written to a device tensor.  The same 32 queries
 are also timed as one ps_batch launch (batched mode).
 
-Prints one JSON line.  The roofline entry covers the PROBE expansion kernel
-(k_expand), timed with HIP events on the stream it runs on; its algorithmic
-bytes per launch come from the kernel's own work counters (expand_bytes).
+Prints one JSON line.  The roofline entry covers the kernel group that takes
+the larger share of GPU time: the push level (k_expand + k_reduce, one launch
+of each per level step) or the pull pass (k_dense + k_dense_fin), each timed
+with HIP events the library records on its own stream around the group; the
+algorithmic bytes per launch follow the per-unit byte counts of the method
+(push_bytes, pull_bytes) applied to the library's work counters.  Every group
+is listed with its fraction of the HBM peak, beside the whole-query effective
+rate.  Also reported: batched and served rates, top-k selection and top-50
+query times, and the CPU oracle on a bounded sample (cpu_baseline).
 """
 
 from __future__ import annotations
@@ -31,80 +37,124 @@ NQ = 32
 HYBRID_C0 = 0.003  # switch constant of Section 4.4 for the hybrid pass (the library's default)
 
 
-def expand_bytes(st: dict) -> float:
-    """Algorithmic bytes moved by k_expand for the given work counters:
-    28 B per expanded entry (list entry 8, scaled score 4, row start/len 8,
-    clearing its 8-byte grid sum),
-    8 B per pushed out-edge (neighbour id 4, 1/|I(v)| 4; levels moved to the
-    dense pass or switched are not pushed),
-    16 B per inner-level contribution (64-bit grid sum read-modify-write),
-    8 B per new next-level entry (list write),
-    16 B per final contribution (FP64 estimate read-modify-write)."""
-    F, E = st["entries_expanded"], st["pushed_edges"]
-    N, Fin = st["next_entries"], st["pushed_final_adds"]
-    inner = max(E - Fin, 0)
-    return 28.0 * F + 8.0 * E + 16.0 * inner + 8.0 * N + 16.0 * Fin
+def push_bytes(st: dict) -> float:
+    """Algorithmic bytes of the push levels (k_expand + k_reduce, one launch
+    of each per level step) for the given work counters: 16 B per expanded
+    frontier entry (node id, score, two row offsets), 8 B per pushed out-edge
+    (neighbour id, 1/|I(v)|), 8 B per distinct next-level entry (written and
+    read back), 16 B per final contribution (FP64 read-modify-write)."""
+    return (16.0 * st["entries_expanded"] + 8.0 * st["pushed_edges"] + 8.0 * st["next_entries"]
+            + 16.0 * st["pushed_final_adds"])
 
 
-def measured_traffic(avg_ms):
-    """HBM bytes per k_expand dispatch from the committed rocprofv3 counter
-    runs (FETCH_SIZE and WRITE_SIZE scaled by a copy-kernel calibration),
-    used only while the kernel source is the one they were taken on; as GB/s
-    over this run's average launch time.  None otherwise."""
+def pull_bytes(st: dict, n: int, m: int) -> float:
+    """Algorithmic bytes of the pull passes (k_dense + k_dense_fin): per
+    pass the in-adjacency and 1/|I(v)| once, 4(n+1) + 4m + 4n, plus per
+    pulled probe level a 4-byte gather per in-edge and a 4-byte write per
+    node, 4m + 4n.  Every pass reads each in-edge once, so passes =
+    pull_edges / m."""
+    passes = st["pull_edges"] / max(m, 1)
+    return passes * (4.0 * (n + 1) + 4.0 * m + 4.0 * n) + st["pull_levels"] * (4.0 * m + 4.0 * n)
+
+
+def walk_bytes(st: dict) -> float:
+    """12 B per walk step (in-row offsets and the chosen in-neighbour)."""
+    return 12.0 * st["walk_nodes"]
+
+
+def counter_traffic(name: str):
+    """HBM bytes per dispatch of the kernels in profiles/<name>.json (the
+    rocprofv3 FETCH_SIZE and WRITE_SIZE runs, each scaled by what the same
+    counter reads for a copy kernel of known size), used only while the
+    library source they were taken on is unchanged; None otherwise."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_expand_cl_1m_10m_traffic.json")
-    if not os.path.exists(path) or avg_ms <= 0:
-        return None, None
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
     with open(path) as f:
         rec = json.load(f)
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None, None
-    b = rec["hbm_bytes_per_dispatch"]
-    return b / (avg_ms * 1e-3) / 1e9, b
+    for src, sha in rec["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None
+    return rec
 
 
-def cpu_baseline(n, s, d, q, seconds_target=15.0, threads=None):
-    """The oracle (Alg. 1, FP64) on the host cores over a bounded sample: the
-    first walks of the first query in chunks of 20, shared by `threads`
-    worker threads (the oracle releases the GIL), for about seconds_target of
-    wall time; scaled to queries/s by n_r (Alg. 1's cost is a sum of
-    independent per-walk costs)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, s, d, q, walks=150, threads=None):
+    """The oracle (Alg. 1, FP64, as it stands) on the host cores over a
+    bounded sample of the workload: walks [0, walks) of each of the first 8
+    query nodes.  Alg. 1's cost is a sum of independent per-walk costs, so a
+    query's time is estimated as its sample's time times n_r / walks.
+    Single thread: the 8 samples one after another (median and largest of
+    the 8 estimates).  All threads: one query's sample per thread, all at
+    once (ctypes releases the GIL), giving queries/s."""
     import threading
+
+    import numpy as np
 
     import oracle
 
     G = oracle.Graph(n, s, d)
     p = oracle.params(n, C, EPS, DELTA)
-    u = int(q[0])
-    threads = threads or max(1, min(16, os.cpu_count() or 1))
-    chunk = 20
-    lock = threading.Lock()
-    state = {"next": 0, "walks": 0}
+    qs = [int(x) for x in q[:8]]
+    scale = p.n_r / walks
+    per_query = []
+    for i, u in enumerate(qs):
+        t0 = time.perf_counter()
+        oracle.single_source(G, u, p, 3 + i, 0, walks)
+        per_query.append((time.perf_counter() - t0) * scale)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = threads or max(1, min(avail, 16))
     t0 = time.perf_counter()
-
-    def worker():
-        while time.perf_counter() - t0 < seconds_target:
-            with lock:
-                k = state["next"]
-                if k >= p.n_r:
-                    return
-                state["next"] = min(k + chunk, p.n_r)
-            oracle.single_source(G, u, p, 3, k, min(k + chunk, p.n_r))
-            with lock:
-                state["walks"] += min(k + chunk, p.n_r) - k
-
-    ts = [threading.Thread(target=worker) for _ in range(threads)]
-    for t in ts:
-        t.start()
-    for t in ts:
-        t.join()
+    ts = [threading.Thread(target=oracle.single_source, args=(G, qs[i % len(qs)], p, 3 + (i % len(qs)), 0, walks))
+          for i in range(threads)]
+    for th in ts:
+        th.start()
+    for th in ts:
+        th.join()
     wall = time.perf_counter() - t0
-    walks = state["walks"]
-    return {"value": walks / wall / p.n_r, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"Alg. 1 oracle, query node {u}, {walks} of its n_r = {p.n_r} walks in chunks of {chunk} "
-                      f"on {threads} threads, {wall:.1f} s, scaled by n_r / {walks}"}
+    qps = threads / (wall * scale)
+    pq = np.array(per_query)
+    return {"value": qps, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(), "cpus_available": avail,
+            "single_thread_median_s": float(np.median(pq)), "single_thread_max_s": float(pq.max()),
+            "single_thread_per_query_s": [round(x, 1) for x in per_query],
+            "sample": f"Alg. 1 oracle (FP64), walks [0, {walks}) of each of 8 query nodes of the workload "
+                      f"(n_r = {p.n_r}), times scaled by n_r / {walks}; single thread: the 8 samples in turn "
+                      f"(the largest of 8 stands for p99); {threads} threads: one sample each, "
+                      f"{wall:.1f} s wall"}
+
+
+def time_topk_select(ps, ctx, vec, u, k=50, reps=20):
+    """Milliseconds per ps_select_topk_noalloc call on a resident device
+    vector: `reps` calls queued back to back (the entry point does not wait),
+    bracketed by device synchronisations."""
+    import torch
+
+    on = torch.empty(k, dtype=torch.int32, device="cuda:0")
+    ov = torch.empty(k, dtype=torch.float64, device="cuda:0")
+    ps.ps_select_topk_noalloc(ctx, vec, u, k, on, ov)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ps.ps_select_topk_noalloc(ctx, vec, u, k, on, ov)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
 
 
 def served(ps, G, q, n, seconds=8.0, rate_frac=0.5, seed=7, **defaults):
@@ -178,6 +228,7 @@ def main():
     ap.add_argument("--nq", type=int, default=NQ, help="query nodes per step (the workload uses 32)")
     ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-topk", action="store_true", help="skip the top-k selection and top-50 query timing")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -234,7 +285,7 @@ def main():
         plain_step(None, "warmup")
     keys = ["expand_ms", "pull_ms", "pull_levels", "pull_edges", "expand_launches", "entries_expanded", "edges_scanned",
             "pushed_edges", "next_entries", "final_adds", "pushed_final_adds",
-            "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned"]
+            "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned", "walk_nodes", "total_ms"]
     acc = {k: 0 for k in keys}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -322,11 +373,38 @@ def main():
             split[f"{name}_qps"] = len(q) / (time.perf_counter() - tv)
         print(f"tuned split: {split}", file=sys.stderr, flush=True)
 
-    alg_bytes = expand_bytes(acc)
-    launches = max(acc["expand_launches"], 1)
-    avg_ms = acc["expand_ms"] / launches
-    achieved = (alg_bytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    traffic, traffic_bytes = measured_traffic(avg_ms)
+    # Roofline per kernel group, bytes from the work counters, times from HIP
+    # events the library records on its stream around each group.
+    m = int(s.size)
+    steps_push = max(acc["expand_launches"], 1)
+    passes = acc["pull_edges"] / max(m, 1)
+    groups = {}
+    pb, lb = push_bytes(acc), pull_bytes(acc, n, m)
+    groups["push"] = {"kernels": "k_expand + k_reduce", "launches_per_query": steps_push / queries,
+                      "avg_launch_ms": acc["expand_ms"] / steps_push, "alg_bytes_per_launch": pb / steps_push}
+    if passes > 0:
+        groups["pull"] = {"kernels": "k_dense + k_dense_fin (+ k_hyb_count)", "launches_per_query": passes / queries,
+                          "avg_launch_ms": acc["pull_ms"] / passes, "alg_bytes_per_launch": lb / passes}
+    prof = counter_traffic("push_pull_cl_1m_10m_traffic")
+    for name, gr in groups.items():
+        gr["achieved_gbs"] = gr["alg_bytes_per_launch"] / (gr["avg_launch_ms"] * 1e-3) / 1e9 if gr["avg_launch_ms"] > 0 else 0.0
+        gr["frac"] = gr["achieved_gbs"] / HBM_PEAK_GBS
+        gr["share_of_gpu_time"] = (acc["expand_ms"] if name == "push" else acc["pull_ms"]) / max(acc["total_ms"], 1e-9)
+        hb = prof["groups"][name]["hbm_bytes_per_launch"] if prof and name in prof.get("groups", {}) else None
+        gr["traffic_bytes_per_launch"] = hb
+        gr["waste_ratio"] = hb / gr["alg_bytes_per_launch"] if hb else None
+    dom = max(groups, key=lambda k: groups[k]["share_of_gpu_time"])
+    D = groups[dom]
+    whole = (pb + lb + walk_bytes(acc)) / queries
+    roofline = {"bound": "hbm", "kernel": f"{dom} level ({D['kernels']})", "achieved": D["achieved_gbs"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": D["frac"],
+                "traffic": (D["traffic_bytes_per_launch"] / (D["avg_launch_ms"] * 1e-3) / 1e9)
+                if D["traffic_bytes_per_launch"] else None,
+                "avg_launch_ms": D["avg_launch_ms"], "alg_bytes_per_launch": D["alg_bytes_per_launch"],
+                "traffic_bytes_per_launch": D["traffic_bytes_per_launch"], "waste_ratio": D["waste_ratio"],
+                "groups": groups,
+                "whole_query": {"alg_bytes": whole, "gpu_ms": acc["total_ms"] / queries,
+                                "effective_gbs": whole / (acc["total_ms"] / queries * 1e-3) / 1e9}}
     result = {
         "metric": "single-source queries/s at eps=0.05 (plain, one query at a time)" + (
             "" if args.probe_mode == "deterministic" else f", {args.probe_mode} PROBE"),
@@ -350,12 +428,32 @@ def main():
         "small_queries": small,
         "probe_variants": variants,
         "tuned_split": split,
-        "roofline": {"bound": "hbm", "kernel": "k_expand", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes / launches,
-                     "hbm_bytes_per_launch": traffic_bytes},
-        "work_per_query": {k: acc[k] / queries for k in keys if k not in ("expand_ms",)},
+        "roofline": roofline,
+        "work_per_query": {k: acc[k] / queries for k in keys},
     }
+    # Top-k (Definition 2): the selection alone on resident vectors (the last
+    # query's 1M estimates; a 40M vector with 1% nonzero entries, the shape
+    # of a 40M-node query's estimates), and whole top-50 queries.
+    sel = None if args.no_topk else {"k": 50, "ms_1m": time_topk_select(ps, ctx, out, int(q[-1]))}
+    if sel is not None:
+        gen = torch.Generator(device="cuda:0")
+        gen.manual_seed(5)
+        big = torch.zeros(40_000_000, dtype=torch.float64, device="cuda:0")
+        nz = torch.randint(0, big.numel(), (400_000,), device="cuda:0", generator=gen)
+        big[nz] = torch.rand(nz.numel(), dtype=torch.float64, device="cuda:0", generator=gen) * 1e-3
+        sel["ms_40m"] = time_topk_select(ps, ctx, big, 0)
+        del big, nz
+        nodes_t = torch.empty(50, dtype=torch.int32, device="cuda:0")
+        vals_t = torch.empty(50, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        tk = time.perf_counter()
+        for i, u in enumerate(q[:8]):
+            ps.ps_topk(G, int(u), 50, C, EPS, DELTA, 3 + i, out_nodes=nodes_t, out_scores=vals_t, slots=args.slots,
+                       pull_edges=args.pull)
+        torch.cuda.synchronize()
+        sel["top50_query_qps"] = 8 / (time.perf_counter() - tk)
+        result["topk"] = sel
+        print(f"top-k: {sel}", file=sys.stderr, flush=True)
     if args.calib_copy:
         a = torch.empty(args.calib_copy << 18, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
