@@ -80,6 +80,8 @@ def lib():
                           P(C.c_double), P(Stats)]
         L.orc_batch_hybrid.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int,
                                        C.c_int, C.c_double, P(C.c_double), P(Stats)]
+        L.orc_merged.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int,
+                                 P(C.c_double), P(Stats)]
         L.orc_topk.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_double)]
         _lib = L
     return _lib
@@ -203,6 +205,21 @@ def batch(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias
     """Alg. 3 (reverse reachability tree) estimate; equal to Alg. 1 up to
     rounding.  probe="hybrid" adds the switch of Section 4.4 at constant c0."""
     return _run(lib().orc_batch, g, u, p, seed, k_begin, k_end, bias_shift, precision, probe, c0)
+
+
+def merged(g: Graph, u: int, p: Params, seed: int, k_begin=None, k_end=None, bias_shift=False):
+    """Alg. 3 with Rule 2 off (p.eps_p must be 0) and the probes of each
+    subtree summed at its root before expansion; FP64.  Equal to batch() at
+    eps_p = 0 up to rounding."""
+    out = np.zeros(g.n, dtype=np.float64)
+    st = Stats()
+    kb = 0 if k_begin is None else int(k_begin)
+    ke = int(p.n_r) if k_end is None else int(k_end)
+    rc = lib().orc_merged(g._h, int(u), C.byref(p), C.c_uint64(seed), kb, ke, int(bias_shift),
+                          out.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
+    if rc != ORC_OK:
+        raise ValueError(f"merged query failed with code {rc}")
+    return out, st.as_dict()
 
 
 def topk(scores: np.ndarray, u: int, k: int):

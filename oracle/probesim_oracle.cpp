@@ -23,6 +23,11 @@
 //   orc_batch           Alg. 3 (reverse reachability tree), same estimate
 //   orc_batch_hybrid    Alg. 3 with the switch of Section 4.4 from
 //                       deterministic to randomized PROBE
+//   orc_merged          Alg. 3 with Rule 2 off, every probe of a subtree
+//                       summed at the subtree's root before it is expanded
+//                       (PROBE is linear in H_0, Lemma 2 / the Score
+//                       equation of Section 3.3); same estimate as orc_batch
+//                       at eps_p = 0
 //   orc_topk            Definition 2 (top-k by sorting the estimates)
 //
 // Readings where the paper is silent or inconsistent (see the design notes):
@@ -655,6 +660,80 @@ int orc_batch_hybrid(const orc_graph* g, int32_t u, const orc_params* p, uint64_
                      int64_t k_end, int bias_shift, int f32, double c0, double* out, orc_stats* st) {
   if (!(c0 >= 0.0)) return ORC_EINVAL;
   return batch(g, u, p, seed, k_begin, k_end, bias_shift, f32 & 1, c0, out, st);
+}
+
+// Merged probing over the reverse reachability tree (Rule 2 off).  A probe
+// of the tree node (u_1..u_i) applies, to H_0 = e_{u_i}, the level maps
+// T_{i-1}, ..., T_1, where T_p sends a score set at walk position p+1 to
+// position p: T_p(H)[v] = sum over x in H with v in O(x), v != u_p, of
+// sqrt(c)/|I(v)| * H[x].  T_p depends on the walk prefix only through u_p,
+// the node of the tree ancestor at depth p, and every T_p is linear, so the
+// weighted probes of a subtree can be added before they are pushed through
+// the maps they share:  X(t) = w(t) e_{node(t)} + sum over the children c of
+// t of T_{depth(t)}(X(c)), for the tree nodes t below the root, and the
+// estimate is X(root) / n_r (the root itself is not probed).  Nodes are taken
+// deepest first; each node's set is expanded once, along its tree edge.
+// Rule 2 prunes per probe and has no merged form, so eps_p must be 0.
+int orc_merged(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed, int64_t k_begin, int64_t k_end,
+               int bias_shift, double* out, orc_stats* st) {
+  if (u < 0 || u >= g->n) return ORC_ERANGE;
+  if (k_begin < 0 || k_end > p->n_r || k_begin > k_end || p->eps_p != 0.0) return ORC_EINVAL;
+  if (st) memset(st, 0, sizeof(*st));
+  std::vector<int64_t> parent(1, -1), weight(1, 0);
+  std::vector<int32_t> node(1, u), depth(1, 1);
+  std::unordered_map<uint64_t, int64_t> child;  // (parent id, graph node) -> id
+  std::vector<int32_t> walk((size_t)p->L);
+  int32_t max_depth = 1;
+  for (int64_t k = k_begin; k < k_end; ++k) {
+    const int32_t len = orc_walk(g, u, k, seed, p, walk.data());
+    if (st) st->walk_nodes += len;
+    int64_t cur = 0;
+    for (int32_t i = 2; i <= len; ++i) {
+      const uint64_t key = ((uint64_t)cur << 32) | (uint32_t)walk[i - 1];
+      auto it = child.find(key);
+      if (it == child.end()) {
+        parent.push_back(cur);
+        node.push_back(walk[i - 1]);
+        depth.push_back(i);
+        weight.push_back(0);
+        it = child.emplace(key, (int64_t)node.size() - 1).first;
+      }
+      cur = it->second;
+      weight[cur]++;
+      max_depth = std::max(max_depth, i);
+    }
+  }
+  const int64_t count = (int64_t)node.size();
+  if (st) st->tree_nodes = count - 1;
+  std::vector<std::vector<int64_t>> by_depth((size_t)max_depth + 1);
+  for (int64_t t = 1; t < count; ++t) by_depth[(size_t)depth[t]].push_back(t);
+  std::vector<std::unordered_map<int32_t, double>> X((size_t)count);
+  const double sc = std::sqrt(p->c);
+  for (int32_t d = max_depth; d >= 2; --d) {
+    for (int64_t t : by_depth[(size_t)d]) {
+      X[(size_t)t][node[t]] += (double)weight[t];  // the node's own probe
+      const int64_t a = parent[t];
+      const int32_t excl = node[a];                 // u at walk position d - 1
+      auto& up = X[(size_t)a];
+      for (const auto& xv : X[(size_t)t]) {
+        const int32_t x = xv.first;
+        if (st) st->entries_expanded++;
+        for (int64_t e = g->out_ptr[x]; e < g->out_ptr[x + 1]; ++e) {
+          const int32_t v = g->out_col[e];
+          if (st) st->edges_scanned++;
+          if (v == excl) continue;
+          up[v] += sc / (double)indeg(g, v) * xv.second;
+        }
+      }
+      if (st) st->probes++;
+      std::unordered_map<int32_t, double>().swap(X[(size_t)t]);
+    }
+  }
+  std::vector<double> acc((size_t)g->n, 0.0);
+  for (const auto& xv : X[0]) acc[(size_t)xv.first] = xv.second;
+  if (st) st->final_entries = (int64_t)X[0].size();
+  finish(g, u, p, bias_shift, acc, out);
+  return ORC_OK;
 }
 
 // Definition 2: the k nodes v != u with the largest estimates; equal

@@ -150,3 +150,34 @@ def test_guarantee_under_proven_rule2_split(orc):
         for precision in ("f64", "f32"):
             est, _ = orc.batch(G, 0, p, seed, precision=precision)
             assert np.abs(est - S[0]).max() <= eps
+
+
+def test_merged_probing_equals_tree_batch_without_pruning(orc):
+    # Merged probing (every probe of a subtree summed at its root before the
+    # shared level maps, Lemma 2 / Section 3.3 linearity) against Alg. 3 with
+    # one probe per tree node, both with Rule 2 off (eps_p = 0): the same
+    # estimate up to FP64 rounding, for whole queries, walk-range shards, the
+    # walk cap and the bias shift.  The merged form never expands more
+    # entries or edges than the per-probe form, whose level sets cover its
+    # summed sets.
+    from synth.graphs import chung_lu, erdos_renyi, query_nodes
+
+    n = 1000
+    s_, d_ = erdos_renyi(n, 10000, seed=1)
+    G = orc.Graph(n, s_, d_)
+    cases = [(G, n, 0, dict(), 1, None, None, False), (G, n, 3, dict(L=6), 2, None, None, False),
+             (G, n, 0, dict(), 1, 100, 900, False), (G, n, 5, dict(), 4, None, None, True)]
+    s2, d2 = chung_lu(5000, 40000, 2.1, seed=3)
+    G2 = orc.Graph(5000, s2, d2)
+    for u in query_nodes(5000, d2, 2, seed=9):
+        cases.append((G2, 5000, int(u), dict(), 7, 0, 400, False))
+    for g, nn, u, kw, seed, a, b, shift in cases:
+        p = orc.params(nn, 0.6, 0.2, 0.01, eps_p=0.0, **kw)
+        m, sm = orc.merged(g, u, p, seed, a, b, bias_shift=shift)
+        t, stt = orc.batch(g, u, p, seed, a, b, bias_shift=shift)
+        assert np.abs(m - t).max() <= 1e-12
+        assert sm["tree_nodes"] == stt["tree_nodes"] and sm["walk_nodes"] == stt["walk_nodes"]
+        assert sm["entries_expanded"] <= stt["entries_expanded"]
+        assert sm["edges_scanned"] <= stt["edges_scanned"]
+    with pytest.raises(ValueError):
+        orc.merged(G, 0, orc.params(n, 0.6, 0.2, 0.01), 1)  # Rule 2 on: no merged form
