@@ -209,6 +209,134 @@ def served(ps, G, q, n, seconds=8.0, rate_frac=0.5, seed=7, **defaults):
         srv.stop()
 
 
+def leg_batched(ps, nq, seed_base=500):
+    """Batched workload: Chung-Lu 5M nodes / 50M edges (exponent 2.1), query
+    nodes stratified by in-degree bucket, eps cycling over 0.1 / 0.05 / 0.02.
+    The queries run one at a time (plain), then all in one ps_batch call;
+    reports both rates, per-query plain latencies and the speed-up."""
+    import numpy as np
+    import torch
+
+    from synth import graphs
+
+    n, s, d = graphs.make_workload("cl_5m_50m")
+    qn = graphs.stratified_query_nodes(n, d, nq)
+    ctx = ps.Context(0)
+    G = ps.Graph(ctx, n, s, d)
+    del s, d
+    eps = (0.1, 0.05, 0.02)
+    qs = [dict(u=int(u), k=0, c=C, eps=eps[i % 3], delta=DELTA, seed=seed_base + i) for i, u in enumerate(qn)]
+    outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in qs]
+    lat = []
+    t0 = time.perf_counter()
+    for q, (o, _) in zip(qs, outs):
+        tq = time.perf_counter()
+        ps.ps_single_source(G, q["u"], C, q["eps"], DELTA, q["seed"], out=o)
+        lat.append(time.perf_counter() - tq)
+    plain = len(qs) / (time.perf_counter() - t0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ps.ps_batch(G, qs, outs=outs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = {"workload": f"Chung-Lu 5M nodes / 50M edges, {len(qs)} degree-stratified queries, eps 0.1/0.05/0.02",
+           "queries": len(qs), "plain_qps": plain, "batched_qps": len(qs) / dt, "batched_speedup": len(qs) / dt / plain,
+           "plain_latency_ms": {str(e): float(np.median([x for x, q in zip(lat, qs) if q["eps"] == e]) * 1e3)
+                                for e in eps},
+           "batched_makespan_s": dt}
+    G.close()
+    ctx.close()
+    return res
+
+
+def leg_served(ps, seconds, eps_mix, rate_frac=0.5, upd_per_s=1000, upd_batch=100, seed=7):
+    """Served workload: Chung-Lu 10M nodes / 200M edges, Poisson arrivals
+    (70% single-source, 30% top-50, eps drawn from eps_mix) at rate_frac
+    times the closed-loop saturation rate, and edge updates (half inserts,
+    half deletes of live edges) at upd_per_s in batches of upd_batch.
+    Latency is submit to result on the host; update latency is the
+    ps_server_update call to the batch applied (the server's counters)."""
+    import threading
+
+    import numpy as np
+
+    from synth import graphs
+
+    n, s, d = graphs.make_workload("cl_10m_200m")
+    qn = graphs.query_nodes(n, d, 64, seed=43)
+    n_upd = int(upd_per_s * seconds * 2) + upd_batch
+    us, ud, op = graphs.update_stream(n, s, d, n_upd, seed=5)
+    ctx = ps.Context(0)
+    G = ps.Graph(ctx, n, s, d)
+    del s, d
+    rng = np.random.default_rng(seed)
+    mix = [(int(qn[i % len(qn)]), 50 if rng.random() < 0.3 else 0, float(rng.choice(eps_mix))) for i in range(4096)]
+    srv = ps.Server(G, max_inflight=32)
+    try:
+        # closed loop: a window of the mix submitted at once
+        t0 = time.perf_counter()
+        ts = [srv.submit(u, C, e, DELTA, 3000 + i, k=k) for i, (u, k, e) in enumerate(mix[:16])]
+        for t in ts:
+            srv.wait(t)
+        x_sat = 16 / (time.perf_counter() - t0)
+        rate = rate_frac * x_sat
+        count = max(8, int(rate * seconds))
+        gaps = rng.exponential(1.0 / rate, size=count)
+        lat = [None] * count
+        lock = threading.Lock()
+        stop = threading.Event()
+        upd_pos = [0]
+
+        def updater():
+            nxt = time.perf_counter()
+            while not stop.is_set() and upd_pos[0] + upd_batch <= n_upd:
+                a = upd_pos[0]
+                srv.update(us[a:a + upd_batch], ud[a:a + upd_batch], op[a:a + upd_batch])
+                upd_pos[0] += upd_batch
+                nxt += upd_batch / upd_per_s
+                time.sleep(max(0.0, nxt - time.perf_counter()))
+
+        def waiter(i, ticket, t_sub):
+            srv.wait(ticket)
+            with lock:
+                lat[i] = time.perf_counter() - t_sub
+
+        up = threading.Thread(target=updater)
+        up.start()
+        start = time.perf_counter()
+        due = start
+        pending = []
+        for i in range(count):
+            due += gaps[i]
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            u, k, e = mix[16 + i]
+            t_sub = time.perf_counter()
+            tk = srv.submit(u, C, e, DELTA, 4000 + i, k=k)
+            th = threading.Thread(target=waiter, args=(i, tk, t_sub))
+            th.start()
+            pending.append(th)
+        for th in pending:
+            th.join()
+        wall = time.perf_counter() - start
+        stop.set()
+        up.join()
+        st = srv.stats()
+    finally:
+        srv.stop()
+    G.close()
+    ctx.close()
+    la = np.array(lat) * 1e3
+    return {"workload": f"Chung-Lu 10M nodes / 200M edges; Poisson arrivals, 70% single-source / 30% top-50, "
+                        f"eps from {list(eps_mix)}; {upd_per_s} edge updates/s in batches of {upd_batch}",
+            "x_sat_qps": x_sat, "offered_qps": rate, "served_qps": count / wall, "queries": count,
+            "p50_ms": float(np.percentile(la, 50)), "p99_ms": float(np.percentile(la, 99)),
+            "updates_applied": st["updates"], "update_batches": st["update_batches"],
+            "update_latency_ms_mean": st["update_latency_ms_mean"], "update_latency_ms_max": st["update_latency_ms_max"],
+            "update_apply_ms_mean": st["update_apply_ms_mean"], "update_apply_ms_max": st["update_apply_ms_max"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +357,12 @@ def main():
     ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-topk", action="store_true", help="skip the top-k selection and top-50 query timing")
+    ap.add_argument("--batched-queries", type=int, default=9,
+                    help="queries of the 5M-node batched leg (0 skips it; the full workload is 256)")
+    ap.add_argument("--served-seconds", type=float, default=20.0,
+                    help="open-loop time of the 10M-node served leg with updates (0 skips it)")
+    ap.add_argument("--served-eps", default="0.1",
+                    help="comma-separated eps values of the served leg's query mix")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run a device-to-device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -466,6 +600,12 @@ def main():
             result["served_tuned"] = served(ps, G, q, n, eps_s=split["eps_s"], eps_t=split["eps_t"],
                                             eps_p=split["eps_p"], probe_mode=ps.PROBE_HYBRID,
                                             hybrid_c0=args.hybrid_c0)
+    if args.batched_queries > 0:
+        result["batched_5m"] = leg_batched(ps, args.batched_queries)
+        print(f"batched 5M: {result['batched_5m']}", file=sys.stderr, flush=True)
+    if args.served_seconds > 0:
+        result["served_10m"] = leg_served(ps, args.served_seconds, [float(x) for x in args.served_eps.split(",")])
+        print(f"served 10M: {result['served_10m']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(n, s, d, q)
     print(json.dumps(result), flush=True)

@@ -131,9 +131,9 @@ typedef struct ps_options {
                          its switches, are the shard's own, so its shards
                          give another valid estimate, not the whole's. */
   int32_t slots;      /* concurrent probes on the device; 0: the graph's autotuned
-                         setting, else automatic (up to 1024).  Clamped so that
-                         the per-slot buffers (52 B per slot and node) fit in
-                         56 GiB. */
+                         setting, else 1024; at most 2000.  A slot holds a few
+                         hundred bytes; its frontier lives in lists shared by
+                         all slots and sized from the graph's edge count. */
   int32_t probe_mode; /* PS_PROBE_DETERMINISTIC (Alg. 2 with Rule 2, the
                          default), PS_PROBE_RANDOMIZED (Alg. 4, Section 4.3:
                          one randomized probe per walk and prefix, no Rule 2;
@@ -149,7 +149,13 @@ typedef struct ps_options {
                          hybrid_c0 * w * n out-edges in total, that probe is
                          dropped and each of the w walks through the node runs
                          Alg. 4 on the prefix, drawing what it draws in
-                         randomized mode) */
+                         randomized mode) or PS_PROBE_MERGED (Alg. 3 with
+                         Rule 2 off, eps_p taken as 0: PROBE is linear in
+                         H_0 (Lemma 2), so the weighted probes of each
+                         subtree are summed at its root and pushed once
+                         through the level maps they share; FP64 sums, the
+                         plain definition's values up to the order of the
+                         additions; not for ps_server) */
   int64_t pull_edges; /* a probe level whose kept entries have at least this many
                          out-edges is computed by pulling along in-edges over
                          all nodes instead of pushing along its out-edges (same
@@ -182,6 +188,7 @@ typedef struct ps_options {
 #define PS_PROBE_DETERMINISTIC 0
 #define PS_PROBE_RANDOMIZED 1
 #define PS_PROBE_HYBRID 2
+#define PS_PROBE_MERGED 3
 
 /* Fills the defaults above. */
 void ps_options_default(ps_options* opt);
@@ -393,16 +400,27 @@ typedef struct ps_server_cfg {
   int32_t slots;          /* probe slots (0: the graph's autotuned setting, else automatic) */
   int32_t reserved;
   int64_t frontier_bytes; /* device memory budget for the queries admitted at once
-                             (0: none beyond max_inflight): each takes 8 * n bytes of
-                             FP64 accumulators and about 92 MB of tree and ring space;
-                             the budget lowers max_inflight to what fits (at least one),
-                             and further queries wait in the request ring */
+                             (0: none beyond max_inflight): a query holds 8 * n bytes of
+                             FP64 accumulators plus its tree region, about 40 bytes per
+                             entry of the power of two covering twice its measured walk
+                             nodes; a query's tree is built only while the admitted
+                             queries fit (one always runs), the others wait */
   const ps_options* defaults; /* nullable: options every served query runs with (the
                                  error split, probe mode and its c0, bias shift), copied
                                  at start; a query's own nonzero probe_mode (and then its
                                  hybrid_c0) overrides them.  Walk ranges must be the
                                  defaults (PS_ERR_INVALID_ARG) */
 } ps_server_cfg;
+
+typedef struct ps_server_stats {
+  int64_t queries_done;          /* results handed back */
+  int64_t update_batches;        /* ps_server_update batches applied */
+  int64_t updates;               /* edge updates in them */
+  double update_latency_ms_mean; /* ps_server_update call to the batch applied */
+  double update_latency_ms_max;
+  double update_apply_ms_mean;   /* host time to apply one batch (new graph version queued) */
+  double update_apply_ms_max;
+} ps_server_stats;
 
 /* Starts a serving loop on the graph's context: a host thread that drains
  * the request ring, admits queries onto the device while slots and the
@@ -411,6 +429,9 @@ typedef struct ps_server_cfg {
  * at the next level step) and applies edge updates between level steps.  The
  * context must not be used directly while the server runs. */
 ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_server** out);
+
+/* Counters of the serving loop so far (thread-safe). */
+ps_status ps_server_get_stats(ps_server* s, ps_server_stats* out);
 
 /* Queues one query.  r->scores / r->nodes must be host buffers that stay
  * valid until ps_wait returns for the ticket.  PS_ERR_BUSY when the ring is

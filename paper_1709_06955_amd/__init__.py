@@ -27,7 +27,7 @@ PS_LOAD_DROP_SELF_LOOPS = 2
 PS_MAX_WALK_LEN = 64
 
 # Every entry point declared in include/probesim.h.
-PROBE_DETERMINISTIC, PROBE_RANDOMIZED, PROBE_HYBRID = 0, 1, 2
+PROBE_DETERMINISTIC, PROBE_RANDOMIZED, PROBE_HYBRID, PROBE_MERGED = 0, 1, 2, 3
 RULE2_AS_STATED, RULE2_PROVEN = 0, 1
 
 EXPORTS = [
@@ -36,7 +36,7 @@ EXPORTS = [
     "ps_derive_params", "ps_walks", "ps_single_source", "ps_single_source_sparse", "ps_topk",
     "ps_select_topk", "ps_select_topk_noalloc", "ps_batch",
     "ps_get_stats",
-    "ps_server_start", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
+    "ps_server_start", "ps_server_get_stats", "ps_submit", "ps_wait", "ps_server_update", "ps_server_stop", "ps_autotune",
     "ps_tune_split",
 ]
 
@@ -104,6 +104,12 @@ class Split(C.Structure):
                 ("ms_per_query", C.c_double), ("default_ms_per_query", C.c_double)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("queries_done", C.c_int64), ("update_batches", C.c_int64), ("updates", C.c_int64),
+                ("update_latency_ms_mean", C.c_double), ("update_latency_ms_max", C.c_double),
+                ("update_apply_ms_mean", C.c_double), ("update_apply_ms_max", C.c_double)]
+
+
 class ServerCfg(C.Structure):
     _fields_ = [("ring", C.c_int32), ("max_inflight", C.c_int32), ("slots", C.c_int32),
                 ("reserved", C.c_int32), ("frontier_bytes", C.c_int64), ("defaults", C.POINTER(Options))]
@@ -164,6 +170,7 @@ def load_library(path: str = LIB_PATH):
         "ps_batch": ([vp, C.c_int32, P(Query), P(Options), P(Result)], C.c_int),
         "ps_get_stats": ([vp, P(Stats)], C.c_int),
         "ps_server_start": ([vp, P(ServerCfg), P(vp)], C.c_int),
+        "ps_server_get_stats": ([vp, P(ServerStats)], C.c_int),
         "ps_submit": ([vp, P(Query), P(Result), P(C.c_uint64)], C.c_int),
         "ps_wait": ([vp, C.c_uint64, C.c_int64], C.c_int),
         "ps_server_update": ([vp, C.c_int64, vp, vp, vp], C.c_int),
@@ -485,6 +492,11 @@ class Server:
         o = np.ascontiguousarray(op, dtype=np.uint8)
         _check(load_library().ps_server_update(self._h, int(s.size), s.ctypes.data, d.ctypes.data, o.ctypes.data),
                "ps_server_update")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load_library().ps_server_get_stats(self._h, C.byref(st)), "ps_server_get_stats")
+        return {k: getattr(st, k) for k, _ in st._fields_}
 
     def stop(self):
         if getattr(self, "_h", None):

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libprobesim.so")
 
-SOURCES = ["graph.hip", "engine.hip", "select.hip", "capi.hip", "server.hip"]
+SOURCES = ["graph.hip", "engine.hip", "select.hip", "merged.hip", "capi.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -149,8 +149,11 @@ ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, doub
   q->walk_end = (opt && opt->walk_end >= 0) ? opt->walk_end : q->prm.n_r;
   q->bias_shift = opt ? opt->bias_shift : 0;
   const int mode = opt ? opt->probe_mode : PS_PROBE_DETERMINISTIC;
-  if (mode != PS_PROBE_DETERMINISTIC && mode != PS_PROBE_RANDOMIZED && mode != PS_PROBE_HYBRID)
+  if (mode != PS_PROBE_DETERMINISTIC && mode != PS_PROBE_RANDOMIZED && mode != PS_PROBE_HYBRID &&
+      mode != PS_PROBE_MERGED)
     return PS_ERR_INVALID_ARG;
+  q->merged = mode == PS_PROBE_MERGED;
+  if (q->merged) q->prm.eps_p = 0.0;  // Rule 2 has no merged form
   q->randomized = mode == PS_PROBE_RANDOMIZED;
   q->hybrid = mode == PS_PROBE_HYBRID;
   q->c0 = q->hybrid ? opt->hybrid_c0 : 0.0;

@@ -290,7 +290,7 @@ __global__ void k_walk_tree(TreeArgs a) {
     // a deterministic probe per tree node; a randomized one per walk and
     // prefix (their draws differ per walk, so sharing saves nothing).  The
     // ring's walk index marks a randomized probe; -1 a deterministic one.
-    if (inserted || q.randomized) {
+    if ((inserted || q.randomized) && !q.merged) {
       atomicAdd(&a.remaining[r], 1ull);
       atomicAdd(&a.ctr[C_LEVELS], (unsigned long long)(len - 1));
       const unsigned long long pos = atomicAdd(&a.ctr[C_TAIL], 1ull);
@@ -1993,6 +1993,37 @@ __global__ void k_finalize(int32_t n, const QueryDev* __restrict__ qr, int r) {
     Q.acc[v] = v == Q.u ? 1.0 : Q.acc[v] * Q.inv_nr + Q.shift;
 }
 
+// Host-to-device uploads of small records travel as kernel arguments, so no
+// host buffer has to outlive the call that queues them.
+constexpr int kListArg = 256;
+struct IdList {
+  int32_t n, off;
+  int32_t id[kListArg];
+};
+__global__ void k_put_list(IdList l, int32_t* __restrict__ dst) {
+  for (int i = threadIdx.x; i < l.n; i += blockDim.x) dst[l.off + i] = l.id[i];
+}
+
+struct ThrRow {
+  float t[PS_MAX_WALK_LEN];
+};
+// Writes record r; a fresh record also gets its Rule 2 thresholds and clears
+// its walk bound, pending-probe count and allowance.
+__global__ void k_put_record(QueryDev d, ThrRow thr, int r, bool fresh, QueryDev* __restrict__ qrec,
+                             float* __restrict__ thr_all, unsigned long long* __restrict__ qbound,
+                             unsigned long long* __restrict__ remaining) {
+  if (threadIdx.x == 0) {
+    qrec[r] = d;
+    if (fresh) {
+      qbound[r] = 0;
+      remaining[r] = 0;
+      *d.flip = 0.0;
+    }
+  }
+  if (fresh)
+    for (int i = threadIdx.x; i < PS_MAX_WALK_LEN; i += blockDim.x) thr_all[(size_t)r * PS_MAX_WALK_LEN + i] = thr.t[i];
+}
+
 // ------------------------------------------------------------- host side ----
 
 uint64_t next_pow2(uint64_t x) {
@@ -2004,6 +2035,18 @@ uint64_t next_pow2(uint64_t x) {
 int grid_for(uint64_t work, int block) {
   const uint64_t g = (work + block - 1) / block;
   return (int)std::max<uint64_t>(1, std::min<uint64_t>(g, 1u << 30));
+}
+
+ps_status put_list(const std::vector<int32_t>& ids, int32_t* dst, hipStream_t st) {
+  for (size_t off = 0; off < ids.size(); off += kListArg) {
+    IdList l;
+    l.n = (int32_t)std::min<size_t>(kListArg, ids.size() - off);
+    l.off = (int32_t)off;
+    for (int i = 0; i < l.n; ++i) l.id[i] = ids[off + (size_t)i];
+    k_put_list<<<1, kListArg, 0, st>>>(l, dst);
+  }
+  PS_HIP(hipGetLastError());
+  return PS_OK;
 }
 
 
@@ -2089,9 +2132,12 @@ void session_free(Session* s) {
                     &s->qbound,    &s->acc,          &s->lq,         &s->flip,       &s->keys,      &s->t_parent,
                     &s->t_node,    &s->t_depth,      &s->t_query,    &s->t_weight,   &s->ring,      &s->ring_k,
                     &s->hyb_edges, &s->t_woff,       &s->t_walks,    &s->wcount,     &s->out_ids,
-                    &s->out_scores, &s->sel.state, &s->sel.keys, &s->sel.ids};
+                    &s->out_scores, &s->sel.state, &s->sel.keys, &s->sel.ids, &s->m_keys[0], &s->m_keys[1],
+                    &s->m_vals[0], &s->m_vals[1], &s->m_list, &s->m_ctr};
   for (DevBuf* b : bufs) devbuf_free(*b);
   if (s->h_ctr) (void)hipHostFree(s->h_ctr);
+  if (s->h_qbound) (void)hipHostFree(s->h_qbound);
+  if (s->begin_ev) (void)hipEventDestroy(s->begin_ev);
   if (s->step_pair) (void)hipGraphExecDestroy(s->step_pair);
   delete s;
 }
@@ -2199,6 +2245,14 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
   PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
   PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
   if (!s->h_ctr) PS_HIP(hipHostMalloc((void**)&s->h_ctr, sizeof(uint64_t) * C_COUNT, 0));
+  if (s->h_qbound_n < s->qmax) {
+    if (s->h_qbound) PS_HIP(hipHostFree(s->h_qbound));
+    s->h_qbound = nullptr;
+    PS_HIP(hipHostMalloc((void**)&s->h_qbound, sizeof(unsigned long long) * (size_t)s->qmax, 0));
+    s->h_qbound_n = s->qmax;
+  }
+  if (!s->begin_ev) PS_HIP(hipEventCreateWithFlags(&s->begin_ev, hipEventDisableTiming));
+  s->begin_pending = false;
   if (s->dense_on) PS_TRY(session_dense(s, st));
   k_reset_lanes<<<1, kLanes, 0, st>>>(s->lane_slot.as<int32_t>());
   PS_HIP(hipMemsetAsync(s->counters.p, 0, sizeof(unsigned long long) * C_COUNT, st));
@@ -2222,18 +2276,15 @@ ps_status session_ensure(ps_ctx* ctx, int32_t n, uint64_t m_cap, int P, int qmax
 
 // Phase 1 of admission: records, walk sampling, tree sizes (one sync).
 ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                        std::vector<int>* recs, std::vector<uint64_t>* bounds) {
+                        std::vector<int>* recs) {
   Session* s = ctx->sess;
   hipStream_t st = ctx->stream;
-  if ((size_t)s->free_recs.size() < qs.size()) return PS_ERR_BUSY;
+  if ((size_t)s->free_recs.size() < qs.size() || s->begin_pending) return PS_ERR_BUSY;
   recs->clear();
-  bounds->assign(qs.size(), 0);
   if (qs.empty()) return PS_OK;
-  // one threshold row per query, alive until the synchronisation below
-  std::vector<float> thr_all(qs.size() * PS_MAX_WALK_LEN, 0.0f);
   int64_t total = 0;
   for (const QueryRun& q : qs) {
-    float* thr = thr_all.data() + recs->size() * PS_MAX_WALK_LEN;
+    ThrRow thr{};
     const int r = s->free_recs.back();
     s->free_recs.pop_back();
     recs->push_back(r);
@@ -2265,6 +2316,7 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     d.flip_unit = q.randomized ? 0.0 : q.prm.eps_p * (1.0 + 1e-4) / (double)q.prm.n_r;
     d.randomized = q.randomized;
     d.hybrid = q.hybrid;
+    d.merged = q.merged;
     d.c0 = q.c0;
     d.t_sc = (uint32_t)std::floor(sc * 4294967296.0);
     d.key2 = make_uint2((uint32_t)q.seed, (uint32_t)(q.seed >> 32) ^ 0x9E3779B9u);
@@ -2277,30 +2329,51 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
     s->rec_version[(size_t)r] = gv;
     // Rule 2 thresholds thr[e] = eps_p / sqrt(c)^e (0 = no pruning)
     for (int x = 1; x < PS_MAX_WALK_LEN; ++x)
-      thr[x] = q.prm.eps_p > 0.0 ? (float)(q.prm.eps_p / std::pow(sc, (double)x)) : 0.0f;
-    PS_HIP(hipMemcpyAsync(s->thr.as<float>() + (size_t)r * PS_MAX_WALK_LEN, thr, sizeof(float) * PS_MAX_WALK_LEN,
-                          hipMemcpyHostToDevice, st));
-    PS_HIP(hipMemcpyAsync(s->qrec.as<QueryDev>() + r, &s->h_rec[(size_t)r], sizeof(QueryDev), hipMemcpyHostToDevice,
-                          st));
+      thr.t[x] = q.prm.eps_p > 0.0 ? (float)(q.prm.eps_p / std::pow(sc, (double)x)) : 0.0f;
+    k_put_record<<<1, PS_MAX_WALK_LEN, 0, st>>>(d, thr, r, true, s->qrec.as<QueryDev>(), s->thr.as<float>(),
+                                                s->qbound.as<unsigned long long>(),
+                                                s->remaining.as<unsigned long long>());
     PS_HIP(hipMemsetAsync(d.acc, 0, sizeof(double) * (size_t)s->n, st));
-    PS_HIP(hipMemsetAsync(s->qbound.as<unsigned long long>() + r, 0, sizeof(unsigned long long), st));
-    PS_HIP(hipMemsetAsync(s->remaining.as<unsigned long long>() + r, 0, sizeof(unsigned long long), st));
-    PS_HIP(hipMemsetAsync(d.flip, 0, sizeof(double), st));
   }
-  PS_HIP(hipMemcpyAsync(s->lq.p, recs->data(), sizeof(int32_t) * recs->size(), hipMemcpyHostToDevice, st));
+  PS_TRY(put_list(*recs, s->lq.as<int32_t>(), st));
   if (total > 0) {
     k_walk_bound<<<grid_for((uint64_t)total, kBlock), kBlock, 0, st>>>(
         s->qrec.as<QueryDev>(), s->lq.as<int32_t>(), (int)recs->size(), total, s->qbound.as<unsigned long long>(),
         s->counters.as<unsigned long long>());
     PS_HIP(hipGetLastError());
   }
-  std::vector<unsigned long long> hb((size_t)s->qmax);
-  PS_HIP(hipMemcpyAsync(hb.data(), s->qbound.p, sizeof(unsigned long long) * (size_t)s->qmax, hipMemcpyDeviceToHost,
+  // the bounds come back through pinned memory; session_bounds reads them
+  PS_HIP(hipMemcpyAsync(s->h_qbound, s->qbound.p, sizeof(unsigned long long) * (size_t)s->qmax, hipMemcpyDeviceToHost,
                         st));
-  PS_HIP(hipStreamSynchronize(st));
-  for (size_t i = 0; i < recs->size(); ++i) (*bounds)[i] = hb[(size_t)(*recs)[i]];
+  PS_HIP(hipEventRecord(s->begin_ev, st));
+  s->begin_pending = true;
   return PS_OK;
 }
+
+ps_status session_bounds(ps_ctx* ctx, const std::vector<int>& recs, std::vector<uint64_t>* bounds, bool wait,
+                         bool* ready) {
+  Session* s = ctx->sess;
+  *ready = false;
+  bounds->assign(recs.size(), 0);
+  if (recs.empty()) {
+    *ready = true;
+    return PS_OK;
+  }
+  if (!s->begin_pending) return PS_ERR_STATE;
+  if (wait) {
+    PS_HIP(hipEventSynchronize(s->begin_ev));
+  } else {
+    const hipError_t e = hipEventQuery(s->begin_ev);
+    if (e == hipErrorNotReady) return PS_OK;
+    PS_HIP(e);
+  }
+  for (size_t i = 0; i < recs.size(); ++i) (*bounds)[i] = s->h_qbound[(size_t)recs[i]];
+  s->begin_pending = false;
+  *ready = true;
+  return PS_OK;
+}
+
+
 
 // Ring entries record r may need: one per tree node, plus one per walk and
 // prefix for the probes a hybrid query switches (Section 4.4).
@@ -2342,13 +2415,13 @@ ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::ve
     s->rec_ring[(size_t)r] = ring_share(s, r, bounds[i]);
     s->ring_outstanding += s->rec_ring[(size_t)r];
     launch.push_back(r);
-    PS_HIP(hipMemcpyAsync(s->qrec.as<QueryDev>() + r, &d, sizeof(QueryDev), hipMemcpyHostToDevice, st));
+    k_put_record<<<1, 1, 0, st>>>(d, ThrRow{}, r, false, s->qrec.as<QueryDev>(), nullptr, nullptr, nullptr);
     PS_HIP(hipMemsetAsync(s->keys.as<unsigned long long>() + d.tree_base, 0xFF,
                           sizeof(unsigned long long) * (d.tree_mask + 1), st));
     PS_HIP(hipMemsetAsync(s->t_weight.as<int32_t>() + d.tree_base, 0, sizeof(int32_t) * (d.tree_mask + 1), st));
   }
   if (launch.empty()) return PS_OK;
-  PS_HIP(hipMemcpyAsync(s->lq.p, launch.data(), sizeof(int32_t) * launch.size(), hipMemcpyHostToDevice, st));
+  PS_TRY(put_list(launch, s->lq.as<int32_t>(), st));
   k_init_roots<<<grid_for(launch.size(), kBlock), kBlock, 0, st>>>(
       s->qrec.as<QueryDev>(), s->lq.as<int32_t>(), (int)launch.size(), s->tree_pool, s->t_parent.as<int32_t>(),
       s->t_node.as<int32_t>(), s->t_depth.as<int32_t>(), s->t_query.as<int32_t>());
@@ -2689,8 +2762,8 @@ ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold) {
   return PS_OK;
 }
 
-ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                     const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt) {
+static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
+                                 const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt) {
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t st = ctx->stream;
   const int32_t n = g->n;
@@ -2714,7 +2787,9 @@ ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vect
 
   std::vector<int> recs;
   std::vector<uint64_t> bounds;
-  PS_TRY(session_begin(ctx, g, gv, qs, &recs, &bounds));
+  PS_TRY(session_begin(ctx, g, gv, qs, &recs));
+  bool ready = false;
+  PS_TRY(session_bounds(ctx, recs, &bounds, true, &ready));
   uint64_t pool_need = 0, ring_need = 0;
   for (size_t i = 0; i < bounds.size(); ++i) {
     const uint64_t b = bounds[i];
@@ -2864,5 +2939,56 @@ ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (!bytes) return PS_OK;
   const hipMemcpyKind kind = ps_is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   PS_HIP(hipMemcpyAsync(dst, src, bytes, kind, st));
+  return PS_OK;
+}
+
+// Queries by merged probing run one at a time on their own path; the others
+// go through the level-step engine together.
+ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
+                     const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt) {
+  std::vector<QueryRun> rest;
+  std::vector<QueryOut> rest_out;
+  std::vector<size_t> merged;
+  for (size_t i = 0; i < qs.size(); ++i) {
+    if (qs[i].merged) {
+      merged.push_back(i);
+    } else {
+      rest.push_back(qs[i]);
+      rest_out.push_back(outs[i]);
+    }
+  }
+  if (merged.empty()) return engine_run_core(ctx, g, gv, qs, outs, slots_opt, pull_opt);
+  const auto t0 = std::chrono::steady_clock::now();
+  ps_stats ms{};
+  const int P = session_slots_for(g->n, slots_opt);
+  const uint64_t m_cap = std::max<uint64_t>(gv->out_store->cap, 1);
+  Session* s = ctx->sess;
+  PS_TRY(session_ensure(ctx, g->n, m_cap, P, std::max<int>((int)qs.size(), s ? s->qmax : 0), s ? s->tree_pool : 0,
+                        s ? s->ring_cap : 0));
+  for (size_t i : merged) {
+    ps_status e = engine_merged(ctx, g, gv, qs[i], outs[i], &ms);
+    if (e != PS_OK) return e;
+  }
+  ms.queries = (int64_t)merged.size();
+  if (!rest.empty()) {
+    PS_TRY(engine_run_core(ctx, g, gv, rest, rest_out, slots_opt, pull_opt));
+    ps_stats& L = ctx->last;
+    L.queries += ms.queries;
+    L.walks += ms.walks;
+    L.tree_nodes += ms.tree_nodes;
+    L.probe_levels += ms.probe_levels;
+    L.steps += ms.steps;
+    L.entries_expanded += ms.entries_expanded;
+    L.edges_scanned += ms.edges_scanned;
+    L.next_entries += ms.next_entries;
+    L.final_adds += ms.final_adds;
+    L.expand_launches += ms.expand_launches;
+    L.expand_ms += ms.expand_ms;
+    L.pushed_edges += ms.pushed_edges;
+    L.pushed_final_adds += ms.pushed_final_adds;
+  } else {
+    ctx->last = ms;
+  }
+  ctx->last.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return PS_OK;
 }

@@ -66,10 +66,18 @@ ps_status alloc_version_arrays(GraphVersion* v, int32_t n) {
 // (Re)builds the heavy in-row lists of a version from its in_rows.  Chunks
 // are bounded by m / kPullChunk + (nodes with long rows) <= m_cap / kPullChunk + n.
 ps_status build_heavy(GraphVersion* v, int32_t n, uint64_t m_cap, hipStream_t st) {
+  const uint64_t chunk_cap = m_cap / kPullChunk + (uint64_t)n + 1;
+  if (v->heavy_chunks && v->heavy_chunk_cap < chunk_cap) {  // a compaction grew the column store
+    (void)hipFree(v->heavy_chunks);
+    v->heavy_chunks = nullptr;
+  }
   if (!v->heavy_nodes) {
     PS_HIP(hipMalloc(&v->heavy_nodes, sizeof(int32_t) * (size_t)n));
-    PS_HIP(hipMalloc(&v->heavy_chunks, sizeof(int2) * (m_cap / kPullChunk + (size_t)n + 1)));
     PS_HIP(hipMalloc(&v->heavy_cnt, sizeof(unsigned long long) * 2));
+  }
+  if (!v->heavy_chunks) {
+    PS_HIP(hipMalloc(&v->heavy_chunks, sizeof(int2) * chunk_cap));
+    v->heavy_chunk_cap = chunk_cap;
   }
   PS_HIP(hipMemsetAsync(v->heavy_cnt, 0, sizeof(unsigned long long) * 2, st));
   k_heavy<<<(n + 255) / 256, 256, 0, st>>>(n, v->in_rows, v->heavy_nodes, v->heavy_chunks, v->heavy_cnt);
@@ -122,7 +130,10 @@ GraphVersion* new_version(ps_graph* g) {
     fresh->in_rows = v->in_rows;
     fresh->out_rows = v->out_rows;
     fresh->inv_indeg = v->inv_indeg;
-    free_heavy(v);
+    fresh->heavy_nodes = v->heavy_nodes;
+    fresh->heavy_chunks = v->heavy_chunks;
+    fresh->heavy_cnt = v->heavy_cnt;
+    fresh->heavy_chunk_cap = v->heavy_chunk_cap;
     delete v;
     return fresh;
   }
@@ -322,6 +333,11 @@ extern "C" void ps_graph_free(ps_graph* g) {
   for (auto* v : g->retired) free_version(v);
   for (auto* v : g->spare) free_version(v);
   free_version(g->cur);
+  for (int i = 0; i < ps_graph::kStages; ++i) {
+    if (g->h_stage[i]) (void)hipHostFree(g->h_stage[i]);
+    devbuf_free(g->d_stage[i]);
+    if (g->stage_ev[i]) (void)hipEventDestroy(g->stage_ev[i]);
+  }
   ps_ctx* ctx = g->ctx;
   delete g;
   ctx_release(ctx);
@@ -439,39 +455,73 @@ ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const 
       v->out_store = old->out_store;
       v->in_store->refs++;
       v->out_store->refs++;
-      // Stage rewritten rows and their (start, len) patches.
-      auto stage = [&](const std::vector<int32_t>& nodes, std::unordered_map<int32_t, std::vector<int32_t>>& mod,
-                       ColStore* store, uint2* rows, float* inv) -> ps_status {
-        std::vector<int32_t> cols, pn;
-        std::vector<uint2> pr;
-        const uint64_t base = store->used;
+      // Rewritten rows go to the end of the column stores' delta regions;
+      // (node, start, len) patches fix the version's row arrays.  Both
+      // directions share one pinned staging fill and one device buffer.
+      struct Part {
+        std::vector<int32_t> cols, nodes;
+        std::vector<uint2> rows;
+        uint64_t base = 0;
+      } parts[2];
+      auto gather = [&](const std::vector<int32_t>& nodes, std::unordered_map<int32_t, std::vector<int32_t>>& mod,
+                        ColStore* store, Part& P) {
+        P.base = store->used;
         for (int32_t a : nodes) {
           auto& r = mod[a];
-          pn.push_back(a);
-          pr.push_back(make_uint2((uint32_t)(base + cols.size()), (uint32_t)r.size()));
-          cols.insert(cols.end(), r.begin(), r.end());
+          P.nodes.push_back(a);
+          P.rows.push_back(make_uint2((uint32_t)(P.base + P.cols.size()), (uint32_t)r.size()));
+          P.cols.insert(P.cols.end(), r.begin(), r.end());
         }
-        if (!cols.empty())
-          PS_HIP(hipMemcpyAsync(store->col + base, cols.data(), sizeof(int32_t) * cols.size(), hipMemcpyHostToDevice, st));
-        store->used = base + cols.size();
-        int32_t* d_node = nullptr;
-        uint2* d_row = nullptr;
-        PS_HIP(hipMalloc(&d_node, sizeof(int32_t) * pn.size()));
-        PS_HIP(hipMalloc(&d_row, sizeof(uint2) * pr.size()));
-        PS_HIP(hipMemcpyAsync(d_node, pn.data(), sizeof(int32_t) * pn.size(), hipMemcpyHostToDevice, st));
-        PS_HIP(hipMemcpyAsync(d_row, pr.data(), sizeof(uint2) * pr.size(), hipMemcpyHostToDevice, st));
-        const int32_t cnt = (int32_t)pn.size();
-        k_patch_rows<<<(cnt + 255) / 256, 256, 0, st>>>(d_node, d_row, cnt, rows, inv);
-        PS_HIP(hipGetLastError());
-        PS_HIP(hipStreamSynchronize(st));
-        (void)hipFree(d_node);
-        (void)hipFree(d_row);
-        return PS_OK;
+        store->used = P.base + P.cols.size();
       };
-      PS_TRY(stage(touched_in, g->mod_in, v->in_store.get(), v->in_rows, v->inv_indeg));
-      PS_TRY(stage(touched_out, g->mod_out, v->out_store.get(), v->out_rows, nullptr));
+      gather(touched_in, g->mod_in, v->in_store.get(), parts[0]);
+      gather(touched_out, g->mod_out, v->out_store.get(), parts[1]);
+      auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+      size_t off[2][3], total = 0;
+      for (int d = 0; d < 2; ++d) {
+        off[d][0] = total;
+        total += up(sizeof(int32_t) * parts[d].cols.size());
+        off[d][1] = total;
+        total += up(sizeof(int32_t) * parts[d].nodes.size());
+        off[d][2] = total;
+        total += up(sizeof(uint2) * parts[d].rows.size());
+      }
+      const int sg = g->stage_next;
+      g->stage_next = (sg + 1) % ps_graph::kStages;
+      if (g->stage_live[sg]) PS_HIP(hipEventSynchronize(g->stage_ev[sg]));  // its last uploads are done
+      if (g->h_stage_bytes[sg] < total) {
+        if (g->h_stage[sg]) PS_HIP(hipHostFree(g->h_stage[sg]));
+        g->h_stage[sg] = nullptr;
+        g->h_stage_bytes[sg] = 0;
+        PS_HIP(hipHostMalloc(&g->h_stage[sg], total, 0));
+        g->h_stage_bytes[sg] = total;
+      }
+      if (!g->stage_ev[sg]) PS_HIP(hipEventCreateWithFlags(&g->stage_ev[sg], hipEventDisableTiming));
+      PS_TRY(devbuf_reserve(g->d_stage[sg], total));
+      char* hs = static_cast<char*>(g->h_stage[sg]);
+      char* ds = static_cast<char*>(g->d_stage[sg].p);
+      for (int d = 0; d < 2; ++d) {
+        Part& P = parts[d];
+        ColStore* store = d == 0 ? v->in_store.get() : v->out_store.get();
+        std::memcpy(hs + off[d][0], P.cols.data(), sizeof(int32_t) * P.cols.size());
+        std::memcpy(hs + off[d][1], P.nodes.data(), sizeof(int32_t) * P.nodes.size());
+        std::memcpy(hs + off[d][2], P.rows.data(), sizeof(uint2) * P.rows.size());
+        if (!P.cols.empty())
+          PS_HIP(hipMemcpyAsync(store->col + P.base, hs + off[d][0], sizeof(int32_t) * P.cols.size(),
+                                hipMemcpyHostToDevice, st));
+        if (P.nodes.empty()) continue;
+        PS_HIP(hipMemcpyAsync(ds + off[d][1], hs + off[d][1], off[d][2] - off[d][1] + sizeof(uint2) * P.rows.size(),
+                              hipMemcpyHostToDevice, st));
+        const int32_t cnt = (int32_t)P.nodes.size();
+        k_patch_rows<<<(cnt + 255) / 256, 256, 0, st>>>(reinterpret_cast<const int32_t*>(ds + off[d][1]),
+                                                        reinterpret_cast<const uint2*>(ds + off[d][2]), cnt,
+                                                        d == 0 ? v->in_rows : v->out_rows,
+                                                        d == 0 ? v->inv_indeg : nullptr);
+        PS_HIP(hipGetLastError());
+      }
+      PS_HIP(hipEventRecord(g->stage_ev[sg], st));
+      g->stage_live[sg] = true;
       PS_TRY(build_heavy(v, g->n, v->in_store->cap, st));
-      PS_HIP(hipStreamSynchronize(st));
     }
     {
       std::lock_guard<std::mutex> lk(g->mu);

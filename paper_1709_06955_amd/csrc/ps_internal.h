@@ -68,6 +68,7 @@ struct GraphVersion {
   int32_t* heavy_nodes = nullptr;
   int2* heavy_chunks = nullptr;          // (node, first in-row offset)
   unsigned long long* heavy_cnt = nullptr;
+  uint64_t heavy_chunk_cap = 0;          // entries of heavy_chunks
   std::shared_ptr<ColStore> in_store, out_store;
   int refs = 0;               // queries reading this version + 1 while current
 };
@@ -83,6 +84,18 @@ struct ps_graph {
   GraphVersion* cur = nullptr;
   std::vector<GraphVersion*> retired;  // superseded versions still read by queries
   std::vector<GraphVersion*> spare;    // freed versions whose row arrays are reused
+  // staging of update batches: rewritten rows and (node, row) patches go
+  // through pinned host memory into a device buffer.  A ring of kStages
+  // buffers: a batch refills the one used kStages batches earlier after its
+  // event shows those uploads done, so a batch rarely waits for the level
+  // steps queued ahead of it.
+  static constexpr int kStages = 4;
+  void* h_stage[kStages] = {};
+  size_t h_stage_bytes[kStages] = {};
+  DevBuf d_stage[kStages];
+  hipEvent_t stage_ev[kStages] = {};
+  bool stage_live[kStages] = {};
+  int stage_next = 0;
   int tuned_slots = 0;                 // autotuned probe slots (0: none)
   int64_t tuned_dense = 0;             // autotuned dense threshold (0: none)
   std::mutex mu;
@@ -135,7 +148,7 @@ struct QueryDev {
   uint2 key2;          // Philox key of Alg. 4's draws
   double c0;           // Section 4.4: switch constant (hybrid queries)
   int32_t hybrid;      // deterministic probes switch to Alg. 4 past c0 * w * n out-edges
-  int32_t pad2;
+  int32_t merged;      // tree only: its probes are merged per depth, not queued
 };
 
 // Host view of a query.
@@ -148,6 +161,7 @@ struct QueryRun {
   int randomized = 0;  // Alg. 4 instead of Alg. 2
   int hybrid = 0;      // Alg. 2 per tree node, switching to Alg. 4 (Section 4.4)
   double c0 = 0.0;     // the switch constant of a hybrid query
+  int merged = 0;      // merged probing over the tree, Rule 2 off (merged.hip)
 };
 
 // A frontier list is kSubLists sub-lists, each with its own counter, so that
@@ -269,6 +283,7 @@ struct Session {
   // node the walks through it (t_walks[t_woff[t] - weight .. t_woff[t]))
   DevBuf hyb_edges, t_woff, t_walks, wcount;
   DevBuf out_ids, out_scores;
+  DevBuf m_keys[2], m_vals[2], m_list, m_ctr;  // merged probing
   SelectBufs sel;
   uint64_t* h_ctr = nullptr;  // pinned mirror of the counters
   uint64_t steps = 0;         // level steps launched (parity of the lists)
@@ -277,6 +292,12 @@ struct Session {
   // host bookkeeping
   std::vector<int> free_recs;
   std::vector<QueryDev> h_rec;
+  // walk-bound read-back of session_begin (pinned, qmax entries) and the
+  // event that marks it complete
+  unsigned long long* h_qbound = nullptr;
+  int h_qbound_n = 0;
+  hipEvent_t begin_ev = nullptr;
+  bool begin_pending = false;
   std::vector<GraphVersion*> rec_version;
   std::vector<std::pair<uint64_t, uint64_t>> tree_free;  // [start, len) free regions
   std::vector<std::pair<uint64_t, uint64_t>> rec_tree;   // region of each record
@@ -312,9 +333,14 @@ void session_clear_guard(Session* s, hipStream_t st);
 void session_free(Session* s);
 int session_slots_for(int32_t n, int opt);
 // Admission, phase 1: takes records for the queries (all reading graph
-// version gv), samples their walks once and returns each tree's size bound.
+// version gv) and queues a pass over their walks that sizes each tree; it
+// does not wait for it.  One such pass may be outstanding at a time.
 ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
-                        std::vector<int>* recs, std::vector<uint64_t>* bounds);
+                        std::vector<int>* recs);
+// The tree-size bounds of the records of the last session_begin, once its
+// walk pass has finished: waits for it (wait) or reports *ready = false.
+ps_status session_bounds(ps_ctx* ctx, const std::vector<int>& recs, std::vector<uint64_t>* bounds, bool wait,
+                         bool* ready);
 // Admission, phase 2: tree regions, tree construction, probes queued.
 // PS_ERR_BUSY when tree or ring space is short.
 ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds);
@@ -350,6 +376,10 @@ ps_status make_query_run(const ps_graph* g, int32_t u, int32_t k, double c, doub
 ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
                      const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt);
 uint64_t pull_threshold(int64_t m, int64_t opt);
+// One query by merged probing (merged.hip): walks, tree, then one expansion
+// per tree node; adds its work to *st and writes the result.
+ps_status engine_merged(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const QueryRun& q, const QueryOut& out,
+                        ps_stats* st);
 ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold);
 
 ps_status engine_walks(ps_ctx* ctx, GraphVersion* gv, int32_t n, const QueryRun& q, int64_t k_begin,

@@ -34,6 +34,7 @@ struct UpdateBatch {
   std::vector<int32_t> src, dst;
   std::vector<uint8_t> op;
   uint64_t seq;
+  std::chrono::steady_clock::time_point t_sub;  // when ps_server_update queued it
 };
 
 struct Staging {
@@ -73,6 +74,8 @@ struct ps_server {
   std::vector<int> staging_free;
   std::vector<hipEvent_t> ev_free;
   ps_status fatal = PS_OK;
+  ps_server_stats stats{};  // under mu
+  double upd_lat_sum = 0.0, upd_apply_sum = 0.0;
 };
 
 namespace {
@@ -82,6 +85,24 @@ struct Admitted {
   QueryRun run;
   uint64_t bound = 0;  // sum over its walks of (len - 1)
   bool built = false;  // tree built, probes queued
+  uint64_t bytes = 0;  // device memory it holds once built
+};
+
+// Device memory of an admitted query: its FP64 accumulators and its tree
+// region (a power of two of entries of about 40 bytes: key, five node
+// fields, walk offset and walk list entry, ring entry).
+uint64_t query_bytes(int32_t n, uint64_t bound) {
+  uint64_t cap = 64;
+  while (cap < 2 * bound) cap <<= 1;
+  return 8ull * (uint64_t)n + 40ull * cap;
+}
+
+// Queries whose walk pass is queued and whose tree sizes are not back yet.
+struct Pending {
+  std::vector<int> recs;
+  std::vector<QueryRun> runs;
+  std::vector<Request> reqs;
+  bool live = false;
 };
 
 void finish_ticket(ps_server* s, uint64_t ticket, ps_status st) {
@@ -116,6 +137,7 @@ void completer(ps_server* s) {
     c.r->status = st;
     c.r->count = st == PS_OK ? c.count : 0;
     std::lock_guard<std::mutex> lk(s->mu);
+    s->stats.queries_done++;
     if (c.staging >= 0) s->staging_free.push_back(c.staging);
     s->ev_free.push_back(c.ev);
     s->finished[c.ticket] = st;
@@ -209,6 +231,8 @@ ps_status serve_loop(ps_server* s) {
   hipStream_t st = ctx->stream;
   std::unordered_map<int, Admitted> admitted;  // record -> query
   std::deque<int> waiting_build;               // records begun, trees not yet built
+  Pending pend;                                // walk pass queued, tree sizes not back yet
+  uint64_t committed = 0;                      // device bytes of the built queries
   Session* ss = ctx->sess;
   // done-ring snapshots, two in flight
   unsigned long long done_seen = 0;
@@ -235,7 +259,7 @@ ps_status serve_loop(ps_server* s) {
     bool stopping;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      auto idle = [&] { return admitted.empty() && waiting_build.empty(); };
+      auto idle = [&] { return admitted.empty() && waiting_build.empty() && !pend.live; };
       if (idle() && s->ring.empty() && s->updates.empty())
         s->cv_work.wait(lk, [&] { return s->stopping || !s->ring.empty() || !s->updates.empty(); });
       stopping = s->stopping;
@@ -246,7 +270,7 @@ ps_status serve_loop(ps_server* s) {
       // next update in submission order, which a later iteration applies.
       const int room = std::min(s->cfg.max_inflight - (int)admitted.size() - (int)waiting_build.size(),
                                 (int)ss->free_recs.size());
-      const bool admit = !s->ring.empty() && room > 0;
+      const bool admit = !s->ring.empty() && room > 0 && !pend.live;
       const uint64_t oldest = s->ring.empty() ? ~0ull : s->ring.front().seq;
       const double since = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - last_update).count();
       if (admit || since >= kUpdateIntervalMs || idle()) {
@@ -264,8 +288,20 @@ ps_status serve_loop(ps_server* s) {
     }
     // (1) edge updates between level steps
     if (!ups.empty()) {
-      for (auto& u : ups)
+      for (auto& u : ups) {
+        const auto t0 = std::chrono::steady_clock::now();
         (void)graph_apply_updates(g, (int64_t)u.src.size(), u.src.data(), u.dst.data(), u.op.data(), nullptr, nullptr);
+        const auto t1 = std::chrono::steady_clock::now();
+        const double apply = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        const double lat = std::chrono::duration<double, std::milli>(t1 - u.t_sub).count();
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stats.update_batches++;
+        s->stats.updates += (int64_t)u.src.size();
+        s->upd_lat_sum += lat;
+        s->upd_apply_sum += apply;
+        s->stats.update_latency_ms_max = std::max(s->stats.update_latency_ms_max, lat);
+        s->stats.update_apply_ms_max = std::max(s->stats.update_apply_ms_max, apply);
+      }
       last_update = std::chrono::steady_clock::now();
     }
     // (2) admission
@@ -281,6 +317,7 @@ ps_status serve_loop(ps_server* s) {
         }
         ps_status vs = make_query_run(g, rq.q.u, rq.q.k, rq.q.c, rq.q.eps, rq.q.delta, rq.q.seed, &opt, &qr);
         if (vs == PS_OK && (!rq.r->scores || (rq.q.k > 0 && !rq.r->nodes))) vs = PS_ERR_INVALID_ARG;
+        if (vs == PS_OK && qr.merged) vs = PS_ERR_INVALID_ARG;  // merged probing runs through ps_single_source
         if (vs != PS_OK) {
           rq.r->status = vs;
           rq.r->count = 0;
@@ -291,10 +328,11 @@ ps_status serve_loop(ps_server* s) {
         ok.push_back(rq);
       }
       if (!runs.empty()) {
+        // the walk pass is queued behind the steps already queued; its tree
+        // sizes are picked up by a later iteration without waiting here
         GraphVersion* gv = graph_acquire(g);
         std::vector<int> recs;
-        std::vector<uint64_t> bounds;
-        ps_status bs = session_begin(ctx, g, gv, runs, &recs, &bounds);
+        ps_status bs = session_begin(ctx, g, gv, runs, &recs);
         graph_release(g, gv);
         if (bs != PS_OK) {
           for (auto& rq : ok) {
@@ -302,21 +340,46 @@ ps_status serve_loop(ps_server* s) {
             finish_ticket(s, rq.ticket, bs);
           }
         } else {
-          for (size_t i = 0; i < recs.size(); ++i) {
-            Admitted a;
-            a.req = ok[i];
-            a.run = runs[i];
-            a.bound = bounds[i];
-            admitted[recs[i]] = a;
-            waiting_build.push_back(recs[i]);
-          }
+          pend.recs = std::move(recs);
+          pend.runs = std::move(runs);
+          pend.reqs = std::move(ok);
+          pend.live = true;
         }
+      }
+    }
+    // tree sizes of the queued walk pass: wait only when nothing else runs
+    if (pend.live) {
+      bool any_built = false;
+      for (auto& kv : admitted) any_built |= kv.second.built;
+      std::vector<uint64_t> bounds;
+      bool ready = false;
+      ps_status bs = session_bounds(ctx, pend.recs, &bounds, !any_built && waiting_build.empty(), &ready);
+      if (bs != PS_OK) {
+        fatal = bs;
+        break;
+      }
+      if (ready) {
+        for (size_t i = 0; i < pend.recs.size(); ++i) {
+          Admitted a;
+          a.req = pend.reqs[i];
+          a.run = pend.runs[i];
+          a.bound = bounds[i];
+          admitted[pend.recs[i]] = a;
+          waiting_build.push_back(pend.recs[i]);
+        }
+        pend = Pending();
       }
     }
     // build trees in arrival order while tree/ring space allows
     while (!waiting_build.empty()) {
       const int r = waiting_build.front();
       Admitted& a = admitted[r];
+      a.bytes = query_bytes(g->n, a.bound);
+      if (s->cfg.frontier_bytes > 0 && committed + a.bytes > (uint64_t)s->cfg.frontier_bytes) {
+        bool any_built = false;
+        for (auto& kv : admitted) any_built |= kv.second.built;
+        if (any_built) break;  // the memory budget frees up as running queries finish
+      }
       ps_status bs = session_build(ctx, {r}, {a.bound});
       if (bs == PS_ERR_BUSY) {
         bool any_built = false;
@@ -337,7 +400,9 @@ ps_status serve_loop(ps_server* s) {
         break;
       }
       a.built = true;
+      committed += a.bytes;
       if (a.bound == 0) {  // no probe: the estimate is e_u
+        committed -= a.bytes;
         ps_status cs = complete_record(s, r, a);
         if (cs != PS_OK) fatal = cs;
         admitted.erase(r);
@@ -379,6 +444,7 @@ ps_status serve_loop(ps_server* s) {
         const int r = snap_ring[look][done_seen % (unsigned long long)ss->qmax];
         auto it = admitted.find(r);
         if (it == admitted.end()) continue;
+        committed -= it->second.bytes;
         ps_status cs = complete_record(s, r, it->second);
         if (cs != PS_OK) fatal = cs;
         admitted.erase(it);
@@ -398,6 +464,10 @@ ps_status serve_loop(ps_server* s) {
     for (auto& kv : admitted) {
       kv.second.req.r->status = fatal;
       finish_ticket(s, kv.second.req.ticket, fatal);
+    }
+    for (auto& rq : pend.reqs) {
+      rq.r->status = fatal;
+      finish_ticket(s, rq.ticket, fatal);
     }
     std::lock_guard<std::mutex> lk(s->mu);
     for (auto& rq : s->ring) {
@@ -432,7 +502,8 @@ extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_s
   if (cfg) s->cfg = *cfg;
   ps_options_default(&s->defaults);
   if (s->cfg.defaults) {
-    if (s->cfg.defaults->walk_begin != 0 || s->cfg.defaults->walk_end >= 0) {
+    if (s->cfg.defaults->walk_begin != 0 || s->cfg.defaults->walk_end >= 0 ||
+        s->cfg.defaults->probe_mode == PS_PROBE_MERGED) {
       delete s;
       return PS_ERR_INVALID_ARG;
     }
@@ -448,7 +519,7 @@ extern "C" ps_status ps_server_start(ps_graph* g, const ps_server_cfg* cfg, ps_s
     // share of the tree pool (key, five int32 node fields, walk offset and
     // walk list per entry) and of the ring; the budget caps how many are
     // admitted at once (at least one), the others wait in the request ring
-    const uint64_t each = 8ull * (uint64_t)g->n + 40ull * per_q + 4ull * per_q;
+    const uint64_t each = query_bytes(g->n, 0);
     const uint64_t fit = std::max<uint64_t>((uint64_t)s->cfg.frontier_bytes / each, 1);
     s->cfg.max_inflight = (int32_t)std::min<uint64_t>((uint64_t)s->cfg.max_inflight, fit);
   }
@@ -505,6 +576,7 @@ extern "C" ps_status ps_server_update(ps_server* s, int64_t k, const int32_t* sr
   b.src.assign(src, src + k);
   b.dst.assign(dst, dst + k);
   b.op.assign(op, op + k);
+  b.t_sub = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stopping) return PS_ERR_STATE;
   b.seq = s->next_seq++;
@@ -528,4 +600,15 @@ extern "C" ps_status ps_server_stop(ps_server* s) {
   const ps_status st = s->fatal;
   delete s;
   return st;
+}
+
+extern "C" ps_status ps_server_get_stats(ps_server* s, ps_server_stats* out) {
+  if (!s || !out) return PS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->stats;
+  if (s->stats.update_batches) {
+    out->update_latency_ms_mean = s->upd_lat_sum / (double)s->stats.update_batches;
+    out->update_apply_ms_mean = s->upd_apply_sum / (double)s->stats.update_batches;
+  }
+  return PS_OK;
 }

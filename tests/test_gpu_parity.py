@@ -59,6 +59,19 @@ def _parity64(gpu, ref, stats, what, gpu_flip):
     assert err.max() <= tol, what
 
 
+def _parity64_of(gpu, res64, what, gpu_flip, st32):
+    """The same result against the oracle's plain FP64 evaluation.  A hybrid
+    query whose FP64 run switches other tree nodes than the FP32 model (a
+    switch test near its limit) draws other random probes: then only the
+    switch counts are reported."""
+    ref, st = res64
+    if "switched" in st and st["switched"] != st32.get("switched", st["switched"]):
+        print(f"{what}: FP64 switches {st['switched']} tree nodes, the FP32 model {st32['switched']}: "
+              f"not compared", flush=True)
+        return
+    _parity64(gpu, ref, st, f"{what} vs FP64", gpu_flip)
+
+
 def _alone(ps, G, q):
     """The query run alone, and its Rule-2 near-threshold allowance."""
     kw = {k: q[k] for k in ("probe_mode", "hybrid_c0") if k in q}
@@ -119,6 +132,7 @@ def test_single_source_er_workload(ps, er, orc):
     gpu = ps.ps_single_source(G, 0, 0.6, 0.1, 0.01, 1)
     ref, st = orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1, precision="f32")
     _parity(gpu, ref, st, "er u=0")
+    _parity64_of(gpu, orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1, precision="f64"), "er u=0", G.ctx.stats()["flip_allowance"], st)
     assert gpu[0] == 1.0
 
 
@@ -129,6 +143,7 @@ def test_single_source_power_law(ps, cl20k, orc, eps):
         gpu = ps.ps_single_source(G, int(u), 0.6, eps, 0.01, 3 + i)
         ref, st = orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i, precision="f32")
         _parity(gpu, ref, st, f"cl20k u={u} eps={eps}")
+        _parity64_of(gpu, orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i, precision="f64"), f"cl20k u={u} eps={eps}", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_single_source_small_slot_count(ps, cl20k, orc):
@@ -138,6 +153,7 @@ def test_single_source_small_slot_count(ps, cl20k, orc):
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 8, slots=3)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8, precision="f32")
     _parity(gpu, ref, st, "cl20k slots=3")
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8, precision="f64"), "cl20k slots=3", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_no_pruning_and_walk_cap(ps, cl20k, orc):
@@ -146,6 +162,7 @@ def test_no_pruning_and_walk_cap(ps, cl20k, orc):
     gpu = ps.ps_single_source(G, u, 0.6, 0.2, 0.01, 4, eps_p=0.0, max_len=6)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4, precision="f32")
     _parity(gpu, ref, st, "no pruning L=6")
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4, precision="f64"), "no pruning L=6", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_walk_range_shards_add_up(ps, cl20k, orc):
@@ -163,6 +180,7 @@ def test_walk_range_shards_add_up(ps, cl20k, orc):
     _same_query(tot, sum(flips), full, ff, "walk shards vs whole")
     ref, st = orc.batch(O, u, p, 5, 1000, 1001, precision="f32")
     _parity(parts[1], ref, st, "single-walk shard")
+    _parity64_of(parts[1], orc.batch(O, u, p, 5, 1000, 1001, precision="f64"), "single-walk shard", flips[1], st)
 
 
 def test_bias_shift(ps, er, orc):
@@ -170,6 +188,7 @@ def test_bias_shift(ps, er, orc):
     gpu = ps.ps_single_source(G, 3, 0.6, 0.1, 0.01, 2, bias_shift=1)
     ref, st = orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True, precision="f32")
     _parity(gpu, ref, st, "bias shift")
+    _parity64_of(gpu, orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True, precision="f64"), "bias shift", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_degenerate_queries(ps, ctx):
@@ -292,6 +311,7 @@ def test_hybrid_probe_matches_oracle(ps, ctx, cl20k, er, orc, pull):
                 if pull == 1 and n == 20_000:
                     assert st["pull_levels"] > 0
                 _parity(gpu, ref, ost, what)
+                _parity64_of(gpu, orc.batch(O, int(u), p, 5 + i, precision="f64", probe="hybrid", c0=c0), what, G.ctx.stats()["flip_allowance"], ost)
 
 
 def test_hybrid_limits_equal_the_two_probes(ps, ctx, cl20k):
@@ -313,7 +333,7 @@ def test_hybrid_limits_equal_the_two_probes(ps, ctx, cl20k):
         with pytest.raises(ps.ProbeSimError):
             ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=2, hybrid_c0=bad)
     with pytest.raises(ps.ProbeSimError):
-        ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=3)
+        ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 3, probe_mode=4)
 
 
 def test_hybrid_in_batch_shards_and_server(ps, ctx, cl20k, orc):
@@ -345,6 +365,7 @@ def test_hybrid_in_batch_shards_and_server(ps, ctx, cl20k, orc):
         ref, ost = orc.batch(O, q["u"], p, q["seed"], a, b, precision="f32", probe="hybrid", c0=q["hybrid_c0"])
         assert sw == ost["switched"]
         _parity(part, ref, ost, f"hybrid shard [{a}, {b})")
+        _parity64_of(part, orc.batch(O, q["u"], p, q["seed"], a, b, precision="f64", probe="hybrid", c0=q["hybrid_c0"]), f"hybrid shard [{a}, {b})", G.ctx.stats()["flip_allowance"], ost)
     srv = ps.Server(G, max_inflight=3)
     try:
         tickets = [srv.submit(q["u"], q["c"], q["eps"], q["delta"], q["seed"], k=q["k"],
@@ -466,6 +487,7 @@ def test_device_output_tensor(ps, er, orc):
     torch.cuda.synchronize()
     ref, st = orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3, precision="f32")
     _parity(out.cpu().numpy(), ref, st, "device output")
+    _parity64_of(out.cpu().numpy(), orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3, precision="f64"), "device output", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_dynamic_graph_equals_rebuilt(ps, ctx, orc):
@@ -489,6 +511,7 @@ def test_dynamic_graph_equals_rebuilt(ps, ctx, orc):
     O = orc.Graph(n, es, ed)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5, precision="f32")
     _parity(a, ref, st, "updated graph vs oracle")
+    _parity64_of(a, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5, precision="f64"), "updated graph vs oracle", fa, st)
     _same_query(a, fa, b, fb, "updated vs rebuilt graph")
     # invalid updates are reported per edge and skipped
     pe, _ = G.update([es[0], 1, 2], [ed[0], 1, (ed[0] + 1) % n], [0, 0, 1])
@@ -514,6 +537,18 @@ def test_full_size_power_law_walk_shards(ps, ctx, orc):
         gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3 + i, walk_begin=0, walk_end=120)
         ref, st = orc.single_source(O, u, p, 3 + i, 0, 120, precision="f32")
         _parity(gpu, ref, st, f"cl1m u={u} walks [0,120)")
+        _parity64_of(gpu, orc.single_source(O, u, p, 3 + i, 0, 120, precision="f64"), f"cl1m u={u} walks [0,120)", G.ctx.stats()["flip_allowance"], st)
+    # A shard whose probes outnumber the 1,024 slots (the pending ring wraps)
+    # and whose deepest levels are pulled, against the oracle.
+    u = int(q[0])
+    gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3, walk_begin=0, walk_end=2000)
+    st = G.ctx.stats()
+    fg = st["flip_allowance"]
+    print(f"cl1m u={u} walks [0,2000): tree nodes {st['tree_nodes']}, pulled levels {st['pull_levels']}", flush=True)
+    assert st["tree_nodes"] > 1024 and st["pull_levels"] > 0
+    ref, ost = orc.batch(O, u, p, 3, 0, 2000, precision="f32")
+    _parity(gpu, ref, ost, f"cl1m u={u} walks [0,2000)")
+    _parity64_of(gpu, orc.batch(O, u, p, 3, 0, 2000, precision="f64"), f"cl1m u={u} walks [0,2000)", fg, ost)
     full = ps.ps_single_source(G, int(q[0]), 0.6, 0.05, 0.01, 3)
     assert full[int(q[0])] == 1.0 and full.min() >= 0.0
     off = np.delete(full, int(q[0]))
@@ -541,6 +576,7 @@ def test_full_size_hybrid_walk_shards(ps, ctx, orc):
                   flush=True)
             assert sw == st["switched"]
             _parity(gpu, ref, st, f"cl1m hybrid u={u} walks [{a},{b})")
+            _parity64_of(gpu, orc.batch(O, u, p, 3 + i, a, b, precision="f64", probe="hybrid", c0=c0), f"cl1m hybrid u={u} walks [{a},{b})", G.ctx.stats()["flip_allowance"], st)
     full = ps.ps_single_source(G, int(q[0]), 0.6, 0.05, 0.01, 3, probe_mode=2)
     assert full[int(q[0])] == 1.0 and full.min() >= 0.0
     assert np.delete(full, int(q[0])).max() <= 1.0
@@ -600,6 +636,7 @@ def test_server_interleaves_updates(ps, ctx, orc, mode):
         ref, st = orc.batch(O2, u, orc.params(n, 0.6, 0.1, 0.01), 9, precision="f32", probe="hybrid", c0=0.05)
         assert 0 < st["switched"] < st["tree_nodes"]
         _parity(r2, ref, st, "served hybrid after the update")
+        _parity64_of(r2, orc.batch(O2, u, orc.params(n, 0.6, 0.1, 0.01), 9, precision="f64", probe="hybrid", c0=0.05), "served hybrid after the update", f2, st)
 
 
 def test_server_defaults_apply_to_every_query(ps, ctx, cl20k):
@@ -681,6 +718,7 @@ def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
         assert st["pushed_edges"] == st["edges_scanned"] and st["pushed_final_adds"] == st["final_adds"]
     ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f32")
     _parity(gpu, ref, ost, f"pull_edges={pull}")
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f64"), f"pull_edges={pull}", G.ctx.stats()["flip_allowance"], ost)
 
 
 @pytest.mark.parametrize("mode", [0, 2])
@@ -707,6 +745,7 @@ def test_tune_split_meets_theorem2_and_matches_oracle(ps, ctx, cl20k, orc, mode)
     probe = "hybrid" if mode == 2 else "deterministic"
     ref, st = orc.batch(O, u, p, 17, precision="f32", probe=probe, c0=ps.options().hybrid_c0 if mode == 2 else None)
     _parity(gpu, ref, st, f"tuned split mode {mode}")
+    _parity64_of(gpu, orc.batch(O, u, p, 17, precision="f64", probe=probe, c0=ps.options().hybrid_c0 if mode == 2 else None), f"tuned split mode {mode}", G.ctx.stats()["flip_allowance"], st)
     with pytest.raises(ps.ProbeSimError):
         ps.ps_tune_split(G, sample, c, eps, delta, eps_s=0.02)
 
@@ -724,6 +763,7 @@ def test_autotune_keeps_results(ps, ctx, cl20k, orc, tmp_path):
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 19)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19, precision="f32")
     _parity(gpu, ref, st, f"autotuned {t}")
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19, precision="f64"), f"autotuned {t}", G.ctx.stats()["flip_allowance"], st)
 
 
 _T0 = time.perf_counter()
@@ -771,10 +811,11 @@ def test_full_size_batched_mixed_eps(ps, ctx, orc):
         fg = G.ctx.stats()["flip_allowance"]
         ref, st = orc.single_source(O, q["u"], p, q["seed"], 0, 40, precision="f32")
         _parity(gpu, ref, st, f"cl5m u={q['u']} eps={q['eps']} walks [0,40)")
+        _parity64_of(gpu, orc.single_source(O, q["u"], p, q["seed"], 0, 40, precision="f64"), f"cl5m u={q['u']} eps={q['eps']} walks [0,40)", fg, st)
 
 
 @pytest.mark.skipif(os.environ.get("PS_SKIP_FULL") == "1", reason="full-size case skipped")
-def test_full_size_served_dynamic_graph(ps, ctx):
+def test_full_size_served_dynamic_graph(ps, ctx, orc):
     # 10M nodes / 200M edges served with edge updates interleaved between
     # queries (half inserts, half deletes); single-source and top-k (k = 50)
     # queries.  Each served result equals the query run alone on a second
@@ -822,6 +863,18 @@ def test_full_size_served_dynamic_graph(ps, ctx):
         r, fr = served[i]
         a, fa = _alone(ps, R, x)
         _same_query(r, fr, a, fa, f"cl10m served vs alone {i} u={x['u']} eps={x['eps']} k={x['k']}")
+        # the oracle on the edge set this query read: a walk-range shard
+        es_v, ed_v = R.edges()
+        O = orc.Graph(n, es_v, ed_v)
+        del es_v, ed_v
+        p = orc.params(n, 0.6, x["eps"], 0.01)
+        part = ps.ps_single_source(R, x["u"], 0.6, x["eps"], 0.01, x["seed"], walk_begin=0, walk_end=40)
+        fg = R.ctx.stats()["flip_allowance"]
+        ref, st = orc.single_source(O, x["u"], p, x["seed"], 0, 40, precision="f32")
+        what = f"cl10m query {i} on the replayed edge set, walks [0,40)"
+        _parity(part, ref, st, what)
+        _parity64_of(part, orc.single_source(O, x["u"], p, x["seed"], 0, 40, precision="f64"), what, fg, st)
+        del O
         _say(f"query {i} checked (allowances {fr:.2e}, {fa:.2e})")
         i += 1
     es, ed = G.edges()
@@ -829,7 +882,7 @@ def test_full_size_served_dynamic_graph(ps, ctx):
     assert es.size == fs.size and (es == fs).all() and (ed == fd).all()
 
 
-@pytest.mark.skipif(os.environ.get("PS_FULL_BILLION") != "1", reason="billion-edge case runs with PS_FULL_BILLION=1")
+@pytest.mark.skipif(os.environ.get("PS_SKIP_BILLION") == "1", reason="billion-edge case skipped")
 def test_full_size_billion_edge_topk(ps, ctx, orc):
     # 40M nodes / 1.4B edges, exponent 2.0, top-50 at eps = 0.025 (n_r =
     # 254,703 walks).  A whole query scans far more edges than a test can
@@ -852,6 +905,7 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
     gpu = ps.ps_single_source(G, u, 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=20)
     ref, st = orc.single_source(O, u, p, seed, 0, 20, precision="f32")
     _parity(gpu, ref, st, f"cl40m u={u} walks [0,20)")
+    _parity64_of(gpu, orc.single_source(O, u, p, seed, 0, 20, precision="f64"), f"cl40m u={u} walks [0,20)", G.ctx.stats()["flip_allowance"], st)
     for q in qn[:2]:
         t0 = time.perf_counter()
         whole = ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000)
@@ -882,6 +936,7 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
     ref, st = orc.batch(O, u, p, seed, 0, 20, precision="f32", probe="hybrid", c0=c0)
     assert sw == st["switched"]
     _parity(gpu, ref, st, f"cl40m hybrid u={u} walks [0,20), switched {sw} of {st['tree_nodes']}")
+    _parity64_of(gpu, orc.batch(O, u, p, seed, 0, 20, precision="f64", probe="hybrid", c0=c0), f"cl40m hybrid u={u} walks [0,20), switched {sw} of {st['tree_nodes']}", G.ctx.stats()["flip_allowance"], st)
     for q in qn[:2]:
         t0 = time.perf_counter()
         ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000, probe_mode=2)
@@ -928,6 +983,7 @@ def test_hub_rows_compaction_and_long_rows(ps, ctx, orc):
             _same_query(a, 0.0, b, 0.0, f"hub graph updated vs rebuilt u={u} pull={pull}")
         ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 13, precision="f32")
         _parity(a, ref, st, f"hub graph u={u}")
+        _parity64_of(a, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 13, precision="f64"), f"hub graph u={u}", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_parameter_extremes(ps, ctx, er, orc):
@@ -939,6 +995,7 @@ def test_parameter_extremes(ps, ctx, er, orc):
     gpu = ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=64, eps_t=1e-30)
     ref, st = orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f32")
     _parity(gpu, ref, st, "walk cap 64")
+    _parity64_of(gpu, orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f64"), "walk cap 64", G.ctx.stats()["flip_allowance"], st)
     with pytest.raises(ps.ProbeSimError):
         ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=65)
     # eps close to 1 (few walks), c close to 0 and 1
@@ -946,6 +1003,7 @@ def test_parameter_extremes(ps, ctx, er, orc):
         gpu = ps.ps_single_source(G, 9, c, eps, 0.01, 4)
         ref, st = orc.batch(O, 9, orc.params(n, c, eps, 0.01), 4, precision="f32")
         _parity(gpu, ref, st, f"c={c} eps={eps}")
+        _parity64_of(gpu, orc.batch(O, 9, orc.params(n, c, eps, 0.01), 4, precision="f64"), f"c={c} eps={eps}", G.ctx.stats()["flip_allowance"], st)
     # top-k with k = n - 1 (every other node) and beyond
     nodes, vals = ps.ps_topk(G, 9, n - 1, 0.6, 0.2, 0.01, 4)
     assert sorted(nodes.tolist()) == [v for v in range(n) if v != 9]
@@ -963,5 +1021,75 @@ def test_parameter_extremes(ps, ctx, er, orc):
     assert ctx.stats()["switched_probes"] == st["switched"] > 0
     _parity(gpu, ref, st, "hybrid, walk cap 64")
     assert ps.ps_single_source(G1, 0, 0.6, 0.1, 0.01, 1, probe_mode=2).tolist() == [1.0]
+    # merged probing (Rule 2 off) with the walk cap and a tiny graph
+    gpu = ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=64, eps_t=1e-30, probe_mode=3)
+    ref, st = orc.merged(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64, eps_p=0.0), 2)
+    assert np.abs(gpu - ref).max() <= TOL_MODEL
+    assert ps.ps_single_source(G1, 0, 0.6, 0.1, 0.01, 1, probe_mode=3).tolist() == [1.0]
     with pytest.raises(ps.ProbeSimError):
-        ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, probe_mode=3)
+        ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, probe_mode=4)
+
+
+def test_merged_probing_matches_oracle(ps, ctx, cl20k, er, orc):
+    # Merged probing (Rule 2 off, every probe of a subtree summed at its root,
+    # FP64) against the oracle's merged form and against Alg. 3 with one probe
+    # per tree node at eps_p = 0: the same numbers up to FP64 summation order.
+    # The work is deterministic: tree nodes, entries and edges equal the
+    # oracle's counts exactly.
+    for n, s, d, G, O in (er, cl20k):
+        for i, u in enumerate(graphs.query_nodes(n, d, 2, seed=71)):
+            u = int(u)
+            p = orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0)
+            for a, b in ((0, p.n_r), (100, 700)):
+                gpu = ps.ps_single_source(G, u, 0.6, 0.2, 0.01, 80 + i, probe_mode=ps.PROBE_MERGED, walk_begin=a,
+                                          walk_end=b)
+                st = ctx.stats()
+                ref, ost = orc.merged(O, u, p, 80 + i, a, b)
+                err = float(np.abs(gpu - ref).max())
+                what = f"merged n={n} u={u} walks [{a},{b})"
+                print(f"{what}: max|gpu-oracle| = {err:.3e}, tree nodes {st['tree_nodes']}, edges {st['edges_scanned']}"
+                      f" (oracle {ost['edges_scanned']})", flush=True)
+                assert err <= TOL_MODEL, what
+                assert st["tree_nodes"] == ost["tree_nodes"] and st["edges_scanned"] == ost["edges_scanned"], what
+                assert st["entries_expanded"] == ost["entries_expanded"], what
+                ref_b, _ = orc.batch(O, u, p, 80 + i, a, b)
+                assert np.abs(gpu - ref_b).max() <= TOL_MODEL, what
+    # top-k and the bias shift through the merged path
+    n, s, d, G, O = cl20k
+    u = int(graphs.query_nodes(n, d, 1, seed=72)[0])
+    p = orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0)
+    ref, _ = orc.merged(O, u, p, 5, bias_shift=True)
+    gpu = ps.ps_single_source(G, u, 0.6, 0.2, 0.01, 5, probe_mode=ps.PROBE_MERGED, bias_shift=1)
+    assert np.abs(gpu - ref).max() <= TOL_MODEL
+    nodes, vals = ps.ps_topk(G, u, 40, 0.6, 0.2, 0.01, 5, probe_mode=ps.PROBE_MERGED, bias_shift=1)
+    assert np.abs(vals - np.sort(np.delete(ref, u))[::-1][:40]).max() <= TOL_MODEL
+
+
+def test_merged_probing_full_size_shard(ps, ctx, orc):
+    # The 1M-node / 10M-edge workload: a 30-walk shard by merged probing
+    # against the oracle, and the work against per-probe Alg. 3 with Rule 2
+    # off on the same shard (without pruning a shard's frontiers reach much
+    # of the graph, so the shard is small).
+    n, s, d = graphs.make_workload("cl_1m_10m")
+    G = ps.Graph(ctx, n, s, d)
+    O = orc.Graph(n, s, d)
+    u = int(graphs.query_nodes(n, d, 32)[0])
+    p = orc.params(n, 0.6, 0.05, 0.01, eps_p=0.0)
+    gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3, probe_mode=ps.PROBE_MERGED, walk_begin=0, walk_end=30)
+    st = ctx.stats()
+    ref, ost = orc.merged(O, u, p, 3, 0, 30)
+    err = float(np.abs(gpu - ref).max())
+    print(f"cl1m merged u={u} walks [0,30): max|gpu-oracle| = {err:.3e}; edges {st['edges_scanned']}", flush=True)
+    assert err <= TOL_MODEL
+    assert st["edges_scanned"] == ost["edges_scanned"]
+    # per-probe Alg. 3 with Rule 2 off: in FP64 (the oracle) it expands every
+    # entry, however small; the kernels' FP32 score model drops contributions
+    # below its 2^-62 grid, which prunes most of the far frontier
+    _, sb = orc.batch(O, u, p, 3, 0, 30)
+    gpu2 = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3, eps_p=0.0, walk_begin=0, walk_end=30)
+    st2 = ctx.stats()
+    print(f"edges: merged {st['edges_scanned']}, per-probe FP64 {sb['edges_scanned']} "
+          f"({sb['edges_scanned'] / max(st['edges_scanned'], 1):.1f}x), per-probe FP32 model {st2['edges_scanned']}",
+          flush=True)
+    assert np.abs(gpu2 - gpu).max() <= 1e-6
+    assert st["edges_scanned"] <= sb["edges_scanned"]
