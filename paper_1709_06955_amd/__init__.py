@@ -10,6 +10,7 @@ from __future__ import annotations
 import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -116,17 +117,25 @@ class ServerCfg(C.Structure):
 
 
 _lib = None
-_exiting = False
+_live = []  # weak references to open servers, graphs and contexts, in creation order
 
 
-def _at_exit():
-    # Interpreter shutdown: leave device memory to process exit instead of
-    # freeing it from finalizers that may run after the HIP runtime is gone.
-    global _exiting
-    _exiting = True
+def _track(obj):
+    _live.append(weakref.ref(obj))
 
 
-atexit.register(_at_exit)
+def _teardown():
+    """Closes what is still open at interpreter exit, newest first (servers,
+    then their graphs, then contexts).  Registered right after torch is
+    imported, so it runs before torch's own exit handlers, while the HIP
+    runtime is still up."""
+    while _live:
+        obj = _live.pop()()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 def load_library(path: str = LIB_PATH):
@@ -143,6 +152,7 @@ def load_library(path: str = LIB_PATH):
         import torch  # noqa: F401
     except ImportError:
         pass
+    atexit.register(_teardown)  # after torch's handlers, so it runs before them
     L = C.CDLL(path)
     P, vp = C.POINTER, C.c_void_p
     sig = {
@@ -225,6 +235,7 @@ class Context:
         _check(L.ps_ctx_create(int(device), s, C.byref(h)), "ps_ctx_create")
         self._h = h
         self.device = device
+        _track(self)
 
     def set_timing(self, on: bool):
         _check(load_library().ps_ctx_set_timing(self._h, int(on)), "ps_ctx_set_timing")
@@ -236,8 +247,7 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            if not _exiting:
-                load_library().ps_ctx_destroy(self._h)
+            load_library().ps_ctx_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -271,6 +281,7 @@ class Graph:
         _check(load_library().ps_graph_load(ctx._h, int(n), int(sm), sp, dp, int(flags), C.byref(h)),
                "ps_graph_load")
         self._h = h
+        _track(self)
         self.ctx = ctx
         self.n = int(n)
 
@@ -301,8 +312,7 @@ class Graph:
 
     def close(self):
         if getattr(self, "_h", None):
-            if not _exiting:
-                load_library().ps_graph_free(self._h)
+            load_library().ps_graph_free(self._h)
             self._h = None
 
     def __del__(self):
@@ -457,6 +467,7 @@ class Server:
         h = C.c_void_p()
         _check(load_library().ps_server_start(g._h, C.byref(cfg), C.byref(h)), "ps_server_start")
         self._h = h
+        _track(self)
         self.g = g
         self._pending = {}
 
@@ -500,9 +511,11 @@ class Server:
 
     def stop(self):
         if getattr(self, "_h", None):
-            if not _exiting:
-                _check(load_library().ps_server_stop(self._h), "ps_server_stop")
+            _check(load_library().ps_server_stop(self._h), "ps_server_stop")
             self._h = None
+
+    def close(self):
+        self.stop()
 
     def __del__(self):
         try:

@@ -133,3 +133,29 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_exit_teardown_closes_newest_first():
+    # At interpreter exit the binding closes whatever is still open, newest
+    # first (servers, their graphs, then contexts), before torch's handlers.
+    import paper_1709_06955_amd as ps
+
+    order = []
+
+    class Obj:
+        def __init__(self, name):
+            self.name = name
+
+        def close(self):
+            order.append(self.name)
+
+    objs = [Obj("ctx"), Obj("graph"), Obj("server")]
+    saved = list(ps._live)
+    ps._live.clear()
+    try:
+        for o in objs:
+            ps._track(o)
+        ps._teardown()
+        assert order == ["server", "graph", "ctx"] and not ps._live
+    finally:
+        ps._live[:] = saved

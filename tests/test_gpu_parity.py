@@ -1093,3 +1093,52 @@ def test_merged_probing_full_size_shard(ps, ctx, orc):
           flush=True)
     assert np.abs(gpu2 - gpu).max() <= 1e-6
     assert st["edges_scanned"] <= sb["edges_scanned"]
+
+
+def test_interpreter_exit_with_open_objects():
+    # A process that leaves a context, a graph and a server open exits
+    # cleanly: the binding's exit handler stops and frees them in order while
+    # the HIP runtime is still up.
+    import subprocess
+    import sys
+
+    code = (
+        "import numpy as np, paper_1709_06955_amd as ps\n"
+        "from synth import graphs\n"
+        "n, s, d = graphs.make_workload('er_1k_10k')\n"
+        "ctx = ps.Context(0)\n"
+        "G = ps.Graph(ctx, n, s, d)\n"
+        "srv = ps.Server(G, max_inflight=2)\n"
+        "t = srv.submit(0, 0.6, 0.1, 0.01, 1)\n"
+        "r = srv.wait(t)\n"
+        "assert r[0] == 1.0\n"
+        "print('exiting with open objects', flush=True)\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    print(r.stdout[-500:], r.stderr[-500:], flush=True)
+    assert r.returncode == 0 and "exiting with open objects" in r.stdout
+
+
+def test_abs_error_over_many_queries_and_runs(ps, ctx, er):
+    # Section 6.1's AbsError: max_v |s^(u, v) - s(u, v)| against the Power
+    # Method, averaged over 100 query nodes and 10 runs (seeds) each, at
+    # eps = 0.1 on the 1,000-node graph, for deterministic PROBE and the
+    # merged form; every single query within eps (delta = 1e-4 per query),
+    # and the mean printed.  Runs go through ps_batch, 100 queries a batch.
+    from oracle import refs
+
+    n, s, d, G = er[:4]
+    S = refs.power_method(n, s, d, 0.6, iters=55)
+    qn = [int(u) for u in graphs.query_nodes(n, d, 100, seed=113)]
+    for mode in (ps.PROBE_DETERMINISTIC, ps.PROBE_MERGED):
+        errs = []
+        for run in range(10):
+            qs = [dict(u=u, k=0, c=0.6, eps=0.1, delta=1e-4, seed=1000 * run + i, probe_mode=mode)
+                  for i, u in enumerate(qn)]
+            for q, est in zip(qs, ps.ps_batch(G, qs)):
+                errs.append(float(np.abs(est - S[q["u"]]).max()))
+        errs = np.array(errs)
+        print(f"er1k mode={mode}: AbsError mean {errs.mean():.5f}, max {errs.max():.5f} over {errs.size} queries",
+              flush=True)
+        assert errs.max() <= 0.1
