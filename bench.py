@@ -357,6 +357,7 @@ def main():
     ap.add_argument("--pull", type=int, default=0, help="pull threshold in out-edges (0 automatic, -1 never)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-topk", action="store_true", help="skip the top-k selection and top-50 query timing")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched pass over the same queries")
     ap.add_argument("--batched-queries", type=int, default=9,
                     help="queries of the 5M-node batched leg (0 skips it; the full workload is 256)")
     ap.add_argument("--served-seconds", type=float, default=20.0,
@@ -433,13 +434,15 @@ def main():
     # Batched: the same 32 queries in one launch.
     outs = [(torch.empty(n, dtype=torch.float64, device="cuda:0"), None) for _ in range(len(q))]
     qlist = [dict(u=int(u), k=0, c=C, eps=EPS, delta=DELTA, seed=3 + i, **mode_kw) for i, u in enumerate(q)]
-    ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
-    torch.cuda.synchronize()
-    tb = time.perf_counter()
-    ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
-    torch.cuda.synchronize()
-    batched_qps = len(q) / (time.perf_counter() - tb)
-    print(f"batched: {batched_qps:.2f} queries/s", file=sys.stderr, flush=True)
+    batched_qps = None
+    if not args.no_batched:
+        ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ps.ps_batch(G, qlist, outs=outs, slots=args.slots, pull_edges=args.pull)
+        torch.cuda.synchronize()
+        batched_qps = len(q) / (time.perf_counter() - tb)
+        print(f"batched: {batched_qps:.2f} queries/s", file=sys.stderr, flush=True)
 
     # Smaller queries (eps = 0.1, about a quarter of the walks): one query no
     # longer keeps every probe slot busy to its end, which batching recovers.
@@ -558,7 +561,7 @@ def main():
                                "delta=0.01", "queries_per_step": len(q)},
         "autotune": tune,
         "batched_qps": batched_qps,
-        "batched_speedup": batched_qps / qps,
+        "batched_speedup": batched_qps / qps if batched_qps else None,
         "small_queries": small,
         "probe_variants": variants,
         "tuned_split": split,

@@ -1140,7 +1140,6 @@ __global__ void __launch_bounds__(kThreads) k_expand(ExpandArgs a) {
   __shared__ uint32_t s_pref[kTile + 1];
   __shared__ int32_t s_slot[kTile];  // slot, with kBigFlag set for a randomized probe
   __shared__ const int32_t* s_col[kTile];  // the entry's out-row
-  __shared__ const float* s_inv[kTile];    // 1/|I(.)| of its graph version
   __shared__ int32_t s_excl[kTile];
   __shared__ float s_sv[kTile];
   __shared__ int32_t s_x[kTile];
@@ -1339,7 +1338,6 @@ __global__ void __launch_bounds__(kThreads) k_expand(ExpandArgs a) {
           deg = row.y;
           s_slot[tid] = sl.mode ? (int32_t)((uint32_t)it.x | kBigFlag) : it.x;
           s_col[tid] = sl.out_col + row.x;
-          s_inv[tid] = sl.inv_indeg;
           s_excl[tid] = sl.excl;
           s_x[tid] = it.y;
           s_sv[tid] = a.cur.val[i] * sl.sc;  // fl32(Score(x) * sqrt c)
@@ -1359,7 +1357,6 @@ __global__ void __launch_bounds__(kThreads) k_expand(ExpandArgs a) {
     __syncthreads();
     for (uint32_t e0 = 0; e0 < total; e0 += kThreads * kEdgeBatch) {
       int32_t v[kEdgeBatch], lo[kEdgeBatch];
-      float inv[kEdgeBatch];
 #pragma unroll
       for (int k = 0; k < kEdgeBatch; ++k) {
         const uint32_t e = e0 + (uint32_t)(k * kThreads + tid);
@@ -1371,17 +1368,11 @@ __global__ void __launch_bounds__(kThreads) k_expand(ExpandArgs a) {
         }
       }
 #pragma unroll
-      for (int k = 0; k < kEdgeBatch; ++k) {  // Alg. 2: contributions of the deterministic entries
-        inv[k] = 0.0f;
-        if (v[k] >= 0 && s_slot[lo[k]] >= 0 && v[k] != s_excl[lo[k]]) inv[k] = s_inv[lo[k]][v[k]];
-      }
-#pragma unroll
-      for (int k = 0; k < kEdgeBatch; ++k) {
+      for (int k = 0; k < kEdgeBatch; ++k) {  // Alg. 2: the deterministic entries' records
         const int32_t s = s_slot[lo[k]];
         if (v[k] >= 0 && s >= 0 && v[k] != s_excl[lo[k]] && !skip) {
-          const float c = s_sv[lo[k]] * inv[k];
           const uint32_t pos = atomicAdd(&s_hist[(uint32_t)v[k] >> sh], 1u);
-          a.rec[pos] = make_uint2(((uint32_t)s << sh) | ((uint32_t)v[k] & vmask), __float_as_uint(c));
+          a.rec[pos] = make_uint2(((uint32_t)s << sh) | ((uint32_t)v[k] & vmask), __float_as_uint(s_sv[lo[k]]));
         }
       }
 #pragma unroll
@@ -1428,20 +1419,16 @@ __global__ void __launch_bounds__(kThreads) k_expand(ExpandArgs a) {
     if (!sl.mode) {  // Alg. 2
       for (uint32_t t0 = b; t0 < e; t0 += 64 * kEdgeBatch) {
         int32_t v[kEdgeBatch];
-        float inv[kEdgeBatch];
 #pragma unroll
         for (int k = 0; k < kEdgeBatch; ++k) {
           const uint32_t t = t0 + (uint32_t)(k * 64 + lane);
           v[k] = t < e ? col[t] : -1;
         }
 #pragma unroll
-        for (int k = 0; k < kEdgeBatch; ++k) inv[k] = v[k] >= 0 && v[k] != sl.excl ? sl.inv_indeg[v[k]] : 0.0f;
-#pragma unroll
         for (int k = 0; k < kEdgeBatch; ++k) {
           if (v[k] >= 0 && v[k] != sl.excl && !skip) {
-            const float c = sv * inv[k];
             const uint32_t pos = atomicAdd(&s_hist[(uint32_t)v[k] >> sh], 1u);
-            a.rec[pos] = make_uint2(((uint32_t)s << sh) | ((uint32_t)v[k] & vmask), __float_as_uint(c));
+            a.rec[pos] = make_uint2(((uint32_t)s << sh) | ((uint32_t)v[k] & vmask), __float_as_uint(sv));
           }
         }
       }
@@ -1505,6 +1492,7 @@ struct ReduceArgs {
 };
 
 constexpr int kRecBatch = 4;  // records a thread loads before it inserts them
+constexpr int kEmit = 3;      // table places a thread emits at a time
 
 // Sums the records of each bin per (slot, node) exactly: 64-bit integer
 // adds on the grid 2^-62 in an LDS hash table (linear probing) of at least
@@ -1598,12 +1586,24 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
             rc[k] = a.rec[s_st[lo] + (i - s_pre[lo])];
           }
         }
+        // the contribution fl32(Score(x) sqrt(c)) * fl32(1/|I(v)|): the record
+        // carries the first factor, the target's 1/|I(v)| (its slot's graph
+        // version) is read here, where a bin's targets are a narrow node range
+        float inv[kRecBatch];
+#pragma unroll
+        for (int k = 0; k < kRecBatch; ++k) {
+          inv[k] = 0.0f;
+          if (rc[k].x != kNoKey && (fmix32(rc[k].x) & (M - 1u)) == r) {
+            const Slot& S = a.slots[rc[k].x >> sh];
+            inv[k] = S.inv_indeg[(b << sh) | (rc[k].x & vmask)];
+          }
+        }
 #pragma unroll
         for (int k = 0; k < kRecBatch; ++k) {
           if (rc[k].x == kNoKey) continue;
           const uint32_t h = fmix32(rc[k].x);
           if ((h & (M - 1u)) != r) continue;
-          const long long q = to_grid(__uint_as_float(rc[k].y));
+          const long long q = to_grid(__uint_as_float(rc[k].y) * inv[k]);
           if (q == 0) continue;  // below the grid
           uint32_t p = h >> (32 - tb);
           for (int probe = 0;; ++probe) {
@@ -1639,48 +1639,83 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
         M *= 2u;
         continue;
       }
-      for (uint32_t t0 = 0; t0 < T; t0 += kThreads) {
-        const uint32_t t = t0 + tid;
-        const uint32_t key = t < T ? s_key[t] : kNoKey;
-        bool want = false;
-        int32_t s = 0, v = 0;
-        float h = 0.0f;
-        uint2 row = make_uint2(0u, 0u);
-        if (key != kNoKey) {
-          const long long q = (long long)s_val[t];
-          s_key[t] = kNoKey;
-          s_val[t] = 0ull;
-          s = (int32_t)(key >> sh);
-          v = (int32_t)((b << sh) | (key & vmask));
-          const Slot& S = a.slots[s];
-          if (S.last) {  // the returned level: weight * exact sum into the estimate
-            unsafeAtomicAdd(&S.acc[v], grid_f64(q) * S.w);
-            ++nfin;
-          } else {
-            ++nnext;
-            h = grid_f32(q);
+      // Emit the sums, kEmit table places per thread at a time: the table
+      // reads, then the slot fields, then the out-rows of kept nodes, each a
+      // round of independent loads.
+      for (uint32_t t0 = 0; t0 < T; t0 += kThreads * kEmit) {
+        uint32_t key[kEmit];
+        long long q[kEmit];
+        int32_t s[kEmit], v[kEmit], last[kEmit];
+        float thr[kEmit], h[kEmit];
+        const uint2* orow[kEmit];
+        uint2 row[kEmit];
+        bool want[kEmit];
+#pragma unroll
+        for (int j = 0; j < kEmit; ++j) {
+          const uint32_t t = t0 + (uint32_t)j * kThreads + tid;
+          key[j] = t < T ? s_key[t] : kNoKey;
+          q[j] = 0;
+          s[j] = 0;
+          v[j] = 0;
+          if (key[j] != kNoKey) {
+            q[j] = (long long)s_val[t];
+            s_key[t] = kNoKey;
+            s_val[t] = 0ull;
+            s[j] = (int32_t)(key[j] >> sh);
+            v[j] = (int32_t)((b << sh) | (key[j] & vmask));
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kEmit; ++j) {
+          last[j] = 0;
+          thr[j] = 0.0f;
+          orow[j] = nullptr;
+          if (key[j] != kNoKey) {
+            const Slot& S = a.slots[s[j]];
+            last[j] = S.last;
+            thr[j] = S.thr_next;
+            orow[j] = S.out_rows;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kEmit; ++j) {
+          want[j] = false;
+          h[j] = 0.0f;
+          row[j] = make_uint2(0u, 0u);
+          if (key[j] != kNoKey && !last[j]) {
+            h[j] = grid_f32(q[j]);
             // Rule 2 on the next level: keep v when Score(v) > eps_p / sqrt(c)^(i-j-2)
-            const float thr = S.thr_next;
-            if (fabsf(h - thr) <= 1e-5f * thr) {  // FP32 rounding may decide this test
-              ++near;
-              unsafeAtomicAdd(S.flip, S.flip_unit);
-            }
-            if (h > thr) {
-              ++kept;
-              row = S.out_rows[v];
-              want = row.y > 0;
-            } else {
-              ++pruned;
+            if (h[j] > thr[j]) {
+              row[j] = orow[j][v[j]];
+              want[j] = row[j].y > 0;
             }
           }
         }
-        if (want) {
-          a.has_next[s] = 1;
-          atomicAdd(&s_part[s], row.y);
-          atomicAdd(&s_part[a.P + s], 1u);
-          dirty = true;
+#pragma unroll
+        for (int j = 0; j < kEmit; ++j) {
+          if (key[j] != kNoKey) {
+            const Slot& S = a.slots[s[j]];
+            if (last[j]) {  // the returned level: weight * exact sum into the estimate
+              unsafeAtomicAdd(&S.acc[v[j]], grid_f64(q[j]) * S.w);
+              ++nfin;
+            } else {
+              ++nnext;
+              if (fabsf(h[j] - thr[j]) <= 1e-5f * thr[j]) {  // FP32 rounding may decide this test
+                ++near;
+                unsafeAtomicAdd(S.flip, S.flip_unit);
+              }
+              if (h[j] > thr[j]) ++kept;
+              else ++pruned;
+            }
+          }
+          if (want[j]) {
+            a.has_next[s[j]] = 1;
+            atomicAdd(&s_part[s[j]], row[j].y);
+            atomicAdd(&s_part[a.P + s[j]], 1u);
+            dirty = true;
+          }
+          stage_put(want[j], s[j], v[j], h[j], row[j], ws, a.nxt, ctr);
         }
-        stage_put(want, s, v, h, row, ws, a.nxt, ctr);
       }
       // next slice: the sibling of the nearest first-half ancestor
       while (M > 1u && r >= (M >> 1)) {
