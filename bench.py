@@ -415,13 +415,16 @@ def main():
             if acc is not None:
                 for k in acc:
                     acc[k] += st[k]
+                acc_max[0] = max(acc_max[0], st["reduce_max_records"])
 
     for _ in range(args.warmup):
         plain_step(None, "warmup")
     keys = ["expand_ms", "pull_ms", "pull_levels", "pull_edges", "expand_launches", "entries_expanded", "edges_scanned",
             "pushed_edges", "next_entries", "final_adds", "pushed_final_adds",
-            "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned", "walk_nodes", "total_ms"]
+            "tree_nodes", "probe_levels", "steps", "walks", "entries_pruned", "walk_nodes", "total_ms",
+            "reduce_bins", "reduce_slices"]
     acc = {k: 0 for k in keys}
+    acc_max = [0]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -567,6 +570,7 @@ def main():
         "tuned_split": split,
         "roofline": roofline,
         "work_per_query": {k: acc[k] / queries for k in keys},
+        "reduce_max_records_per_bin": acc_max[0],
     }
     # Top-k (Definition 2): the selection alone on resident vectors (the last
     # query's 1M estimates; a 40M vector with 1% nonzero entries, the shape

@@ -388,6 +388,10 @@ typedef struct ps_stats {
   int64_t pushed_edges;     /* edges_scanned less those of levels pulled or switched instead
                                of pushed: the out-edges the push kernel visits */
   int64_t pushed_final_adds; /* final_adds made by the push kernel (the rest by pulls) */
+  int64_t reduce_bins;      /* bins of pushed records summed (per level step: node ranges) */
+  int64_t reduce_slices;    /* passes over those bins (more than one when a bin's keys
+                               overflow the workgroup's table) */
+  int64_t reduce_max_records; /* most records in one bin */
 } ps_stats;
 
 ps_status ps_get_stats(ps_ctx* ctx, ps_stats* out);

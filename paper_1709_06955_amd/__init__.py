@@ -74,7 +74,8 @@ class Stats(C.Structure):
         "pull_edges", "near_threshold")] + [
         ("flip_allowance", C.c_double), ("expand_ms", C.c_double), ("pull_ms", C.c_double), ("total_ms", C.c_double),
         ("level_hist_count", C.c_int64 * 32), ("level_hist_edges", C.c_int64 * 32),
-        ("switched_probes", C.c_int64), ("pushed_edges", C.c_int64), ("pushed_final_adds", C.c_int64)]
+        ("switched_probes", C.c_int64), ("pushed_edges", C.c_int64), ("pushed_final_adds", C.c_int64),
+        ("reduce_bins", C.c_int64), ("reduce_slices", C.c_int64), ("reduce_max_records", C.c_int64)]
 
     def as_dict(self):
         d = {}

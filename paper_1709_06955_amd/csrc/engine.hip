@@ -1563,6 +1563,10 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
       b = bn;
       continue;
     }
+    if (tid == 0) {
+      atomicAdd(&ctr[C_RBINS], 1ull);
+      atomicMax(&ctr[C_RMAX], (unsigned long long)R);
+    }
     uint32_t tb = 9;  // table of 2^tb places, at least 2R
     while (tb < (uint32_t)kTblBits && (1u << tb) < 2u * R) ++tb;
     const uint32_t T = 1u << tb;
@@ -1628,6 +1632,7 @@ __global__ void __launch_bounds__(kThreads) k_reduce(ReduceArgs a) {
         }
       }
       __syncthreads();
+      if (tid == 0) atomicAdd(&ctr[C_RSLICES], 1ull);
       if (s_ovf) {  // split this slice in two and clear the table
         for (uint32_t t = tid; t < T; t += kThreads) {
           s_key[t] = kNoKey;
@@ -2133,6 +2138,7 @@ void report_overflow(const Session* s, const uint64_t* h) {
 
 void session_clear_guard(Session* s, hipStream_t st) {
   k_set_u64<<<1, 1, 0, st>>>(s->counters.as<unsigned long long>() + C_OVERFLOW, 0ull);
+  k_set_u64<<<1, 1, 0, st>>>(s->counters.as<unsigned long long>() + C_RMAX, 0ull);
 }
 
 ps_status devbuf_reserve(DevBuf& b, size_t bytes) {
@@ -2953,6 +2959,9 @@ static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, con
   stats.next_entries = (int64_t)(h[C_NEXT] - before[C_NEXT]);
   stats.final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL] + h[C_FINAL_PULL] - before[C_FINAL_PULL]);
   stats.pushed_final_adds = (int64_t)(h[C_FINAL] - before[C_FINAL]);
+  stats.reduce_bins = (int64_t)(h[C_RBINS] - before[C_RBINS]);
+  stats.reduce_slices = (int64_t)(h[C_RSLICES] - before[C_RSLICES]);
+  stats.reduce_max_records = (int64_t)h[C_RMAX];
   stats.pushed_edges = stats.edges_scanned - (int64_t)(h[C_EDGES_UNPUSHED] - before[C_EDGES_UNPUSHED]);
   stats.expand_launches = (int64_t)total_steps;
   stats.pull_levels = (int64_t)(h[C_PULLS] - before[C_PULLS]);

@@ -237,6 +237,9 @@ enum CounterIdx {
   C_PAUSED,      // slot levels held back a step by the per-step budget
   C_SH,          // bin shift of this step's records
   C_NB,          // bins of this step's records
+  C_RBINS,       // bins summed by k_reduce (with records)
+  C_RSLICES,     // slices summed (a bin whose keys overflow the table is summed in several)
+  C_RMAX,        // most records in one bin
   C_HIST_N,      // 32 bins: probe levels by floor(log2 of their out-edge count)
   C_HIST_E = C_HIST_N + 32,  // 32 bins: out-edges of those levels
   // entries and chunks of the frontier lists: kSubLists counters per parity
