@@ -530,9 +530,10 @@ def main():
         gr["achieved_gbs"] = gr["alg_bytes_per_launch"] / (gr["avg_launch_ms"] * 1e-3) / 1e9 if gr["avg_launch_ms"] > 0 else 0.0
         gr["frac"] = gr["achieved_gbs"] / HBM_PEAK_GBS
         gr["share_of_gpu_time"] = (acc["expand_ms"] if name == "push" else acc["pull_ms"]) / max(acc["total_ms"], 1e-9)
-        hb = prof["groups"][name]["hbm_bytes_per_launch"] if prof and name in prof.get("groups", {}) else None
-        gr["traffic_bytes_per_launch"] = hb
-        gr["waste_ratio"] = hb / gr["alg_bytes_per_launch"] if hb else None
+        pg = prof["groups"].get(name) if prof else None
+        # measured on the profile's own run of this workload (4 of its queries)
+        gr["traffic_bytes_per_launch"] = pg["hbm_bytes_per_launch"] if pg else None
+        gr["waste_ratio"] = pg["waste_ratio"] if pg else None
     dom = max(groups, key=lambda k: groups[k]["share_of_gpu_time"])
     D = groups[dom]
     whole = (pb + lb + walk_bytes(acc)) / queries
