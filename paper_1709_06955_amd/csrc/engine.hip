@@ -2803,6 +2803,39 @@ ps_status session_set_pull(ps_ctx* ctx, uint64_t threshold) {
   return PS_OK;
 }
 
+// Grows the tree pool and the ring to hold the trees of records recs
+// (bounds from session_bounds).  Only valid while no other query is
+// admitted: the buffers are replaced, and the captured level steps, which
+// point at the old ones, are dropped.
+ps_status session_fit_trees(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds) {
+  Session* s = ctx->sess;
+  hipStream_t st = ctx->stream;
+  uint64_t pool_need = 0, ring_need = 0;
+  for (size_t i = 0; i < bounds.size(); ++i) {
+    const uint64_t b = bounds[i];
+    if (b) pool_need += next_pow2(std::max<uint64_t>(2 * b, 64));
+    ring_need += ring_share(s, recs[i], b);
+  }
+  if (pool_need > s->tree_pool || ring_need > s->ring_cap) {
+    if (s->step_pair) {
+      PS_HIP(hipStreamSynchronize(st));
+      (void)hipGraphExecDestroy(s->step_pair);
+      s->step_pair = nullptr;
+    }
+    s->tree_pool = std::max(pool_need, s->tree_pool);
+    s->ring_cap = next_pow2(std::max(ring_need, s->ring_cap));
+    PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
+    for (DevBuf* b : {&s->t_parent, &s->t_node, &s->t_depth, &s->t_query, &s->t_weight})
+      PS_TRY(devbuf_reserve(*b, sizeof(int32_t) * (s->tree_pool + s->qmax)));
+    PS_TRY(devbuf_reserve(s->t_woff, sizeof(uint32_t) * s->tree_pool));
+    PS_TRY(devbuf_reserve(s->t_walks, sizeof(int32_t) * s->tree_pool));
+    PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
+    PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
+    s->tree_free.assign(1, {0, s->tree_pool});
+  }
+  return PS_OK;
+}
+
 static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
                                  const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt) {
   const auto t_start = std::chrono::steady_clock::now();
@@ -2831,32 +2864,7 @@ static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, con
   PS_TRY(session_begin(ctx, g, gv, qs, &recs));
   bool ready = false;
   PS_TRY(session_bounds(ctx, recs, &bounds, true, &ready));
-  uint64_t pool_need = 0, ring_need = 0;
-  for (size_t i = 0; i < bounds.size(); ++i) {
-    const uint64_t b = bounds[i];
-    if (b) pool_need += next_pow2(std::max<uint64_t>(2 * b, 64));
-    ring_need += ring_share(s, recs[i], b);
-  }
-  if (pool_need > s->tree_pool || ring_need > s->ring_cap) {
-    // Grow the tree pool / ring: only this call's records are admitted and
-    // their trees are not built yet, so the buffers can be replaced.  The
-    // captured level steps point at the old buffers and are dropped.
-    if (s->step_pair) {
-      PS_HIP(hipStreamSynchronize(st));
-      (void)hipGraphExecDestroy(s->step_pair);
-      s->step_pair = nullptr;
-    }
-    s->tree_pool = std::max(pool_need, s->tree_pool);
-    s->ring_cap = next_pow2(std::max(ring_need, s->ring_cap));
-    PS_TRY(devbuf_reserve(s->keys, sizeof(unsigned long long) * s->tree_pool));
-    for (DevBuf* b : {&s->t_parent, &s->t_node, &s->t_depth, &s->t_query, &s->t_weight})
-      PS_TRY(devbuf_reserve(*b, sizeof(int32_t) * (s->tree_pool + s->qmax)));
-    PS_TRY(devbuf_reserve(s->t_woff, sizeof(uint32_t) * s->tree_pool));
-    PS_TRY(devbuf_reserve(s->t_walks, sizeof(int32_t) * s->tree_pool));
-    PS_TRY(devbuf_reserve(s->ring, sizeof(int32_t) * s->ring_cap));
-    PS_TRY(devbuf_reserve(s->ring_k, sizeof(int32_t) * s->ring_cap));
-    s->tree_free.assign(1, {0, s->tree_pool});
-  }
+  PS_TRY(session_fit_trees(ctx, recs, bounds));
   PS_TRY(session_build(ctx, recs, bounds));
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));

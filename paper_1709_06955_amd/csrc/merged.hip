@@ -34,6 +34,8 @@ constexpr int kMBlock = 256;
 constexpr int kMaxDepth = PS_MAX_WALK_LEN + 1;
 constexpr unsigned long long kNone = ~0ull;
 constexpr uint32_t kWaveRow = 16;  // rows longer than this are swept by the whole wavefront
+constexpr uint64_t kMaxTable = 1ull << 30;  // places of one level's table (16 GB of keys and sums)
+constexpr int kMaxProbeM = 4096;             // linear-probe steps before an add is refused
 
 enum MCounter { M_OVERFLOW = 0, M_ENTRIES, M_EDGES, M_FINAL, M_COUNT };
 
@@ -47,13 +49,14 @@ __device__ __forceinline__ unsigned long long mmix(unsigned long long k) {
 }
 
 // Adds x to the entry of key, inserting it (linear probing).  A table holds
-// at least twice the entries it can receive; should it fill anyway the add
-// is dropped and the overflow counter set (the call then fails).
+// at least twice the entries it can receive unless capped at kMaxTable; a
+// probe sequence longer than kMaxProbeM (a table near full) drops the add
+// and sets the overflow counter, and the call fails with PS_ERR_OOM.
 __device__ __forceinline__ void table_add(unsigned long long* __restrict__ keys, double* __restrict__ vals,
                                           uint64_t mask, unsigned long long key, double x,
                                           unsigned long long* __restrict__ ctr) {
   uint64_t h = mmix(key) & mask;
-  for (uint64_t probe = 0; probe <= mask; ++probe) {
+  for (int probe = 0; probe < kMaxProbeM; ++probe) {
     const unsigned long long cur = keys[h];
     if (cur == key) {
       unsafeAtomicAdd(&vals[h], x);
@@ -67,6 +70,8 @@ __device__ __forceinline__ void table_add(unsigned long long* __restrict__ keys,
       }
     }
     h = (h + 1) & mask;
+    if ((probe & 255) == 255 && __hip_atomic_load(&ctr[M_OVERFLOW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return;  // the call already failed
   }
   atomicAdd(&ctr[M_OVERFLOW], 1ull);
 }
@@ -162,6 +167,9 @@ __global__ void __launch_bounds__(kMBlock) k_m_expand(ExpandArgs a) {
   const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   unsigned long long nfinal = 0;
   for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w * 64 < a.cap; w += waves) {
+    // once a table has refused an add the call fails: stop pushing
+    const unsigned long long ovf = __hip_atomic_load(&a.ctr[M_OVERFLOW], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (__builtin_amdgcn_readfirstlane((uint32_t)(ovf != 0))) break;  // wavefront-uniform
     const uint64_t slot = w * 64 + (uint64_t)lane;
     const unsigned long long k = slot < a.cap ? a.keys[slot] : kNone;
     const bool occ = k != kNone;
@@ -213,6 +221,7 @@ ps_status engine_merged(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const QueryR
   PS_TRY(session_begin(ctx, g, gv, {q}, &recs));
   bool ready = false;
   PS_TRY(session_bounds(ctx, recs, &bounds, true, &ready));
+  PS_TRY(session_fit_trees(ctx, recs, bounds));
   PS_TRY(session_build(ctx, recs, bounds));
   const int r = recs[0];
   const QueryDev d = s->h_rec[(size_t)r];
@@ -294,7 +303,9 @@ ps_status engine_merged(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const QueryR
         // distinct (parent, v) pairs: at most the pushed edges plus the
         // starts of depth dd-1, and at most (tree nodes of depth dd-1) * n
         const uint64_t bound = std::min<uint64_t>(sz[1] + hc[dd - 1], (uint64_t)hc[dd - 1] * (uint64_t)g->n);
-        ncap = pow2_at_least(std::max<uint64_t>(2 * bound, 1024));
+        // (at most kMaxTable places: a level with more distinct pairs than
+        // that holds fails the call with PS_ERR_OOM through the overflow flag)
+        ncap = std::min<uint64_t>(pow2_at_least(std::max<uint64_t>(2 * bound, 1024)), kMaxTable);
         PS_TRY(devbuf_reserve(s->m_keys[nxt], sizeof(unsigned long long) * ncap));
         PS_TRY(devbuf_reserve(s->m_vals[nxt], sizeof(double) * ncap));
         k_m_clear<<<m_grid(ncap), kMBlock, 0, stm>>>(s->m_keys[nxt].as<unsigned long long>(),

@@ -344,6 +344,9 @@ ps_status session_begin(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::v
 // walk pass has finished: waits for it (wait) or reports *ready = false.
 ps_status session_bounds(ps_ctx* ctx, const std::vector<int>& recs, std::vector<uint64_t>* bounds, bool wait,
                          bool* ready);
+// Grows the tree pool and the ring to hold the trees of records recs; only
+// while no other query is admitted.
+ps_status session_fit_trees(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds);
 // Admission, phase 2: tree regions, tree construction, probes queued.
 // PS_ERR_BUSY when tree or ring space is short.
 ps_status session_build(ps_ctx* ctx, const std::vector<int>& recs, const std::vector<uint64_t>& bounds);

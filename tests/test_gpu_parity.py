@@ -1142,3 +1142,19 @@ def test_abs_error_over_many_queries_and_runs(ps, ctx, er):
         print(f"er1k mode={mode}: AbsError mean {errs.mean():.5f}, max {errs.max():.5f} over {errs.size} queries",
               flush=True)
         assert errs.max() <= 0.1
+
+
+def test_merged_probing_on_a_fresh_context(ps, orc):
+    # The first call of a context sizes its tree pool from the query's walks
+    # (a regression test: merged probing once skipped that and returned
+    # PS_ERR_BUSY on a fresh context).
+    n, s, d = graphs.make_workload("er_1k_10k")
+    c = ps.Context(0)
+    try:
+        G = ps.Graph(c, n, s, d)
+        gpu = ps.ps_single_source(G, 0, 0.6, 0.1, 0.01, 1, probe_mode=ps.PROBE_MERGED)
+        ref, _ = orc.merged(orc.Graph(n, s, d), 0, orc.params(n, 0.6, 0.1, 0.01, eps_p=0.0), 1)
+        assert np.abs(gpu - ref).max() <= TOL_MODEL
+        G.close()
+    finally:
+        c.close()
