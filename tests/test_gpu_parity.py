@@ -132,7 +132,8 @@ def test_single_source_er_workload(ps, er, orc):
     gpu = ps.ps_single_source(G, 0, 0.6, 0.1, 0.01, 1)
     ref, st = orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1, precision="f32")
     _parity(gpu, ref, st, "er u=0")
-    _parity64_of(gpu, orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1, precision="f64"), "er u=0", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, 0, orc.params(n, 0.6, 0.1, 0.01), 1, precision="f64"),
+                 "er u=0", G.ctx.stats()["flip_allowance"], st)
     assert gpu[0] == 1.0
 
 
@@ -143,7 +144,8 @@ def test_single_source_power_law(ps, cl20k, orc, eps):
         gpu = ps.ps_single_source(G, int(u), 0.6, eps, 0.01, 3 + i)
         ref, st = orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i, precision="f32")
         _parity(gpu, ref, st, f"cl20k u={u} eps={eps}")
-        _parity64_of(gpu, orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i, precision="f64"), f"cl20k u={u} eps={eps}", G.ctx.stats()["flip_allowance"], st)
+        _parity64_of(gpu, orc.batch(O, int(u), orc.params(n, 0.6, eps, 0.01), 3 + i, precision="f64"),
+                     f"cl20k u={u} eps={eps}", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_single_source_small_slot_count(ps, cl20k, orc):
@@ -153,7 +155,8 @@ def test_single_source_small_slot_count(ps, cl20k, orc):
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 8, slots=3)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8, precision="f32")
     _parity(gpu, ref, st, "cl20k slots=3")
-    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8, precision="f64"), "cl20k slots=3", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 8, precision="f64"),
+                 "cl20k slots=3", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_no_pruning_and_walk_cap(ps, cl20k, orc):
@@ -162,7 +165,8 @@ def test_no_pruning_and_walk_cap(ps, cl20k, orc):
     gpu = ps.ps_single_source(G, u, 0.6, 0.2, 0.01, 4, eps_p=0.0, max_len=6)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4, precision="f32")
     _parity(gpu, ref, st, "no pruning L=6")
-    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4, precision="f64"), "no pruning L=6", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.2, 0.01, eps_p=0.0, L=6), 4, precision="f64"),
+                 "no pruning L=6", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_walk_range_shards_add_up(ps, cl20k, orc):
@@ -188,7 +192,8 @@ def test_bias_shift(ps, er, orc):
     gpu = ps.ps_single_source(G, 3, 0.6, 0.1, 0.01, 2, bias_shift=1)
     ref, st = orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True, precision="f32")
     _parity(gpu, ref, st, "bias shift")
-    _parity64_of(gpu, orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True, precision="f64"), "bias shift", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, 3, orc.params(n, 0.6, 0.1, 0.01), 2, bias_shift=True, precision="f64"),
+                 "bias shift", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_degenerate_queries(ps, ctx):
@@ -311,7 +316,8 @@ def test_hybrid_probe_matches_oracle(ps, ctx, cl20k, er, orc, pull):
                 if pull == 1 and n == 20_000:
                     assert st["pull_levels"] > 0
                 _parity(gpu, ref, ost, what)
-                _parity64_of(gpu, orc.batch(O, int(u), p, 5 + i, precision="f64", probe="hybrid", c0=c0), what, G.ctx.stats()["flip_allowance"], ost)
+                _parity64_of(gpu, orc.batch(O, int(u), p, 5 + i, precision="f64", probe="hybrid", c0=c0),
+                             what, G.ctx.stats()["flip_allowance"], ost)
 
 
 def test_hybrid_limits_equal_the_two_probes(ps, ctx, cl20k):
@@ -365,7 +371,8 @@ def test_hybrid_in_batch_shards_and_server(ps, ctx, cl20k, orc):
         ref, ost = orc.batch(O, q["u"], p, q["seed"], a, b, precision="f32", probe="hybrid", c0=q["hybrid_c0"])
         assert sw == ost["switched"]
         _parity(part, ref, ost, f"hybrid shard [{a}, {b})")
-        _parity64_of(part, orc.batch(O, q["u"], p, q["seed"], a, b, precision="f64", probe="hybrid", c0=q["hybrid_c0"]), f"hybrid shard [{a}, {b})", G.ctx.stats()["flip_allowance"], ost)
+        _parity64_of(part, orc.batch(O, q["u"], p, q["seed"], a, b, precision="f64", probe="hybrid", c0=q["hybrid_c0"]),
+                     f"hybrid shard [{a}, {b})", G.ctx.stats()["flip_allowance"], ost)
     srv = ps.Server(G, max_inflight=3)
     try:
         tickets = [srv.submit(q["u"], q["c"], q["eps"], q["delta"], q["seed"], k=q["k"],
@@ -487,7 +494,8 @@ def test_device_output_tensor(ps, er, orc):
     torch.cuda.synchronize()
     ref, st = orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3, precision="f32")
     _parity(out.cpu().numpy(), ref, st, "device output")
-    _parity64_of(out.cpu().numpy(), orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3, precision="f64"), "device output", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(out.cpu().numpy(), orc.batch(O, 7, orc.params(n, 0.6, 0.1, 0.01), 3, precision="f64"),
+                 "device output", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_dynamic_graph_equals_rebuilt(ps, ctx, orc):
@@ -511,7 +519,8 @@ def test_dynamic_graph_equals_rebuilt(ps, ctx, orc):
     O = orc.Graph(n, es, ed)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5, precision="f32")
     _parity(a, ref, st, "updated graph vs oracle")
-    _parity64_of(a, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5, precision="f64"), "updated graph vs oracle", fa, st)
+    _parity64_of(a, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 5, precision="f64"),
+                 "updated graph vs oracle", fa, st)
     _same_query(a, fa, b, fb, "updated vs rebuilt graph")
     # invalid updates are reported per edge and skipped
     pe, _ = G.update([es[0], 1, 2], [ed[0], 1, (ed[0] + 1) % n], [0, 0, 1])
@@ -537,7 +546,8 @@ def test_full_size_power_law_walk_shards(ps, ctx, orc):
         gpu = ps.ps_single_source(G, u, 0.6, 0.05, 0.01, 3 + i, walk_begin=0, walk_end=120)
         ref, st = orc.single_source(O, u, p, 3 + i, 0, 120, precision="f32")
         _parity(gpu, ref, st, f"cl1m u={u} walks [0,120)")
-        _parity64_of(gpu, orc.single_source(O, u, p, 3 + i, 0, 120, precision="f64"), f"cl1m u={u} walks [0,120)", G.ctx.stats()["flip_allowance"], st)
+        _parity64_of(gpu, orc.single_source(O, u, p, 3 + i, 0, 120, precision="f64"),
+                     f"cl1m u={u} walks [0,120)", G.ctx.stats()["flip_allowance"], st)
     # A shard whose probes outnumber the 1,024 slots (the pending ring wraps)
     # and whose deepest levels are pulled, against the oracle.
     u = int(q[0])
@@ -576,7 +586,8 @@ def test_full_size_hybrid_walk_shards(ps, ctx, orc):
                   flush=True)
             assert sw == st["switched"]
             _parity(gpu, ref, st, f"cl1m hybrid u={u} walks [{a},{b})")
-            _parity64_of(gpu, orc.batch(O, u, p, 3 + i, a, b, precision="f64", probe="hybrid", c0=c0), f"cl1m hybrid u={u} walks [{a},{b})", G.ctx.stats()["flip_allowance"], st)
+            _parity64_of(gpu, orc.batch(O, u, p, 3 + i, a, b, precision="f64", probe="hybrid", c0=c0),
+                         f"cl1m hybrid u={u} walks [{a},{b})", G.ctx.stats()["flip_allowance"], st)
     full = ps.ps_single_source(G, int(q[0]), 0.6, 0.05, 0.01, 3, probe_mode=2)
     assert full[int(q[0])] == 1.0 and full.min() >= 0.0
     assert np.delete(full, int(q[0])).max() <= 1.0
@@ -636,7 +647,8 @@ def test_server_interleaves_updates(ps, ctx, orc, mode):
         ref, st = orc.batch(O2, u, orc.params(n, 0.6, 0.1, 0.01), 9, precision="f32", probe="hybrid", c0=0.05)
         assert 0 < st["switched"] < st["tree_nodes"]
         _parity(r2, ref, st, "served hybrid after the update")
-        _parity64_of(r2, orc.batch(O2, u, orc.params(n, 0.6, 0.1, 0.01), 9, precision="f64", probe="hybrid", c0=0.05), "served hybrid after the update", f2, st)
+        _parity64_of(r2, orc.batch(O2, u, orc.params(n, 0.6, 0.1, 0.01), 9, precision="f64", probe="hybrid", c0=0.05),
+                     "served hybrid after the update", f2, st)
 
 
 def test_server_defaults_apply_to_every_query(ps, ctx, cl20k):
@@ -718,7 +730,8 @@ def test_push_and_pull_levels_match_oracle(ps, ctx, cl20k, orc, pull):
         assert st["pushed_edges"] == st["edges_scanned"] and st["pushed_final_adds"] == st["final_adds"]
     ref, ost = orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f32")
     _parity(gpu, ref, ost, f"pull_edges={pull}")
-    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f64"), f"pull_edges={pull}", G.ctx.stats()["flip_allowance"], ost)
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.05, 0.01), 11, precision="f64"),
+                 f"pull_edges={pull}", G.ctx.stats()["flip_allowance"], ost)
 
 
 @pytest.mark.parametrize("mode", [0, 2])
@@ -745,7 +758,8 @@ def test_tune_split_meets_theorem2_and_matches_oracle(ps, ctx, cl20k, orc, mode)
     probe = "hybrid" if mode == 2 else "deterministic"
     ref, st = orc.batch(O, u, p, 17, precision="f32", probe=probe, c0=ps.options().hybrid_c0 if mode == 2 else None)
     _parity(gpu, ref, st, f"tuned split mode {mode}")
-    _parity64_of(gpu, orc.batch(O, u, p, 17, precision="f64", probe=probe, c0=ps.options().hybrid_c0 if mode == 2 else None), f"tuned split mode {mode}", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, u, p, 17, precision="f64", probe=probe, c0=ps.options().hybrid_c0 if mode == 2 else None),
+                 f"tuned split mode {mode}", G.ctx.stats()["flip_allowance"], st)
     with pytest.raises(ps.ProbeSimError):
         ps.ps_tune_split(G, sample, c, eps, delta, eps_s=0.02)
 
@@ -763,7 +777,8 @@ def test_autotune_keeps_results(ps, ctx, cl20k, orc, tmp_path):
     gpu = ps.ps_single_source(G, u, 0.6, 0.1, 0.01, 19)
     ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19, precision="f32")
     _parity(gpu, ref, st, f"autotuned {t}")
-    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19, precision="f64"), f"autotuned {t}", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 19, precision="f64"),
+                 f"autotuned {t}", G.ctx.stats()["flip_allowance"], st)
 
 
 _T0 = time.perf_counter()
@@ -811,7 +826,8 @@ def test_full_size_batched_mixed_eps(ps, ctx, orc):
         fg = G.ctx.stats()["flip_allowance"]
         ref, st = orc.single_source(O, q["u"], p, q["seed"], 0, 40, precision="f32")
         _parity(gpu, ref, st, f"cl5m u={q['u']} eps={q['eps']} walks [0,40)")
-        _parity64_of(gpu, orc.single_source(O, q["u"], p, q["seed"], 0, 40, precision="f64"), f"cl5m u={q['u']} eps={q['eps']} walks [0,40)", fg, st)
+        _parity64_of(gpu, orc.single_source(O, q["u"], p, q["seed"], 0, 40, precision="f64"),
+                     f"cl5m u={q['u']} eps={q['eps']} walks [0,40)", fg, st)
 
 
 @pytest.mark.skipif(os.environ.get("PS_SKIP_FULL") == "1", reason="full-size case skipped")
@@ -905,7 +921,8 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
     gpu = ps.ps_single_source(G, u, 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=20)
     ref, st = orc.single_source(O, u, p, seed, 0, 20, precision="f32")
     _parity(gpu, ref, st, f"cl40m u={u} walks [0,20)")
-    _parity64_of(gpu, orc.single_source(O, u, p, seed, 0, 20, precision="f64"), f"cl40m u={u} walks [0,20)", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.single_source(O, u, p, seed, 0, 20, precision="f64"),
+                 f"cl40m u={u} walks [0,20)", G.ctx.stats()["flip_allowance"], st)
     for q in qn[:2]:
         t0 = time.perf_counter()
         whole = ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000)
@@ -936,7 +953,9 @@ def test_full_size_billion_edge_topk(ps, ctx, orc):
     ref, st = orc.batch(O, u, p, seed, 0, 20, precision="f32", probe="hybrid", c0=c0)
     assert sw == st["switched"]
     _parity(gpu, ref, st, f"cl40m hybrid u={u} walks [0,20), switched {sw} of {st['tree_nodes']}")
-    _parity64_of(gpu, orc.batch(O, u, p, seed, 0, 20, precision="f64", probe="hybrid", c0=c0), f"cl40m hybrid u={u} walks [0,20), switched {sw} of {st['tree_nodes']}", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, u, p, seed, 0, 20, precision="f64", probe="hybrid", c0=c0),
+                 f"cl40m hybrid u={u} walks [0,20), switched {sw} of {st['tree_nodes']}",
+                 G.ctx.stats()["flip_allowance"], st)
     for q in qn[:2]:
         t0 = time.perf_counter()
         ps.ps_single_source(G, int(q), 0.6, 0.025, 0.01, seed, walk_begin=0, walk_end=2000, probe_mode=2)
@@ -983,7 +1002,8 @@ def test_hub_rows_compaction_and_long_rows(ps, ctx, orc):
             _same_query(a, 0.0, b, 0.0, f"hub graph updated vs rebuilt u={u} pull={pull}")
         ref, st = orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 13, precision="f32")
         _parity(a, ref, st, f"hub graph u={u}")
-        _parity64_of(a, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 13, precision="f64"), f"hub graph u={u}", G.ctx.stats()["flip_allowance"], st)
+        _parity64_of(a, orc.batch(O, u, orc.params(n, 0.6, 0.1, 0.01), 13, precision="f64"),
+                     f"hub graph u={u}", G.ctx.stats()["flip_allowance"], st)
 
 
 def test_parameter_extremes(ps, ctx, er, orc):
@@ -995,7 +1015,8 @@ def test_parameter_extremes(ps, ctx, er, orc):
     gpu = ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=64, eps_t=1e-30)
     ref, st = orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f32")
     _parity(gpu, ref, st, "walk cap 64")
-    _parity64_of(gpu, orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f64"), "walk cap 64", G.ctx.stats()["flip_allowance"], st)
+    _parity64_of(gpu, orc.batch(O, 5, orc.params(n, 0.6, 0.3, 0.01, eps_t=1e-30, L=64), 2, precision="f64"),
+                 "walk cap 64", G.ctx.stats()["flip_allowance"], st)
     with pytest.raises(ps.ProbeSimError):
         ps.ps_single_source(G, 5, 0.6, 0.3, 0.01, 2, max_len=65)
     # eps close to 1 (few walks), c close to 0 and 1
@@ -1003,7 +1024,8 @@ def test_parameter_extremes(ps, ctx, er, orc):
         gpu = ps.ps_single_source(G, 9, c, eps, 0.01, 4)
         ref, st = orc.batch(O, 9, orc.params(n, c, eps, 0.01), 4, precision="f32")
         _parity(gpu, ref, st, f"c={c} eps={eps}")
-        _parity64_of(gpu, orc.batch(O, 9, orc.params(n, c, eps, 0.01), 4, precision="f64"), f"c={c} eps={eps}", G.ctx.stats()["flip_allowance"], st)
+        _parity64_of(gpu, orc.batch(O, 9, orc.params(n, c, eps, 0.01), 4, precision="f64"),
+                     f"c={c} eps={eps}", G.ctx.stats()["flip_allowance"], st)
     # top-k with k = n - 1 (every other node) and beyond
     nodes, vals = ps.ps_topk(G, 9, n - 1, 0.6, 0.2, 0.01, 4)
     assert sorted(nodes.tolist()) == [v for v in range(n) if v != 9]
