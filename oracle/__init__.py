@@ -83,6 +83,8 @@ def lib():
         L.orc_merged.argtypes = [C.c_void_p, C.c_int32, P(Params), C.c_uint64, C.c_int64, C.c_int64, C.c_int,
                                  P(C.c_double), P(Stats)]
         L.orc_topk.argtypes = [P(C.c_double), C.c_int32, C.c_int32, C.c_int32, P(C.c_int32), P(C.c_double)]
+        L.orc_pair_mc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_int64, C.c_int64,
+                                  P(C.c_int64)]
         _lib = L
     return _lib
 
@@ -231,3 +233,32 @@ def topk(scores: np.ndarray, u: int, k: int):
     if rc != ORC_OK:
         raise ValueError(f"topk failed with code {rc}")
     return nodes, vals
+
+
+def pair_mc(g: Graph, u: int, vs, c: float, r: int, seed: int, threads: int = 0) -> np.ndarray:
+    """Section 2.2's pairwise Monte Carlo: for each v in vs, the fraction of
+    r sample pairs of sqrt(c)-walks from u and v that meet, an unbiased
+    estimate of s(u, v) with standard deviation sqrt(s (1 - s) / r).  The
+    samples of each pair are split into ranges run on `threads` threads (the
+    C calls release the GIL); a sample's random numbers depend only on
+    (seed, v, sample index), so the result does not depend on the threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    vs = [int(v) for v in vs]
+    threads = threads or min(16, os.cpu_count() or 1)
+    parts = max(1, min(threads, int(r) // 4096))
+    bounds = [int(r) * i // parts for i in range(parts + 1)]
+
+    def run(task):
+        v, i = task
+        h = C.c_int64()
+        rc = lib().orc_pair_mc(g._h, int(u), v, c, C.c_uint64(seed), bounds[i], bounds[i + 1], C.byref(h))
+        if rc != ORC_OK:
+            raise ValueError(f"pair Monte Carlo failed with code {rc}")
+        return h.value
+
+    tasks = [(v, i) for v in vs for i in range(parts)]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        hits = list(ex.map(run, tasks))
+    per = np.array(hits, dtype=np.int64).reshape(len(vs), parts).sum(axis=1)
+    return per / float(r)

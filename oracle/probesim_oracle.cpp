@@ -28,6 +28,10 @@
 //                       (PROBE is linear in H_0, Lemma 2 / the Score
 //                       equation of Section 3.3); same estimate as orc_batch
 //                       at eps_p = 0
+//   orc_pair_mc         Section 2.2's pairwise Monte Carlo: the fraction of
+//                       pairs of sqrt(c)-walks from u and v that meet (an
+//                       unbiased estimate of s(u, v), the reference of the
+//                       pooled top-k evaluation on large graphs)
 //   orc_topk            Definition 2 (top-k by sorting the estimates)
 //
 // Readings where the paper is silent or inconsistent (see the design notes):
@@ -733,6 +737,57 @@ int orc_merged(const orc_graph* g, int32_t u, const orc_params* p, uint64_t seed
   for (const auto& xv : X[0]) acc[(size_t)xv.first] = xv.second;
   if (st) st->final_entries = (int64_t)X[0].size();
   finish(g, u, p, bias_shift, acc, out);
+  return ORC_OK;
+}
+
+// Pairwise Monte Carlo (Section 2.2, the baseline the paper compares with):
+// s(u, v) is the probability that a sqrt(c)-walk from u and one from v meet,
+// that is, stand on the same node after the same number of steps.  Sample k
+// runs the two walks in lockstep.  At step t each walk draws its own Philox
+// block, key (seed_lo, seed_hi ^ v), counter (k_lo, k_hi, t, side) with side
+// 0 for the walk from u and 1 for the walk from v; the walk stops when its
+// node has no in-neighbour or word 0 is below floor((1 - sqrt c) 2^32), else
+// it moves to the in-neighbour that words 2:1 pick, as in orc_walk.  The
+// sample ends when either walk stops, and counts a meeting when both move
+// onto the same node.  Walks are not truncated, so the fraction of samples
+// that meet is an unbiased estimate of s(u, v) itself.  Writes the meetings
+// among samples [k_begin, k_end); every sample meets when u = v.
+int orc_pair_mc(const orc_graph* g, int32_t u, int32_t v, double c, uint64_t seed, int64_t k_begin,
+                int64_t k_end, int64_t* hits) {
+  if (u < 0 || u >= g->n || v < 0 || v >= g->n) return ORC_ERANGE;
+  if (!(c > 0.0 && c < 1.0) || k_begin < 0 || k_end < k_begin) return ORC_EINVAL;
+  if (u == v) {
+    *hits = k_end - k_begin;
+    return ORC_OK;
+  }
+  const uint32_t t_stop = (uint32_t)std::floor((1.0 - std::sqrt(c)) * 4294967296.0);
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32) ^ (uint32_t)v};
+  int64_t met = 0;
+  for (int64_t k = k_begin; k < k_end; ++k) {
+    int32_t x[2] = {u, v};
+    for (uint32_t t = 0;; ++t) {
+      bool stop = false;
+      for (uint32_t side = 0; side < 2 && !stop; ++side) {
+        const uint32_t ctr[4] = {(uint32_t)k, (uint32_t)((uint64_t)k >> 32), t, side};
+        uint32_t w[4];
+        orc_philox4x32_10(ctr, key, w);
+        const int64_t d = indeg(g, x[side]);
+        if (d == 0 || w[0] < t_stop) {
+          stop = true;
+          break;
+        }
+        const uint64_t r = ((uint64_t)w[2] << 32) | w[1];
+        const uint64_t idx = (uint64_t)(((unsigned __int128)r * (uint64_t)d) >> 64);
+        x[side] = g->in_col[g->in_ptr[x[side]] + (int64_t)idx];
+      }
+      if (stop) break;
+      if (x[0] == x[1]) {
+        ++met;
+        break;
+      }
+    }
+  }
+  *hits = met;
   return ORC_OK;
 }
 

@@ -181,3 +181,33 @@ def test_merged_probing_equals_tree_batch_without_pruning(orc):
         assert sm["edges_scanned"] <= stt["edges_scanned"]
     with pytest.raises(ValueError):
         orc.merged(G, 0, orc.params(n, 0.6, 0.2, 0.01), 1)  # Rule 2 on: no merged form
+
+
+def test_pair_monte_carlo_against_closed_forms_and_exact_simrank(orc):
+    # Section 2.2: s(u, v) is the probability that sqrt(c)-walks from u and v
+    # meet.  Closed forms: a and b whose only in-neighbour is x meet after one
+    # step of each walk, s = c; one level further up (a <- x <- z, b <- y <- z)
+    # s = c^2; nodes without in-neighbours never meet, s = 0; s(u, u) = 1.
+    # Then every pair of a 40-node random graph against the exact solution of
+    # the SimRank equations, within 5 standard deviations of the estimate.
+    # The samples' random numbers depend only on (seed, v, sample), so the
+    # estimate does not depend on the thread count.
+    c, r = 0.6, 200_000
+    g = orc.Graph(3, [0, 0], [1, 2])
+    est = orc.pair_mc(g, 1, [2, 1, 0], c, r, 7)
+    assert abs(est[0] - c) <= 5 * math.sqrt(c * (1 - c) / r)
+    assert est[1] == 1.0 and est[2] == 0.0
+    g2 = orc.Graph(5, [4, 4, 2, 3], [2, 3, 0, 1])  # z=4 -> x=2, y=3; x -> a=0, y -> b=1
+    e2 = orc.pair_mc(g2, 0, [1], c, r, 9)[0]
+    assert abs(e2 - c * c) <= 5 * math.sqrt(c * c * (1 - c * c) / r)
+    s_, d_ = refs.random_graph(40, 0.1, 3)
+    S = refs.exact_simrank(40, s_, d_, c)
+    G = orc.Graph(40, s_, d_)
+    for u in (0, 7):
+        vs = list(range(40))
+        est = orc.pair_mc(G, u, vs, c, r, 11 + u)
+        sig = np.sqrt(np.maximum(S[u] * (1 - S[u]), 1.0 / r) / r)
+        assert np.all(np.abs(est - S[u]) <= 5 * sig), np.abs(est - S[u]) / sig
+    a = orc.pair_mc(G, 0, range(40), c, 20_000, 5, threads=1)
+    b = orc.pair_mc(G, 0, range(40), c, 20_000, 5, threads=6)
+    assert np.array_equal(a, b)
