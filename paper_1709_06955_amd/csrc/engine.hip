@@ -1851,22 +1851,57 @@ __device__ __forceinline__ long long pull_term(float h, float thr, float sc, flo
   return h > thr ? to_grid((h * sc) * inv) : 0ll;
 }
 
-// Score of in-neighbour x in this lane's column.  With kMap the row is read
-// only when the row map says it may be nonzero (all lanes of a wavefront
-// share x); that saves the gathers of a sparse matrix and costs a dependent
-// load on a dense one.
+constexpr uint32_t kPullBatch = 4;  // rows each lane group gathers per round
+
+// Grid sum of this lane's column over in-edges cols[0, cnt) of one target,
+// for lane group grp of T groups.  Per 64 edges: each lane loads one in-edge
+// source (and, with kMap, that row's map byte: the row is read only when it
+// may hold a nonzero score), the sources kept are packed into the low lanes
+// by a forward lane permute, and then each group gathers its share of the
+// kept rows kPullBatch at a time, so a target's edges cost a few rounds of
+// independent loads rather than a chain of dependent ones.  Every lane of the
+// wavefront must call this (the lanes act as edge slots first); only the
+// loads of inactive columns are skipped.  The sum is exact on the grid, so
+// the order of the edges does not matter.
 template <bool kMap>
-__device__ __forceinline__ float lane_score(const DenseArgs& a, const float* m, int32_t x) {
-  if (kMap && !a.map_cur[x]) return 0.0f;
-  return m[(size_t)x * kLanes];
+__device__ __forceinline__ long long pull_edges(const DenseArgs& a, const LaneInfo& li, const float* m,
+                                                const int32_t* __restrict__ cols, uint32_t cnt, float inv, int grp,
+                                                uint32_t T) {
+  const int lane = lane_id();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  long long sum = 0;
+  for (uint32_t b = 0; b < cnt; b += 64) {
+    const uint32_t k = b + (uint32_t)lane;
+    const int32_t x = k < cnt ? cols[k] : -1;
+    bool keep = x >= 0;
+    if (kMap && keep) keep = a.map_cur[x] != 0;
+    const unsigned long long mk = __ballot(keep);
+    const uint32_t nk = (uint32_t)__popcll(mk);
+    // kept sources to lanes 0..nk-1 in edge order, the others after them
+    const uint32_t pos = keep ? (uint32_t)__popcll(mk & lt) : nk + (uint32_t)__popcll(~mk & lt);
+    const int32_t xc = __builtin_amdgcn_ds_permute((int)(pos << 2), x);
+    for (uint32_t j = 0; j < nk; j += T * kPullBatch) {
+      float h[kPullBatch];
+#pragma unroll
+      for (uint32_t t = 0; t < kPullBatch; ++t) {
+        const uint32_t q = j + t * T + (uint32_t)grp;
+        const int32_t xs = __shfl(xc, (int)(q & 63u), 64);
+        h[t] = 0.0f;
+        if (li.active && q < nk) h[t] = m[(size_t)xs * kLanes];
+      }
+#pragma unroll
+      for (uint32_t t = 0; t < kPullBatch; ++t) sum += pull_term(h[t], li.thr, li.sc, inv);
+    }
+  }
+  return sum;
 }
 
 // The pulls of one pass.  A wavefront works on one target at a time; its 64
 // lanes form 64/L groups of L lanes (L = the power of two covering the
-// columns in use), lane g handling column g % L of every L-th in-edge, so few
-// columns still keep the whole wavefront busy.  Group sums are combined by
-// shuffles.  Short in-rows are finished per target, long in-rows summed in
-// kPullChunk-edge chunks into partial sums.
+// columns in use), lane g handling column g % L of every (64/L)-th kept
+// in-edge, so few columns still keep the whole wavefront busy.  Group sums
+// are combined by shuffles.  Short in-rows are finished per target, long
+// in-rows summed in kPullChunk-edge chunks into partial sums.
 template <bool kMap>
 __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& li, const DenseVer& dv, int col,
                                            int grp, int L, uint64_t wave, uint64_t nwaves, unsigned long long gw,
@@ -1878,18 +1913,7 @@ __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& l
   for (uint64_t v = wave; v < (uint64_t)a.n; v += nwaves) {
     const uint2 row = dv.in_rows[v];
     if (row.y > kPullLane) continue;  // long in-row: chunks + k_dense_fin
-    long long s0 = 0, s1 = 0;
-    if (li.active) {
-      const float inv = dv.inv_indeg[v];
-      uint32_t k = (uint32_t)grp;
-      for (; k + T < row.y; k += 2 * T) {
-        const int32_t x0 = dv.in_col[row.x + k], x1 = dv.in_col[row.x + k + T];
-        s0 += pull_term(lane_score<kMap>(a, m, x0), li.thr, li.sc, inv);
-        s1 += pull_term(lane_score<kMap>(a, m, x1), li.thr, li.sc, inv);
-      }
-      if (k < row.y) s0 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k]), li.thr, li.sc, inv);
-    }
-    long long q = s0 + s1;
+    long long q = pull_edges<kMap>(a, li, m, dv.in_col + row.x, row.y, dv.inv_indeg[v], grp, T);
     for (int off = L; off < 64; off <<= 1) q += __shfl_xor(q, off, 64);
     inedges += row.y;
     const bool nz = dense_finish(a, li, col, writer, (int32_t)v, q, gw, nfinal, nzrows);
@@ -1901,17 +1925,8 @@ __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& l
     const uint2 row = dv.in_rows[ch.x];
     const uint32_t e = min(row.y, (uint32_t)ch.y + kPullChunk);
     inedges += e - (uint32_t)ch.y;
-    long long s0 = 0, s1 = 0;
-    if (li.active) {
-      const float inv = dv.inv_indeg[ch.x];
-      uint32_t k = (uint32_t)ch.y + (uint32_t)grp;
-      for (; k + T < e; k += 2 * T) {
-        s0 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k]), li.thr, li.sc, inv);
-        s1 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k + T]), li.thr, li.sc, inv);
-      }
-      if (k < e) s0 += pull_term(lane_score<kMap>(a, m, dv.in_col[row.x + k]), li.thr, li.sc, inv);
-    }
-    long long part = s0 + s1;
+    long long part =
+        pull_edges<kMap>(a, li, m, dv.in_col + row.x + ch.y, e - (uint32_t)ch.y, dv.inv_indeg[ch.x], grp, T);
     for (int off = L; off < 64; off <<= 1) part += __shfl_xor(part, off, 64);
     if (writer && li.active && part > 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(&a.npart[(size_t)ch.x * kLanes + col]),
@@ -1919,7 +1934,7 @@ __device__ __forceinline__ void dense_rows(const DenseArgs& a, const LaneInfo& l
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_dense(DenseArgs a) {
+__global__ void __launch_bounds__(kBlock, 8) k_dense(DenseArgs a) {
   __shared__ unsigned long long s_nz;
   const unsigned long long ghi = a.ctr[C_GHI], gw = a.ctr[C_GW];
   if (gw == 0) return;

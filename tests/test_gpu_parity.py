@@ -1180,3 +1180,51 @@ def test_merged_probing_on_a_fresh_context(ps, orc):
         G.close()
     finally:
         c.close()
+
+
+def test_pooled_topk_accuracy_on_the_1m_graph(ps, ctx, orc):
+    # Section 6.2 judges top-k answers on graphs too large for the Power
+    # Method by pooling: the top-k lists of the compared methods are merged,
+    # each pooled node's s(u, v) is estimated by pairwise Monte Carlo
+    # (Section 2.2) to an error far below theirs, and the best k of the pool
+    # stand for the truth.  Pooled here: the three PROBE forms (Alg. 2,
+    # Alg. 4, the switch of Section 4.4) on the 1M-node / 10M-edge workload at
+    # eps = 0.05, k = 50, for three query nodes; every pooled node gets 4e6
+    # Monte Carlo samples (standard deviation at most 2.5e-4).  Asserted for
+    # every method: Definition 1 on each pooled node, |s^(u,v) - s(u,v)| <=
+    # eps, and at every rank i the pooled truth's i-th value exceeds the
+    # method's i-th by at most 2 eps (the pool's i-th best is at most the
+    # graph's, and sorting eps-accurate estimates loses at most 2 eps), both
+    # with 5 reference standard deviations added.  AbsError over the pool,
+    # Precision@50, NDCG@50 and tau_50 are printed.
+    from tests import topk_metrics as tm
+
+    n, s, d = graphs.make_workload("cl_1m_10m")
+    G = ps.Graph(ctx, n, s, d)
+    O = orc.Graph(n, s, d)
+    q = graphs.query_nodes(n, d, 32)
+    eps, k, r = 0.05, 50, 4_000_000
+    for i in (0, 5, 17):
+        u = int(q[i])
+        est, lists = {}, {}
+        for mode, name in ((0, "deterministic"), (1, "randomized"), (2, "switch")):
+            est[name] = ps.ps_single_source(G, u, 0.6, eps, 0.01, 40 + i, probe_mode=mode)
+            lists[name] = tm.true_topk(est[name], u, k)
+        pool = np.unique(np.concatenate(list(lists.values())))
+        t0 = time.time()
+        ref = orc.pair_mc(O, u, pool, 0.6, r, 500 + i)
+        sig = float(np.sqrt(np.maximum(ref * (1 - ref), 1.0 / r) / r).max())
+        row = np.zeros(n)
+        row[pool] = ref
+        truth = tm.true_topk(row, u, k)
+        print(f"cl1m pooled u={u}: {pool.size} pooled nodes, reference in {time.time() - t0:.1f} s "
+              f"(max sd {sig:.1e}), pooled truth {row[truth[0]]:.4f} .. {row[truth[-1]]:.4f}", flush=True)
+        for name in est:
+            e = np.abs(est[name][pool] - ref)
+            gap = float((row[truth] - row[lists[name]]).max())
+            print(f"  {name}: AbsError over the pool mean {e.mean():.5f} max {e.max():.5f}, worst rank gap "
+                  f"{gap:.4f}, Precision@50 {tm.precision_at_k(lists[name], truth):.3f}, NDCG@50 "
+                  f"{tm.ndcg_at_k(lists[name], truth, row):.4f}, tau_50 {tm.kendall_tau_k(lists[name], row):.3f}",
+                  flush=True)
+            assert e.max() <= eps + 5 * sig
+            assert gap <= 2 * eps + 5 * sig
