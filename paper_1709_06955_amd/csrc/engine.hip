@@ -2664,6 +2664,7 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* 
       ctx->ev_pool.push_back(ev);
     }
     for (uint64_t t = 0; t < count; ++t) {
+      TraceRange tr("probesim level step");
       launch_step(s, (int)(s->steps & 1), st, ctx->ev_pool[3 * t], ctx->ev_pool[3 * t + 1],
                   ctx->ev_pool[3 * t + 2]);
       s->steps++;
@@ -2700,11 +2701,13 @@ ps_status session_steps(ps_ctx* ctx, uint64_t count, double* expand_ms, double* 
       PS_HIP(e);
     }
     for (; count >= 2; count -= 2) {
+      TraceRange tr("probesim level steps (2, graph)");
       PS_HIP(hipGraphLaunch(s->step_pair, st));
       s->steps += 2;
     }
   }
   for (; count > 0; --count) {
+    TraceRange tr("probesim level step");
     launch_step(s, (int)(s->steps & 1), st, nullptr, nullptr, nullptr);
     s->steps++;
   }
@@ -2876,11 +2879,14 @@ static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, con
 
   std::vector<int> recs;
   std::vector<uint64_t> bounds;
-  PS_TRY(session_begin(ctx, g, gv, qs, &recs));
-  bool ready = false;
-  PS_TRY(session_bounds(ctx, recs, &bounds, true, &ready));
-  PS_TRY(session_fit_trees(ctx, recs, bounds));
-  PS_TRY(session_build(ctx, recs, bounds));
+  {
+    TraceRange tr("probesim walks and trees");
+    PS_TRY(session_begin(ctx, g, gv, qs, &recs));
+    bool ready = false;
+    PS_TRY(session_bounds(ctx, recs, &bounds, true, &ready));
+    PS_TRY(session_fit_trees(ctx, recs, bounds));
+    PS_TRY(session_build(ctx, recs, bounds));
+  }
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
   uint64_t levels = s->h_ctr[C_LEVELS] - before[C_LEVELS];
@@ -2901,6 +2907,7 @@ static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, con
   uint64_t total_steps = 0;
   // runs `cnt` level steps (in batches of 256 when progress is printed)
   auto run_steps = [&](uint64_t cnt) -> ps_status {
+    TraceRange tr("probesim level steps");
     while (cnt) {
       const uint64_t b = progress ? std::min<uint64_t>(cnt, 256) : cnt;
       PS_TRY(session_steps(ctx, b, &expand_ms, &pull_ms));
@@ -2956,10 +2963,13 @@ static ps_status engine_run_core(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, con
     }
   }
   std::vector<double> flips((size_t)nq, 0.0);
-  for (int i = 0; i < nq; ++i) {
-    QueryOut o = outs[(size_t)i];
-    if (!o.flip) o.flip = &flips[(size_t)i];
-    PS_TRY(session_finish(ctx, g, recs[(size_t)i], qs[(size_t)i], o));
+  {
+    TraceRange tr("probesim finish");
+    for (int i = 0; i < nq; ++i) {
+      QueryOut o = outs[(size_t)i];
+      if (!o.flip) o.flip = &flips[(size_t)i];
+      PS_TRY(session_finish(ctx, g, recs[(size_t)i], qs[(size_t)i], o));
+    }
   }
   PS_HIP(hipMemcpyAsync(s->h_ctr, s->counters.p, sizeof(uint64_t) * C_COUNT, hipMemcpyDeviceToHost, st));
   PS_HIP(hipStreamSynchronize(st));
@@ -3013,6 +3023,7 @@ ps_status copy_out(void* dst, const void* src, size_t bytes, hipStream_t st) {
 // go through the level-step engine together.
 ps_status engine_run(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const std::vector<QueryRun>& qs,
                      const std::vector<QueryOut>& outs, int slots_opt, int64_t pull_opt) {
+  TraceRange tr("probesim queries");
   std::vector<QueryRun> rest;
   std::vector<QueryOut> rest_out;
   std::vector<size_t> merged;

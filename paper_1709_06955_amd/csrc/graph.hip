@@ -370,6 +370,7 @@ extern "C" ps_status ps_graph_edges(const ps_graph* g, int64_t cap, int32_t* src
 
 ps_status graph_apply_updates(ps_graph* g, int64_t k, const int32_t* src, const int32_t* dst, const uint8_t* op,
                               int32_t* per_edge, uint64_t* version) {
+  TraceRange tr("probesim graph update");
   if (!g || k < 0 || (k > 0 && (!src || !dst || !op))) return PS_ERR_INVALID_ARG;
   for (int64_t i = 0; i < k; ++i) {
     if (src[i] < 0 || src[i] >= g->n || dst[i] < 0 || dst[i] >= g->n) return PS_ERR_NODE_RANGE;

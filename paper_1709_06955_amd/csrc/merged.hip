@@ -214,6 +214,7 @@ uint64_t pow2_at_least(uint64_t x) {
 
 ps_status engine_merged(ps_ctx* ctx, ps_graph* g, GraphVersion* gv, const QueryRun& q, const QueryOut& out,
                         ps_stats* st) {
+  TraceRange tr("probesim merged probing");
   Session* s = ctx->sess;
   hipStream_t stm = ctx->stream;
   std::vector<int> recs;

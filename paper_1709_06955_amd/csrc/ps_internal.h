@@ -13,7 +13,19 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "probesim.h"
+
+// A named range on a profiler's host timeline (rocprofv3 --marker-trace):
+// the query phases, each batch of level steps, graph updates and top-k
+// selections.  Without a profiler attached it costs one library call.
+struct TraceRange {
+  explicit TraceRange(const char* what) { roctxRangePushA(what); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 #define PS_HIP(x)                                  \
   do {                                             \

@@ -404,6 +404,7 @@ int64_t padded_for(int32_t k) {
 ps_status select_topk(SelectBufs& b, const double* s, int32_t n, int32_t u, int32_t k, int32_t* out_ids,
                       double* out_s, hipStream_t st) {
   if (k < 1 || k > n - 1) return PS_ERR_INVALID_ARG;
+  TraceRange tr("probesim top-k selection");
   const int64_t padded = padded_for(k);
   PS_TRY(devbuf_reserve(b.state, sizeof(SelState)));
   PS_TRY(devbuf_reserve(b.keys, sizeof(unsigned long long) * (size_t)padded));
