@@ -1183,7 +1183,7 @@ def test_merged_probing_on_a_fresh_context(ps, orc):
 
 
 def test_pooled_topk_accuracy_on_the_1m_graph(ps, ctx, orc):
-    # Section 6.2 judges top-k answers on graphs too large for the Power
+    # Section 6.2 evaluates top-k answers on graphs too large for the Power
     # Method by pooling: the top-k lists of the compared methods are merged,
     # each pooled node's s(u, v) is estimated by pairwise Monte Carlo
     # (Section 2.2) to an error far below theirs, and the best k of the pool
